@@ -1,0 +1,215 @@
+"""ctypes front-end of the CPU ABEA oracle -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It builds ``oracle/liboracle.so`` from
+``abea_oracle.c`` with gcc when the library is missing.  Nothing here is shared
+with the HIP library.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "abea_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+READ_OK, READ_EMPTY, READ_BAND_LOST, READ_BAD_RANK = 0, 1, 2, 3
+STATUS_NAMES = {0: "ok", 1: "empty", 2: "band_lost", 3: "bad_rank"}
+
+FORM_LITERAL = 1
+PLANT_SK_REVERSED = 2
+PLANT_DROP_UP_EMISSION = 4
+PLANT_EVENT_OFF_BY_ONE = 8
+
+GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-pthread"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, no fused multiply-add except the
+    explicit fmaf of the model scaling)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", *GCC_FLAGS, SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("cells", ctypes.c_int64),
+        ("n_bands", ctypes.c_int64),
+        ("kmer_moves", ctypes.c_int64),
+        ("path_len", ctypes.c_int64),
+        ("min_margin", ctypes.c_double),
+        ("min_move_margin", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i64, i32, u32, f32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_float
+        L.oracle_transitions.argtypes = [i64, i64, P]
+        L.oracle_transitions.restype = None
+        L.oracle_model_terms.argtypes = [i64, P, P, P]
+        L.oracle_model_terms.restype = None
+        L.oracle_emission.argtypes = [f32, f32, f32, f32, f32, u32]
+        L.oracle_emission.restype = f32
+        L.oracle_band_limits.argtypes = [i64, i64, i64, i64, i32, P, P]
+        L.oracle_band_limits.restype = None
+        L.oracle_align.argtypes = [P, i64, i64, P, i64, P, P, P, P, i64, f32, f32, i32, u32,
+                                   P, P, P, P, P]
+        L.oracle_align.restype = ctypes.c_int
+        L.oracle_align_batch.argtypes = [i32, P, i64, P, P, P, P, P, P, P, P, P, i64, i32, u32, i32,
+                                         P, P, P, P, P, P]
+        L.oracle_align_batch.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def transitions(n_events: int, n_kmers: int) -> np.ndarray:
+    out = np.zeros(3, np.float32)
+    lib().oracle_transitions(n_events, n_kmers, _p(out))
+    return out
+
+
+def model_terms(level_stdv: np.ndarray):
+    s = np.ascontiguousarray(level_stdv, np.float32)
+    c = np.zeros_like(s)
+    h = np.zeros_like(s)
+    lib().oracle_model_terms(s.shape[0], _p(s), _p(c), _p(h))
+    return c, h
+
+
+def emission(x, mu, sigma, c, h, flags: int = 0) -> np.float32:
+    return np.float32(lib().oracle_emission(float(x), float(mu), float(sigma), float(c), float(h), flags))
+
+
+def band_limits(E: int, K: int, n_e: int, n_k: int, W: int):
+    lo = np.zeros(1, np.int64)
+    hi = np.zeros(1, np.int64)
+    lib().oracle_band_limits(E, K, n_e, n_k, W, _p(lo), _p(hi))
+    return int(lo[0]), int(hi[0])
+
+
+@dataclasses.dataclass
+class Result:
+    status: int
+    score: np.float32
+    pairs: np.ndarray  # int32 [n, 2] (event_idx, kmer_idx)
+    cells: int
+    n_bands: int
+    kmer_moves: int
+    min_margin: float
+    min_move_margin: float
+    trace: Optional[np.ndarray] = None  # uint8 [n_bands, W]
+    ll: Optional[np.ndarray] = None  # int64 [n_bands, 2]
+
+
+class Model:
+    """Pore model with its emission terms, prepared once."""
+
+    def __init__(self, level_mean: np.ndarray, level_stdv: np.ndarray):
+        self.level_mean = np.ascontiguousarray(level_mean, np.float32)
+        self.level_stdv = np.ascontiguousarray(level_stdv, np.float32)
+        self.c, self.h = model_terms(self.level_stdv)
+
+    @property
+    def n(self) -> int:
+        return int(self.level_mean.shape[0])
+
+
+def align(
+    event_mean: np.ndarray,
+    ranks: np.ndarray,
+    model: Model,
+    scale: float,
+    shift: float,
+    W: int,
+    flags: int = 0,
+    want_trace: bool = False,
+) -> Result:
+    """Align one read.  ``event_mean`` is a float32 vector (or an [n, 3] event
+    table whose first column is the mean)."""
+    ev = np.ascontiguousarray(event_mean, np.float32)
+    stride = 1 if ev.ndim == 1 else ev.shape[1]
+    n_e = ev.shape[0]
+    rk = np.ascontiguousarray(ranks, np.uint32)
+    n_k = rk.shape[0]
+    pairs = np.zeros((n_e + n_k + 1, 2), np.int32)
+    score = np.zeros(1, np.float32)
+    st = _Stats()
+    nb = n_e + n_k + 1
+    trace = np.zeros((nb, W), np.uint8) if want_trace else None
+    ll = np.zeros((nb, 2), np.int64) if want_trace else None
+    s = lib().oracle_align(
+        _p(ev), stride, n_e, _p(rk), n_k, _p(model.level_mean), _p(model.level_stdv),
+        _p(model.c), _p(model.h), model.n, float(np.float32(scale)), float(np.float32(shift)),
+        W, flags, _p(pairs), _p(score), ctypes.byref(st),
+        _p(trace) if want_trace else None, _p(ll) if want_trace else None,
+    )
+    if s < 0:
+        raise RuntimeError(f"oracle_align error {s}")
+    return Result(
+        s, score[0], pairs[: st.path_len].copy(), st.cells, st.n_bands, st.kmer_moves,
+        st.min_margin, st.min_move_margin, trace, ll,
+    )
+
+
+@dataclasses.dataclass
+class BatchResult:
+    status: np.ndarray
+    score: np.ndarray
+    path_len: np.ndarray
+    cells: np.ndarray
+    pair_slot: np.ndarray
+    pairs: np.ndarray  # int32 [capacity, 2]
+
+    def read_pairs(self, r: int) -> np.ndarray:
+        s = int(self.pair_slot[r])
+        return self.pairs[s : s + int(self.path_len[r])]
+
+
+def align_batch(batch, model: Model, W: int, n_threads: int = 1, flags: int = 0) -> BatchResult:
+    """Align a synthetic batch (``paper_2101_05012_amd.synth.Batch``) on
+    ``n_threads`` host threads."""
+    n = batch.n_reads
+    ev = np.ascontiguousarray(batch.events, np.float32)
+    sizes = np.diff(batch.event_offset) + np.diff(batch.kmer_offset)
+    slot = np.zeros(n + 1, np.uint64)
+    np.cumsum(sizes, out=slot[1:])
+    pairs = np.zeros((int(slot[-1]) + 1, 2), np.int32)
+    path_len = np.zeros(n, np.int64)
+    score = np.zeros(n, np.float32)
+    status = np.zeros(n, np.int32)
+    cells = np.zeros(n, np.int64)
+    eo = np.ascontiguousarray(batch.event_offset, np.uint64)
+    ko = np.ascontiguousarray(batch.kmer_offset, np.uint64)
+    rk = np.ascontiguousarray(batch.ranks, np.uint32)
+    sc = np.ascontiguousarray(batch.scale, np.float32)
+    sh = np.ascontiguousarray(batch.shift, np.float32)
+    err = lib().oracle_align_batch(
+        n, _p(ev), 3, _p(eo), _p(rk), _p(ko), _p(sc), _p(sh),
+        _p(model.level_mean), _p(model.level_stdv), _p(model.c), _p(model.h), model.n,
+        W, flags, n_threads, _p(slot), _p(pairs), _p(path_len), _p(score), _p(status), _p(cells),
+    )
+    if err < 0:
+        raise RuntimeError(f"oracle_align_batch error {err}")
+    return BatchResult(status, score, path_len, cells, slot[:-1], pairs)

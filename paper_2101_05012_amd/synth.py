@@ -1,0 +1,253 @@
+"""Seeded synthetic ABEA inputs: pore models, reads, events and batches.
+
+This module only draws random numbers and lays them out; it holds none of the
+alignment's arithmetic, so both the HIP path and the CPU oracle can take their
+inputs from it.
+
+The workloads stand in for the nanopore datasets the thesis measures on
+(Ch. 5, Table "Information of the datasets": NA12878 D_small, D_ligation,
+D_rapid), which are not available here.  What is drawn, and why:
+
+* Pore model over all 4^k k-mers (Ch. 5 §5.2.1, figure "an example
+  pore-model"): level_mean ~ U(60, 130) pA, level_stdv ~ U(1, 3), float32.
+  The k-mer rank is the base-4 number of the k-mer (A=0, C=1, G=2, T=3, first
+  base most significant).
+* A read is a uniform i.i.d. ACGT reference of length L; it has n_k = L-k+1
+  k-mers.  Per read, scale ~ U(0.9, 1.1) and shift ~ U(-5, 5) (the per-read
+  read-model scaling paragraph after Alg. 5.3).
+* Events: each k-mer position is skipped (0 events) with probability 0.05,
+  otherwise it emits Geometric(p=1/1.8) events on {1, 2, ...} (mean 1.8), so
+  there are about 1.71 events per k-mer (over-segmentation, §5.2.3: "usually
+  by a factor 1.5-2").  Each event has mean ~ N(level_mean*scale + shift,
+  level_stdv), stdv ~ U(0.5, 3), duration ~ Exp(mean 2.5 ms), all float32.
+  Only the mean is read by the alignment (Alg. 5.3).
+
+Every read draws from its own stream ``default_rng([config_seed, read_id])``,
+so a read's bytes do not depend on which batch it is in or where.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+
+MODEL_SEED_BASE = 1000
+CONFIG_SEED_BASE = 2026_0000
+
+SKIP_PROB = 0.05
+EVENTS_PER_KMER_MEAN = 1.8
+
+# Workload shapes.  W is the band width, k the k-mer length.
+CONFIGS = {
+    0: dict(name="plain-64x1kb", n_reads=64, W=100, k=6, lengths="fixed1000"),
+    1: dict(name="plain-4000-lognormal5kb", n_reads=4000, W=100, k=6, lengths="lognormal5k"),
+    2: dict(name="uneven-20000", n_reads=20000, W=100, k=6, lengths="mixed"),
+    3: dict(name="serving-lognormal8kb", n_reads=None, W=100, k=6, lengths="lognormal8k"),
+    4: dict(name="ultralong-200", n_reads=200, W=100, k=6, lengths="ultralong"),
+}
+
+
+@dataclasses.dataclass
+class PoreModel:
+    k: int
+    level_mean: np.ndarray  # float32 [4^k]
+    level_stdv: np.ndarray  # float32 [4^k]
+
+
+@dataclasses.dataclass
+class Read:
+    events: np.ndarray  # float32 [n_e, 3] = (mean, stdv, duration)
+    ranks: np.ndarray  # uint32 [n_k]
+    scale: np.float32
+    shift: np.float32
+
+
+@dataclasses.dataclass
+class Batch:
+    """Concatenated reads with exclusive prefix-sum offsets (the serialised
+    batch layout of Ch. 5 §5.4.2.1, Alg. 5.9)."""
+
+    events: np.ndarray  # float32 [sum n_e, 3]
+    event_offset: np.ndarray  # uint64 [n+1]
+    ranks: np.ndarray  # uint32 [sum n_k]
+    kmer_offset: np.ndarray  # uint64 [n+1]
+    scale: np.ndarray  # float32 [n]
+    shift: np.ndarray  # float32 [n]
+
+    @property
+    def n_reads(self) -> int:
+        return int(self.scale.shape[0])
+
+    def n_events(self, i: int) -> int:
+        return int(self.event_offset[i + 1] - self.event_offset[i])
+
+    def n_kmers(self, i: int) -> int:
+        return int(self.kmer_offset[i + 1] - self.kmer_offset[i])
+
+    def read(self, i: int) -> Read:
+        e0, e1 = int(self.event_offset[i]), int(self.event_offset[i + 1])
+        k0, k1 = int(self.kmer_offset[i]), int(self.kmer_offset[i + 1])
+        return Read(self.events[e0:e1], self.ranks[k0:k1], self.scale[i], self.shift[i])
+
+    def subset(self, idx: Sequence[int]) -> "Batch":
+        return make_batch([self.read(int(i)) for i in idx])
+
+
+def pore_model(k: int, seed: Optional[int] = None) -> PoreModel:
+    rng = np.random.default_rng(MODEL_SEED_BASE + k if seed is None else seed)
+    n = 4**k
+    lm = rng.uniform(60.0, 130.0, n).astype(np.float32)
+    ls = rng.uniform(1.0, 3.0, n).astype(np.float32)
+    return PoreModel(k, lm, ls)
+
+
+def kmer_ranks(bases: np.ndarray, k: int) -> np.ndarray:
+    """Rank of every k-mer of a base array (values 0..3), first base most
+    significant."""
+    L = bases.shape[0]
+    n = L - k + 1
+    if n <= 0:
+        return np.zeros(0, np.uint32)
+    r = np.zeros(n, np.uint64)
+    for t in range(k):
+        r = r * np.uint64(4) + bases[t : t + n].astype(np.uint64)
+    return r.astype(np.uint32)
+
+
+def draw_length(rng: np.random.Generator, kind: str) -> int:
+    if kind == "fixed1000":
+        return 1000
+    if kind == "lognormal5k":
+        return int(np.clip(round(math.exp(rng.normal(math.log(5000.0), 1.0))), 200, 100_000))
+    if kind == "lognormal8k":
+        return int(np.clip(round(math.exp(rng.normal(math.log(8000.0), 1.0))), 200, 1_000_000))
+    if kind == "mixed":
+        if rng.random() < 0.7:
+            return int(rng.integers(500, 5001))
+        return int(rng.integers(20_000, 200_001))
+    if kind == "ultralong":
+        return int(rng.integers(200_000, 1_000_001))
+    raise ValueError(kind)
+
+
+def gen_read(
+    rng: np.random.Generator,
+    L: int,
+    model: PoreModel,
+    noiseless: bool = False,
+) -> Read:
+    """Draw one read of reference length L (see the module docstring).
+
+    ``noiseless``: one event per k-mer, scale 1, shift 0 and every event mean
+    equal to the model level of its k-mer, so the model levels need no scaling.
+    """
+    k = model.k
+    bases = rng.integers(0, 4, L).astype(np.uint8)
+    ranks = kmer_ranks(bases, k)
+    n_k = ranks.shape[0]
+    if noiseless:
+        ev = np.zeros((n_k, 3), np.float32)
+        ev[:, 0] = model.level_mean[ranks]
+        ev[:, 1] = 1.0
+        ev[:, 2] = 0.0025
+        return Read(ev, ranks, np.float32(1.0), np.float32(0.0))
+    scale = np.float32(rng.uniform(0.9, 1.1))
+    shift = np.float32(rng.uniform(-5.0, 5.0))
+    skipped = rng.random(n_k) < SKIP_PROB
+    cnt = rng.geometric(1.0 / EVENTS_PER_KMER_MEAN, n_k)
+    cnt[skipped] = 0
+    r_ev = np.repeat(ranks, cnt)
+    n_e = r_ev.shape[0]
+    loc = model.level_mean[r_ev].astype(np.float64) * float(scale) + float(shift)
+    ev = np.empty((n_e, 3), np.float32)
+    ev[:, 0] = rng.normal(loc, model.level_stdv[r_ev].astype(np.float64))
+    ev[:, 1] = rng.uniform(0.5, 3.0, n_e)
+    ev[:, 2] = rng.exponential(0.0025, n_e)
+    return Read(ev, ranks, scale, shift)
+
+
+def make_batch(reads: Sequence[Read]) -> Batch:
+    n = len(reads)
+    ne = np.array([r.events.shape[0] for r in reads], np.uint64)
+    nk = np.array([r.ranks.shape[0] for r in reads], np.uint64)
+    eo = np.zeros(n + 1, np.uint64)
+    ko = np.zeros(n + 1, np.uint64)
+    np.cumsum(ne, out=eo[1:])
+    np.cumsum(nk, out=ko[1:])
+    ev = np.concatenate([r.events for r in reads]) if n else np.zeros((0, 3), np.float32)
+    rk = np.concatenate([r.ranks for r in reads]) if n else np.zeros(0, np.uint32)
+    return Batch(
+        np.ascontiguousarray(ev, np.float32).reshape(-1, 3),
+        eo,
+        np.ascontiguousarray(rk, np.uint32),
+        ko,
+        np.array([r.scale for r in reads], np.float32),
+        np.array([r.shift for r in reads], np.float32),
+    )
+
+
+def config_seed(config_id: int) -> int:
+    return CONFIG_SEED_BASE + config_id
+
+
+def read_rng(config_id: int, read_id: int) -> np.random.Generator:
+    return np.random.default_rng([config_seed(config_id), read_id])
+
+
+def config_read(config_id: int, read_id: int, model: PoreModel) -> Read:
+    """Read ``read_id`` of a workload; identical whatever batch it is in."""
+    rng = read_rng(config_id, read_id)
+    L = draw_length(rng, CONFIGS[config_id]["lengths"])
+    return gen_read(rng, L, model)
+
+
+def config_batch(
+    config_id: int,
+    model: Optional[PoreModel] = None,
+    read_ids: Optional[Sequence[int]] = None,
+) -> Batch:
+    cfg = CONFIGS[config_id]
+    if model is None:
+        model = pore_model(cfg["k"])
+    if read_ids is None:
+        read_ids = range(cfg["n_reads"])
+    return make_batch([config_read(config_id, int(i), model) for i in read_ids])
+
+
+def config_lengths(config_id: int, read_ids: Sequence[int]) -> np.ndarray:
+    """Reference lengths only (cheap: draws the first number of each stream)."""
+    kind = CONFIGS[config_id]["lengths"]
+    return np.array([draw_length(read_rng(config_id, int(i)), kind) for i in read_ids], np.int64)
+
+
+def noiseless_batch(n_reads: int, L: int, model: PoreModel, seed: int = 7) -> Batch:
+    return make_batch(
+        [gen_read(np.random.default_rng([seed, i]), L, model, noiseless=True) for i in range(n_reads)]
+    )
+
+
+def serving_arrivals(
+    n_channels: int = 512,
+    bases_per_s: float = 400.0,
+    duration_s: float = 10.0,
+    mean_len: Optional[float] = None,
+    seed: int = CONFIG_SEED_BASE + 3,
+) -> np.ndarray:
+    """Arrival times (s) of reads from ``n_channels`` independent Poisson
+    channels, each delivering ``bases_per_s`` on average (a simulated
+    sequencer).  The expected read length of the serving workload
+    (log-normal, median 8 kb, sigma 1, clipped) sets the per-channel rate."""
+    if mean_len is None:
+        mean_len = 8000.0 * math.exp(0.5)
+    rate = bases_per_s / mean_len
+    rng = np.random.default_rng(seed)
+    times = []
+    for _ in range(n_channels):
+        t = rng.exponential(1.0 / rate)
+        while t < duration_s:
+            times.append(t)
+            t += rng.exponential(1.0 / rate)
+    return np.sort(np.array(times, np.float64))
