@@ -1,0 +1,176 @@
+/*
+ * abea.h -- C ABI of the MI355X (gfx950) Adaptive Banded Event Alignment
+ * library (libabea.so).
+ *
+ * The operation is the alignment of nanopore signal events against the
+ * k-mers of a read under a pore model, by the adaptive banded dynamic
+ * programme of the thesis "Computer Architecture-Aware Optimisation of DNA
+ * Analysis Systems", Ch. 5 (GPU Accelerated Adaptive Banded Event Alignment):
+ *   - inputs and outputs of Alg. 5.1 (§5.2.3): the read's k-mers, the pore
+ *     model and the event table {mean, stdv, duration}; the output alignment
+ *     is a list of {event index, k-mer index} pairs;
+ *   - cell score and log-emission of Alg. 5.2 and 5.3 (only the event mean is
+ *     read); per-read model scaling mu = level_mean*scale + shift (paragraph
+ *     after Alg. 5.3);
+ *   - batches are serialised as concatenated arrays with exclusive prefix-sum
+ *     offsets (§5.4.2.1 "Data array serialisation", Alg. 5.9).
+ *
+ * All functions return an int status: ABEA_OK (0) or a negative ABEA_E_*
+ * code.  None throws, aborts or exits.  Per-read outcomes are reported per read
+ * and do not fail the call.
+ */
+#ifndef ABEA_H
+#define ABEA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define ABEA_OK 0
+#define ABEA_E_INVAL (-1)       /* bad argument: null pointer, n_reads < 0, W out of range,
+                                   k out of range, offsets not starting at 0 or decreasing */
+#define ABEA_E_NOMEM (-2)       /* a device or pinned-host allocation failed */
+#define ABEA_E_HIP (-3)         /* the HIP runtime reported an error (see abea_last_error) */
+#define ABEA_E_CAPACITY (-4)    /* result.pair_capacity is too small; nothing was written */
+#define ABEA_E_UNSUPPORTED (-5) /* valid request the build cannot serve */
+
+/* ---- per-read outcome (result.status[r]) ------------------------------ */
+#define ABEA_READ_OK 0
+#define ABEA_READ_EMPTY 1     /* the read has no events or no k-mers */
+#define ABEA_READ_BAND_LOST 2 /* terminal cell (n_e-1, n_k-1) outside the last band, or -inf */
+#define ABEA_READ_BAD_RANK 3  /* a k-mer rank >= 4^k */
+
+/* Failed reads (status != ABEA_READ_OK) get zero pairs and log_likelihood = -INFINITY. */
+
+/* ---- limits ------------------------------------------------------------ */
+#define ABEA_MAX_BANDWIDTH 512 /* band width W: 2 <= W <= 512 */
+#define ABEA_MAX_K 12          /* k-mer length: 1 <= k <= 12 (model has 4^k entries) */
+
+/* ---- config flags -------------------------------------------------------- */
+#define ABEA_F_TIMING 1u /* record device time of every kernel of each call (abea_get_timings) */
+
+/* One event of the event table (Alg. 5.1 input "events[]": mean, stdv, n).
+ * 12 bytes; only .mean is read (Alg. 5.3). */
+typedef struct {
+  float mean;
+  float stdv;
+  float duration;
+} abea_event_t;
+
+/* One alignment pair (Alg. 5.1 output "alignment[]"). */
+typedef struct {
+  int32_t event_idx;
+  int32_t kmer_idx;
+} abea_pair_t;
+
+/* Pore model (Ch. 5 §5.2.1, "pore-model"): 4^k entries indexed by k-mer rank
+ * (base-4 number of the k-mer, first base most significant).  level_stdv > 0.
+ * Host pointers; copied by abea_create. */
+typedef struct {
+  uint32_t k;
+  const float *level_mean;
+  const float *level_stdv;
+} abea_model_t;
+
+typedef struct {
+  int32_t bandwidth;    /* W, the band width (thesis: typically 100) */
+  int32_t device;       /* HIP device ordinal */
+  uint64_t arena_bytes; /* reserved for a future fixed-size device arena; 0 = grow on demand */
+  uint32_t flags;       /* ABEA_F_* */
+} abea_config_t;
+
+/*
+ * A batch of reads, serialised (Alg. 5.9): read r owns
+ *   events    [event_offset[r], event_offset[r+1])
+ *   kmer_rank [kmer_offset[r],  kmer_offset[r+1])
+ * event_offset and kmer_offset hold n_reads+1 exclusive prefix sums starting
+ * at 0.  scale[r] and shift[r] scale the model means for read r.
+ */
+typedef struct {
+  int32_t n_reads;
+  const abea_event_t *events;
+  const uint64_t *event_offset;
+  const uint32_t *kmer_rank;
+  const uint64_t *kmer_offset;
+  const float *scale;
+  const float *shift;
+} abea_batch_t;
+
+/*
+ * Results.  Read r's pairs are pairs[pair_offset[r] .. pair_offset[r+1]) in
+ * path order, from (0, 0) to (n_e-1, n_k-1); every cell of the path is a pair
+ * (a k-mer entered by a skip too).  pair_capacity must be at least
+ * sum_r max(0, n_e_r + n_k_r - 1) (a path never has more cells).
+ */
+typedef struct {
+  abea_pair_t *pairs;
+  uint64_t pair_capacity;
+  uint64_t *pair_offset;  /* [n_reads+1] */
+  float *log_likelihood;  /* [n_reads]: score of the terminal cell */
+  int32_t *status;        /* [n_reads]: ABEA_READ_* */
+  uint64_t *cells;        /* [n_reads] or NULL: DP cells filled inside the table */
+} abea_result_t;
+
+typedef struct abea_ctx abea_ctx;
+
+/*
+ * Create a context on cfg->device: copies the pore model to the device and
+ * precomputes its per-entry emission terms (Alg. 5.3).  *out receives the
+ * context; the caller owns it and frees it with abea_destroy.
+ * Errors: ABEA_E_INVAL (null pointer, W or k out of range, non-positive or
+ * non-finite level_stdv), ABEA_E_NOMEM, ABEA_E_HIP.
+ */
+int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **out);
+
+/*
+ * Align a batch held in host memory; synchronous.  Every pointer in *batch
+ * and *res is a host pointer; the call copies the inputs to the device, runs
+ * the alignment and copies the results back before returning, and keeps no
+ * reference to the caller's buffers.  A context is not thread-safe.
+ * Errors: ABEA_E_INVAL, ABEA_E_CAPACITY (nothing written), ABEA_E_NOMEM,
+ * ABEA_E_HIP.
+ */
+int abea_align_batch(abea_ctx *ctx, const abea_batch_t *batch, abea_result_t *res);
+
+/*
+ * Align a batch whose arrays are already in device memory; asynchronous.
+ *   batch->event_offset, batch->kmer_offset : HOST arrays (n_reads+1); the
+ *       library plans the batch from them and uploads what the kernels need;
+ *   batch->events, ->kmer_rank, ->scale, ->shift : DEVICE pointers;
+ *   res->pairs, ->pair_offset, ->log_likelihood, ->status, ->cells : DEVICE
+ *       pointers (cells may be NULL);
+ *   stream : a hipStream_t (NULL = the default stream).
+ * The work is enqueued on `stream` and the call returns; results are valid
+ * once the stream is synchronised.  Device buffers of the context are reused
+ * by the next call on the same context, so calls on one context must be
+ * ordered on one stream.
+ * Errors as abea_align_batch.
+ */
+int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *batch,
+                            const abea_result_t *res, void *stream);
+
+/*
+ * Device time in milliseconds of each kernel of the last call, when the
+ * context was created with ABEA_F_TIMING: out[0] k-mer parameter
+ * preparation, out[1] band fill, out[2] backtrack, out[3] compaction.
+ * Synchronises the stream of the last call.  n is the length of out.
+ */
+int abea_get_timings(abea_ctx *ctx, float *out, int n);
+
+/* Free the context and all its device memory.  NULL is allowed. */
+void abea_destroy(abea_ctx *ctx);
+
+/* Static description of a status code. */
+const char *abea_strerror(int status);
+
+/* Message of the last error on this context ("" if none). */
+const char *abea_last_error(const abea_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABEA_H */

@@ -1,0 +1,304 @@
+"""Python binding of libabea.so (include/abea.h): argument marshalling only.
+
+Every step of the alignment runs in the HIP library; this module converts
+numpy arrays / torch tensors to the C structs and back.  PyTorch is used only
+to hold device memory and to name a stream.  If the library is not built the
+import of the binding fails loudly: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libabea.so")
+
+ABEA_OK = 0
+ABEA_E_INVAL = -1
+ABEA_E_NOMEM = -2
+ABEA_E_HIP = -3
+ABEA_E_CAPACITY = -4
+ABEA_E_UNSUPPORTED = -5
+
+READ_OK, READ_EMPTY, READ_BAND_LOST, READ_BAD_RANK = 0, 1, 2, 3
+ABEA_MAX_BANDWIDTH = 512
+ABEA_MAX_K = 12
+ABEA_F_TIMING = 1
+
+EXPORTED = (
+    "abea_create",
+    "abea_align_batch",
+    "abea_align_batch_device",
+    "abea_get_timings",
+    "abea_destroy",
+    "abea_strerror",
+    "abea_last_error",
+)
+
+
+class AbeaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class abea_event_t(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_float), ("stdv", ctypes.c_float), ("duration", ctypes.c_float)]
+
+
+class abea_pair_t(ctypes.Structure):
+    _fields_ = [("event_idx", ctypes.c_int32), ("kmer_idx", ctypes.c_int32)]
+
+
+class abea_model_t(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("level_mean", ctypes.c_void_p), ("level_stdv", ctypes.c_void_p)]
+
+
+class abea_config_t(ctypes.Structure):
+    _fields_ = [
+        ("bandwidth", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("arena_bytes", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class abea_batch_t(ctypes.Structure):
+    _fields_ = [
+        ("n_reads", ctypes.c_int32),
+        ("events", ctypes.c_void_p),
+        ("event_offset", ctypes.c_void_p),
+        ("kmer_rank", ctypes.c_void_p),
+        ("kmer_offset", ctypes.c_void_p),
+        ("scale", ctypes.c_void_p),
+        ("shift", ctypes.c_void_p),
+    ]
+
+
+class abea_result_t(ctypes.Structure):
+    _fields_ = [
+        ("pairs", ctypes.c_void_p),
+        ("pair_capacity", ctypes.c_uint64),
+        ("pair_offset", ctypes.c_void_p),
+        ("log_likelihood", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+        ("cells", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        # One HIP runtime per process: torch bundles its own libamdhip64 with
+        # the same SONAME as the system one.  Loading torch first makes the
+        # library bind to that copy instead of bringing a second runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+                "(the HIP library is the only implementation)"
+            )
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.abea_create.argtypes = [ctypes.POINTER(abea_config_t), ctypes.POINTER(abea_model_t), ctypes.POINTER(P)]
+        L.abea_create.restype = ctypes.c_int
+        L.abea_align_batch.argtypes = [P, ctypes.POINTER(abea_batch_t), ctypes.POINTER(abea_result_t)]
+        L.abea_align_batch.restype = ctypes.c_int
+        L.abea_align_batch_device.argtypes = [P, ctypes.POINTER(abea_batch_t), ctypes.POINTER(abea_result_t), P]
+        L.abea_align_batch_device.restype = ctypes.c_int
+        L.abea_get_timings.argtypes = [P, P, ctypes.c_int]
+        L.abea_get_timings.restype = ctypes.c_int
+        L.abea_destroy.argtypes = [P]
+        L.abea_destroy.restype = None
+        L.abea_strerror.argtypes = [ctypes.c_int]
+        L.abea_strerror.restype = ctypes.c_char_p
+        L.abea_last_error.argtypes = [P]
+        L.abea_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())  # torch tensor
+
+
+@dataclasses.dataclass
+class HostResult:
+    pairs: np.ndarray  # int32 [total, 2]
+    pair_offset: np.ndarray  # uint64 [n+1]
+    log_likelihood: np.ndarray  # float32 [n]
+    status: np.ndarray  # int32 [n]
+    cells: np.ndarray  # uint64 [n]
+
+    def read_pairs(self, r: int) -> np.ndarray:
+        return self.pairs[int(self.pair_offset[r]) : int(self.pair_offset[r + 1])]
+
+
+def pair_capacity(event_offset: np.ndarray, kmer_offset: np.ndarray) -> int:
+    ne = np.diff(np.asarray(event_offset, np.int64))
+    nk = np.diff(np.asarray(kmer_offset, np.int64))
+    return int(np.where((ne > 0) & (nk > 0), ne + nk - 1, 0).sum())
+
+
+class Aligner:
+    """One library context (pore model on the device, band width W)."""
+
+    def __init__(self, level_mean, level_stdv, k: int, W: int = 100, device: int = 0, timing: bool = False):
+        self._lm = np.ascontiguousarray(level_mean, np.float32)
+        self._ls = np.ascontiguousarray(level_stdv, np.float32)
+        cfg = abea_config_t(W, device, 0, ABEA_F_TIMING if timing else 0)
+        mdl = abea_model_t(k, self._lm.ctypes.data, self._ls.ctypes.data)
+        h = ctypes.c_void_p()
+        rc = lib().abea_create(ctypes.byref(cfg), ctypes.byref(mdl), ctypes.byref(h))
+        if rc != ABEA_OK:
+            raise AbeaError(rc, "abea_create: " + lib().abea_strerror(rc).decode())
+        self.handle = h
+        self.W = W
+        self.k = k
+        self.device = device
+
+    def _check(self, rc: int, what: str):
+        if rc != ABEA_OK:
+            msg = lib().abea_last_error(self.handle).decode()
+            raise AbeaError(rc, f"{what}: {lib().abea_strerror(rc).decode()}: {msg}")
+
+    def align(self, batch) -> HostResult:
+        """Host-memory batch (``synth.Batch``-like) through abea_align_batch."""
+        n = batch.n_reads
+        ev = np.ascontiguousarray(batch.events, np.float32)
+        eo = np.ascontiguousarray(batch.event_offset, np.uint64)
+        ko = np.ascontiguousarray(batch.kmer_offset, np.uint64)
+        rk = np.ascontiguousarray(batch.ranks, np.uint32)
+        sc = np.ascontiguousarray(batch.scale, np.float32)
+        sh = np.ascontiguousarray(batch.shift, np.float32)
+        cap = pair_capacity(eo, ko)
+        pairs = np.zeros((max(cap, 1), 2), np.int32)
+        po = np.zeros(n + 1, np.uint64)
+        ll = np.zeros(n, np.float32)
+        st = np.zeros(n, np.int32)
+        cells = np.zeros(n, np.uint64)
+        b = abea_batch_t(n, _ptr(ev), _ptr(eo), _ptr(rk), _ptr(ko), _ptr(sc), _ptr(sh))
+        r = abea_result_t(_ptr(pairs), cap, _ptr(po), _ptr(ll), _ptr(st), _ptr(cells))
+        self._check(lib().abea_align_batch(self.handle, ctypes.byref(b), ctypes.byref(r)), "abea_align_batch")
+        return HostResult(pairs[: int(po[-1])], po, ll, st, cells)
+
+    def align_device(self, dbatch: "DeviceBatch", dres: "DeviceResult", stream=None) -> None:
+        """Device-resident batch through abea_align_batch_device (asynchronous
+        on ``stream``: a torch.cuda.Stream, a raw hipStream_t int, or None for
+        torch's current stream)."""
+        if stream is None:
+            import torch
+
+            stream = torch.cuda.current_stream(self.device)
+        sp = stream if isinstance(stream, int) else int(stream.cuda_stream)
+        b = abea_batch_t(
+            dbatch.n_reads, _ptr(dbatch.events), _ptr(dbatch.event_offset), _ptr(dbatch.ranks),
+            _ptr(dbatch.kmer_offset), _ptr(dbatch.scale), _ptr(dbatch.shift),
+        )
+        r = abea_result_t(
+            _ptr(dres.pairs), dres.capacity, _ptr(dres.pair_offset), _ptr(dres.log_likelihood),
+            _ptr(dres.status), _ptr(dres.cells),
+        )
+        self._check(
+            lib().abea_align_batch_device(self.handle, ctypes.byref(b), ctypes.byref(r), ctypes.c_void_p(sp)),
+            "abea_align_batch_device",
+        )
+
+    def timings(self) -> np.ndarray:
+        """Milliseconds of [prep, band, backtrack, compaction] of the last call."""
+        out = np.zeros(4, np.float32)
+        self._check(lib().abea_get_timings(self.handle, _ptr(out), 4), "abea_get_timings")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().abea_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class DeviceBatch:
+    n_reads: int
+    events: object  # torch float32 [N, 3] on the device
+    ranks: object  # torch int32 [K] (uint32 bits) on the device
+    scale: object
+    shift: object
+    event_offset: np.ndarray  # host uint64 [n+1]
+    kmer_offset: np.ndarray  # host uint64 [n+1]
+
+    @property
+    def capacity(self) -> int:
+        return pair_capacity(self.event_offset, self.kmer_offset)
+
+
+def to_device(batch, device: int = 0) -> DeviceBatch:
+    import torch
+
+    dev = torch.device("cuda", device)
+    return DeviceBatch(
+        batch.n_reads,
+        torch.from_numpy(np.ascontiguousarray(batch.events, np.float32)).to(dev),
+        torch.from_numpy(np.ascontiguousarray(batch.ranks, np.uint32).view(np.int32)).to(dev),
+        torch.from_numpy(np.ascontiguousarray(batch.scale, np.float32)).to(dev),
+        torch.from_numpy(np.ascontiguousarray(batch.shift, np.float32)).to(dev),
+        np.ascontiguousarray(batch.event_offset, np.uint64),
+        np.ascontiguousarray(batch.kmer_offset, np.uint64),
+    )
+
+
+@dataclasses.dataclass
+class DeviceResult:
+    pairs: object  # torch int32 [cap, 2]
+    capacity: int
+    pair_offset: object  # torch int64 [n+1] (uint64 bits)
+    log_likelihood: object  # torch float32 [n]
+    status: object  # torch int32 [n]
+    cells: object  # torch int64 [n] (uint64 bits)
+
+    @staticmethod
+    def empty(dbatch: DeviceBatch, device: int = 0) -> "DeviceResult":
+        import torch
+
+        dev = torch.device("cuda", device)
+        cap = dbatch.capacity
+        n = dbatch.n_reads
+        return DeviceResult(
+            torch.empty((max(cap, 1), 2), dtype=torch.int32, device=dev),
+            cap,
+            torch.empty(n + 1, dtype=torch.int64, device=dev),
+            torch.empty(max(n, 1), dtype=torch.float32, device=dev),
+            torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+            torch.empty(max(n, 1), dtype=torch.int64, device=dev),
+        )
+
+    def to_host(self, n: int) -> HostResult:
+        po = self.pair_offset.cpu().numpy().view(np.uint64)
+        total = int(po[-1])
+        return HostResult(
+            self.pairs[:total].cpu().numpy(),
+            po,
+            self.log_likelihood[:n].cpu().numpy(),
+            self.status[:n].cpu().numpy(),
+            self.cells[:n].cpu().numpy().view(np.uint64),
+        )

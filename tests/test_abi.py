@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every function include/abea.h declares
+(no compute call: this runs without a GPU)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2101_05012_amd import abea
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "abea.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(abea_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("abea_create", "abea_align_batch", "abea_destroy", "abea_align_batch_device"):
+        assert n in names
+    assert set(names) == set(abea.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(abea.LIB_PATH):
+        pytest.fail("libabea.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(abea.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_strerror_without_gpu():
+    lib = abea.lib()
+    assert lib.abea_strerror(0) == b"ok"
+    assert lib.abea_strerror(-4) == b"pair capacity too small"
+    assert lib.abea_last_error(None) == b""
+
+
+def test_create_rejects_bad_config_without_touching_the_gpu():
+    lib = abea.lib()
+    import numpy as np
+
+    lm = np.full(16, 80, np.float32)
+    ls = np.full(16, 2, np.float32)
+    mdl = abea.abea_model_t(2, lm.ctypes.data, ls.ctypes.data)
+    h = ctypes.c_void_p()
+    for W in (1, 0, 513):
+        cfg = abea.abea_config_t(W, 0, 0, 0)
+        assert lib.abea_create(ctypes.byref(cfg), ctypes.byref(mdl), ctypes.byref(h)) == abea.ABEA_E_INVAL
+    cfg = abea.abea_config_t(100, 0, 0, 0)
+    bad = abea.abea_model_t(13, lm.ctypes.data, ls.ctypes.data)
+    assert lib.abea_create(ctypes.byref(cfg), ctypes.byref(bad), ctypes.byref(h)) == abea.ABEA_E_INVAL
+    ls0 = ls.copy()
+    ls0[3] = 0
+    bad2 = abea.abea_model_t(2, lm.ctypes.data, ls0.ctypes.data)
+    assert lib.abea_create(ctypes.byref(cfg), ctypes.byref(bad2), ctypes.byref(h)) == abea.ABEA_E_INVAL

@@ -1,0 +1,193 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+The bar: per read, the same status, the same number of DP cells, a
+bit-identical float32 log-likelihood and bit-identical alignment pairs.  Both
+sides round every float32 operation the same way, so no tolerance is needed;
+the acceptance of the specification (pairs identical on reads whose decision
+margins exceed 1e-3 and on >= 99.9% of all reads, score relative error
+<= 1e-5) is implied and also asserted explicitly.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2101_05012_amd import abea, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def m6():
+    return synth.pore_model(6)
+
+
+@pytest.fixture(scope="module")
+def om6(oracle_mod, m6):
+    return oracle_mod.Model(m6.level_mean, m6.level_stdv)
+
+
+_aligners = {}
+
+
+def aligner(model, W):
+    key = (model.k, W, id(model))
+    if key not in _aligners:
+        _aligners[key] = abea.Aligner(model.level_mean, model.level_stdv, model.k, W=W)
+    return _aligners[key]
+
+
+def check_parity(batch, gres, O, om, W, idx=None, flags=0, threads=8):
+    """Compare GPU results with the oracle on reads ``idx`` (default all)."""
+    idx = range(batch.n_reads) if idx is None else list(idx)
+    sub = batch.subset(idx) if list(idx) != list(range(batch.n_reads)) else batch
+    ores = O.align_batch(sub, om, W, n_threads=threads, flags=flags)
+    rel_bad = 0
+    for t, r in enumerate(idx):
+        assert gres.status[r] == ores.status[t], (r, gres.status[r], ores.status[t])
+        assert int(gres.cells[r]) == int(ores.cells[t]) or gres.status[r] != 0, (r, gres.cells[r], ores.cells[t])
+        if ores.status[t] != 0:
+            assert gres.log_likelihood[r] == np.float32(-np.inf)
+            assert len(gres.read_pairs(r)) == 0
+            continue
+        gs, os_ = gres.log_likelihood[r], ores.score[t]
+        if abs(float(gs) - float(os_)) > 1e-5 * abs(float(os_)):
+            rel_bad += 1
+        assert gs == os_, (r, gs, os_)
+        gp = gres.read_pairs(r)
+        op = ores.read_pairs(t)
+        assert gp.shape == op.shape and np.array_equal(gp, op), (r, gp.shape, op.shape)
+    assert rel_bad == 0
+
+
+def test_config0_all_reads_bit_exact(oracle_mod, m6, om6):
+    b = synth.config_batch(0, m6)
+    say("gpu: config0 64 reads W=100 host API")
+    g = aligner(m6, 100).align(b)
+    check_parity(b, g, oracle_mod, om6, 100)
+    assert np.all(g.status == 0)
+
+
+def test_device_api_matches_host_api(m6):
+    import torch
+
+    b = synth.config_batch(0, m6, read_ids=range(64, 128))
+    al = aligner(m6, 100)
+    h = al.align(b)
+    say("gpu: device API 64 reads")
+    db = abea.to_device(b)
+    dr = abea.DeviceResult.empty(db)
+    al.align_device(db, dr)
+    torch.cuda.synchronize()
+    d = dr.to_host(b.n_reads)
+    assert np.array_equal(h.pair_offset, d.pair_offset)
+    assert np.array_equal(h.pairs, d.pairs)
+    assert np.array_equal(h.log_likelihood, d.log_likelihood)
+    assert np.array_equal(h.status, d.status) and np.array_equal(h.cells, d.cells)
+
+
+def test_config1_full_batch_sampled_reads(oracle_mod, m6, om6):
+    """The 4000-read log-normal workload in one launch (device API, the bench
+    configuration); the oracle checks the 12 longest reads and 52 others."""
+    import torch
+
+    b = synth.config_batch(1, m6)
+    say("gpu: config1 4000 reads device API")
+    db = abea.to_device(b)
+    dr = abea.DeviceResult.empty(db)
+    al = aligner(m6, 100)
+    al.align_device(db, dr)
+    torch.cuda.synchronize()
+    g = dr.to_host(b.n_reads)
+    assert np.all(g.status == 0)
+    L = np.diff(b.kmer_offset)
+    longest = list(np.argsort(-L, kind="stable")[:12])
+    rng = np.random.default_rng(5)
+    others = list(rng.choice(b.n_reads, 52, replace=False))
+    idx = sorted(set(int(x) for x in longest + others))
+    check_parity(b, g, oracle_mod, om6, 100, idx=idx)
+    # the pair layout is compact and ordered by read
+    po = g.pair_offset.astype(np.int64)
+    assert po[0] == 0 and np.all(np.diff(po) > 0) and po[-1] == len(g.pairs)
+
+
+def _edge_batch(m, rng):
+    reads = []
+    nmodel = m.level_mean.shape[0]
+    reads.append(synth.Read(np.zeros((0, 3), np.float32), np.array([1, 2, 3], np.uint32), np.float32(1), np.float32(0)))
+    reads.append(synth.Read(np.array([[80, 1, 0]], np.float32), np.zeros(0, np.uint32), np.float32(1), np.float32(0)))
+    reads.append(synth.Read(np.array([[80, 1, 0]], np.float32), np.array([7], np.uint32), np.float32(1), np.float32(0)))
+    bad = rng.integers(0, nmodel, 30).astype(np.uint32)
+    bad[11] = nmodel
+    reads.append(synth.Read(np.array([[90, 1, 0]] * 40, np.float32), bad, np.float32(1), np.float32(0)))
+    for L in (7, 8, 9, 20, 63, 64, 65, 129, 300):
+        reads.append(synth.gen_read(rng, L, m))
+    reads.append(synth.gen_read(rng, 200, m, noiseless=True))
+    return synth.make_batch(reads)
+
+
+@pytest.mark.parametrize("W", [2, 3, 17, 64, 65, 100, 101, 127, 128, 129, 200, 250, 256, 257, 511, 512])
+def test_band_widths_and_edge_cases(oracle_mod, m6, om6, W):
+    rng = np.random.default_rng(1000 + W)
+    b = _edge_batch(m6, rng)
+    say(f"gpu: edge batch W={W} n={b.n_reads}")
+    g = aligner(m6, W).align(b)
+    check_parity(b, g, oracle_mod, om6, W)
+    assert g.status[0] == abea.READ_EMPTY and g.status[1] == abea.READ_EMPTY
+    assert g.status[3] == abea.READ_BAD_RANK
+
+
+def test_noiseless_reads_align_on_diagonal(m6):
+    b = synth.noiseless_batch(8, 3000, m6, seed=3)
+    say("gpu: noiseless 8x3000")
+    g = aligner(m6, 100).align(b)
+    for r in range(b.n_reads):
+        n = b.n_kmers(r)
+        assert np.array_equal(g.read_pairs(r), np.stack([np.arange(n), np.arange(n)], 1))
+
+
+def test_read_result_same_alone_and_in_batch(m6):
+    b = synth.config_batch(1, m6, read_ids=range(100, 164))
+    al = aligner(m6, 100)
+    say("gpu: alone vs in batch")
+    whole = al.align(b)
+    for r in (0, 17, 63):
+        alone = al.align(b.subset([r]))
+        assert alone.log_likelihood[0] == whole.log_likelihood[r]
+        assert np.array_equal(alone.read_pairs(0), whole.read_pairs(r))
+
+
+def test_k9_model_and_wide_band(oracle_mod):
+    m9 = synth.pore_model(9)
+    om9 = oracle_mod.Model(m9.level_mean, m9.level_stdv)
+    rng = np.random.default_rng(9)
+    b = synth.make_batch([synth.gen_read(rng, int(L), m9) for L in rng.integers(500, 6000, 24)])
+    for W in (100, 250):
+        say(f"gpu: k=9 W={W}")
+        g = aligner(m9, W).align(b)
+        check_parity(b, g, oracle_mod, om9, W)
+
+
+def test_capacity_error_writes_nothing(m6):
+    import ctypes
+
+    b = synth.config_batch(0, m6, read_ids=range(4))
+    al = aligner(m6, 100)
+    ev = np.ascontiguousarray(b.events)
+    cap = abea.pair_capacity(b.event_offset, b.kmer_offset)
+    pairs = np.full((cap, 2), -7, np.int32)
+    po = np.zeros(5, np.uint64)
+    ll = np.zeros(4, np.float32)
+    st = np.zeros(4, np.int32)
+    bb = abea.abea_batch_t(4, ev.ctypes.data, b.event_offset.ctypes.data, b.ranks.ctypes.data,
+                           b.kmer_offset.ctypes.data, b.scale.ctypes.data, b.shift.ctypes.data)
+    rr = abea.abea_result_t(pairs.ctypes.data, cap - 1, po.ctypes.data, ll.ctypes.data, st.ctypes.data, None)
+    rc = abea.lib().abea_align_batch(al.handle, ctypes.byref(bb), ctypes.byref(rr))
+    assert rc == abea.ABEA_E_CAPACITY
+    assert np.all(pairs == -7)
