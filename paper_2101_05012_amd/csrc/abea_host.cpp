@@ -37,7 +37,6 @@ struct Plan {
   int n = 0;
   std::vector<int> order;
   uint64_t n_trace = 0;   /* uint2 words */
-  uint64_t n_moves = 0;   /* uint32 words */
   uint64_t n_scratch = 0; /* pair slots */
   uint64_t n_events = 0;
   uint64_t n_kmers = 0;
@@ -50,7 +49,6 @@ struct abea_ctx {
   int device = 0;
   int W = 100;
   int cpl = 2;
-  int lanes = 50;
   uint32_t flags = 0;
   uint32_t k = 6;
   uint32_t n_model = 0;
@@ -58,7 +56,7 @@ struct abea_ctx {
   hipStream_t own_stream = nullptr;
   hipStream_t last_stream = nullptr;
   /* planned-batch state */
-  DevBuf reads, rstat, band_end, kparam, trace, moves, scratch, path_len, path_src;
+  DevBuf reads, rstat, xmean, kparam, trace, scratch, path_len, path_src;
   /* host-API copies of inputs and outputs */
   DevBuf events, ranks, scale, shift, pairs, pair_offset, ll, status, cells;
   /* pinned staging of the plan */
@@ -177,7 +175,7 @@ int plan_batch(abea_ctx *ctx, int n, const uint64_t *eo, const uint64_t *ko, uin
   ctx->staging_pending = false;
 
   const int G = bands_per_group(ctx->cpl);
-  uint64_t tr = 0, mv = 0, pr = 0;
+  uint64_t tr = 0, pr = 0;
   for (int s = 0; s < n; ++s) {
     const int r = P.order[s];
     ReadDesc &d = ctx->h_reads[s];
@@ -188,7 +186,7 @@ int plan_batch(abea_ctx *ctx, int n, const uint64_t *eo, const uint64_t *ko, uin
     d.n_k = (int32_t)nk;
     d.orig = r;
     d.tr_off = tr;
-    d.mv_off = mv;
+    d.spare = 0;
     d.pr_off = pr;
     d.lp_skip = d.lp_stay = d.lp_step = 0.f;
     if (ne == 0 || nk == 0) {
@@ -198,12 +196,10 @@ int plan_batch(abea_ctx *ctx, int n, const uint64_t *eo, const uint64_t *ko, uin
     ctx->h_rstat[s] = READ_OK;
     transitions((int64_t)ne, (int64_t)nk, &d.lp_skip, &d.lp_stay, &d.lp_step);
     const uint64_t computed = ne + nk - 1; /* bands 2 .. n_e+n_k */
-    tr += ((computed + G - 1) / G) * (uint64_t)ctx->lanes;
-    mv += (computed + 31) / 32;
+    tr += ((computed + G - 1) / G) * 64u; /* 64 lanes x uint2 per group of G bands */
     pr += computed;
   }
   P.n_trace = tr;
-  P.n_moves = mv;
   P.n_scratch = pr;
   P.n_events = eo[n];
   P.n_kmers = ko[n];
@@ -229,10 +225,9 @@ int run_planned(abea_ctx *ctx, const DevIO &io, hipStream_t st) {
   int rc;
   if ((rc = ensure(ctx, ctx->reads, sizeof(ReadDesc) * (size_t)n))) return rc;
   if ((rc = ensure(ctx, ctx->rstat, sizeof(int32_t) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, ctx->band_end, sizeof(int32_t) * (size_t)n))) return rc;
+  if ((rc = ensure(ctx, ctx->xmean, sizeof(float) * (size_t)P.n_events))) return rc;
   if ((rc = ensure(ctx, ctx->kparam, sizeof(KParam) * (size_t)P.n_kmers))) return rc;
   if ((rc = ensure(ctx, ctx->trace, sizeof(uint2) * (size_t)P.n_trace))) return rc;
-  if ((rc = ensure(ctx, ctx->moves, sizeof(uint32_t) * (size_t)P.n_moves))) return rc;
   if ((rc = ensure(ctx, ctx->scratch, sizeof(int2) * (size_t)P.n_scratch))) return rc;
   if ((rc = ensure(ctx, ctx->path_len, sizeof(uint64_t) * (size_t)n))) return rc;
   if ((rc = ensure(ctx, ctx->path_src, sizeof(uint64_t) * (size_t)n))) return rc;
@@ -247,38 +242,32 @@ int run_planned(abea_ctx *ctx, const DevIO &io, hipStream_t st) {
   int32_t *rstat = (int32_t *)ctx->rstat.p;
   const bool timed = (ctx->flags & ABEA_F_TIMING) != 0;
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[0], st));
-  HIP_TRY(ctx, launch_prep(reads, n, io.ranks, io.scale, io.shift, (const ModelEntry *)ctx->model.p,
-                           ctx->n_model, (KParam *)ctx->kparam.p, rstat, st));
+  HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ranks, io.scale, io.shift,
+                           (const ModelEntry *)ctx->model.p, ctx->n_model, (float *)ctx->xmean.p,
+                           (KParam *)ctx->kparam.p, rstat, st));
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[1], st));
 
   BandArgs ba;
   ba.reads = reads;
-  ba.events = io.events;
+  ba.xmean = (const float *)ctx->xmean.p;
   ba.kparam = (const KParam *)ctx->kparam.p;
   ba.rstat = rstat;
-  ba.band_end = (int32_t *)ctx->band_end.p;
   ba.trace = (uint2 *)ctx->trace.p;
-  ba.moves = (uint32_t *)ctx->moves.p;
   ba.out_ll = io.ll;
   ba.out_cells = io.cells;
   ba.W = ctx->W;
-  ba.lanes_used = ctx->lanes;
   HIP_TRY(ctx, launch_band(ba, n, ctx->cpl, st));
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2], st));
 
   BacktrackArgs bt;
   bt.reads = reads;
   bt.rstat = rstat;
-  bt.band_end = (const int32_t *)ctx->band_end.p;
   bt.trace = (const uint2 *)ctx->trace.p;
-  bt.moves = (const uint32_t *)ctx->moves.p;
   bt.scratch = (int2 *)ctx->scratch.p;
   bt.path_len = (uint64_t *)ctx->path_len.p;
   bt.path_src = (uint64_t *)ctx->path_src.p;
   bt.out_status = io.status;
   bt.out_ll = io.ll;
-  bt.W = ctx->W;
-  bt.lanes_used = ctx->lanes;
   HIP_TRY(ctx, launch_backtrack(bt, n, ctx->cpl, st));
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[3], st));
 
@@ -348,7 +337,6 @@ int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **
   ctx->device = cfg->device;
   ctx->W = cfg->bandwidth;
   ctx->cpl = cells_per_lane(ctx->W);
-  ctx->lanes = lanes_used(ctx->W, ctx->cpl);
   ctx->flags = cfg->flags;
   ctx->k = model->k;
   ctx->n_model = n_model;
@@ -380,8 +368,8 @@ void abea_destroy(abea_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  DevBuf *bufs[] = {&ctx->model, &ctx->reads, &ctx->rstat, &ctx->band_end, &ctx->kparam,
-                    &ctx->trace, &ctx->moves, &ctx->scratch, &ctx->path_len, &ctx->path_src,
+  DevBuf *bufs[] = {&ctx->model, &ctx->reads, &ctx->rstat, &ctx->xmean, &ctx->kparam,
+                    &ctx->trace, &ctx->scratch, &ctx->path_len, &ctx->path_src,
                     &ctx->events, &ctx->ranks, &ctx->scale, &ctx->shift, &ctx->pairs,
                     &ctx->pair_offset, &ctx->ll, &ctx->status, &ctx->cells};
   for (DevBuf *b : bufs) free_buf(*b);

@@ -16,7 +16,7 @@ struct ReadDesc {
   uint64_t ev_off;  /* first event of the read in the batch event table */
   uint64_t km_off;  /* first k-mer of the read */
   uint64_t tr_off;  /* first trace tile word (uint2 units) */
-  uint64_t mv_off;  /* first band-move word (uint32 units) */
+  uint64_t spare;
   uint64_t pr_off;  /* first slot of the read's pair scratch (n_e+n_k-1 slots) */
   int32_t n_e;
   int32_t n_k;
@@ -47,50 +47,45 @@ struct KParam {
 
 enum : int32_t { READ_OK = 0, READ_EMPTY = 1, READ_BAND_LOST = 2, READ_BAD_RANK = 3 };
 
-/* Cells per lane for a band width: smallest power of two with 64*cpl >= W. */
+/* Slots per lane for a band width: smallest power of two with 64*cpl > W
+ * (one slot more than the band, so that k-mer k and k+N never share a slot
+ * while either is in a band). */
 inline int cells_per_lane(int W) {
   int c = 1;
-  while (64 * c < W) c <<= 1;
+  while (64 * c <= W) c <<= 1;
   return c;
 }
-/* Bands per trace tile word: every lane packs cpl cells x 1 bit per band into
+/* Bands per trace tile word: every lane packs cpl slots x 1 bit per band into
  * a 32-bit word per bit plane. */
 inline int bands_per_group(int cpl) { return 32 / cpl; }
-inline int lanes_used(int W, int cpl) { return (W + cpl - 1) / cpl; }
 
 struct BandArgs {
   const ReadDesc *reads;
-  const float *events; /* abea_event_t array viewed as floats (stride 3) */
+  const float *xmean;  /* event means, compacted by k_prep (batch event order) */
   const KParam *kparam;
-  int32_t *rstat;     /* [n_planned] status; in: OK/EMPTY/BAD_RANK, out: final */
-  int32_t *band_end;  /* [n_planned] lower-left event index of the last band */
-  uint2 *trace;       /* bit-plane trace tiles */
-  uint32_t *moves;    /* band-move bits */
-  float *out_ll;      /* [n_reads] by original index */
+  int32_t *rstat;      /* [n_planned] status; in: OK/EMPTY/BAD_RANK, out: final */
+  uint2 *trace;        /* bit-plane trace tiles: 64 lanes x uint2 per group of bands */
+  float *out_ll;       /* [n_reads] by original index */
   uint64_t *out_cells; /* [n_reads] by original index, or null */
   int32_t W;
-  int32_t lanes_used;
 };
 
 struct BacktrackArgs {
   const ReadDesc *reads;
   const int32_t *rstat;
-  const int32_t *band_end;
   const uint2 *trace;
-  const uint32_t *moves;
   int2 *scratch;         /* reversed-path pair scratch */
   uint64_t *path_len;    /* [n_reads] by original index */
   uint64_t *path_src;    /* [n_reads] by original index: first scratch slot of the path */
   int32_t *out_status;   /* [n_reads] by original index */
   float *out_ll;         /* [n_reads] by original index (set to -inf if the walk fails) */
-  int32_t W;
-  int32_t lanes_used;
 };
 
 /* Kernel launchers (abea_kernels.hip). */
-hipError_t launch_prep(const ReadDesc *reads, int n_planned, const uint32_t *ranks,
-                       const float *scale, const float *shift, const ModelEntry *model,
-                       uint32_t n_model, KParam *kparam, int32_t *rstat, hipStream_t st);
+hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
+                       const uint32_t *ranks, const float *scale, const float *shift,
+                       const ModelEntry *model, uint32_t n_model, float *xmean, KParam *kparam,
+                       int32_t *rstat, hipStream_t st);
 hipError_t launch_band(const BandArgs &a, int n_planned, int cpl, hipStream_t st);
 hipError_t launch_backtrack(const BacktrackArgs &a, int n_planned, int cpl, hipStream_t st);
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st);

@@ -1,29 +1,34 @@
 /*
  * abea_kernels.hip -- gfx950 kernels of Adaptive Banded Event Alignment.
  *
- * Thesis Ch. 5 ("GPU Accelerated Adaptive Banded Event Alignment") splits the
- * work into a pre-kernel (§5.4.1.1, Alg. 5.5: first bands and the per-read
- * "kcache" of model entries), a core-kernel (§5.4.1.2, Alg. 5.6-5.8: the band
- * loop) and a post-kernel (§5.4.1.3: backtrack).  The same three stages are
- * here, re-designed for CDNA4:
+ * The thesis (Ch. 5 "GPU Accelerated Adaptive Banded Event Alignment")
+ * splits the work into a pre-kernel (§5.4.1.1, Alg. 5.5: first bands and the
+ * per-read "kcache" of model entries), a core-kernel (§5.4.1.2, Alg. 5.6-5.8:
+ * the band loop, one thread block per read, four block barriers per band) and
+ * a post-kernel (§5.4.1.3: one thread per read backtracks).  The same three
+ * stages are here, re-designed for CDNA4:
  *
- *  k_prep      one workgroup per read gathers the model entry of every k-mer
- *              position once and applies the read's scaling, mu' =
- *              fma(mean, scale, shift) (paragraph after Alg. 5.3), so the band
- *              loop streams its k-parameters sequentially.
- *  k_band      one 64-lane wavefront per read.  Band offset j lives in lane
- *              j / CPL, register j % CPL (CPL = cells per lane).  The two
- *              previous bands stay in VGPRs; the neighbour shift of one offset
- *              is a DPP wave_shl/wave_shr move whose edge lane receives -inf
- *              (or the entering event / k-mer parameter).  The band move
- *              (Suzuki-Kasahara rule) is a wave-uniform scalar decision from
- *              two readlanes -- no barrier, no LDS.  Only 2 trace bits per cell
- *              (two bit planes, packed across 32/CPL bands per 32-bit word) and
- *              one move bit per band reach HBM; scores never leave registers.
+ *  k_prep      one workgroup per read: the scaled model level of every k-mer
+ *              position, mu' = fma(mean, scale, shift) (paragraph after
+ *              Alg. 5.3), with its emission terms (the kcache), and a compact
+ *              copy of the event means.
+ *  k_band      one 64-lane wavefront per read, no barrier and no score in
+ *              memory.  K-mer k of a band lives in slot k mod N (N = 64*CPL >
+ *              W; slot s is lane s / CPL, register s % CPL), so a cell's up
+ *              neighbour is the same slot of the previous band and its left
+ *              and diagonal neighbours are slot s-1 of the two previous bands:
+ *              one DPP wave_ror:1 per band each.  The k-mer parameters of a
+ *              slot never move; only the slot a k-mer step frees is refilled.
+ *              The event window rotates one slot per band.  The band move
+ *              (Suzuki-Kasahara rule) is a wave-uniform scalar decision.
+ *              Entering events and k-mer parameters stream through per-wave
+ *              LDS rings refilled a quarter ahead.  Only two trace bits per
+ *              slot reach HBM (two bit planes, 32/CPL bands per 32-bit word).
  *  k_backtrack one wavefront per read walks the path with wave-uniform scalar
- *              state, reading trace words with readlane from a register ring
- *              of prefetched tiles; pairs are gathered 64 at a time in lanes
- *              and stored coalesced.
+ *              state: the trace bits of cell (e, k) are in group (e+k)/G, lane
+ *              (k mod N)/CPL, so no band positions are needed.  Trace tiles
+ *              stream through an LDS ring; pairs are gathered 64 at a time in
+ *              lanes and stored coalesced.
  *  k_scan/k_compact turn per-read path lengths into the caller's compact
  *              pair layout.
  *
@@ -34,21 +39,23 @@
  */
 #include "abea_internal.h"
 
+#include <type_traits>
+
 #pragma clang fp contract(off)
 
 namespace abea {
 
 #define ABEA_NINF (-__builtin_inff())
 
-/* lane l receives v of lane l+1; lane 63 receives fill (DPP wave_shl:1) */
-__device__ __forceinline__ float from_next_lane(float v, float fill) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v),
-                                                    0x130, 0xF, 0xF, false));
-}
-/* lane l receives v of lane l-1; lane 0 receives fill (DPP wave_shr:1) */
-__device__ __forceinline__ float from_prev_lane(float v, float fill) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v),
-                                                    0x138, 0xF, 0xF, false));
+template <int CPL>
+struct Log2 {
+  static constexpr int v = CPL == 1 ? 0 : CPL == 2 ? 1 : CPL == 4 ? 2 : CPL == 8 ? 3 : 4;
+};
+
+/* lane l receives v of lane l-1, lane 0 receives lane 63 (DPP wave_ror:1) */
+__device__ __forceinline__ float rot_up(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x13C,
+                                                    0xF, 0xF, false));
 }
 __device__ __forceinline__ float rlane(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -56,43 +63,77 @@ __device__ __forceinline__ float rlane(float v, int lane) {
 __device__ __forceinline__ uint32_t rlane_u(uint32_t v, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
-
-/* Value at band offset (lane, reg) of a CPL-register band, as a scalar. */
-template <int CPL>
-__device__ __forceinline__ float read_offset(const float (&v)[CPL], int reg, int lane) {
-  float r = rlane(v[0], lane);
-#pragma unroll
-  for (int c = 1; c < CPL; ++c) {
-    float t = rlane(v[c], lane);
-    r = (reg == c) ? t : r;
-  }
+/* per lane: bit set in `mask` selects if_set, else if_clear (one v_cndmask) */
+__device__ __forceinline__ float sel(float if_clear, float if_set, uint64_t mask) {
+  float r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(mask));
   return r;
 }
-
-/* new[j] = old[j-1] for every offset j; offset 0 takes fill */
-template <int CPL>
-__device__ __forceinline__ void shift_to_higher(float (&x)[CPL], float fill) {
-  float t = from_prev_lane(x[CPL - 1], fill);
-#pragma unroll
-  for (int c = CPL - 1; c >= 1; --c) x[c] = x[c - 1];
-  x[0] = t;
+__device__ __forceinline__ int seli(int if_clear, int if_set, uint64_t mask) {
+  int r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(mask));
+  return r;
 }
-/* new[j] = old[j+1] for every offset j; offset 64*CPL-1 takes fill */
+/* in place: lanes whose bit is set in `mask` take `val` (one v_cndmask) */
+__device__ __forceinline__ void put(float &dst, float val, uint64_t mask) {
+  asm("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(dst) : "v"(val), "s"(mask));
+}
+/* per lane: acc*2 + (bit of `mask`), one v_addc */
+__device__ __forceinline__ uint32_t shift_in(uint32_t acc, uint64_t mask) {
+  uint32_t r;
+  uint64_t co;
+  asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=s"(co) : "v"(acc), "s"(mask));
+  return r;
+}
+__device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
+#define ABEA_NINF_BITS ((int)0xff800000)
+
+/* Order-preserving key of the bits of a non-NaN float (-0 and +0 equal). */
+__device__ __forceinline__ int32_t fkey_bits(int32_t b) {
+  b = (b == (int32_t)0x80000000) ? 0 : b;
+  return b ^ ((b >> 31) & 0x7fffffff);
+}
+
+/* Bits of the value held by slot `slot` of a band, as a scalar. */
 template <int CPL>
-__device__ __forceinline__ void shift_to_lower(float (&x)[CPL], float fill) {
-  float t = from_next_lane(x[0], fill);
+__device__ __forceinline__ int read_slot_bits(const float (&v)[CPL], int slot) {
+  const int ln = slot >> Log2<CPL>::v;
+  const int r = slot & (CPL - 1);
+  int t = __builtin_amdgcn_readlane(__float_as_int(v[0]), ln);
 #pragma unroll
-  for (int c = 0; c < CPL - 1; ++c) x[c] = x[c + 1];
-  x[CPL - 1] = t;
+  for (int c = 1; c < CPL; ++c) {
+    const int u = __builtin_amdgcn_readlane(__float_as_int(v[c]), ln);
+    t = (r == c) ? u : t;
+  }
+  return t;
+}
+
+/* Value held by slot `slot` of a band, as a scalar. */
+template <int CPL>
+__device__ __forceinline__ float read_slot(const float (&v)[CPL], int slot) {
+  const int ln = slot >> Log2<CPL>::v;
+  const int r = slot & (CPL - 1);
+  /* read every register, then pick the scalar: a per-lane select over the
+   * registers would be turned into an indexed (memory) access */
+  float t = rlane(v[0], ln);
+#pragma unroll
+  for (int c = 1; c < CPL; ++c) {
+    const float u = rlane(v[c], ln);
+    t = (r == c) ? u : t;
+  }
+  return t;
 }
 
 /* ------------------------------------------------------------------ prep */
 
 __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads,
+                                              const float *__restrict__ events,
                                               const uint32_t *__restrict__ ranks,
                                               const float *__restrict__ scale,
                                               const float *__restrict__ shift,
                                               const ModelEntry *__restrict__ model, uint32_t n_model,
+                                              float *__restrict__ xmean,
                                               KParam *__restrict__ kparam,
                                               int32_t *__restrict__ rstat) {
   const ReadDesc rd = reads[blockIdx.x];
@@ -102,7 +143,8 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
   int bad = 0;
   for (int k = threadIdx.x; k < rd.n_k; k += blockDim.x) {
     const uint32_t r = ranks[rd.km_off + k];
-    KParam p = {0.f, 0.f, 0.f, 0.f};
+    KParam p;
+    p.mu = p.c = p.h = p.pad = 0.0f;
     if (r < n_model) {
       const ModelEntry me = model[r];
       p.mu = __builtin_fmaf(me.mean, sc, sh);
@@ -113,15 +155,55 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
     }
     kparam[rd.km_off + k] = p;
   }
+  for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x)
+    xmean[rd.ev_off + e] = events[3 * (rd.ev_off + e)];
   if (__syncthreads_or(bad) && threadIdx.x == 0) rstat[blockIdx.x] = READ_BAD_RANK;
 }
 
 /* ------------------------------------------------------------------ band */
 
+/* Band move of the Suzuki-Kasahara rule from the bits of the two end cells
+ * of the previous band: 1 (k-mer move) if lo < hi, 0 (event move) otherwise,
+ * and `par` (alternation) when both are -inf.  Float compare on the VALU, the
+ * rest on the SALU; the result is an SGPR. */
+__device__ __forceinline__ int sk_move(int lo, int hi, int par) {
+  int m, t;
+  float tv;
+  uint64_t cm;
+  asm volatile(
+      "v_mov_b32 %[tv], %[hi]\n\t"
+      "v_cmp_lt_f32_e64 %[cm], %[lo], %[tv]\n\t"
+      "s_and_b64 %[cm], %[cm], exec\n\t"
+      "s_cselect_b32 %[m], 1, 0\n\t"
+      "s_cmp_eq_u32 %[lo], %[hi]\n\t"
+      "s_cselect_b32 %[t], %[lo], 0\n\t"
+      "s_cmp_eq_u32 %[t], 0xff800000\n\t"
+      "s_cselect_b32 %[m], %[par], %[m]"
+      : [m] "=&s"(m), [t] "=&s"(t), [tv] "=&v"(tv), [cm] "=&s"(cm)
+      : [lo] "s"(lo), [hi] "s"(hi), [par] "s"(par)
+      : "scc");
+  return m;
+}
+
+/* The register of slot (.. % CPL == r) of every lane, as one VGPR. */
+template <int CPL>
+__device__ __forceinline__ float pick(const float (&v)[CPL], int r) {
+  float t = v[0];
+#pragma unroll
+  for (int c = 1; c < CPL; ++c) t = sel(t, v[c], ballot(r == c));
+  return t;
+}
+
 template <int CPL>
 __global__ __launch_bounds__(64) void k_band(const BandArgs a) {
-  constexpr int N = 64 * CPL;  /* offsets held by the wave */
-  constexpr int G = 32 / CPL;  /* bands per trace word */
+  constexpr int N = 64 * CPL;       /* slots held by the wave */
+  constexpr int LC = Log2<CPL>::v;
+  constexpr int G = 32 / CPL;       /* bands per trace word (even) */
+  constexpr int RING = 256;         /* entries per LDS stream ring */
+  constexpr int Q = 64;             /* ring refill quarter */
+  __shared__ float lx[RING];
+  __shared__ float4 lk[RING];
+
   const int lane = threadIdx.x;
   const int s = blockIdx.x;
   const ReadDesc rd = a.reads[s];
@@ -136,194 +218,229 @@ __global__ __launch_bounds__(64) void k_band(const BandArgs a) {
     return;
   }
   const float lp_skip = rd.lp_skip, lp_stay = rd.lp_stay, lp_step = rd.lp_step;
-  const float *__restrict__ ev = a.events + rd.ev_off * 3;
-  const KParam *__restrict__ kp = a.kparam + rd.km_off;
+  const float *__restrict__ xm = a.xmean + rd.ev_off;
+  const float4 *__restrict__ kp = reinterpret_cast<const float4 *>(a.kparam + rd.km_off);
   const int H = W / 2;
+  const float NI = ABEA_NINF;
 
-  int jv[CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) jv[c] = lane * CPL + c;
-
-  auto load_ev = [&](int e) -> float {
-    float x = 0.0f;
-    if (e >= 0 && e < n_e) x = ev[3 * (int64_t)e];
-    return x;
+  auto ldx = [&](int e) -> float {
+    float v = 0.0f;
+    if (e >= 0 && e < n_e) v = xm[e];
+    return v;
   };
-  auto load_kp = [&](int k) -> KParam {
-    KParam p;
-    p.mu = p.c = p.h = p.pad = 0.0f;
-    if (k >= 0 && k < n_k) p = kp[k];
-    return p;
+  auto ldk = [&](int k) -> float4 {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k >= 0 && k < n_k) v = kp[k];
+    return v;
   };
 
-  /* bands 0 and 1 (initialise_first_two_bands): all -inf except the virtual
-   * origin (-1,-1) at offset W/2 of band 0.  Band 0's lower-left is
-   * (W/2-1, -1-W/2); band 1 is band 0 moved by one k-mer. */
-  float A[CPL], B[CPL];
+  /* Band 1 (initialise_first_two_bands): band 0 has lower-left (W/2-1,
+   * -1-W/2) and holds only the virtual origin (-1,-1) with score 0; band 1 is
+   * band 0 moved one k-mer and is all -inf.  A band is identified by its
+   * first k-mer K; the slots hold k-mers K .. K+N-1 (the first W are the
+   * band, the rest look ahead and hold -inf). */
+  int K = -H;    /* first k-mer of band 1 */
+  int E = H - 1; /* event of band 1's first cell */
+  float Spp[CPL], Sp[CPL], X[CPL], PM[CPL], PC[CPL], PH[CPL];
+  uint64_t wm[CPL]; /* slots inside the current band's k-mer window */
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
-    A[c] = (jv[c] == H) ? 0.0f : ABEA_NINF;
-    B[c] = ABEA_NINF;
+    const int slot = lane * CPL + c;
+    const int kv = K + ((slot - K) & (N - 1));
+    X[c] = ldx(-1 - kv); /* band 1: cell (e, k) has e + k = -1 */
+    const float4 p = ldk(kv);
+    PM[c] = p.x;
+    PC[c] = p.y;
+    PH[c] = p.z;
+    Spp[c] = (kv == -1) ? 0.0f : NI; /* band 0: the origin, k-mer -1 */
+    Sp[c] = NI;
+    wm[c] = ballot(kv <= K + W - 1);
   }
-  int E = H - 1, K = -H; /* lower-left of band 1 */
-  int m_prev = 1;
 
-  /* event and k-parameter windows of band 1: offset j is event E-j, k-mer K+j */
-  float X[CPL], PM[CPL], PC[CPL], PH[CPL];
+  /* LDS rings.  Events enter at event moves in order E_1+1, E_1+2, ...;
+   * k-mers enter at k-mer moves in order K_1+N, K_1+N+1, ...  Quarter q of a
+   * ring holds indices [64q, 64q+64); quarters xq..xq+2 are written, xq+3
+   * waits in registers. */
+  int xq = (E + 1) >> 6;
+  int kq = (K + N) >> 6;
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) {
-    X[c] = load_ev(E - jv[c]);
-    const KParam p = load_kp(K + jv[c]);
-    PM[c] = p.mu;
-    PC[c] = p.c;
-    PH[c] = p.h;
+  for (int t = 0; t < 3; ++t) {
+    lx[((xq + t) * Q + lane) & (RING - 1)] = ldx((xq + t) * Q + lane);
+    lk[((kq + t) * Q + lane) & (RING - 1)] = ldk((kq + t) * Q + lane);
   }
-  /* chunks of the values that enter the windows next: lane l of NX holds
-   * event xb+l; lane l of NP holds the k-parameters of k-mer kb+l. */
-  int xb = E + 1;
-  float NX = load_ev(xb + lane), NXn = load_ev(xb + 64 + lane);
-  int kb = K + N;
-  KParam NP = load_kp(kb + lane), NPn = load_kp(kb + 64 + lane);
+  float xpend = ldx((xq + 3) * Q + lane);
+  float4 kpend = ldk((kq + 3) * Q + lane);
 
-  const int hi_lane = (W - 1) / CPL, hi_reg = (W - 1) % CPL;
+  /* per group of bands: lane l of xc / kc holds the (l+1)-th next entering
+   * event / k-mer; ne / nk count the ones used */
+  float xc;
+  float4 kc;
+  int ne = 0, nk = 0;
+  auto load_chunks = [&]() {
+    if (((E + 64) >> 6) > xq + 2) {
+      ++xq;
+      lx[((xq + 2) * Q + lane) & (RING - 1)] = xpend;
+      xpend = ldx((xq + 3) * Q + lane);
+    }
+    if (((K + N + 63) >> 6) > kq + 2) {
+      ++kq;
+      lk[((kq + 2) * Q + lane) & (RING - 1)] = kpend;
+      kpend = ldk((kq + 3) * Q + lane);
+    }
+    xc = lx[(E + 1 + lane) & (RING - 1)];
+    kc = lk[(K + N + lane) & (RING - 1)];
+    ne = 0;
+    nk = 0;
+  };
+
   const int last = n_e + n_k;
   uint32_t TU = 0, TL = 0;
-  int gb = 0;
-  uint64_t g = 0;
-  uint32_t mv = 0;
   uint64_t cells = 0;
   uint2 *__restrict__ trace = a.trace + rd.tr_off;
-  uint32_t *__restrict__ moves = a.moves + rd.mv_off;
-  const int lu = a.lanes_used;
 
-  /* One band: Spp = band i-2 (overwritten by band i), Sp = band i-1. */
-  auto step = [&](float(&Spp)[CPL], float(&Sp)[CPL], int i) {
-    /* Suzuki-Kasahara placement: towards the better end of band i-1;
-     * alternate while both ends are -inf. */
-    const float lo = rlane(Sp[0], 0);
-    const float hi = read_offset<CPL>(Sp, hi_reg, hi_lane);
-    int m;
-    if (lo == ABEA_NINF && hi == ABEA_NINF)
-      m = i & 1;
-    else
-      m = (lo < hi) ? 1 : 0;
+  /* One band i: Spp = band i-2 (overwritten by band i), Sp = band i-1.
+   * INTERIOR: all W cells of band i are inside the DP table. */
+  auto band = [&](auto interior_tag, float(&Spp)[CPL], const float(&Sp)[CPL], int i) {
+    constexpr bool INTERIOR = decltype(interior_tag)::value;
+    /* the band position is wave-uniform: keep it in SGPRs */
+    K = __builtin_amdgcn_readfirstlane(K);
+    E = __builtin_amdgcn_readfirstlane(E);
+    ne = __builtin_amdgcn_readfirstlane(ne);
+    nk = __builtin_amdgcn_readfirstlane(nk);
+    /* Suzuki-Kasahara placement from the two end cells of band i-1 */
+    const int sf = K & (N - 1); /* slot of the first k-mer */
+    const int sh = (K + W - 1) & (N - 1);
+    const int lo = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(Sp, sf & (CPL - 1))), sf >> LC);
+    const int hi = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(Sp, sh & (CPL - 1))), sh >> LC);
+    const int m = __builtin_amdgcn_readfirstlane(sk_move(lo, hi, i & 1));
+    const uint64_t bf = 1ull << (sf >> LC);
 
-    float U[CPL], L[CPL], D[CPL];
-    if (m) { /* k-mer move: offsets now see k-mer K+1+j */
-      K += 1;
-      const int kk = K + N - 1;
-      if (kk - kb >= 64) {
-        NP = NPn;
-        kb += 64;
-        NPn = load_kp(kb + 64 + lane);
-      }
-      const int ql = kk - kb;
-      shift_to_lower<CPL>(PM, rlane(NP.mu, ql));
-      shift_to_lower<CPL>(PC, rlane(NP.c, ql));
-      shift_to_lower<CPL>(PH, rlane(NP.h, ql));
-      /* up (e-1,k) is offset j+1 of band i-1, left (e,k-1) is offset j */
+    /* the event of every slot advances by one: slot s takes slot s-1's */
+    {
+      const float t = rot_up(X[CPL - 1]);
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        U[c] = Sp[c];
-        L[c] = Sp[c];
-      }
-      shift_to_lower<CPL>(U, ABEA_NINF);
-    } else { /* event move: offsets now see event E+1-j */
-      E += 1;
-      if (E - xb >= 64) {
-        NX = NXn;
-        xb += 64;
-        NXn = load_ev(xb + 64 + lane);
-      }
-      shift_to_higher<CPL>(X, rlane(NX, E - xb));
-      /* up is offset j of band i-1, left is offset j-1 */
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        U[c] = Sp[c];
-        L[c] = Sp[c];
-      }
-      shift_to_higher<CPL>(L, ABEA_NINF);
+      for (int c = CPL - 1; c >= 1; --c) X[c] = X[c - 1];
+      X[0] = t;
     }
-    /* diagonal (e-1,k-1) is offset j + m_i + m_{i-1} - 1 of band i-2 */
-    const int dd = m + m_prev - 1;
+    /* k-mer move (m = 1): the slot of k-mer K leaves the band and will hold
+     * k-mer K+N, the slot of k-mer K+W enters the band.  Event move (m = 0):
+     * the first k-mer's cell takes the new event E+1.  Both are applied under
+     * lane masks (no branch). */
+    {
+      const float pm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc.x), nk));
+      const float pc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc.y), nk));
+      const float ph = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc.z), nk));
+      const float xv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xc), ne));
+      const uint64_t bk = m ? bf : 0ull;
+      const uint64_t be = m ? 0ull : bf;
+      const int sn = (K + W) & (N - 1);
+      const uint64_t bn = m ? (1ull << (sn >> LC)) : 0ull;
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) D[c] = Spp[c];
-    if (dd > 0)
-      shift_to_lower<CPL>(D, ABEA_NINF);
-    else if (dd < 0)
-      shift_to_higher<CPL>(D, ABEA_NINF);
-    m_prev = m;
+      for (int c = 0; c < CPL; ++c) {
+        const bool here = (sf & (CPL - 1)) == c;
+        const uint64_t mk = here ? bk : 0ull;
+        put(PM[c], pm, mk);
+        put(PC[c], pc, mk);
+        put(PH[c], ph, mk);
+        put(X[c], xv, here ? be : 0ull);
+        wm[c] = (wm[c] & ~mk) | (((sn & (CPL - 1)) == c) ? bn : 0ull);
+      }
+      nk += m;
+      ne += 1 - m;
+      K += m;
+      E += 1 - m;
+    }
 
-    /* limits in the band: cells inside the DP table */
-    const int min_j = max(0, max(E - (n_e - 1), -K));
-    const int max_j = min(W - 1, min(E, (n_k - 1) - K));
-    if (max_j >= min_j) cells += (uint64_t)(max_j - min_j + 1);
-
+    int klo = K, khi = K + W - 1;
+    if (!INTERIOR) {
+      klo = max(K, max(0, i - 1 - n_e));
+      khi = min(K + W - 1, min(n_k - 1, i - 2));
+      if (khi >= klo) cells += (uint64_t)(khi - klo + 1);
+    }
+    const float lf0 = rot_up(Sp[CPL - 1]);  /* left  (e, k-1): band i-1, slot s-1 */
+    const float dg0 = rot_up(Spp[CPL - 1]); /* diag (e-1, k-1): band i-2, slot s-1 */
+    float nv[CPL]; /* band i; band i-2 is still read below */
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
+      const float up = Sp[c]; /* up (e-1, k): band i-1, slot s */
+      const float left = (c == 0) ? lf0 : Sp[c - 1];
+      const float diag = (c == 0) ? dg0 : Spp[c - 1];
       /* Alg. 5.3 log-emission and Alg. 5.2 cell score */
       const float d = X[c] - PM[c];
       const float t = d * d;
       const float u = t * PH[c];
       const float em = PC[c] - u;
-      const float sd = (D[c] + lp_step) + em;
-      const float su = (U[c] + lp_stay) + em;
-      const float sl = L[c] + lp_skip;
-      bool bu = su > sd;
-      const float s1 = bu ? su : sd;
-      bool bl = sl > s1;
-      float sv = bl ? sl : s1;
-      /* trace code in two bit planes: (0,0) diagonal, (1,0) up, (0,1) left,
-       * (1,1) a cell outside the table */
-      bu = bu && !bl;
-      const bool valid = (jv[c] >= min_j) && (jv[c] <= max_j);
-      sv = valid ? sv : ABEA_NINF;
-      bu = bu || !valid;
-      bl = bl || !valid;
-      Spp[c] = sv;
-      TU = TU + TU + (bu ? 1u : 0u);
-      TL = TL + TL + (bl ? 1u : 0u);
+      const float sd = (diag + lp_step) + em;
+      const float su = (up + lp_stay) + em;
+      const float sl = left + lp_skip;
+      uint64_t mu = ballot(su > sd);
+      const float s1 = sel(sd, su, mu);
+      uint64_t ml = ballot(sl > s1);
+      const float sv = sel(s1, sl, ml);
+      /* trace planes: (0,0) diagonal, (1,0) up, (0,1) left, (1,1) outside */
+      mu &= ~ml;
+      uint64_t valid = wm[c];
+      if (!INTERIOR) {
+        const int kv = K + ((lane * CPL + c - K) & (N - 1));
+        valid = ballot(kv >= klo) & ballot(kv <= khi);
+        mu |= ~valid;
+        ml |= ~valid;
+      }
+      nv[c] = sel(NI, sv, valid);
+      TU = shift_in(TU, mu);
+      TL = shift_in(TL, ml);
     }
-
-    if (++gb == G) {
-      if (lane < lu) trace[g * (uint64_t)lu + lane] = make_uint2(TU, TL);
-      ++g;
-      gb = 0;
-    }
-    const int t = i - 2;
-    mv |= (uint32_t)m << (t & 31);
-    if ((t & 31) == 31) {
-      if (lane == 0) moves[t >> 5] = mv;
-      mv = 0;
-    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) Spp[c] = nv[c];
   };
 
+  /* Full groups of G bands (band i = 2 + t, group t / G): refill and
+   * interior test once per group, one trace word per lane per group. */
   int i = 2;
-  for (;;) {
-    step(A, B, i);
-    if (++i > last) break;
-    step(B, A, i);
-    if (++i > last) break;
+  uint64_t g = 0;
+  while (i + G - 1 <= last) {
+    load_chunks();
+    const bool interior = (K >= 0) & (E >= W - 1) & (E + G <= n_e - 1) & (K + G + W - 1 <= n_k - 1);
+    if (interior) {
+#pragma unroll
+      for (int b = 0; b < G; b += 2) {
+        band(std::true_type(), Spp, Sp, i + b);
+        band(std::true_type(), Sp, Spp, i + b + 1);
+      }
+      cells += (uint64_t)W * G;
+    } else {
+#pragma unroll
+      for (int b = 0; b < G; b += 2) {
+        band(std::false_type(), Spp, Sp, i + b);
+        band(std::false_type(), Sp, Spp, i + b + 1);
+      }
+    }
+    trace[g * 64 + lane] = make_uint2(TU, TL);
+    ++g;
+    i += G;
   }
-  /* flush the partial trace word and move word */
-  if (gb > 0) {
+  /* the last, partial group */
+  if (i <= last) {
+    load_chunks();
+    const int gb = last - i + 1;
+    for (;;) {
+      band(std::false_type(), Spp, Sp, i);
+      if (++i > last) break;
+      band(std::false_type(), Sp, Spp, i);
+      if (++i > last) break;
+    }
     const int sh = (G - gb) * CPL;
-    if (lane < lu) trace[g * (uint64_t)lu + lane] = make_uint2(TU << sh, TL << sh);
-  }
-  if (((last - 2) & 31) != 31) {
-    if (lane == 0) moves[(last - 2) >> 5] = mv;
+    trace[g * 64 + lane] = make_uint2(TU << sh, TL << sh);
   }
 
-  /* terminal cell (n_e-1, n_k-1) sits at offset E - (n_e-1) of the last band */
+  /* terminal cell (n_e-1, n_k-1) is in the last band if its k-mer is */
   float F[CPL];
 #pragma unroll
-  for (int c = 0; c < CPL; ++c) F[c] = (last & 1) ? B[c] : A[c];
-  const int jt = E - (n_e - 1);
+  for (int c = 0; c < CPL; ++c) F[c] = (last & 1) ? Sp[c] : Spp[c];
   float sc = ABEA_NINF;
-  if (jt >= 0 && jt < W) sc = read_offset<CPL>(F, jt % CPL, jt / CPL);
+  if (n_k - 1 >= K && n_k - 1 <= K + W - 1) sc = read_slot<CPL>(F, (n_k - 1) & (N - 1));
   if (lane == 0) {
-    a.rstat[s] = (sc == ABEA_NINF) ? READ_BAND_LOST : READ_OK;
-    a.band_end[s] = E;
+    a.rstat[s] = (__float_as_int(sc) == ABEA_NINF_BITS) ? READ_BAND_LOST : READ_OK;
     a.out_ll[rd.orig] = sc;
     if (a.out_cells) a.out_cells[rd.orig] = cells;
   }
@@ -333,8 +450,14 @@ __global__ __launch_bounds__(64) void k_band(const BandArgs a) {
 
 template <int CPL>
 __global__ __launch_bounds__(64) void k_backtrack(const BacktrackArgs a) {
+  constexpr int N = 64 * CPL;
+  constexpr int LC = Log2<CPL>::v;
   constexpr int G = 32 / CPL;
-  constexpr int P = 8; /* trace tiles in flight */
+  constexpr int LG = 5 - LC; /* log2(G) */
+  constexpr int RG = 64;     /* tile groups in the LDS ring */
+  constexpr int QG = 16;     /* groups per refill quarter */
+  __shared__ uint2 ring[RG * 64];
+
   const int lane = threadIdx.x;
   const int s = blockIdx.x;
   const ReadDesc rd = a.reads[s];
@@ -348,34 +471,30 @@ __global__ __launch_bounds__(64) void k_backtrack(const BacktrackArgs a) {
     }
     return;
   }
-  const int n_e = rd.n_e, n_k = rd.n_k, lu = a.lanes_used;
+  const int n_e = rd.n_e, n_k = rd.n_k;
   const uint2 *__restrict__ tr = a.trace + rd.tr_off;
-  const uint32_t *__restrict__ mvp = a.moves + rd.mv_off;
-  const int n_words = (n_e + n_k - 1 + 31) >> 5;
-
-  auto load_tile = [&](int grp) -> uint2 {
+  const int gmax = (n_e + n_k - 2) >> LG; /* last trace group of the read */
+  auto ldt = [&](int grp) -> uint2 {
     uint2 v = make_uint2(0u, 0u);
-    if (grp >= 0 && lane < lu) v = tr[(uint64_t)grp * lu + lane];
-    return v;
-  };
-  auto load_mv = [&](int w) -> uint32_t {
-    uint32_t v = 0u;
-    if (w >= 0 && w < n_words) v = mvp[w];
+    if (grp >= 0 && grp <= gmax) v = tr[(uint64_t)grp * 64 + lane];
     return v;
   };
 
-  int e = n_e - 1, k = n_k - 1, i = n_e + n_k;
-  int E = a.band_end[s];
-
-  int gcur = (i - 2) / G;
-  uint2 T[P];
+  int e = n_e - 1, k = n_k - 1;
+  int gcur = (e + k) >> LG;
+  /* quarters of QG groups, walked downwards: quarters qa, qa-1, qa-2 are in
+   * the ring, qa-3 waits in registers */
+  int qa = gcur / QG;
+  for (int t = 0; t < 3; ++t)
+    for (int p = 0; p < QG; ++p) {
+      const int grp = (qa - t) * QG + p;
+      ring[(grp & (RG - 1)) * 64 + lane] = ldt(grp);
+    }
+  uint2 pend[QG];
 #pragma unroll
-  for (int p = 0; p < P; ++p) T[p] = load_tile(gcur - p);
-
-  int wcur = (i - 2) >> 5;
-  int mb = wcur - 63;
-  uint32_t MV = load_mv(mb + lane), MVn = load_mv(mb - 64 + lane);
-  uint32_t mword = rlane_u(MV, wcur - mb);
+  for (int p = 0; p < QG; ++p) pend[p] = ldt((qa - 3) * QG + p);
+  uint2 T = ring[(gcur & (RG - 1)) * 64 + lane];
+  uint2 Tn = ring[((gcur - 1) & (RG - 1)) * 64 + lane];
 
   int PE = 0, PK = 0;
   uint64_t q = 0;
@@ -385,59 +504,42 @@ __global__ __launch_bounds__(64) void k_backtrack(const BacktrackArgs a) {
 
   for (;;) {
     /* emit the cell; every 64 cells go out in one coalesced store */
+    e = __builtin_amdgcn_readfirstlane(e);
+    k = __builtin_amdgcn_readfirstlane(k);
     const int slot = (int)(q & 63);
-    PE = (lane == slot) ? e : PE;
-    PK = (lane == slot) ? k : PK;
+    asm volatile("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %3, m0\n\tv_writelane_b32 %1, %4, m0"
+                 : "+v"(PE), "+v"(PK)
+                 : "s"(slot), "s"(e), "s"(k)
+                 : "m0");
     ++q;
     if ((q & 63) == 0) out[res_end - 1 - (q - 64 + lane)] = make_int2(PE, PK);
 
-    const int t = i - 2;
-    const int gi = t / G;
-    while (gcur > gi) {
+    const int t = e + k; /* band t + 2 */
+    const int gi = t >> LG;
+    if (gi != gcur) { /* the walk moved down by one group */
+      gcur = gi;
+      T = Tn;
+      if (gcur - 1 < (qa - 1) * QG) {
+        --qa;
 #pragma unroll
-      for (int p = 0; p < P - 1; ++p) T[p] = T[p + 1];
-      T[P - 1] = load_tile(gcur - P);
-      --gcur;
+        for (int p = 0; p < QG; ++p) ring[(((qa - 2) * QG + p) & (RG - 1)) * 64 + lane] = pend[p];
+#pragma unroll
+        for (int p = 0; p < QG; ++p) pend[p] = ldt((qa - 3) * QG + p);
+      }
+      Tn = ring[((gcur - 1) & (RG - 1)) * 64 + lane];
     }
-    const int j = E - e;
-    const int ln = j / CPL;
-    const int c = j - ln * CPL;
-    const int bit = 31 - ((t - gi * G) * CPL + c);
-    const uint32_t ub = (rlane_u(T[0].x, ln) >> bit) & 1u;
-    const uint32_t lb = (rlane_u(T[0].y, ln) >> bit) & 1u;
-    int steps;
-    if (lb && ub) {
+    const int sl = k & (N - 1);
+    const int bit = 31 - (((t & (G - 1)) << LC) + (sl & (CPL - 1)));
+    const uint32_t ub = (rlane_u(T.x, sl >> LC) >> bit) & 1u;
+    const uint32_t lb = (rlane_u(T.y, sl >> LC) >> bit) & 1u;
+    if (ub & lb) {
       ok = false;
       break;
-    } else if (lb) {
-      k -= 1;
-      steps = 1;
-    } else if (ub) {
-      e -= 1;
-      steps = 1;
-    } else {
-      e -= 1;
-      k -= 1;
-      steps = 2;
     }
+    /* diagonal (0,0): e-1, k-1; up (1,0): e-1; left (0,1): k-1 */
+    e -= 1 - (int)lb;
+    k -= 1 - (int)ub;
     if (e < 0 || k < 0) break;
-    /* lower-left event index of the new band from the move bits:
-     * E(i-1) = E(i) - (1 - m_i) */
-    for (int r = 0; r < steps; ++r) {
-      const int tt = i - 2;
-      const int wi = tt >> 5;
-      while (wcur > wi) {
-        --wcur;
-        if (wcur < mb) {
-          MV = MVn;
-          mb -= 64;
-          MVn = load_mv(mb - 64 + lane);
-        }
-        mword = rlane_u(MV, wcur - mb);
-      }
-      E -= 1 - (int)((mword >> (tt & 31)) & 1u);
-      --i;
-    }
   }
   if (ok && !(e == -1 && k == -1)) ok = false;
   const int rem = (int)(q & 63);
@@ -490,12 +592,13 @@ __global__ __launch_bounds__(256) void k_compact(const int2 *__restrict__ scratc
 
 /* ------------------------------------------------------------- launchers */
 
-hipError_t launch_prep(const ReadDesc *reads, int n_planned, const uint32_t *ranks,
-                       const float *scale, const float *shift, const ModelEntry *model,
-                       uint32_t n_model, KParam *kparam, int32_t *rstat, hipStream_t st) {
+hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
+                       const uint32_t *ranks, const float *scale, const float *shift,
+                       const ModelEntry *model, uint32_t n_model, float *xmean, KParam *kparam,
+                       int32_t *rstat, hipStream_t st) {
   if (n_planned <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(256), 0, st, reads, ranks, scale, shift,
-                     model, n_model, kparam, rstat);
+  hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(256), 0, st, reads, events, ranks, scale, shift,
+                     model, n_model, xmean, kparam, rstat);
   return hipGetLastError();
 }
 
@@ -506,6 +609,7 @@ hipError_t launch_band(const BandArgs &a, int n_planned, int cpl, hipStream_t st
     case 2: hipLaunchKernelGGL(k_band<2>, dim3(n_planned), dim3(64), 0, st, a); break;
     case 4: hipLaunchKernelGGL(k_band<4>, dim3(n_planned), dim3(64), 0, st, a); break;
     case 8: hipLaunchKernelGGL(k_band<8>, dim3(n_planned), dim3(64), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_band<16>, dim3(n_planned), dim3(64), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -518,6 +622,7 @@ hipError_t launch_backtrack(const BacktrackArgs &a, int n_planned, int cpl, hipS
     case 2: hipLaunchKernelGGL(k_backtrack<2>, dim3(n_planned), dim3(64), 0, st, a); break;
     case 4: hipLaunchKernelGGL(k_backtrack<4>, dim3(n_planned), dim3(64), 0, st, a); break;
     case 8: hipLaunchKernelGGL(k_backtrack<8>, dim3(n_planned), dim3(64), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_backtrack<16>, dim3(n_planned), dim3(64), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -132,7 +132,7 @@ def _edge_batch(m, rng):
     return synth.make_batch(reads)
 
 
-@pytest.mark.parametrize("W", [2, 3, 17, 64, 65, 100, 101, 127, 128, 129, 200, 250, 256, 257, 511, 512])
+@pytest.mark.parametrize("W", [2, 3, 17, 63, 64, 65, 100, 101, 127, 128, 129, 200, 250, 255, 256, 257, 511, 512])
 def test_band_widths_and_edge_cases(oracle_mod, m6, om6, W):
     rng = np.random.default_rng(1000 + W)
     b = _edge_batch(m6, rng)
