@@ -77,6 +77,13 @@ def main():
     ap.add_argument("--workload", default="plain-4000-lognormal5kb", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=1000)
+    ap.add_argument(
+        "--inflight",
+        type=int,
+        default=3,
+        help="batches in flight: each has its own context and stream, so one batch's longest "
+        "reads overlap the next batch's work (1 = strictly one batch after the other)",
+    )
     args = ap.parse_args()
     if args.gpus != 1:
         print(
@@ -98,30 +105,51 @@ def main():
     n = batch.n_reads
     dev = 0
     torch.cuda.set_device(dev)
-    al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True)
-    db = abea.to_device(batch, dev)
-    dr = abea.DeviceResult.empty(db, dev)
-    stream = torch.cuda.current_stream(dev)
+    P = max(1, args.inflight)
+    db = abea.to_device(batch, dev)  # inputs resident in HBM, shared by all slots
+    slots = []
+    for _ in range(P):
+        al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True)
+        slots.append((al, abea.DeviceResult.empty(db, dev), torch.cuda.Stream(dev)))
     torch.cuda.synchronize()
+
+    def run(steps, kt=None):
+        """Issue `steps` batches round-robin over the slots; before a slot is
+        reused its previous batch must be finished (its kernel times are read
+        then), so at most P batches are in flight."""
+        pending = [False] * P
+        for t in range(steps):
+            si = t % P
+            al, dr, st = slots[si]
+            if pending[si]:
+                ms = al.timings()  # waits for this slot's previous batch
+                if kt is not None:
+                    kt += ms
+            al.align_device(db, dr, st)
+            pending[si] = True
+        for si in range(P):
+            if pending[si]:
+                ms = slots[si][0].timings()
+                if kt is not None:
+                    kt += ms
 
     log(f"bench: warmup {args.warmup}")
-    for _ in range(args.warmup):
-        al.align_device(db, dr, stream)
-        al.timings()
+    run(args.warmup)
     torch.cuda.synchronize()
-    cells_per_step = int(dr.cells[:n].sum().item())
-    status = dr.status[:n].cpu().numpy()
+    dr0 = slots[0][1]
+    cells_per_step = int(dr0.cells[:n].sum().item())
+    status = dr0.status[:n].cpu().numpy()
 
-    log(f"bench: timing {args.steps} steps")
+    log(f"bench: timing {args.steps} steps, {P} in flight")
     kt = np.zeros(4, np.float64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        al.align_device(db, dr, stream)
-        kt += al.timings()  # per-kernel HIP-event times on the launch stream
+    run(args.steps, kt)  # per-kernel HIP-event times on each launch stream
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log("bench: timed region done")
+    for al, _, _ in slots:
+        al.close()
 
     ms_step = dt / args.steps * 1e3
     gcups = cells_per_step * args.steps / dt / 1e9
@@ -148,6 +176,7 @@ def main():
             "k": k,
             "cells_per_step": cells_per_step,
             "parallelism": "one wavefront per read",
+            "batches_in_flight": P,
         },
         "reads_per_s": round(n * args.steps / dt, 1),
         "kernel_gcups": round(cells_per_step / (kms.sum() / 1e3) / 1e9, 3),
@@ -171,7 +200,6 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(batch, model, W, min(args.cpu_sample_reads, n))
-    al.close()
     print(json.dumps(out), flush=True)
 
 

@@ -497,24 +497,49 @@ __global__ __launch_bounds__(64) void k_backtrack(const BacktrackArgs a) {
   uint2 Tn = ring[((gcur - 1) & (RG - 1)) * 64 + lane];
 
   int PE = 0, PK = 0;
-  uint64_t q = 0;
+  uint64_t q = 0; /* cells emitted and stored */
+  int qs = 0;     /* cells gathered in the lanes, not stored yet */
   const uint64_t res_end = rd.pr_off + (uint64_t)(n_e + n_k - 1);
   int2 *__restrict__ out = a.scratch;
   bool ok = true;
 
   for (;;) {
-    /* emit the cell; every 64 cells go out in one coalesced store */
-    e = __builtin_amdgcn_readfirstlane(e);
-    k = __builtin_amdgcn_readfirstlane(k);
-    const int slot = (int)(q & 63);
-    asm volatile("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %3, m0\n\tv_writelane_b32 %1, %4, m0"
-                 : "+v"(PE), "+v"(PK)
-                 : "s"(slot), "s"(e), "s"(k)
-                 : "m0");
-    ++q;
-    if ((q & 63) == 0) out[res_end - 1 - (q - 64 + lane)] = make_int2(PE, PK);
-
-    const int t = e + k; /* band t + 2 */
+    /* the cells of the current group: one dependent step per cell */
+    const int lower = gcur << LG;
+    int t = e + k;
+    int bad = 0;
+    for (;;) {
+      e = __builtin_amdgcn_readfirstlane(e);
+      k = __builtin_amdgcn_readfirstlane(k);
+      /* emit the cell; every 64 cells go out in one coalesced store */
+      asm volatile("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %3, m0\n\tv_writelane_b32 %1, %4, m0"
+                   : "+v"(PE), "+v"(PK)
+                   : "s"(qs), "s"(e), "s"(k)
+                   : "m0");
+      ++qs;
+      const int sl = k & (N - 1);
+      const int bit = 31 - (((t & (G - 1)) << LC) + (sl & (CPL - 1)));
+      const int ub = (int)((rlane_u(T.x, sl >> LC) >> bit) & 1u);
+      const int lb = (int)((rlane_u(T.y, sl >> LC) >> bit) & 1u);
+      bad = ub & lb;
+      /* diagonal (0,0): e-1, k-1; up (1,0): e-1; left (0,1): k-1 */
+      e -= 1 - lb;
+      k -= 1 - ub;
+      t = e + k;
+      /* stop when 64 cells are gathered, the walk left the table or the
+       * group, or the trace is inconsistent (each term < 0 means stop) */
+      if ((((63 - qs) | e | k | (t - lower)) < 0) | bad) break;
+    }
+    if (qs == 64) {
+      q += 64;
+      out[res_end - q + (63 - lane)] = make_int2(PE, PK);
+      qs = 0;
+    }
+    if (bad) {
+      ok = false;
+      break;
+    }
+    if ((e | k) < 0) break;
     const int gi = t >> LG;
     if (gi != gcur) { /* the walk moved down by one group */
       gcur = gi;
@@ -528,22 +553,11 @@ __global__ __launch_bounds__(64) void k_backtrack(const BacktrackArgs a) {
       }
       Tn = ring[((gcur - 1) & (RG - 1)) * 64 + lane];
     }
-    const int sl = k & (N - 1);
-    const int bit = 31 - (((t & (G - 1)) << LC) + (sl & (CPL - 1)));
-    const uint32_t ub = (rlane_u(T.x, sl >> LC) >> bit) & 1u;
-    const uint32_t lb = (rlane_u(T.y, sl >> LC) >> bit) & 1u;
-    if (ub & lb) {
-      ok = false;
-      break;
-    }
-    /* diagonal (0,0): e-1, k-1; up (1,0): e-1; left (0,1): k-1 */
-    e -= 1 - (int)lb;
-    k -= 1 - (int)ub;
-    if (e < 0 || k < 0) break;
   }
+  q += qs;
   if (ok && !(e == -1 && k == -1)) ok = false;
-  const int rem = (int)(q & 63);
-  if (rem > 0 && lane < rem) out[res_end - 1 - (q - rem + lane)] = make_int2(PE, PK);
+  /* the last qs cells: lane l holds cell q - qs + l counted from the end */
+  if (lane < qs) out[res_end - 1 - (q - qs + lane)] = make_int2(PE, PK);
   if (lane == 0) {
     a.path_len[orig] = ok ? q : 0;
     a.path_src[orig] = res_end - q;
