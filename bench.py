@@ -84,6 +84,14 @@ def main():
         help="batches in flight: each has its own context and stream, so one batch's longest "
         "reads overlap the next batch's work (1 = strictly one batch after the other)",
     )
+    ap.add_argument(
+        "--workers",
+        type=int,
+        default=0,
+        help="launch form: -1 split band/backtrack kernels, 0 one fused wavefront per read, "
+        ">0 a persistent pool of that many wavefronts with a device work queue",
+    )
+    ap.add_argument("--wpg", type=int, default=1, help="wavefronts (reads) per workgroup of the fused kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print(
@@ -109,7 +117,8 @@ def main():
     db = abea.to_device(batch, dev)  # inputs resident in HBM, shared by all slots
     slots = []
     for _ in range(P):
-        al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True)
+        al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True,
+                          workers=args.workers, waves_per_group=args.wpg)
         slots.append((al, abea.DeviceResult.empty(db, dev), torch.cuda.Stream(dev)))
     torch.cuda.synchronize()
 

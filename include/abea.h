@@ -79,7 +79,9 @@ typedef struct {
 typedef struct {
   int32_t bandwidth;    /* W, the band width (thesis: typically 100) */
   int32_t device;       /* HIP device ordinal */
-  uint64_t arena_bytes; /* reserved for a future fixed-size device arena; 0 = grow on demand */
+  uint64_t arena_bytes; /* traceback budget of one batch in bytes (0 = unbounded): the fused
+                           kernel runs only as many reads at once as their trace fits in it
+                           (admission by traceback bytes); see abea_launch_t */
   uint32_t flags;       /* ABEA_F_* */
 } abea_config_t;
 
@@ -154,12 +156,75 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *batch,
                             const abea_result_t *res, void *stream);
 
 /*
- * Device time in milliseconds of each kernel of the last call, when the
- * context was created with ABEA_F_TIMING: out[0] k-mer parameter
- * preparation, out[1] band fill, out[2] backtrack, out[3] compaction.
+ * Device time in milliseconds of each stage of the last direct call
+ * (abea_align_batch or abea_align_batch_device), when the context was
+ * created with ABEA_F_TIMING: out[0] k-mer parameter preparation, out[1] band
+ * fill (split kernels) or band fill + backtrack (fused kernel), out[2]
+ * backtrack (split kernels; 0 for the fused kernel), out[3] compaction.
  * Synchronises the stream of the last call.  n is the length of out.
  */
 int abea_get_timings(abea_ctx *ctx, float *out, int n);
+
+/* ---- launch form ----------------------------------------------------------
+ * How the band fill (Alg. 5.1-5.3) and the backtrack are scheduled; every
+ * form gives bit-identical results.  The thesis runs a pre-kernel, a
+ * core-kernel with one thread block per read and a post-kernel (Ch. 5
+ * §5.4.1) and pre-allocates memory for a batch with a CPU fall-back for reads
+ * that do not fit (§5.4.2.2, §5.4.3); here:
+ *   workers == ABEA_WORKERS_SPLIT : one wavefront per read, band fill and
+ *       backtrack as two kernels (every read's trace is in memory at once);
+ *   workers == 0 : one fused kernel, one wavefront per read that fills the
+ *       bands and then backtracks (the default; one launch per batch);
+ *   workers  > 0 : the fused kernel as a persistent pool of that many
+ *       wavefronts (capped by residency and by arena_bytes) that take reads,
+ *       longest first, from a device work queue; trace memory is that of the
+ *       `workers` longest reads only.
+ * waves_per_group: wavefronts (reads) per workgroup of the fused kernel, 1, 2
+ * or 4.  cells_per_lane: band slots per lane, 0 = the smallest power of two
+ * with 64*c > W, else a power of two at least that and at most 16.
+ * Applies to later calls and graphs; waits for the context's queued work.
+ * Errors: ABEA_E_INVAL.
+ */
+#define ABEA_WORKERS_SPLIT (-1)
+typedef struct {
+  int32_t workers;
+  int32_t waves_per_group;
+  int32_t cells_per_lane;
+  int32_t reserved; /* 0 */
+} abea_launch_t;
+int abea_set_launch(abea_ctx *ctx, const abea_launch_t *launch);
+
+/* How a batch was planned: the context's last direct call, or a graph. */
+typedef struct {
+  int32_t n_reads;
+  int32_t workers;         /* fused-kernel wavefronts (0: split kernels) */
+  int32_t cells_per_lane;
+  int32_t waves_per_group;
+  uint64_t trace_bytes;    /* device trace memory of the batch */
+  uint64_t scratch_bytes;  /* device pair scratch of the batch */
+} abea_plan_info_t;
+int abea_get_plan_info(const abea_ctx *ctx, abea_plan_info_t *info);
+
+/* ---- captured batches (HIP graphs) ------------------------------------------
+ * abea_graph_create plans a device-resident batch (pointers as in
+ * abea_align_batch_device) with the context's current launch form, gives it
+ * device buffers of its own, uploads the plan and captures the batch's
+ * kernels into a HIP graph.  abea_graph_launch replays the graph on `stream`
+ * (asynchronous; results valid once the stream is synchronised); each replay
+ * recomputes every output from the batch's inputs, so the caller may change
+ * the input values (not their sizes) between replays.  The batch and result
+ * buffers must stay valid until abea_graph_destroy.  Replays of one graph
+ * must not overlap each other; different graphs may run concurrently on
+ * different streams.  The graph holds no reference to the context's own
+ * buffers; the context must outlive it.
+ * Errors: as abea_align_batch_device.
+ */
+typedef struct abea_graph abea_graph;
+int abea_graph_create(abea_ctx *ctx, const abea_batch_t *batch, const abea_result_t *res,
+                      abea_graph **out);
+int abea_graph_launch(abea_graph *graph, void *stream);
+int abea_graph_info(const abea_graph *graph, abea_plan_info_t *info);
+void abea_graph_destroy(abea_graph *graph);
 
 /* Free the context and all its device memory.  NULL is allowed. */
 void abea_destroy(abea_ctx *ctx);

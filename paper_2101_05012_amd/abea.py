@@ -29,12 +29,19 @@ READ_OK, READ_EMPTY, READ_BAND_LOST, READ_BAD_RANK = 0, 1, 2, 3
 ABEA_MAX_BANDWIDTH = 512
 ABEA_MAX_K = 12
 ABEA_F_TIMING = 1
+ABEA_WORKERS_SPLIT = -1
 
 EXPORTED = (
     "abea_create",
     "abea_align_batch",
     "abea_align_batch_device",
     "abea_get_timings",
+    "abea_set_launch",
+    "abea_get_plan_info",
+    "abea_graph_create",
+    "abea_graph_launch",
+    "abea_graph_info",
+    "abea_graph_destroy",
     "abea_destroy",
     "abea_strerror",
     "abea_last_error",
@@ -91,6 +98,29 @@ class abea_result_t(ctypes.Structure):
     ]
 
 
+class abea_launch_t(ctypes.Structure):
+    _fields_ = [
+        ("workers", ctypes.c_int32),
+        ("waves_per_group", ctypes.c_int32),
+        ("cells_per_lane", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class abea_plan_info_t(ctypes.Structure):
+    _fields_ = [
+        ("n_reads", ctypes.c_int32),
+        ("workers", ctypes.c_int32),
+        ("cells_per_lane", ctypes.c_int32),
+        ("waves_per_group", ctypes.c_int32),
+        ("trace_bytes", ctypes.c_uint64),
+        ("scratch_bytes", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -119,6 +149,18 @@ def lib() -> ctypes.CDLL:
         L.abea_align_batch_device.restype = ctypes.c_int
         L.abea_get_timings.argtypes = [P, P, ctypes.c_int]
         L.abea_get_timings.restype = ctypes.c_int
+        L.abea_set_launch.argtypes = [P, ctypes.POINTER(abea_launch_t)]
+        L.abea_set_launch.restype = ctypes.c_int
+        L.abea_get_plan_info.argtypes = [P, ctypes.POINTER(abea_plan_info_t)]
+        L.abea_get_plan_info.restype = ctypes.c_int
+        L.abea_graph_create.argtypes = [P, ctypes.POINTER(abea_batch_t), ctypes.POINTER(abea_result_t), ctypes.POINTER(P)]
+        L.abea_graph_create.restype = ctypes.c_int
+        L.abea_graph_launch.argtypes = [P, P]
+        L.abea_graph_launch.restype = ctypes.c_int
+        L.abea_graph_info.argtypes = [P, ctypes.POINTER(abea_plan_info_t)]
+        L.abea_graph_info.restype = ctypes.c_int
+        L.abea_graph_destroy.argtypes = [P]
+        L.abea_graph_destroy.restype = None
         L.abea_destroy.argtypes = [P]
         L.abea_destroy.restype = None
         L.abea_strerror.argtypes = [ctypes.c_int]
@@ -158,10 +200,22 @@ def pair_capacity(event_offset: np.ndarray, kmer_offset: np.ndarray) -> int:
 class Aligner:
     """One library context (pore model on the device, band width W)."""
 
-    def __init__(self, level_mean, level_stdv, k: int, W: int = 100, device: int = 0, timing: bool = False):
+    def __init__(
+        self,
+        level_mean,
+        level_stdv,
+        k: int,
+        W: int = 100,
+        device: int = 0,
+        timing: bool = False,
+        arena_bytes: int = 0,
+        workers: int = 0,
+        waves_per_group: int = 1,
+        cells_per_lane: int = 0,
+    ):
         self._lm = np.ascontiguousarray(level_mean, np.float32)
         self._ls = np.ascontiguousarray(level_stdv, np.float32)
-        cfg = abea_config_t(W, device, 0, ABEA_F_TIMING if timing else 0)
+        cfg = abea_config_t(W, device, int(arena_bytes), ABEA_F_TIMING if timing else 0)
         mdl = abea_model_t(k, self._lm.ctypes.data, self._ls.ctypes.data)
         h = ctypes.c_void_p()
         rc = lib().abea_create(ctypes.byref(cfg), ctypes.byref(mdl), ctypes.byref(h))
@@ -171,6 +225,27 @@ class Aligner:
         self.W = W
         self.k = k
         self.device = device
+        if (workers, waves_per_group, cells_per_lane) != (0, 1, 0):
+            self.set_launch(workers, waves_per_group, cells_per_lane)
+
+    def set_launch(self, workers: int = 0, waves_per_group: int = 1, cells_per_lane: int = 0) -> None:
+        """Launch form (abea_set_launch): workers -1 split kernels, 0 one fused
+        wavefront per read, > 0 a persistent pool with a device work queue."""
+        L = abea_launch_t(int(workers), int(waves_per_group), int(cells_per_lane), 0)
+        self._check(lib().abea_set_launch(self.handle, ctypes.byref(L)), "abea_set_launch")
+
+    def plan_info(self) -> dict:
+        info = abea_plan_info_t()
+        self._check(lib().abea_get_plan_info(self.handle, ctypes.byref(info)), "abea_get_plan_info")
+        return info.as_dict()
+
+    def graph(self, dbatch: "DeviceBatch", dres: "DeviceResult") -> "Graph":
+        """Capture the batch's kernels into a HIP graph (abea_graph_create)."""
+        b, r = _dev_structs(dbatch, dres)
+        g = ctypes.c_void_p()
+        self._check(lib().abea_graph_create(self.handle, ctypes.byref(b), ctypes.byref(r), ctypes.byref(g)),
+                    "abea_graph_create")
+        return Graph(self, g, dbatch, dres)
 
     def _check(self, rc: int, what: str):
         if rc != ABEA_OK:
@@ -201,21 +276,10 @@ class Aligner:
         """Device-resident batch through abea_align_batch_device (asynchronous
         on ``stream``: a torch.cuda.Stream, a raw hipStream_t int, or None for
         torch's current stream)."""
-        if stream is None:
-            import torch
-
-            stream = torch.cuda.current_stream(self.device)
-        sp = stream if isinstance(stream, int) else int(stream.cuda_stream)
-        b = abea_batch_t(
-            dbatch.n_reads, _ptr(dbatch.events), _ptr(dbatch.event_offset), _ptr(dbatch.ranks),
-            _ptr(dbatch.kmer_offset), _ptr(dbatch.scale), _ptr(dbatch.shift),
-        )
-        r = abea_result_t(
-            _ptr(dres.pairs), dres.capacity, _ptr(dres.pair_offset), _ptr(dres.log_likelihood),
-            _ptr(dres.status), _ptr(dres.cells),
-        )
+        b, r = _dev_structs(dbatch, dres)
         self._check(
-            lib().abea_align_batch_device(self.handle, ctypes.byref(b), ctypes.byref(r), ctypes.c_void_p(sp)),
+            lib().abea_align_batch_device(self.handle, ctypes.byref(b), ctypes.byref(r),
+                                          ctypes.c_void_p(_stream_ptr(stream, self.device))),
             "abea_align_batch_device",
         )
 
@@ -228,6 +292,56 @@ class Aligner:
     def close(self):
         if getattr(self, "handle", None):
             lib().abea_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(stream, device: int) -> int:
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream(device)
+    return stream if isinstance(stream, int) else int(stream.cuda_stream)
+
+
+def _dev_structs(dbatch: "DeviceBatch", dres: "DeviceResult"):
+    b = abea_batch_t(
+        dbatch.n_reads, _ptr(dbatch.events), _ptr(dbatch.event_offset), _ptr(dbatch.ranks),
+        _ptr(dbatch.kmer_offset), _ptr(dbatch.scale), _ptr(dbatch.shift),
+    )
+    r = abea_result_t(
+        _ptr(dres.pairs), dres.capacity, _ptr(dres.pair_offset), _ptr(dres.log_likelihood),
+        _ptr(dres.status), _ptr(dres.cells),
+    )
+    return b, r
+
+
+class Graph:
+    """A captured batch (abea_graph_*): replay with ``launch(stream)``."""
+
+    def __init__(self, aligner: Aligner, handle, dbatch, dres):
+        self.aligner = aligner
+        self.handle = handle
+        self.dbatch = dbatch  # keeps the device buffers alive
+        self.dres = dres
+
+    def launch(self, stream=None) -> None:
+        rc = lib().abea_graph_launch(self.handle, ctypes.c_void_p(_stream_ptr(stream, self.aligner.device)))
+        self.aligner._check(rc, "abea_graph_launch")
+
+    def info(self) -> dict:
+        info = abea_plan_info_t()
+        self.aligner._check(lib().abea_graph_info(self.handle, ctypes.byref(info)), "abea_graph_info")
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().abea_graph_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

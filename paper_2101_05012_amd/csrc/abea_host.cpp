@@ -35,7 +35,9 @@ struct DevBuf {
 
 struct Plan {
   int n = 0;
-  std::vector<int> order;
+  int workers = 0;        /* fused kernel: wavefronts (0 for the split kernels) */
+  int cpl = 2;            /* slots per lane the plan was made for */
+  int wpg = 1;            /* wavefronts per workgroup of the fused kernel */
   uint64_t n_trace = 0;   /* uint2 words */
   uint64_t n_scratch = 0; /* pair slots */
   uint64_t n_events = 0;
@@ -43,32 +45,48 @@ struct Plan {
   uint64_t pairs_needed = 0;
 };
 
-}  // namespace
-
-struct abea_ctx {
-  int device = 0;
-  int W = 100;
-  int cpl = 2;
-  uint32_t flags = 0;
-  uint32_t k = 6;
-  uint32_t n_model = 0;
-  DevBuf model;
-  hipStream_t own_stream = nullptr;
-  hipStream_t last_stream = nullptr;
-  /* planned-batch state */
-  DevBuf reads, rstat, xmean, kparam, trace, scratch, path_len, path_src;
-  /* host-API copies of inputs and outputs */
-  DevBuf events, ranks, scale, shift, pairs, pair_offset, ll, status, cells;
-  /* pinned staging of the plan */
-  ReadDesc *h_reads = nullptr;
-  int32_t *h_rstat = nullptr;
+/* Device buffers and staging of one planned batch.  The context owns one for
+ * its direct calls; every captured graph owns its own, so graphs can run
+ * concurrently on different streams. */
+struct Work {
+  Plan plan;
+  std::vector<int> order;
+  DevBuf reads, rstat, queue, xmean, kparam, trace, scratch, path_len, path_src;
+  ReadDesc *h_reads = nullptr; /* pinned staging of the plan */
   size_t h_cap = 0;
   hipEvent_t staging_done = nullptr;
   bool staging_pending = false;
   hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
-  Plan plan;
+  hipStream_t last_stream = nullptr;
+};
+
+}  // namespace
+
+struct abea_ctx {
+  int device = 0;
+  int W = 100;
+  uint32_t flags = 0;
+  uint32_t k = 6;
+  uint32_t n_model = 0;
+  uint64_t arena_bytes = 0; /* trace budget of one batch (0 = unbounded) */
+  int num_cus = 0;
+  abea_launch_t launch = {0, 1, 0, 0};
+  int cpl = 2; /* slots per lane in use */
+  DevBuf model;
+  hipStream_t own_stream = nullptr;
+  Work main;
+  /* host-API copies of inputs and outputs */
+  DevBuf events, ranks, scale, shift, pairs, pair_offset, ll, status, cells;
   std::string err;
+};
+
+struct abea_graph {
+  abea_ctx *ctx = nullptr;
+  Work work;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -93,11 +111,11 @@ int fail(abea_ctx *ctx, int code, const char *fmt, ...) {
                   #expr, hipGetErrorString(e_));                                            \
   } while (0)
 
-int ensure(abea_ctx *ctx, DevBuf &b, size_t bytes) {
+int ensure(abea_ctx *ctx, Work *w, DevBuf &b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (bytes <= b.cap) return ABEA_OK;
   /* kernels queued by earlier calls may still use the old buffer */
-  if (ctx->last_stream) HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  if (w && w->last_stream) HIP_TRY(ctx, hipStreamSynchronize(w->last_stream));
   HIP_TRY(ctx, hipDeviceSynchronize());
   if (b.p) HIP_TRY(ctx, hipFree(b.p));
   b.p = nullptr;
@@ -119,6 +137,27 @@ void free_buf(DevBuf &b) {
   b.cap = 0;
 }
 
+int work_init(abea_ctx *ctx, Work &w) {
+  HIP_TRY(ctx, hipEventCreateWithFlags(&w.staging_done, hipEventDisableTiming));
+  for (auto &ev : w.tev) HIP_TRY(ctx, hipEventCreate(&ev));
+  return ABEA_OK;
+}
+
+void work_free(Work &w) {
+  DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.xmean, &w.kparam,
+                    &w.trace, &w.scratch, &w.path_len, &w.path_src};
+  for (DevBuf *b : bufs) free_buf(*b);
+  if (w.h_reads) (void)hipHostFree(w.h_reads);
+  w.h_reads = nullptr;
+  w.h_cap = 0;
+  if (w.staging_done) (void)hipEventDestroy(w.staging_done);
+  w.staging_done = nullptr;
+  for (auto &ev : w.tev) {
+    if (ev) (void)hipEventDestroy(ev);
+    ev = nullptr;
+  }
+}
+
 /* Alg. 5.2 transition constants, each computed in double and rounded once;
  * the printed epsilon "1^{-10}" reads as 1e-10. */
 void transitions(int64_t n_events, int64_t n_kmers, float *skip, float *stay, float *step) {
@@ -131,15 +170,30 @@ void transitions(int64_t n_events, int64_t n_kmers, float *skip, float *stay, fl
   *step = (float)lstep;
 }
 
-/* Plan a batch from host offsets: sort reads longest first (so the longest
- * band chains start first), give each read its trace, move-bit and pair
- * scratch regions, and compute its constants. */
-int plan_batch(abea_ctx *ctx, int n, const uint64_t *eo, const uint64_t *ko, uint64_t pair_capacity) {
-  Plan &P = ctx->plan;
+bool split_kernels(const abea_ctx *ctx) { return ctx->launch.workers == ABEA_WORKERS_SPLIT; }
+
+/* Wavefronts of the fused kernel that are resident at once on the device. */
+int resident_workers(abea_ctx *ctx) {
+  const int gpc = align_groups_per_cu(ctx->cpl, ctx->launch.waves_per_group);
+  return std::max(1, gpc * ctx->num_cus * ctx->launch.waves_per_group);
+}
+
+/* Plan a batch from host offsets.
+ *  - Reads are sorted by computed bands (n_e + n_k - 1, 0 for an empty read),
+ *    longest first, so the longest band chains start first and every read
+ *    fits the trace region of any read planned before it.
+ *  - Pair scratch: n_e + n_k - 1 slots per read (a path never has more).
+ *  - Trace: fused kernel with P workers: read s < P gets its own region and
+ *    worker s reuses it for every later read it takes; P is the requested
+ *    worker count, capped by residency and by the trace budget (admission by
+ *    traceback bytes).  Split kernels: every read gets its own region. */
+int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t *ko,
+               uint64_t pair_capacity) {
+  Plan &P = w.plan;
   if (eo[0] != 0 || ko[0] != 0) return fail(ctx, ABEA_E_INVAL, "offsets must start at 0");
   P.n = n;
-  P.order.resize(n);
-  std::vector<uint64_t> len(n);
+  w.order.resize(n);
+  std::vector<uint64_t> comp(n);
   uint64_t need = 0;
   for (int r = 0; r < n; ++r) {
     if (eo[r + 1] < eo[r] || ko[r + 1] < ko[r])
@@ -147,57 +201,69 @@ int plan_batch(abea_ctx *ctx, int n, const uint64_t *eo, const uint64_t *ko, uin
     const uint64_t ne = eo[r + 1] - eo[r], nk = ko[r + 1] - ko[r];
     if (ne > 0x3fffffffull || nk > 0x3fffffffull)
       return fail(ctx, ABEA_E_INVAL, "read %d is too long", r);
-    len[r] = ne + nk;
-    if (ne > 0 && nk > 0) need += ne + nk - 1;
+    comp[r] = (ne > 0 && nk > 0) ? ne + nk - 1 : 0;
+    need += comp[r];
   }
   P.pairs_needed = need;
   if (pair_capacity < need)
     return fail(ctx, ABEA_E_CAPACITY, "pair_capacity %llu < %llu", (unsigned long long)pair_capacity,
                 (unsigned long long)need);
-  std::iota(P.order.begin(), P.order.end(), 0);
-  std::stable_sort(P.order.begin(), P.order.end(), [&](int a, int b) { return len[a] > len[b]; });
+  std::iota(w.order.begin(), w.order.end(), 0);
+  std::stable_sort(w.order.begin(), w.order.end(), [&](int a, int b) { return comp[a] > comp[b]; });
 
-  if ((size_t)n > ctx->h_cap) {
-    if (ctx->staging_pending) HIP_TRY(ctx, hipEventSynchronize(ctx->staging_done));
-    ctx->staging_pending = false;
-    if (ctx->h_reads) (void)hipHostFree(ctx->h_reads);
-    if (ctx->h_rstat) (void)hipHostFree(ctx->h_rstat);
-    ctx->h_reads = nullptr;
-    ctx->h_rstat = nullptr;
-    ctx->h_cap = 0;
-    const size_t cap = std::max<size_t>(n, 1024);
-    HIP_TRY(ctx, hipHostMalloc((void **)&ctx->h_reads, cap * sizeof(ReadDesc), hipHostMallocDefault));
-    HIP_TRY(ctx, hipHostMalloc((void **)&ctx->h_rstat, cap * sizeof(int32_t), hipHostMallocDefault));
-    ctx->h_cap = cap;
-  }
-  /* the previous call's upload must have left the staging buffers */
-  if (ctx->staging_pending) HIP_TRY(ctx, hipEventSynchronize(ctx->staging_done));
-  ctx->staging_pending = false;
-
+  /* trace words of planned read s, and the worker count */
   const int G = bands_per_group(ctx->cpl);
+  auto words = [&](int s) -> uint64_t { return ((comp[w.order[s]] + G - 1) / G) * 64u; };
+  int workers = n;
+  if (!split_kernels(ctx) && ctx->launch.workers > 0)
+    workers = std::min(n, std::min(ctx->launch.workers, resident_workers(ctx)));
+  if (ctx->arena_bytes > 0) {
+    uint64_t sum = 0;
+    int fit = 0;
+    while (fit < workers && (sum + words(fit)) * sizeof(uint2) <= ctx->arena_bytes) sum += words(fit++);
+    if (fit < workers) {
+      if (split_kernels(ctx) || fit == 0)
+        return fail(ctx, ABEA_E_NOMEM, "trace of %s needs more than arena_bytes = %llu",
+                    fit == 0 ? "the longest read" : "the batch", (unsigned long long)ctx->arena_bytes);
+      workers = fit;
+    }
+  }
+  P.workers = split_kernels(ctx) ? 0 : workers;
+  P.cpl = ctx->cpl;
+  P.wpg = ctx->launch.waves_per_group;
+
+  if ((size_t)n > w.h_cap) {
+    if (w.staging_pending) HIP_TRY(ctx, hipEventSynchronize(w.staging_done));
+    w.staging_pending = false;
+    if (w.h_reads) (void)hipHostFree(w.h_reads);
+    w.h_reads = nullptr;
+    w.h_cap = 0;
+    const size_t cap = std::max<size_t>(n, 1024);
+    HIP_TRY(ctx, hipHostMalloc((void **)&w.h_reads, cap * sizeof(ReadDesc), hipHostMallocDefault));
+    w.h_cap = cap;
+  }
+  /* the previous call's upload must have left the staging buffer */
+  if (w.staging_pending) HIP_TRY(ctx, hipEventSynchronize(w.staging_done));
+  w.staging_pending = false;
+
   uint64_t tr = 0, pr = 0;
   for (int s = 0; s < n; ++s) {
-    const int r = P.order[s];
-    ReadDesc &d = ctx->h_reads[s];
+    const int r = w.order[s];
+    ReadDesc &d = w.h_reads[s];
     const uint64_t ne = eo[r + 1] - eo[r], nk = ko[r + 1] - ko[r];
     d.ev_off = eo[r];
     d.km_off = ko[r];
     d.n_e = (int32_t)ne;
     d.n_k = (int32_t)nk;
     d.orig = r;
-    d.tr_off = tr;
+    d.tr_off = (s < workers) ? tr : 0;
     d.spare = 0;
     d.pr_off = pr;
     d.lp_skip = d.lp_stay = d.lp_step = 0.f;
-    if (ne == 0 || nk == 0) {
-      ctx->h_rstat[s] = READ_EMPTY;
-      continue;
-    }
-    ctx->h_rstat[s] = READ_OK;
+    if (comp[r] == 0) continue;
     transitions((int64_t)ne, (int64_t)nk, &d.lp_skip, &d.lp_stay, &d.lp_step);
-    const uint64_t computed = ne + nk - 1; /* bands 2 .. n_e+n_k */
-    tr += ((computed + G - 1) / G) * 64u; /* 64 lanes x uint2 per group of G bands */
-    pr += computed;
+    if (s < workers) tr += words(s);
+    pr += comp[r];
   }
   P.n_trace = tr;
   P.n_scratch = pr;
@@ -218,65 +284,77 @@ struct DevIO {
   uint64_t *cells;
 };
 
-/* Enqueue the planned batch on `st`. */
-int run_planned(abea_ctx *ctx, const DevIO &io, hipStream_t st) {
-  const Plan &P = ctx->plan;
-  const int n = P.n;
+int ensure_work(abea_ctx *ctx, Work &w) {
+  const Plan &P = w.plan;
+  const size_t n = (size_t)std::max(P.n, 1);
   int rc;
-  if ((rc = ensure(ctx, ctx->reads, sizeof(ReadDesc) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, ctx->rstat, sizeof(int32_t) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, ctx->xmean, sizeof(float) * (size_t)P.n_events))) return rc;
-  if ((rc = ensure(ctx, ctx->kparam, sizeof(KParam) * (size_t)P.n_kmers))) return rc;
-  if ((rc = ensure(ctx, ctx->trace, sizeof(uint2) * (size_t)P.n_trace))) return rc;
-  if ((rc = ensure(ctx, ctx->scratch, sizeof(int2) * (size_t)P.n_scratch))) return rc;
-  if ((rc = ensure(ctx, ctx->path_len, sizeof(uint64_t) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, ctx->path_src, sizeof(uint64_t) * (size_t)n))) return rc;
-  ctx->last_stream = st;
-
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->reads.p, ctx->h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->rstat.p, ctx->h_rstat, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipEventRecord(ctx->staging_done, st));
-  ctx->staging_pending = true;
-
-  const ReadDesc *reads = (const ReadDesc *)ctx->reads.p;
-  int32_t *rstat = (int32_t *)ctx->rstat.p;
-  const bool timed = (ctx->flags & ABEA_F_TIMING) != 0;
-  if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[0], st));
-  HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ranks, io.scale, io.shift,
-                           (const ModelEntry *)ctx->model.p, ctx->n_model, (float *)ctx->xmean.p,
-                           (KParam *)ctx->kparam.p, rstat, st));
-  if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[1], st));
-
-  BandArgs ba;
-  ba.reads = reads;
-  ba.xmean = (const float *)ctx->xmean.p;
-  ba.kparam = (const KParam *)ctx->kparam.p;
-  ba.rstat = rstat;
-  ba.trace = (uint2 *)ctx->trace.p;
-  ba.out_ll = io.ll;
-  ba.out_cells = io.cells;
-  ba.W = ctx->W;
-  HIP_TRY(ctx, launch_band(ba, n, ctx->cpl, st));
-  if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[2], st));
-
-  BacktrackArgs bt;
-  bt.reads = reads;
-  bt.rstat = rstat;
-  bt.trace = (const uint2 *)ctx->trace.p;
-  bt.scratch = (int2 *)ctx->scratch.p;
-  bt.path_len = (uint64_t *)ctx->path_len.p;
-  bt.path_src = (uint64_t *)ctx->path_src.p;
-  bt.out_status = io.status;
-  bt.out_ll = io.ll;
-  HIP_TRY(ctx, launch_backtrack(bt, n, ctx->cpl, st));
-  if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[3], st));
-
-  HIP_TRY(ctx, launch_scan((const uint64_t *)ctx->path_len.p, n, io.pair_offset, st));
-  HIP_TRY(ctx, launch_compact((const int2 *)ctx->scratch.p, (const uint64_t *)ctx->path_src.p,
-                              io.pair_offset, n, io.pairs, st));
-  if (timed) HIP_TRY(ctx, hipEventRecord(ctx->tev[4], st));
-  ctx->timed = timed;
+  if ((rc = ensure(ctx, &w, w.reads, sizeof(ReadDesc) * n))) return rc;
+  if ((rc = ensure(ctx, &w, w.rstat, sizeof(int32_t) * n))) return rc;
+  if ((rc = ensure(ctx, &w, w.queue, sizeof(uint32_t)))) return rc;
+  if ((rc = ensure(ctx, &w, w.xmean, sizeof(float) * (size_t)P.n_events))) return rc;
+  if ((rc = ensure(ctx, &w, w.kparam, sizeof(KParam) * (size_t)P.n_kmers))) return rc;
+  if ((rc = ensure(ctx, &w, w.trace, sizeof(uint2) * (size_t)P.n_trace))) return rc;
+  if ((rc = ensure(ctx, &w, w.scratch, sizeof(int2) * (size_t)P.n_scratch))) return rc;
+  if ((rc = ensure(ctx, &w, w.path_len, sizeof(uint64_t) * n))) return rc;
+  if ((rc = ensure(ctx, &w, w.path_src, sizeof(uint64_t) * n))) return rc;
   return ABEA_OK;
+}
+
+/* Enqueue the kernels of a planned batch whose plan is on the device. */
+int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, bool timed) {
+  const Plan &P = w.plan;
+  const int n = P.n;
+  const ReadDesc *reads = (const ReadDesc *)w.reads.p;
+  int32_t *rstat = (int32_t *)w.rstat.p;
+  if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[0], st));
+  HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ranks, io.scale, io.shift,
+                           (const ModelEntry *)ctx->model.p, ctx->n_model, (float *)w.xmean.p,
+                           (KParam *)w.kparam.p, rstat, (uint32_t *)w.queue.p, st));
+  if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[1], st));
+
+  AlignArgs a;
+  a.reads = reads;
+  a.xmean = (const float *)w.xmean.p;
+  a.kparam = (const KParam *)w.kparam.p;
+  a.rstat = rstat;
+  a.trace = (uint2 *)w.trace.p;
+  a.scratch = (int2 *)w.scratch.p;
+  a.path_len = (uint64_t *)w.path_len.p;
+  a.path_src = (uint64_t *)w.path_src.p;
+  a.out_ll = io.ll;
+  a.out_cells = io.cells;
+  a.out_status = io.status;
+  a.queue = (uint32_t *)w.queue.p;
+  a.n_reads = n;
+  a.n_workers = P.workers;
+  a.W = ctx->W;
+  if (P.workers == 0) {
+    HIP_TRY(ctx, launch_band(a, P.cpl, st));
+    if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[2], st));
+    HIP_TRY(ctx, launch_backtrack(a, P.cpl, st));
+  } else {
+    HIP_TRY(ctx, launch_align(a, P.cpl, P.wpg, st));
+    if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[2], st));
+  }
+  if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[3], st));
+
+  HIP_TRY(ctx, launch_scan((const uint64_t *)w.path_len.p, n, io.pair_offset, st));
+  HIP_TRY(ctx, launch_compact((const int2 *)w.scratch.p, (const uint64_t *)w.path_src.p,
+                              io.pair_offset, n, io.pairs, st));
+  if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[4], st));
+  w.timed = timed;
+  return ABEA_OK;
+}
+
+/* Upload the plan and enqueue the batch on `st`. */
+int run_planned(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st) {
+  int rc;
+  if ((rc = ensure_work(ctx, w))) return rc;
+  w.last_stream = st;
+  HIP_TRY(ctx, hipMemcpyAsync(w.reads.p, w.h_reads, sizeof(ReadDesc) * w.plan.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipEventRecord(w.staging_done, st));
+  w.staging_pending = true;
+  return enqueue_kernels(ctx, w, io, st, (ctx->flags & ABEA_F_TIMING) != 0);
 }
 
 int check_batch(abea_ctx *ctx, const abea_batch_t *b, const abea_result_t *r) {
@@ -340,21 +418,19 @@ int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **
   ctx->flags = cfg->flags;
   ctx->k = model->k;
   ctx->n_model = n_model;
+  ctx->arena_bytes = cfg->arena_bytes;
   int rc = ABEA_OK;
   do {
     hipError_t e = hipSetDevice(cfg->device);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "hipSetDevice: %s", hipGetErrorString(e)); break; }
-    if ((rc = ensure(ctx, ctx->model, sizeof(ModelEntry) * n_model))) break;
+    e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
+    if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "device attribute: %s", hipGetErrorString(e)); break; }
+    if ((rc = ensure(ctx, nullptr, ctx->model, sizeof(ModelEntry) * n_model))) break;
     e = hipMemcpy(ctx->model.p, me.data(), sizeof(ModelEntry) * n_model, hipMemcpyHostToDevice);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "model upload: %s", hipGetErrorString(e)); break; }
     e = hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "stream: %s", hipGetErrorString(e)); break; }
-    e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming);
-    if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "event: %s", hipGetErrorString(e)); break; }
-    for (auto &ev : ctx->tev) {
-      e = hipEventCreate(&ev);
-      if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "event: %s", hipGetErrorString(e)); break; }
-    }
+    if ((rc = work_init(ctx, ctx->main))) break;
   } while (0);
   if (rc != ABEA_OK) {
     abea_destroy(ctx);
@@ -368,18 +444,41 @@ void abea_destroy(abea_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  DevBuf *bufs[] = {&ctx->model, &ctx->reads, &ctx->rstat, &ctx->xmean, &ctx->kparam,
-                    &ctx->trace, &ctx->scratch, &ctx->path_len, &ctx->path_src,
-                    &ctx->events, &ctx->ranks, &ctx->scale, &ctx->shift, &ctx->pairs,
-                    &ctx->pair_offset, &ctx->ll, &ctx->status, &ctx->cells};
+  work_free(ctx->main);
+  DevBuf *bufs[] = {&ctx->model, &ctx->events, &ctx->ranks, &ctx->scale, &ctx->shift,
+                    &ctx->pairs, &ctx->pair_offset, &ctx->ll, &ctx->status, &ctx->cells};
   for (DevBuf *b : bufs) free_buf(*b);
-  if (ctx->h_reads) (void)hipHostFree(ctx->h_reads);
-  if (ctx->h_rstat) (void)hipHostFree(ctx->h_rstat);
-  if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
-  for (auto &ev : ctx->tev)
-    if (ev) (void)hipEventDestroy(ev);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
   delete ctx;
+}
+
+int abea_set_launch(abea_ctx *ctx, const abea_launch_t *l) {
+  if (!ctx) return ABEA_E_INVAL;
+  if (!l) return fail(ctx, ABEA_E_INVAL, "null launch");
+  if (l->workers < ABEA_WORKERS_SPLIT) return fail(ctx, ABEA_E_INVAL, "workers < -1");
+  if (l->waves_per_group != 1 && l->waves_per_group != 2 && l->waves_per_group != 4)
+    return fail(ctx, ABEA_E_INVAL, "waves_per_group must be 1, 2 or 4");
+  const int minc = cells_per_lane(ctx->W);
+  int c = l->cells_per_lane == 0 ? minc : l->cells_per_lane;
+  if (c < minc || c > 16 || (c & (c - 1)) != 0)
+    return fail(ctx, ABEA_E_INVAL, "cells_per_lane %d: need a power of two in [%d, 16]", l->cells_per_lane, minc);
+  /* buffers of an earlier call may still be in use by queued kernels */
+  if (ctx->main.last_stream) HIP_TRY(ctx, hipStreamSynchronize(ctx->main.last_stream));
+  ctx->launch = *l;
+  ctx->cpl = c;
+  return ABEA_OK;
+}
+
+int abea_get_plan_info(const abea_ctx *ctx, abea_plan_info_t *info) {
+  if (!ctx || !info) return ABEA_E_INVAL;
+  const Plan &P = ctx->main.plan;
+  info->n_reads = P.n;
+  info->workers = P.workers;
+  info->cells_per_lane = P.cpl;
+  info->waves_per_group = P.wpg;
+  info->trace_bytes = P.n_trace * sizeof(uint2);
+  info->scratch_bytes = P.n_scratch * sizeof(int2);
+  return ABEA_OK;
 }
 
 int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *b, const abea_result_t *r, void *stream) {
@@ -389,7 +488,7 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int n = b->n_reads;
-  if ((rc = plan_batch(ctx, n, b->event_offset, b->kmer_offset, r->pair_capacity))) return rc;
+  if ((rc = plan_batch(ctx, ctx->main, n, b->event_offset, b->kmer_offset, r->pair_capacity))) return rc;
   if (n == 0) {
     /* a one-block kernel writes pair_offset[0] = 0 (no memset node, so the
      * call stays safe to capture in a graph) */
@@ -406,7 +505,7 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   io.ll = r->log_likelihood;
   io.status = r->status;
   io.cells = r->cells;
-  return run_planned(ctx, io, st);
+  return run_planned(ctx, ctx->main, io, st);
 }
 
 int abea_align_batch(abea_ctx *ctx, const abea_batch_t *b, abea_result_t *r) {
@@ -414,23 +513,24 @@ int abea_align_batch(abea_ctx *ctx, const abea_batch_t *b, abea_result_t *r) {
   if (rc) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const int n = b->n_reads;
-  if ((rc = plan_batch(ctx, n, b->event_offset, b->kmer_offset, r->pair_capacity))) return rc;
+  if ((rc = plan_batch(ctx, ctx->main, n, b->event_offset, b->kmer_offset, r->pair_capacity))) return rc;
   if (n == 0) {
     r->pair_offset[0] = 0;
     return ABEA_OK;
   }
-  if (ctx->plan.pairs_needed > 0 && !r->pairs) return fail(ctx, ABEA_E_INVAL, "null pairs");
-  const Plan &P = ctx->plan;
+  const Plan &P = ctx->main.plan;
+  if (P.pairs_needed > 0 && !r->pairs) return fail(ctx, ABEA_E_INVAL, "null pairs");
   hipStream_t st = ctx->own_stream;
-  if ((rc = ensure(ctx, ctx->events, sizeof(abea_event_t) * (size_t)P.n_events))) return rc;
-  if ((rc = ensure(ctx, ctx->ranks, sizeof(uint32_t) * (size_t)P.n_kmers))) return rc;
-  if ((rc = ensure(ctx, ctx->scale, sizeof(float) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, ctx->shift, sizeof(float) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, ctx->pairs, sizeof(abea_pair_t) * (size_t)P.pairs_needed))) return rc;
-  if ((rc = ensure(ctx, ctx->pair_offset, sizeof(uint64_t) * (size_t)(n + 1)))) return rc;
-  if ((rc = ensure(ctx, ctx->ll, sizeof(float) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, ctx->status, sizeof(int32_t) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, ctx->cells, sizeof(uint64_t) * (size_t)n))) return rc;
+  Work *w = &ctx->main;
+  if ((rc = ensure(ctx, w, ctx->events, sizeof(abea_event_t) * (size_t)P.n_events))) return rc;
+  if ((rc = ensure(ctx, w, ctx->ranks, sizeof(uint32_t) * (size_t)P.n_kmers))) return rc;
+  if ((rc = ensure(ctx, w, ctx->scale, sizeof(float) * (size_t)n))) return rc;
+  if ((rc = ensure(ctx, w, ctx->shift, sizeof(float) * (size_t)n))) return rc;
+  if ((rc = ensure(ctx, w, ctx->pairs, sizeof(abea_pair_t) * (size_t)P.pairs_needed))) return rc;
+  if ((rc = ensure(ctx, w, ctx->pair_offset, sizeof(uint64_t) * (size_t)(n + 1)))) return rc;
+  if ((rc = ensure(ctx, w, ctx->ll, sizeof(float) * (size_t)n))) return rc;
+  if ((rc = ensure(ctx, w, ctx->status, sizeof(int32_t) * (size_t)n))) return rc;
+  if ((rc = ensure(ctx, w, ctx->cells, sizeof(uint64_t) * (size_t)n))) return rc;
   if (P.n_events)
     HIP_TRY(ctx, hipMemcpyAsync(ctx->events.p, b->events, sizeof(abea_event_t) * P.n_events,
                                 hipMemcpyHostToDevice, st));
@@ -449,7 +549,7 @@ int abea_align_batch(abea_ctx *ctx, const abea_batch_t *b, abea_result_t *r) {
   io.ll = (float *)ctx->ll.p;
   io.status = (int32_t *)ctx->status.p;
   io.cells = (uint64_t *)ctx->cells.p;
-  if ((rc = run_planned(ctx, io, st))) return rc;
+  if ((rc = run_planned(ctx, ctx->main, io, st))) return rc;
   HIP_TRY(ctx, hipMemcpyAsync(r->pair_offset, io.pair_offset, sizeof(uint64_t) * (n + 1),
                               hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipMemcpyAsync(r->log_likelihood, io.ll, sizeof(float) * n, hipMemcpyDeviceToHost, st));
@@ -467,14 +567,106 @@ int abea_align_batch(abea_ctx *ctx, const abea_batch_t *b, abea_result_t *r) {
 
 int abea_get_timings(abea_ctx *ctx, float *out, int n) {
   if (!ctx || !out || n < 0) return ABEA_E_INVAL;
-  if (!ctx->timed) return fail(ctx, ABEA_E_UNSUPPORTED, "context not created with ABEA_F_TIMING");
-  HIP_TRY(ctx, hipEventSynchronize(ctx->tev[4]));
+  Work &w = ctx->main;
+  if (!w.timed) return fail(ctx, ABEA_E_UNSUPPORTED, "context not created with ABEA_F_TIMING");
+  HIP_TRY(ctx, hipEventSynchronize(w.tev[4]));
   for (int q = 0; q < n && q < 4; ++q) {
     float ms = 0.f;
-    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->tev[q], ctx->tev[q + 1]));
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, w.tev[q], w.tev[q + 1]));
     out[q] = ms;
   }
   return ABEA_OK;
+}
+
+/* ---- captured graphs --------------------------------------------------- */
+
+int abea_graph_create(abea_ctx *ctx, const abea_batch_t *b, const abea_result_t *r, abea_graph **out) {
+  if (!out) return fail(ctx, ABEA_E_INVAL, "null graph out");
+  *out = nullptr;
+  int rc = check_batch(ctx, b, r);
+  if (rc) return rc;
+  if (b->n_reads > 0 && (!r->pairs && r->pair_capacity > 0)) return fail(ctx, ABEA_E_INVAL, "null pairs");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  abea_graph *g = new (std::nothrow) abea_graph();
+  if (!g) return ABEA_E_NOMEM;
+  g->ctx = ctx;
+  Work &w = g->work;
+  const int n = b->n_reads;
+  hipError_t e;
+  do {
+    if ((rc = work_init(ctx, w))) break;
+    if ((rc = plan_batch(ctx, w, n, b->event_offset, b->kmer_offset, r->pair_capacity))) break;
+    if ((rc = ensure_work(ctx, w))) break;
+    /* the plan goes to the device once; replays do not copy */
+    if (n > 0) {
+      e = hipMemcpy(w.reads.p, w.h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice);
+      if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "plan upload: %s", hipGetErrorString(e)); break; }
+    }
+    e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "stream: %s", hipGetErrorString(e)); break; }
+    e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "begin capture: %s", hipGetErrorString(e)); break; }
+    int erc = ABEA_OK;
+    if (n == 0) {
+      hipError_t le = launch_scan(nullptr, 0, r->pair_offset, g->cap_stream);
+      if (le != hipSuccess) erc = fail(ctx, ABEA_E_HIP, "capture: %s", hipGetErrorString(le));
+    } else {
+      DevIO io;
+      io.events = (const float *)b->events;
+      io.ranks = b->kmer_rank;
+      io.scale = b->scale;
+      io.shift = b->shift;
+      io.pairs = (int2 *)r->pairs;
+      io.pair_offset = r->pair_offset;
+      io.ll = r->log_likelihood;
+      io.status = r->status;
+      io.cells = r->cells;
+      erc = enqueue_kernels(ctx, w, io, g->cap_stream, false);
+    }
+    e = hipStreamEndCapture(g->cap_stream, &g->graph);
+    if (erc != ABEA_OK) { rc = erc; break; }
+    if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "end capture: %s", hipGetErrorString(e)); break; }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "instantiate: %s", hipGetErrorString(e)); break; }
+  } while (0);
+  if (rc != ABEA_OK) {
+    abea_graph_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return ABEA_OK;
+}
+
+int abea_graph_launch(abea_graph *g, void *stream) {
+  if (!g || !g->exec) return ABEA_E_INVAL;
+  abea_ctx *ctx = g->ctx;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  g->work.last_stream = (hipStream_t)stream;
+  HIP_TRY(ctx, hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return ABEA_OK;
+}
+
+int abea_graph_info(const abea_graph *g, abea_plan_info_t *info) {
+  if (!g || !info) return ABEA_E_INVAL;
+  const Plan &P = g->work.plan;
+  info->n_reads = P.n;
+  info->workers = P.workers;
+  info->cells_per_lane = P.cpl;
+  info->waves_per_group = P.wpg;
+  info->trace_bytes = P.n_trace * sizeof(uint2);
+  info->scratch_bytes = P.n_scratch * sizeof(int2);
+  return ABEA_OK;
+}
+
+void abea_graph_destroy(abea_graph *g) {
+  if (!g) return;
+  (void)hipSetDevice(g->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  work_free(g->work);
+  delete g;
 }
 
 }  // extern "C"

@@ -59,35 +59,39 @@ inline int cells_per_lane(int W) {
  * a 32-bit word per bit plane. */
 inline int bands_per_group(int cpl) { return 32 / cpl; }
 
-struct BandArgs {
-  const ReadDesc *reads;
-  const float *xmean;  /* event means, compacted by k_prep (batch event order) */
-  const KParam *kparam;
-  int32_t *rstat;      /* [n_planned] status; in: OK/EMPTY/BAD_RANK, out: final */
-  uint2 *trace;        /* bit-plane trace tiles: 64 lanes x uint2 per group of bands */
-  float *out_ll;       /* [n_reads] by original index */
-  uint64_t *out_cells; /* [n_reads] by original index, or null */
-  int32_t W;
-};
+/* Trace-tile groups held in a wavefront's LDS ring during the backtrack. */
+constexpr int BT_RING_GROUPS = 16;
 
-struct BacktrackArgs {
-  const ReadDesc *reads;
-  const int32_t *rstat;
-  const uint2 *trace;
+/* Arguments of the band, backtrack and fused alignment kernels. */
+struct AlignArgs {
+  const ReadDesc *reads; /* [n_reads] planned reads, longest first */
+  const float *xmean;    /* event means, compacted by k_prep (batch event order) */
+  const KParam *kparam;
+  int32_t *rstat;        /* [n_reads] status from k_prep; k_band writes the band outcome */
+  uint2 *trace;          /* bit-plane trace tiles: 64 lanes x uint2 per group of bands */
   int2 *scratch;         /* reversed-path pair scratch */
-  uint64_t *path_len;    /* [n_reads] by original index */
-  uint64_t *path_src;    /* [n_reads] by original index: first scratch slot of the path */
-  int32_t *out_status;   /* [n_reads] by original index */
-  float *out_ll;         /* [n_reads] by original index (set to -inf if the walk fails) */
+  uint64_t *path_len;    /* [caller reads] by original index */
+  uint64_t *path_src;    /* [caller reads] by original index: first scratch slot of the path */
+  float *out_ll;         /* [caller reads] by original index */
+  uint64_t *out_cells;   /* [caller reads] by original index, or null */
+  int32_t *out_status;   /* [caller reads] by original index */
+  uint32_t *queue;       /* fused kernel: work-queue counter, zeroed by k_prep */
+  int32_t n_reads;       /* planned reads */
+  int32_t n_workers;     /* fused kernel: wavefronts; worker w starts with read w */
+  int32_t W;
 };
 
 /* Kernel launchers (abea_kernels.hip). */
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
                        const uint32_t *ranks, const float *scale, const float *shift,
                        const ModelEntry *model, uint32_t n_model, float *xmean, KParam *kparam,
-                       int32_t *rstat, hipStream_t st);
-hipError_t launch_band(const BandArgs &a, int n_planned, int cpl, hipStream_t st);
-hipError_t launch_backtrack(const BacktrackArgs &a, int n_planned, int cpl, hipStream_t st);
+                       int32_t *rstat, uint32_t *queue, hipStream_t st);
+hipError_t launch_band(const AlignArgs &a, int cpl, hipStream_t st);
+hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st);
+/* fused band + backtrack with a.n_workers wavefronts, wpg per workgroup */
+hipError_t launch_align(const AlignArgs &a, int cpl, int wpg, hipStream_t st);
+/* resident workgroups of the fused kernel per CU (occupancy) */
+int align_groups_per_cu(int cpl, int wpg);
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st);
 hipError_t launch_compact(const int2 *scratch, const uint64_t *path_src, const uint64_t *offset,
                           int n, int2 *pairs, hipStream_t st);

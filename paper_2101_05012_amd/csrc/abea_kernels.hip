@@ -86,6 +86,9 @@ __device__ __forceinline__ uint32_t shift_in(uint32_t acc, uint64_t mask) {
   return r;
 }
 __device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+/* lane `lane` of the result is `val` (uniform), the others keep `old`
+ * (v_writelane; the compiler places the lane index in M0) */
+__device__ int writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
 #define ABEA_NINF_BITS ((int)0xff800000)
 
@@ -135,9 +138,15 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
                                               const ModelEntry *__restrict__ model, uint32_t n_model,
                                               float *__restrict__ xmean,
                                               KParam *__restrict__ kparam,
-                                              int32_t *__restrict__ rstat) {
+                                              int32_t *__restrict__ rstat,
+                                              uint32_t *__restrict__ queue) {
+  /* the work-queue counter of the alignment kernel that follows */
+  if (blockIdx.x == 0 && threadIdx.x == 0 && queue) *queue = 0u;
   const ReadDesc rd = reads[blockIdx.x];
-  if (rd.n_e <= 0 || rd.n_k <= 0) return;
+  if (rd.n_e <= 0 || rd.n_k <= 0) {
+    if (threadIdx.x == 0) rstat[blockIdx.x] = READ_EMPTY;
+    return;
+  }
   const float sc = scale[rd.orig];
   const float sh = shift[rd.orig];
   int bad = 0;
@@ -157,7 +166,8 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
   }
   for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x)
     xmean[rd.ev_off + e] = events[3 * (rd.ev_off + e)];
-  if (__syncthreads_or(bad) && threadIdx.x == 0) rstat[blockIdx.x] = READ_BAD_RANK;
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) rstat[blockIdx.x] = bad ? READ_BAD_RANK : READ_OK;
 }
 
 /* ------------------------------------------------------------------ band */
@@ -194,29 +204,36 @@ __device__ __forceinline__ float pick(const float (&v)[CPL], int r) {
   return t;
 }
 
+constexpr int BAND_RING = 256; /* entries per LDS stream ring of the band fill */
+
+/* LDS of one wavefront: the band fill's event and k-mer rings, or the
+ * backtrack's trace-tile ring (the two phases of a read never overlap). */
+struct WaveLds {
+  union {
+    struct {
+      float lx[BAND_RING];
+      float4 lk[BAND_RING];
+    } band;
+    uint2 ring[BT_RING_GROUPS * 64];
+  };
+};
+
+/* Band fill of one read whose status is READ_OK (Alg. 5.1 loop, Alg. 5.2,
+ * 5.3), by the calling wavefront: writes the read's trace tiles, its
+ * log-likelihood and cell count, and returns READ_OK or READ_BAND_LOST. */
 template <int CPL>
-__global__ __launch_bounds__(64) void k_band(const BandArgs a) {
+__device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd, uint2 *trace,
+                                         float *__restrict__ lx, float4 *__restrict__ lk) {
   constexpr int N = 64 * CPL;       /* slots held by the wave */
   constexpr int LC = Log2<CPL>::v;
   constexpr int G = 32 / CPL;       /* bands per trace word (even) */
-  constexpr int RING = 256;         /* entries per LDS stream ring */
+  constexpr int RING = BAND_RING;
   constexpr int Q = 64;             /* ring refill quarter */
-  __shared__ float lx[RING];
-  __shared__ float4 lk[RING];
 
-  const int lane = threadIdx.x;
-  const int s = blockIdx.x;
-  const ReadDesc rd = a.reads[s];
+  const int lane = threadIdx.x & 63;
   const int n_e = rd.n_e, n_k = rd.n_k;
   const int W = a.W;
 
-  if (a.rstat[s] != READ_OK) {
-    if (lane == 0) {
-      a.out_ll[rd.orig] = ABEA_NINF;
-      if (a.out_cells) a.out_cells[rd.orig] = 0;
-    }
-    return;
-  }
   const float lp_skip = rd.lp_skip, lp_stay = rd.lp_stay, lp_step = rd.lp_step;
   const float *__restrict__ xm = a.xmean + rd.ev_off;
   const float4 *__restrict__ kp = reinterpret_cast<const float4 *>(a.kparam + rd.km_off);
@@ -296,7 +313,6 @@ __global__ __launch_bounds__(64) void k_band(const BandArgs a) {
   const int last = n_e + n_k;
   uint32_t TU = 0, TL = 0;
   uint64_t cells = 0;
-  uint2 *__restrict__ trace = a.trace + rd.tr_off;
 
   /* One band i: Spp = band i-2 (overwritten by band i), Sp = band i-1.
    * INTERIOR: all W cells of band i are inside the DP table. */
@@ -440,29 +456,53 @@ __global__ __launch_bounds__(64) void k_band(const BandArgs a) {
   float sc = ABEA_NINF;
   if (n_k - 1 >= K && n_k - 1 <= K + W - 1) sc = read_slot<CPL>(F, (n_k - 1) & (N - 1));
   if (lane == 0) {
-    a.rstat[s] = (__float_as_int(sc) == ABEA_NINF_BITS) ? READ_BAND_LOST : READ_OK;
     a.out_ll[rd.orig] = sc;
     if (a.out_cells) a.out_cells[rd.orig] = cells;
   }
+  return (__float_as_int(sc) == ABEA_NINF_BITS) ? READ_BAND_LOST : READ_OK;
+}
+
+/* Outputs of a read whose band fill did not run (empty read, bad rank). */
+__device__ __forceinline__ void band_skipped(const AlignArgs &a, const ReadDesc &rd) {
+  if ((threadIdx.x & 63) == 0) {
+    a.out_ll[rd.orig] = ABEA_NINF;
+    if (a.out_cells) a.out_cells[rd.orig] = 0;
+  }
+}
+
+/* Band fill alone, one wavefront per planned read. */
+template <int CPL>
+__global__ __launch_bounds__(64) void k_band(const AlignArgs a) {
+  __shared__ WaveLds lds;
+  const int s = blockIdx.x;
+  const ReadDesc rd = a.reads[s];
+  if (a.rstat[s] != READ_OK) {
+    band_skipped(a, rd);
+    return;
+  }
+  const int st = band_read<CPL>(a, rd, a.trace + rd.tr_off, lds.band.lx, lds.band.lk);
+  if (threadIdx.x == 0) a.rstat[s] = st;
 }
 
 /* ------------------------------------------------------------- backtrack */
 
+/* Backtrack of one read (Alg. 5.1, after the band loop) by the calling
+ * wavefront, from its trace tiles: writes the path's pairs backwards into
+ * the read's scratch slots, its length and first slot, and its final status
+ * (and -inf as log-likelihood if the walk fails). */
 template <int CPL>
-__global__ __launch_bounds__(64) void k_backtrack(const BacktrackArgs a) {
+__device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDesc &rd, int status,
+                                               const uint2 *__restrict__ tr,
+                                               uint2 *__restrict__ ring) {
   constexpr int N = 64 * CPL;
   constexpr int LC = Log2<CPL>::v;
   constexpr int G = 32 / CPL;
-  constexpr int LG = 5 - LC; /* log2(G) */
-  constexpr int RG = 64;     /* tile groups in the LDS ring */
-  constexpr int QG = 16;     /* groups per refill quarter */
-  __shared__ uint2 ring[RG * 64];
+  constexpr int LG = 5 - LC;           /* log2(G) */
+  constexpr int RG = BT_RING_GROUPS;   /* tile groups in the LDS ring */
+  constexpr int QG = RG / 4;           /* groups per refill quarter */
 
-  const int lane = threadIdx.x;
-  const int s = blockIdx.x;
-  const ReadDesc rd = a.reads[s];
+  const int lane = threadIdx.x & 63;
   const int orig = rd.orig;
-  const int status = a.rstat[s];
   if (status != READ_OK) {
     if (lane == 0) {
       a.path_len[orig] = 0;
@@ -472,7 +512,6 @@ __global__ __launch_bounds__(64) void k_backtrack(const BacktrackArgs a) {
     return;
   }
   const int n_e = rd.n_e, n_k = rd.n_k;
-  const uint2 *__restrict__ tr = a.trace + rd.tr_off;
   const int gmax = (n_e + n_k - 2) >> LG; /* last trace group of the read */
   auto ldt = [&](int grp) -> uint2 {
     uint2 v = make_uint2(0u, 0u);
@@ -512,10 +551,8 @@ __global__ __launch_bounds__(64) void k_backtrack(const BacktrackArgs a) {
       e = __builtin_amdgcn_readfirstlane(e);
       k = __builtin_amdgcn_readfirstlane(k);
       /* emit the cell; every 64 cells go out in one coalesced store */
-      asm volatile("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %3, m0\n\tv_writelane_b32 %1, %4, m0"
-                   : "+v"(PE), "+v"(PK)
-                   : "s"(qs), "s"(e), "s"(k)
-                   : "m0");
+      PE = writelane(e, qs, PE);
+      PK = writelane(k, qs, PK);
       ++qs;
       const int sl = k & (N - 1);
       const int bit = 31 - (((t & (G - 1)) << LC) + (sl & (CPL - 1)));
@@ -566,6 +603,52 @@ __global__ __launch_bounds__(64) void k_backtrack(const BacktrackArgs a) {
   }
 }
 
+/* Backtrack alone, one wavefront per planned read. */
+template <int CPL>
+__global__ __launch_bounds__(64) void k_backtrack(const AlignArgs a) {
+  __shared__ WaveLds lds;
+  const int s = blockIdx.x;
+  const ReadDesc rd = a.reads[s];
+  backtrack_read<CPL>(a, rd, a.rstat[s], a.trace + rd.tr_off, lds.ring);
+}
+
+/* ----------------------------------------------------------------- fused */
+
+/* Band fill and backtrack of a read by one wavefront, with a device work
+ * queue.  Worker w (wavefront w of the grid, w < n_workers) first aligns
+ * planned read w, then takes reads n_workers + q for q = 0, 1, ... from the
+ * queue counter until they run out.  Reads are planned longest first, so
+ * every later read fits the trace slab of the worker's first read: worker w
+ * keeps read w's trace region for all its reads.  n_workers = n_reads is the
+ * plain one-launch form; fewer workers bound the trace memory (admission by
+ * traceback bytes) and let the longest reads of the batch overlap the rest. */
+template <int CPL, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
+  __shared__ WaveLds lds[WPG];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = blockIdx.x * WPG + wv;
+  if (w >= a.n_workers) return;
+  uint2 *slab = a.trace + a.reads[w].tr_off;
+  int s = w;
+  while (s < a.n_reads) {
+    const ReadDesc rd = a.reads[s];
+    int st = a.rstat[s];
+    if (st == READ_OK)
+      st = band_read<CPL>(a, rd, slab, lds[wv].band.lx, lds[wv].band.lk);
+    else
+      band_skipped(a, rd);
+    /* the walk reads back what this wavefront's lanes just stored (each lane
+     * its own words); keep the compiler from moving loads above the stores */
+    __builtin_amdgcn_s_waitcnt(0);
+    asm volatile("" ::: "memory");
+    backtrack_read<CPL>(a, rd, st, slab, lds[wv].ring);
+    asm volatile("" ::: "memory");
+    uint32_t q = 0;
+    if ((threadIdx.x & 63) == 0) q = atomicAdd(a.queue, 1u);
+    s = a.n_workers + (int)__builtin_amdgcn_readfirstlane(q);
+  }
+}
+
 /* ------------------------------------------------------- scan + compact */
 
 __global__ __launch_bounds__(1024) void k_scan(const uint64_t *__restrict__ len, int n,
@@ -609,37 +692,80 @@ __global__ __launch_bounds__(256) void k_compact(const int2 *__restrict__ scratc
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
                        const uint32_t *ranks, const float *scale, const float *shift,
                        const ModelEntry *model, uint32_t n_model, float *xmean, KParam *kparam,
-                       int32_t *rstat, hipStream_t st) {
+                       int32_t *rstat, uint32_t *queue, hipStream_t st) {
   if (n_planned <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(256), 0, st, reads, events, ranks, scale, shift,
-                     model, n_model, xmean, kparam, rstat);
+                     model, n_model, xmean, kparam, rstat, queue);
   return hipGetLastError();
 }
 
-hipError_t launch_band(const BandArgs &a, int n_planned, int cpl, hipStream_t st) {
-  if (n_planned <= 0) return hipSuccess;
-  switch (cpl) {
-    case 1: hipLaunchKernelGGL(k_band<1>, dim3(n_planned), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_band<2>, dim3(n_planned), dim3(64), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_band<4>, dim3(n_planned), dim3(64), 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_band<8>, dim3(n_planned), dim3(64), 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_band<16>, dim3(n_planned), dim3(64), 0, st, a); break;
+#define ABEA_CPL_SWITCH(cpl, CALL)      \
+  switch (cpl) {                        \
+    case 1: CALL(1); break;             \
+    case 2: CALL(2); break;             \
+    case 4: CALL(4); break;             \
+    case 8: CALL(8); break;             \
+    case 16: CALL(16); break;           \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_band(const AlignArgs &a, int cpl, hipStream_t st) {
+  if (a.n_reads <= 0) return hipSuccess;
+#define ABEA_L(C) hipLaunchKernelGGL(k_band<C>, dim3(a.n_reads), dim3(64), 0, st, a)
+  ABEA_CPL_SWITCH(cpl, ABEA_L)
+#undef ABEA_L
+  return hipGetLastError();
+}
+
+hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st) {
+  if (a.n_reads <= 0) return hipSuccess;
+#define ABEA_L(C) hipLaunchKernelGGL(k_backtrack<C>, dim3(a.n_reads), dim3(64), 0, st, a)
+  ABEA_CPL_SWITCH(cpl, ABEA_L)
+#undef ABEA_L
+  return hipGetLastError();
+}
+
+template <int CPL>
+static hipError_t launch_align_c(const AlignArgs &a, int wpg, hipStream_t st) {
+  const dim3 grid((a.n_workers + wpg - 1) / wpg);
+  switch (wpg) {
+    case 1: hipLaunchKernelGGL((k_align<CPL, 1>), grid, dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_align<CPL, 2>), grid, dim3(128), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_align<CPL, 4>), grid, dim3(256), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_backtrack(const BacktrackArgs &a, int n_planned, int cpl, hipStream_t st) {
-  if (n_planned <= 0) return hipSuccess;
-  switch (cpl) {
-    case 1: hipLaunchKernelGGL(k_backtrack<1>, dim3(n_planned), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_backtrack<2>, dim3(n_planned), dim3(64), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_backtrack<4>, dim3(n_planned), dim3(64), 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_backtrack<8>, dim3(n_planned), dim3(64), 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_backtrack<16>, dim3(n_planned), dim3(64), 0, st, a); break;
-    default: return hipErrorInvalidValue;
+hipError_t launch_align(const AlignArgs &a, int cpl, int wpg, hipStream_t st) {
+  if (a.n_reads <= 0 || a.n_workers <= 0) return hipSuccess;
+  if (a.n_workers > a.n_reads) return hipErrorInvalidValue;
+#define ABEA_L(C) return launch_align_c<C>(a, wpg, st)
+  ABEA_CPL_SWITCH(cpl, ABEA_L)
+#undef ABEA_L
+}
+
+template <int CPL>
+static int groups_per_cu_c(int wpg) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (wpg) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, 1>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, 2>, 128, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, 4>, 256, 0); break;
   }
-  return hipGetLastError();
+  return e == hipSuccess ? n : 0;
+}
+
+int align_groups_per_cu(int cpl, int wpg) {
+  switch (cpl) {
+    case 1: return groups_per_cu_c<1>(wpg);
+    case 2: return groups_per_cu_c<2>(wpg);
+    case 4: return groups_per_cu_c<4>(wpg);
+    case 8: return groups_per_cu_c<8>(wpg);
+    case 16: return groups_per_cu_c<16>(wpg);
+  }
+  return 0;
 }
 
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st) {
