@@ -181,7 +181,7 @@ int abea_get_timings(abea_ctx *ctx, float *out, int n);
  *       `workers` longest reads only.
  * waves_per_group: wavefronts (reads) per workgroup of the fused kernel, 1, 2
  * or 4.  cells_per_lane: band slots per lane, 0 = the smallest power of two
- * with 64*c > W, else a power of two at least that and at most 16.
+ * with 64*c >= W + 2, else a power of two at least that and at most 16.
  * Applies to later calls and graphs; waits for the context's queued work.
  * Errors: ABEA_E_INVAL.
  */

@@ -43,6 +43,7 @@ struct Plan {
   uint64_t n_events = 0;
   uint64_t n_kmers = 0;
   uint64_t pairs_needed = 0;
+  int32_t urgent_len = 0x7fffffff;
 };
 
 /* Device buffers and staging of one planned batch.  The context owns one for
@@ -174,7 +175,7 @@ bool split_kernels(const abea_ctx *ctx) { return ctx->launch.workers == ABEA_WOR
 
 /* Wavefronts of the fused kernel that are resident at once on the device. */
 int resident_workers(abea_ctx *ctx) {
-  const int gpc = align_groups_per_cu(ctx->cpl, ctx->launch.waves_per_group);
+  const int gpc = align_groups_per_cu(ctx->cpl, refills_per_group(ctx->W, ctx->cpl), ctx->launch.waves_per_group);
   return std::max(1, gpc * ctx->num_cus * ctx->launch.waves_per_group);
 }
 
@@ -267,6 +268,11 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
   }
   P.n_trace = tr;
   P.n_scratch = pr;
+  /* the 256 longest reads (about one per CU) issue at raised priority */
+  {
+    const int u = std::min(n, 256) - 1;
+    P.urgent_len = u >= 0 ? (int32_t)std::max<uint64_t>(comp[w.order[u]] + 1, 1) : 0x7fffffff;
+  }
   P.n_events = eo[n];
   P.n_kmers = ko[n];
   return ABEA_OK;
@@ -328,12 +334,13 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   a.n_reads = n;
   a.n_workers = P.workers;
   a.W = ctx->W;
+  a.urgent_len = P.urgent_len;
   if (P.workers == 0) {
-    HIP_TRY(ctx, launch_band(a, P.cpl, st));
+    HIP_TRY(ctx, launch_band(a, P.cpl, refills_per_group(ctx->W, P.cpl), st));
     if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[2], st));
     HIP_TRY(ctx, launch_backtrack(a, P.cpl, st));
   } else {
-    HIP_TRY(ctx, launch_align(a, P.cpl, P.wpg, st));
+    HIP_TRY(ctx, launch_align(a, P.cpl, refills_per_group(ctx->W, P.cpl), P.wpg, st));
     if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[2], st));
   }
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[3], st));
@@ -462,6 +469,7 @@ int abea_set_launch(abea_ctx *ctx, const abea_launch_t *l) {
   int c = l->cells_per_lane == 0 ? minc : l->cells_per_lane;
   if (c < minc || c > 16 || (c & (c - 1)) != 0)
     return fail(ctx, ABEA_E_INVAL, "cells_per_lane %d: need a power of two in [%d, 16]", l->cells_per_lane, minc);
+  if (refills_per_group(ctx->W, c) == 0) return fail(ctx, ABEA_E_INVAL, "cells_per_lane %d too small", c);
   /* buffers of an earlier call may still be in use by queued kernels */
   if (ctx->main.last_stream) HIP_TRY(ctx, hipStreamSynchronize(ctx->main.last_stream));
   ctx->launch = *l;

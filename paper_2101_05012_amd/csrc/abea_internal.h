@@ -47,17 +47,29 @@ struct KParam {
 
 enum : int32_t { READ_OK = 0, READ_EMPTY = 1, READ_BAND_LOST = 2, READ_BAD_RANK = 3 };
 
-/* Slots per lane for a band width: smallest power of two with 64*cpl > W
- * (one slot more than the band, so that k-mer k and k+N never share a slot
- * while either is in a band). */
-inline int cells_per_lane(int W) {
-  int c = 1;
-  while (64 * c <= W) c <<= 1;
-  return c;
-}
 /* Bands per trace tile word: every lane packs cpl slots x 1 bit per band into
  * a 32-bit word per bit plane. */
 inline int bands_per_group(int cpl) { return 32 / cpl; }
+
+/* The band fill relabels its slots rpg times per group of bands, every
+ * 32/cpl/rpg bands; a k-mer that leaves the band keeps its slot until then,
+ * so 64*cpl - W must be at least that interval (see band_read). */
+inline bool band_shape_ok(int W, int cpl, int rpg) {
+  const int rf = bands_per_group(cpl) / rpg;
+  return rf >= 2 && 64 * cpl - W >= rf;
+}
+/* Refills per group for W and cpl: 1 if it fits, else 2, else 0 (no fit). */
+inline int refills_per_group(int W, int cpl) {
+  if (band_shape_ok(W, cpl, 1)) return 1;
+  if (band_shape_ok(W, cpl, 2)) return 2;
+  return 0;
+}
+/* Slots per lane for a band width: the smallest power of two that fits. */
+inline int cells_per_lane(int W) {
+  int c = 1;
+  while (c < 16 && refills_per_group(W, c) == 0) c <<= 1;
+  return c;
+}
 
 /* Trace-tile groups held in a wavefront's LDS ring during the backtrack. */
 constexpr int BT_RING_GROUPS = 16;
@@ -79,6 +91,7 @@ struct AlignArgs {
   int32_t n_reads;       /* planned reads */
   int32_t n_workers;     /* fused kernel: wavefronts; worker w starts with read w */
   int32_t W;
+  int32_t urgent_len;    /* reads with n_e + n_k >= this run at raised wave priority */
 };
 
 /* Kernel launchers (abea_kernels.hip). */
@@ -86,12 +99,12 @@ hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events
                        const uint32_t *ranks, const float *scale, const float *shift,
                        const ModelEntry *model, uint32_t n_model, float *xmean, KParam *kparam,
                        int32_t *rstat, uint32_t *queue, hipStream_t st);
-hipError_t launch_band(const AlignArgs &a, int cpl, hipStream_t st);
+hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st);
 hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st);
 /* fused band + backtrack with a.n_workers wavefronts, wpg per workgroup */
-hipError_t launch_align(const AlignArgs &a, int cpl, int wpg, hipStream_t st);
+hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, hipStream_t st);
 /* resident workgroups of the fused kernel per CU (occupancy) */
-int align_groups_per_cu(int cpl, int wpg);
+int align_groups_per_cu(int cpl, int rpg, int wpg);
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st);
 hipError_t launch_compact(const int2 *scratch, const uint64_t *path_src, const uint64_t *offset,
                           int n, int2 *pairs, hipStream_t st);

@@ -204,15 +204,31 @@ __device__ __forceinline__ float pick(const float (&v)[CPL], int r) {
   return t;
 }
 
-constexpr int BAND_RING = 256; /* entries per LDS stream ring of the band fill */
+/* Sizes of the band fill for CPL slots per lane.
+ *   N   slots of the wave (64*CPL >= W + 2)
+ *   G   bands per trace word (32/CPL, even)
+ *   RX  entries of the event ring: holds every event of the band window
+ *       plus the next G, in quarters of 64, one quarter spare (W + G <= RX - 128)
+ *   RK  entries of the k-mer ring: holds k-mers K .. K+N+G, same rule */
+template <int CPL>
+struct Geom {
+  static constexpr int N = 64 * CPL;
+  static constexpr int LC = Log2<CPL>::v;
+  static constexpr int G = 32 / CPL;
+  static constexpr int RX = CPL == 1 ? 256 : (128 * CPL > 1024 ? 1024 : 128 * CPL);
+  static constexpr int RK = CPL == 1 ? 256 : 128 * CPL;
+};
 
-/* LDS of one wavefront: the band fill's event and k-mer rings, or the
- * backtrack's trace-tile ring (the two phases of a read never overlap). */
+/* LDS of one wavefront: the band fill's event ring (with a mirror of its
+ * first G entries behind the end, so that a run of G reads never wraps) and
+ * k-mer ring, or the backtrack's trace-tile ring; the two phases of a read
+ * never overlap. */
+template <int CPL>
 struct WaveLds {
   union {
     struct {
-      float lx[BAND_RING];
-      float4 lk[BAND_RING];
+      float lx[Geom<CPL>::RX + Geom<CPL>::G];
+      float4 lk[Geom<CPL>::RK];
     } band;
     uint2 ring[BT_RING_GROUPS * 64];
   };
@@ -220,15 +236,26 @@ struct WaveLds {
 
 /* Band fill of one read whose status is READ_OK (Alg. 5.1 loop, Alg. 5.2,
  * 5.3), by the calling wavefront: writes the read's trace tiles, its
- * log-likelihood and cell count, and returns READ_OK or READ_BAND_LOST. */
-template <int CPL>
+ * log-likelihood and cell count, and returns READ_OK or READ_BAND_LOST.
+ *
+ * Slot s (lane s / CPL, register s % CPL) holds k-mer kv(s) = K_r + ((s -
+ * K_r) mod N), fixed from one refill to the next (every RF bands, RF <= N - W
+ * and RF <= G): a k-mer that leaves the band keeps its slot, masked, until
+ * the next refill relabels the slot as the k-mer N higher, which cannot enter
+ * the band before then.  At a refill the wavefront loads each slot's k-mer
+ * parameters (mu', c, h) from the k-mer ring and the LDS address of its event
+ * at the refill band; band b after it reads the event of the slot from that
+ * address + b (the event of a cell (e, k) in band i is i - 2 - k). */
+template <int CPL, int RPG>
 __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd, uint2 *trace,
                                          float *__restrict__ lx, float4 *__restrict__ lk) {
-  constexpr int N = 64 * CPL;       /* slots held by the wave */
-  constexpr int LC = Log2<CPL>::v;
-  constexpr int G = 32 / CPL;       /* bands per trace word (even) */
-  constexpr int RING = BAND_RING;
-  constexpr int Q = 64;             /* ring refill quarter */
+  constexpr int N = Geom<CPL>::N;
+  constexpr int LC = Geom<CPL>::LC;
+  constexpr int G = Geom<CPL>::G;
+  constexpr int RX = Geom<CPL>::RX;
+  constexpr int RK = Geom<CPL>::RK;
+  constexpr int RF = G / RPG; /* bands between slot refills (RPG refills per group) */
+  static_assert(RF >= 2 && RF % 2 == 0, "refill interval must be an even band count");
 
   const int lane = threadIdx.x & 63;
   const int n_e = rd.n_e, n_k = rd.n_k;
@@ -250,158 +277,137 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     if (k >= 0 && k < n_k) v = kp[k];
     return v;
   };
+  auto put_x = [&](int q, float v) {
+    const int idx = (q * 64 + lane) & (RX - 1);
+    lx[idx] = v;
+    if (idx < G) lx[RX + idx] = v;
+  };
+  auto put_k = [&](int q, float4 v) { lk[(q * 64 + lane) & (RK - 1)] = v; };
 
   /* Band 1 (initialise_first_two_bands): band 0 has lower-left (W/2-1,
    * -1-W/2) and holds only the virtual origin (-1,-1) with score 0; band 1 is
-   * band 0 moved one k-mer and is all -inf.  A band is identified by its
-   * first k-mer K; the slots hold k-mers K .. K+N-1 (the first W are the
-   * band, the rest look ahead and hold -inf). */
-  int K = -H;    /* first k-mer of band 1 */
-  int E = H - 1; /* event of band 1's first cell */
-  float Spp[CPL], Sp[CPL], X[CPL], PM[CPL], PC[CPL], PH[CPL];
-  uint64_t wm[CPL]; /* slots inside the current band's k-mer window */
+   * band 0 moved one k-mer and is all -inf.  K is the first k-mer of the
+   * latest band, E the event of its first cell. */
+  int K = -H;
+  int E = H - 1;
+  float Spp[CPL], Sp[CPL], PM[CPL], PC[CPL], PH[CPL];
+  int dd[CPL]; /* kv(slot) - K_r */
+  int xb[CPL]; /* ring index of the slot's event at band b = 0 of the group */
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
-    const int slot = lane * CPL + c;
-    const int kv = K + ((slot - K) & (N - 1));
-    X[c] = ldx(-1 - kv); /* band 1: cell (e, k) has e + k = -1 */
-    const float4 p = ldk(kv);
-    PM[c] = p.x;
-    PC[c] = p.y;
-    PH[c] = p.z;
+    const int kv = K + ((lane * CPL + c - K) & (N - 1));
     Spp[c] = (kv == -1) ? 0.0f : NI; /* band 0: the origin, k-mer -1 */
     Sp[c] = NI;
-    wm[c] = ballot(kv <= K + W - 1);
+    PM[c] = PC[c] = PH[c] = 0.0f;
+    dd[c] = 0;
+    xb[c] = 0;
   }
+  int Kr = K;
 
-  /* LDS rings.  Events enter at event moves in order E_1+1, E_1+2, ...;
-   * k-mers enter at k-mer moves in order K_1+N, K_1+N+1, ...  Quarter q of a
-   * ring holds indices [64q, 64q+64); quarters xq..xq+2 are written, xq+3
-   * waits in registers. */
-  int xq = (E + 1) >> 6;
-  int kq = (K + N) >> 6;
+  /* Rings: event e at lx[e mod RX], k-mer k at lk[k mod RK], written a
+   * quarter (64 entries) at a time; the quarter after the top one waits in
+   * registers. */
+  int xtop = (E + G) >> 6;
+  int ktop = (K + N + G - 1) >> 6;
+  for (int q = (E - W + 1) >> 6; q <= xtop; ++q) put_x(q, ldx(q * 64 + lane));
+  for (int q = K >> 6; q <= ktop; ++q) put_k(q, ldk(q * 64 + lane));
+  float xpend = ldx((xtop + 1) * 64 + lane);
+  float4 kpend = ldk((ktop + 1) * 64 + lane);
+
+  auto advance_rings = [&]() {
+    if (((E + G) >> 6) > xtop) {
+      ++xtop;
+      put_x(xtop, xpend);
+      xpend = ldx((xtop + 1) * 64 + lane);
+    }
+    if (((K + N + G - 1) >> 6) > ktop) {
+      ++ktop;
+      put_k(ktop, kpend);
+      kpend = ldk((ktop + 1) * 64 + lane);
+    }
+  };
+
+  /* Relabel the slots for the current K (before band i's move) and load
+   * their k-mer parameters and event addresses; b is the band's index in
+   * its group, i = i0 + b. */
+  auto refill = [&](int i, int b) {
+    K = __builtin_amdgcn_readfirstlane(K);
+    Kr = K;
 #pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    lx[((xq + t) * Q + lane) & (RING - 1)] = ldx((xq + t) * Q + lane);
-    lk[((kq + t) * Q + lane) & (RING - 1)] = ldk((kq + t) * Q + lane);
-  }
-  float xpend = ldx((xq + 3) * Q + lane);
-  float4 kpend = ldk((kq + 3) * Q + lane);
-
-  /* per group of bands: lane l of xc / kc holds the (l+1)-th next entering
-   * event / k-mer; ne / nk count the ones used */
-  float xc;
-  float4 kc;
-  int ne = 0, nk = 0;
-  auto load_chunks = [&]() {
-    if (((E + 64) >> 6) > xq + 2) {
-      ++xq;
-      lx[((xq + 2) * Q + lane) & (RING - 1)] = xpend;
-      xpend = ldx((xq + 3) * Q + lane);
+    for (int c = 0; c < CPL; ++c) {
+      const int d = (lane * CPL + c - K) & (N - 1);
+      const int kv = K + d;
+      dd[c] = d;
+      const float4 p = lk[kv & (RK - 1)];
+      PM[c] = p.x;
+      PC[c] = p.y;
+      PH[c] = p.z;
+      xb[c] = ((i - 2 - kv) & (RX - 1)) - b;
     }
-    if (((K + N + 63) >> 6) > kq + 2) {
-      ++kq;
-      lk[((kq + 2) * Q + lane) & (RING - 1)] = kpend;
-      kpend = ldk((kq + 3) * Q + lane);
-    }
-    xc = lx[(E + 1 + lane) & (RING - 1)];
-    kc = lk[(K + N + lane) & (RING - 1)];
-    ne = 0;
-    nk = 0;
   };
 
   const int last = n_e + n_k;
   uint32_t TU = 0, TL = 0;
   uint64_t cells = 0;
 
-  /* One band i: Spp = band i-2 (overwritten by band i), Sp = band i-1.
-   * INTERIOR: all W cells of band i are inside the DP table. */
-  auto band = [&](auto interior_tag, float(&Spp)[CPL], const float(&Sp)[CPL], int i) {
+  /* One band i = i0 + b: Spp = band i-2 (overwritten by band i), Sp = band
+   * i-1.  INTERIOR: all W cells of band i are inside the DP table. */
+  /* the events of the slots for band b (of the current refill interval) */
+  auto load_x = [&](float(&x)[CPL], int b) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) x[c] = lx[xb[c] + b];
+  };
+
+  auto band = [&](auto interior_tag, float(&Spp)[CPL], const float(&Sp)[CPL], int i, int b,
+                  const float(&X)[CPL]) {
     constexpr bool INTERIOR = decltype(interior_tag)::value;
     /* the band position is wave-uniform: keep it in SGPRs */
     K = __builtin_amdgcn_readfirstlane(K);
     E = __builtin_amdgcn_readfirstlane(E);
-    ne = __builtin_amdgcn_readfirstlane(ne);
-    nk = __builtin_amdgcn_readfirstlane(nk);
-    /* Suzuki-Kasahara placement from the two end cells of band i-1 */
-    const int sf = K & (N - 1); /* slot of the first k-mer */
+    /* Suzuki-Kasahara placement from the two end cells of band i-1; i0 is
+     * even, so i is odd when b is */
+    const int sf = K & (N - 1);
     const int sh = (K + W - 1) & (N - 1);
     const int lo = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(Sp, sf & (CPL - 1))), sf >> LC);
     const int hi = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(Sp, sh & (CPL - 1))), sh >> LC);
-    const int m = __builtin_amdgcn_readfirstlane(sk_move(lo, hi, i & 1));
-    const uint64_t bf = 1ull << (sf >> LC);
+    const int m = __builtin_amdgcn_readfirstlane(sk_move(lo, hi, b & 1));
+    K += m;
+    E += 1 - m;
 
-    /* the event of every slot advances by one: slot s takes slot s-1's */
-    {
-      const float t = rot_up(X[CPL - 1]);
-#pragma unroll
-      for (int c = CPL - 1; c >= 1; --c) X[c] = X[c - 1];
-      X[0] = t;
-    }
-    /* k-mer move (m = 1): the slot of k-mer K leaves the band and will hold
-     * k-mer K+N, the slot of k-mer K+W enters the band.  Event move (m = 0):
-     * the first k-mer's cell takes the new event E+1.  Both are applied under
-     * lane masks (no branch). */
-    {
-      const float pm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc.x), nk));
-      const float pc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc.y), nk));
-      const float ph = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kc.z), nk));
-      const float xv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xc), ne));
-      const uint64_t bk = m ? bf : 0ull;
-      const uint64_t be = m ? 0ull : bf;
-      const int sn = (K + W) & (N - 1);
-      const uint64_t bn = m ? (1ull << (sn >> LC)) : 0ull;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const bool here = (sf & (CPL - 1)) == c;
-        const uint64_t mk = here ? bk : 0ull;
-        put(PM[c], pm, mk);
-        put(PC[c], pc, mk);
-        put(PH[c], ph, mk);
-        put(X[c], xv, here ? be : 0ull);
-        wm[c] = (wm[c] & ~mk) | (((sn & (CPL - 1)) == c) ? bn : 0ull);
-      }
-      nk += m;
-      ne += 1 - m;
-      K += m;
-      E += 1 - m;
-    }
-
-    int klo = K, khi = K + W - 1;
+    /* cells of band i inside the band and the table: k-mers kv with
+     * wlo <= kv - K_r < wlo + wlen */
+    int wlo = K - Kr, wlen = W;
     if (!INTERIOR) {
-      klo = max(K, max(0, i - 1 - n_e));
-      khi = min(K + W - 1, min(n_k - 1, i - 2));
-      if (khi >= klo) cells += (uint64_t)(khi - klo + 1);
+      const int klo = max(K, max(0, i - 1 - n_e));
+      const int khi = min(K + W - 1, min(n_k - 1, i - 2));
+      wlen = max(0, khi - klo + 1);
+      wlo = klo - Kr;
+      cells += (uint64_t)wlen;
     }
     const float lf0 = rot_up(Sp[CPL - 1]);  /* left  (e, k-1): band i-1, slot s-1 */
     const float dg0 = rot_up(Spp[CPL - 1]); /* diag (e-1, k-1): band i-2, slot s-1 */
     float nv[CPL]; /* band i; band i-2 is still read below */
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
+      const float x = X[c];
       const float up = Sp[c]; /* up (e-1, k): band i-1, slot s */
       const float left = (c == 0) ? lf0 : Sp[c - 1];
       const float diag = (c == 0) ? dg0 : Spp[c - 1];
       /* Alg. 5.3 log-emission and Alg. 5.2 cell score */
-      const float d = X[c] - PM[c];
+      const float d = x - PM[c];
       const float t = d * d;
       const float u = t * PH[c];
       const float em = PC[c] - u;
       const float sd = (diag + lp_step) + em;
       const float su = (up + lp_stay) + em;
       const float sl = left + lp_skip;
-      uint64_t mu = ballot(su > sd);
+      const uint64_t mu = ballot(su > sd);
       const float s1 = sel(sd, su, mu);
-      uint64_t ml = ballot(sl > s1);
+      const uint64_t ml = ballot(sl > s1);
       const float sv = sel(s1, sl, ml);
-      /* trace planes: (0,0) diagonal, (1,0) up, (0,1) left, (1,1) outside */
-      mu &= ~ml;
-      uint64_t valid = wm[c];
-      if (!INTERIOR) {
-        const int kv = K + ((lane * CPL + c - K) & (N - 1));
-        valid = ballot(kv >= klo) & ballot(kv <= khi);
-        mu |= ~valid;
-        ml |= ~valid;
-      }
+      /* trace planes: up bit (U beats D), left bit (L beats both); a set
+       * left bit means L whatever the up bit */
+      const uint64_t valid = ballot((uint32_t)(dd[c] - wlo) < (uint32_t)wlen);
       nv[c] = sel(NI, sv, valid);
       TU = shift_in(TU, mu);
       TL = shift_in(TL, ml);
@@ -410,26 +416,52 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     for (int c = 0; c < CPL; ++c) Spp[c] = nv[c];
   };
 
-  /* Full groups of G bands (band i = 2 + t, group t / G): refill and
+  /* A full group of G bands from band i: slot refill every RF bands; the
+   * events of the next band pair are read from LDS while the current pair
+   * computes (the scheduling barrier keeps the reads ahead). */
+  auto group = [&](auto interior_tag, int i) {
+    float xa[2][CPL], xn[2][CPL];
+    refill(i, 0);
+    load_x(xa[0], 0);
+    load_x(xa[1], 1);
+#pragma unroll
+    for (int b = 0; b < G; b += 2) {
+      const bool ahead = (b + 2 < G) && ((b + 2) % RF != 0);
+      if (ahead) {
+        load_x(xn[0], b + 2);
+        load_x(xn[1], b + 3);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      band(interior_tag, Spp, Sp, i + b, b, xa[0]);
+      band(interior_tag, Sp, Spp, i + b + 1, b + 1, xa[1]);
+      if (b + 2 < G) {
+        if ((b + 2) % RF == 0) {
+          refill(i + b + 2, b + 2);
+          load_x(xa[0], b + 2);
+          load_x(xa[1], b + 3);
+        } else {
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) {
+            xa[0][c] = xn[0][c];
+            xa[1][c] = xn[1][c];
+          }
+        }
+      }
+    }
+  };
+
+  /* Full groups of G bands (band i = 2 + t, group t / G): ring refill and
    * interior test once per group, one trace word per lane per group. */
   int i = 2;
   uint64_t g = 0;
   while (i + G - 1 <= last) {
-    load_chunks();
+    advance_rings();
     const bool interior = (K >= 0) & (E >= W - 1) & (E + G <= n_e - 1) & (K + G + W - 1 <= n_k - 1);
     if (interior) {
-#pragma unroll
-      for (int b = 0; b < G; b += 2) {
-        band(std::true_type(), Spp, Sp, i + b);
-        band(std::true_type(), Sp, Spp, i + b + 1);
-      }
+      group(std::true_type(), i);
       cells += (uint64_t)W * G;
     } else {
-#pragma unroll
-      for (int b = 0; b < G; b += 2) {
-        band(std::false_type(), Spp, Sp, i + b);
-        band(std::false_type(), Sp, Spp, i + b + 1);
-      }
+      group(std::false_type(), i);
     }
     trace[g * 64 + lane] = make_uint2(TU, TL);
     ++g;
@@ -437,14 +469,19 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   }
   /* the last, partial group */
   if (i <= last) {
-    load_chunks();
+    advance_rings();
     const int gb = last - i + 1;
-    for (;;) {
-      band(std::false_type(), Spp, Sp, i);
-      if (++i > last) break;
-      band(std::false_type(), Sp, Spp, i);
-      if (++i > last) break;
+    for (int b = 0;; b += 2) {
+      if (b % RF == 0) refill(i + b, b);
+      float x0[CPL], x1[CPL];
+      load_x(x0, b);
+      load_x(x1, b + 1);
+      band(std::false_type(), Spp, Sp, i + b, b, x0);
+      if (i + b + 1 > last) break;
+      band(std::false_type(), Sp, Spp, i + b + 1, b + 1, x1);
+      if (i + b + 2 > last) break;
     }
+    i = last + 1;
     const int sh = (G - gb) * CPL;
     trace[g * 64 + lane] = make_uint2(TU << sh, TL << sh);
   }
@@ -471,16 +508,20 @@ __device__ __forceinline__ void band_skipped(const AlignArgs &a, const ReadDesc 
 }
 
 /* Band fill alone, one wavefront per planned read. */
-template <int CPL>
+template <int CPL, int RPG>
 __global__ __launch_bounds__(64) void k_band(const AlignArgs a) {
-  __shared__ WaveLds lds;
+  __shared__ WaveLds<CPL> lds;
   const int s = blockIdx.x;
   const ReadDesc rd = a.reads[s];
   if (a.rstat[s] != READ_OK) {
     band_skipped(a, rd);
     return;
   }
-  const int st = band_read<CPL>(a, rd, a.trace + rd.tr_off, lds.band.lx, lds.band.lk);
+  /* the longest reads set the kernel's duration: let them issue first */
+  const bool urgent = rd.n_e + rd.n_k >= a.urgent_len;
+  if (urgent) __builtin_amdgcn_s_setprio(2);
+  const int st = band_read<CPL, RPG>(a, rd, a.trace + rd.tr_off, lds.band.lx, lds.band.lk);
+  if (urgent) __builtin_amdgcn_s_setprio(0);
   if (threadIdx.x == 0) a.rstat[s] = st;
 }
 
@@ -546,7 +587,6 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
     /* the cells of the current group: one dependent step per cell */
     const int lower = gcur << LG;
     int t = e + k;
-    int bad = 0;
     for (;;) {
       e = __builtin_amdgcn_readfirstlane(e);
       k = __builtin_amdgcn_readfirstlane(k);
@@ -558,23 +598,18 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
       const int bit = 31 - (((t & (G - 1)) << LC) + (sl & (CPL - 1)));
       const int ub = (int)((rlane_u(T.x, sl >> LC) >> bit) & 1u);
       const int lb = (int)((rlane_u(T.y, sl >> LC) >> bit) & 1u);
-      bad = ub & lb;
-      /* diagonal (0,0): e-1, k-1; up (1,0): e-1; left (0,1): k-1 */
+      /* diagonal (0,0): e-1, k-1; up (1,0): e-1; left (x,1): k-1 */
       e -= 1 - lb;
-      k -= 1 - ub;
+      k -= 1 - (ub & (lb ^ 1));
       t = e + k;
-      /* stop when 64 cells are gathered, the walk left the table or the
-       * group, or the trace is inconsistent (each term < 0 means stop) */
-      if ((((63 - qs) | e | k | (t - lower)) < 0) | bad) break;
+      /* stop when 64 cells are gathered, or the walk left the table or the
+       * group (each term < 0 means stop) */
+      if (((63 - qs) | e | k | (t - lower)) < 0) break;
     }
     if (qs == 64) {
       q += 64;
       out[res_end - q + (63 - lane)] = make_int2(PE, PK);
       qs = 0;
-    }
-    if (bad) {
-      ok = false;
-      break;
     }
     if ((e | k) < 0) break;
     const int gi = t >> LG;
@@ -606,7 +641,7 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
 /* Backtrack alone, one wavefront per planned read. */
 template <int CPL>
 __global__ __launch_bounds__(64) void k_backtrack(const AlignArgs a) {
-  __shared__ WaveLds lds;
+  __shared__ WaveLds<CPL> lds;
   const int s = blockIdx.x;
   const ReadDesc rd = a.reads[s];
   backtrack_read<CPL>(a, rd, a.rstat[s], a.trace + rd.tr_off, lds.ring);
@@ -622,9 +657,9 @@ __global__ __launch_bounds__(64) void k_backtrack(const AlignArgs a) {
  * keeps read w's trace region for all its reads.  n_workers = n_reads is the
  * plain one-launch form; fewer workers bound the trace memory (admission by
  * traceback bytes) and let the longest reads of the batch overlap the rest. */
-template <int CPL, int WPG>
+template <int CPL, int RPG, int WPG>
 __global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
-  __shared__ WaveLds lds[WPG];
+  __shared__ WaveLds<CPL> lds[WPG];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int w = blockIdx.x * WPG + wv;
   if (w >= a.n_workers) return;
@@ -633,8 +668,11 @@ __global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
   while (s < a.n_reads) {
     const ReadDesc rd = a.reads[s];
     int st = a.rstat[s];
+    /* the longest reads set the kernel's duration: let them issue first */
+    const bool urgent = rd.n_e + rd.n_k >= a.urgent_len;
+    if (urgent) __builtin_amdgcn_s_setprio(2);
     if (st == READ_OK)
-      st = band_read<CPL>(a, rd, slab, lds[wv].band.lx, lds[wv].band.lk);
+      st = band_read<CPL, RPG>(a, rd, slab, lds[wv].band.lx, lds[wv].band.lk);
     else
       band_skipped(a, rd);
     /* the walk reads back what this wavefront's lanes just stored (each lane
@@ -642,6 +680,7 @@ __global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
     __builtin_amdgcn_s_waitcnt(0);
     asm volatile("" ::: "memory");
     backtrack_read<CPL>(a, rd, st, slab, lds[wv].ring);
+    if (urgent) __builtin_amdgcn_s_setprio(0);
     asm volatile("" ::: "memory");
     uint32_t q = 0;
     if ((threadIdx.x & 63) == 0) q = atomicAdd(a.queue, 1u);
@@ -699,72 +738,80 @@ hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events
   return hipGetLastError();
 }
 
-#define ABEA_CPL_SWITCH(cpl, CALL)      \
-  switch (cpl) {                        \
-    case 1: CALL(1); break;             \
-    case 2: CALL(2); break;             \
-    case 4: CALL(4); break;             \
-    case 8: CALL(8); break;             \
-    case 16: CALL(16); break;           \
-    default: return hipErrorInvalidValue; \
-  }
+/* Kernel variant for (cells per lane, refills per group). */
+#define ABEA_VARIANTS(CALL)              \
+  if (cpl == 1 && rpg == 1) CALL(1, 1);  \
+  if (cpl == 1 && rpg == 2) CALL(1, 2);  \
+  if (cpl == 2 && rpg == 1) CALL(2, 1);  \
+  if (cpl == 2 && rpg == 2) CALL(2, 2);  \
+  if (cpl == 4 && rpg == 1) CALL(4, 1);  \
+  if (cpl == 4 && rpg == 2) CALL(4, 2);  \
+  if (cpl == 8 && rpg == 1) CALL(8, 1);  \
+  if (cpl == 8 && rpg == 2) CALL(8, 2);  \
+  if (cpl == 16 && rpg == 1) CALL(16, 1);
 
-hipError_t launch_band(const AlignArgs &a, int cpl, hipStream_t st) {
+hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st) {
   if (a.n_reads <= 0) return hipSuccess;
-#define ABEA_L(C) hipLaunchKernelGGL(k_band<C>, dim3(a.n_reads), dim3(64), 0, st, a)
-  ABEA_CPL_SWITCH(cpl, ABEA_L)
+#define ABEA_L(C, R)                                                                    \
+  {                                                                                     \
+    hipLaunchKernelGGL((k_band<C, R>), dim3(a.n_reads), dim3(64), 0, st, a);            \
+    return hipGetLastError();                                                           \
+  }
+  ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st) {
   if (a.n_reads <= 0) return hipSuccess;
-#define ABEA_L(C) hipLaunchKernelGGL(k_backtrack<C>, dim3(a.n_reads), dim3(64), 0, st, a)
-  ABEA_CPL_SWITCH(cpl, ABEA_L)
-#undef ABEA_L
-  return hipGetLastError();
-}
-
-template <int CPL>
-static hipError_t launch_align_c(const AlignArgs &a, int wpg, hipStream_t st) {
-  const dim3 grid((a.n_workers + wpg - 1) / wpg);
-  switch (wpg) {
-    case 1: hipLaunchKernelGGL((k_align<CPL, 1>), grid, dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_align<CPL, 2>), grid, dim3(128), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_align<CPL, 4>), grid, dim3(256), 0, st, a); break;
+  switch (cpl) {
+    case 1: hipLaunchKernelGGL(k_backtrack<1>, dim3(a.n_reads), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_backtrack<2>, dim3(a.n_reads), dim3(64), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_backtrack<4>, dim3(a.n_reads), dim3(64), 0, st, a); break;
+    case 8: hipLaunchKernelGGL(k_backtrack<8>, dim3(a.n_reads), dim3(64), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_backtrack<16>, dim3(a.n_reads), dim3(64), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_align(const AlignArgs &a, int cpl, int wpg, hipStream_t st) {
-  if (a.n_reads <= 0 || a.n_workers <= 0) return hipSuccess;
-  if (a.n_workers > a.n_reads) return hipErrorInvalidValue;
-#define ABEA_L(C) return launch_align_c<C>(a, wpg, st)
-  ABEA_CPL_SWITCH(cpl, ABEA_L)
-#undef ABEA_L
+template <int CPL, int RPG>
+static hipError_t launch_align_c(const AlignArgs &a, int wpg, hipStream_t st) {
+  const dim3 grid((a.n_workers + wpg - 1) / wpg);
+  switch (wpg) {
+    case 1: hipLaunchKernelGGL((k_align<CPL, RPG, 1>), grid, dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_align<CPL, RPG, 2>), grid, dim3(128), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_align<CPL, RPG, 4>), grid, dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
-template <int CPL>
+hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, hipStream_t st) {
+  if (a.n_reads <= 0 || a.n_workers <= 0) return hipSuccess;
+  if (a.n_workers > a.n_reads) return hipErrorInvalidValue;
+#define ABEA_L(C, R) return launch_align_c<C, R>(a, wpg, st)
+  ABEA_VARIANTS(ABEA_L)
+#undef ABEA_L
+  return hipErrorInvalidValue;
+}
+
+template <int CPL, int RPG>
 static int groups_per_cu_c(int wpg) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (wpg) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, 1>, 64, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, 2>, 128, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, 4>, 256, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 1>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 2>, 128, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 4>, 256, 0); break;
   }
   return e == hipSuccess ? n : 0;
 }
 
-int align_groups_per_cu(int cpl, int wpg) {
-  switch (cpl) {
-    case 1: return groups_per_cu_c<1>(wpg);
-    case 2: return groups_per_cu_c<2>(wpg);
-    case 4: return groups_per_cu_c<4>(wpg);
-    case 8: return groups_per_cu_c<8>(wpg);
-    case 16: return groups_per_cu_c<16>(wpg);
-  }
+int align_groups_per_cu(int cpl, int rpg, int wpg) {
+#define ABEA_L(C, R) return groups_per_cu_c<C, R>(wpg)
+  ABEA_VARIANTS(ABEA_L)
+#undef ABEA_L
   return 0;
 }
 
