@@ -1,16 +1,34 @@
 """Throughput benchmark of the ABEA hot path on one MI355X.
 
-A step is one pass of the whole path (per-read constants and batch plan,
-k-parameter prep, band fill, backtrack, pair compaction) over one batch of
-synthetic reads already resident in HBM.  The default workload is the
-4000-read log-normal batch (median 5 kb, clipped 200 b..100 kb, W = 100,
-k = 6), aligned with one launch per kernel per batch.
+A step is one pass of the whole path over one batch (job) of synthetic reads
+already resident in HBM:
+  * per-read constants and batch plan;
+  * k-parameter prep;
+  * band fill;
+  * backtrack;
+  * pair compaction.
+
+The default workload is the 4000-read log-normal batch (median 5 kb, clipped
+200 b..100 kb, W = 100, k = 6), aligned with one kernel launch per batch.
+`--inflight P` keeps P batches in flight on P streams.
+
+Other workloads (``--workload``):
+  uneven-20000-w100/w200: 20000 reads, 70% 500 b..5 kb and 30% 20..200 kb.
+      Run as captured graphs of the persistent kernel (device work queue,
+      admission by traceback bytes), with the launch form autotuned
+      (``--tune``).  The plain per-batch kernel runs beside it on the same
+      reads (5 batches of 4000, one launch each).
+  ultralong-200-*: 200 reads of 200 kb..1 Mb (W = 100 or 250, k = 6 or 9).
+      The persistent kernel under a trace budget, and the backtrack's
+      throughput.
 
 Prints one JSON line.  ``value`` is whole-job GCUPS (DP cells filled inside
-the table per second, the same cell count as the CPU oracle's); the line also
-carries reads/s, per-kernel times, the band kernel's fraction of the FP32
-VALU roofline and the CPU oracle timed on the host's cores on a sample of the
-same workload.
+the table per second, the same cell count as the CPU oracle's).  The line
+also carries:
+  * reads/s;
+  * per-kernel times;
+  * the fused or band kernel's fraction of the FP32 VALU roofline;
+  * the CPU oracle timed on the host's cores on a sample of the same workload.
 """
 
 from __future__ import annotations
@@ -36,8 +54,13 @@ OPS_PER_CELL = 11
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 WORKLOADS = {
-    "plain-4000-lognormal5kb": dict(config=1, W=100, k=6),
-    "plain-64x1kb": dict(config=0, W=100, k=6),
+    "plain-4000-lognormal5kb": dict(kind="plain", config=1, W=100, k=6),
+    "plain-64x1kb": dict(kind="plain", config=0, W=100, k=6),
+    "uneven-20000-w100": dict(kind="persistent", config=2, W=100, k=6, plain_batches=5),
+    "uneven-20000-w200": dict(kind="persistent", config=2, W=200, k=6, plain_batches=5),
+    "ultralong-200-w100": dict(kind="persistent", config=4, W=100, k=6, plain_batches=1),
+    "ultralong-200-w250": dict(kind="persistent", config=4, W=250, k=6, plain_batches=1),
+    "ultralong-200-w250-k9": dict(kind="persistent", config=4, W=250, k=9, plain_batches=1),
 }
 
 # HBM traffic of one band-kernel launch on the default workload, from two
@@ -50,62 +73,73 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(batch, model, W, n_reads_sample):
+def cpu_baseline(batch, model, W, idx, what):
+    """The oracle on the host's cores (up to 16 threads) over reads idx."""
     from oracle import oracle as O
 
     cores = min(16, os.cpu_count() or 1)
-    sub = batch.subset(range(n_reads_sample))
+    sub = batch.subset(idx)
     om = O.Model(model.level_mean, model.level_stdv)
     t0 = time.perf_counter()
     res = O.align_batch(sub, om, W, n_threads=cores)
     dt = time.perf_counter() - t0
     cells = int(res.cells.sum())
     return {
-        "value": cells / dt / 1e9,
+        "value": round(cells / dt / 1e9, 4),
         "unit": "GCUPS",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"reads 0..{n_reads_sample - 1} of the same workload, {cells / 1e9:.2f} Gcells, {dt:.2f} s",
+        "sample": f"{what}: {len(idx)} reads, {cells / 1e9:.2f} Gcells, {dt:.2f} s",
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain-4000-lognormal5kb", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-reads", type=int, default=1000)
-    ap.add_argument(
-        "--inflight",
-        type=int,
-        default=3,
-        help="batches in flight: each has its own context and stream, so one batch's longest "
-        "reads overlap the next batch's work (1 = strictly one batch after the other)",
-    )
-    ap.add_argument(
-        "--workers",
-        type=int,
-        default=0,
-        help="launch form: -1 split band/backtrack kernels, 0 one fused wavefront per read, "
-        ">0 a persistent pool of that many wavefronts with a device work queue",
-    )
-    ap.add_argument("--wpg", type=int, default=1, help="wavefronts (reads) per workgroup of the fused kernel")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(
-            f"bench.py runs on one GPU: the alignment of a read never spans devices and this build "
-            f"measures one GPU's share (asked for --gpus {args.gpus})",
-            file=sys.stderr,
-        )
-        sys.exit(2)
+def sample_reads(batch, W, target_cells: float):
+    """Every s-th read, s chosen so that the sample has about target_cells."""
+    n = batch.n_reads
+    per = (np.diff(batch.event_offset.astype(np.float64)) + np.diff(batch.kmer_offset.astype(np.float64))) * W
+    stride = max(1, int(np.ceil(per.sum() / target_cells)))
+    return list(range(0, n, stride))
 
+
+def roofline(cells, kernel_ms, kernel_name):
+    achieved = cells * OPS_PER_CELL / (kernel_ms / 1e3) / 1e12
+    return {
+        "bound": "alu",
+        "kernel": kernel_name,
+        "achieved": round(achieved, 3),
+        "peak": round(VALU_PEAK_TOPS, 2),
+        "unit": "TFLOP/s",
+        "frac": round(achieved / VALU_PEAK_TOPS, 4),
+        "traffic": BAND_TRAFFIC_BYTES if kernel_name in ("k_band", "k_align") else None,
+    }
+
+
+def base_line(args, value, ms_step, workload, cfg_extra):
+    return {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, **cfg_extra},
+    }
+
+
+# --------------------------------------------------------------- plain form
+
+
+def bench_plain(args, wl):
     import torch
 
     from paper_2101_05012_amd import abea, synth
 
-    wl = WORKLOADS[args.workload]
     W, k = wl["W"], wl["k"]
     log(f"bench: generating workload {args.workload}")
     model = synth.pore_model(k)
@@ -157,58 +191,244 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log("bench: timed region done")
+    plan = slots[0][0].plan_info()
     for al, _, _ in slots:
         al.close()
 
     ms_step = dt / args.steps * 1e3
     gcups = cells_per_step * args.steps / dt / 1e9
     kms = kt / args.steps
-    band_s = kms[1] / 1e3
-    achieved = cells_per_step * OPS_PER_CELL / band_s / 1e12
-    out = {
-        "metric": METRIC,
-        "value": round(gcups, 3),
-        "unit": "GCUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": args.workload,
-            "n_reads": n,
-            "bandwidth": W,
-            "k": k,
-            "cells_per_step": cells_per_step,
-            "parallelism": "one wavefront per read",
-            "batches_in_flight": P,
-        },
+    fused = plan["workers"] > 0
+    kname = "k_align" if fused else "k_band"
+    out = base_line(args, gcups, ms_step, args.workload, {
+        "n_reads": n,
+        "bandwidth": W,
+        "k": k,
+        "cells_per_step": cells_per_step,
+        "parallelism": "one wavefront per read",
+        "launch": "fused band+backtrack, one launch per batch" if fused else "band and backtrack kernels",
+        "batches_in_flight": P,
+    })
+    out.update({
         "reads_per_s": round(n * args.steps / dt, 1),
         "kernel_gcups": round(cells_per_step / (kms.sum() / 1e3) / 1e9, 3),
         "kernel_ms": {
             "prep": round(float(kms[0]), 4),
-            "band": round(float(kms[1]), 4),
+            "align" if fused else "band": round(float(kms[1]), 4),
             "backtrack": round(float(kms[2]), 4),
             "compact": round(float(kms[3]), 4),
         },
         "reads_ok": int((status == 0).sum()),
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_band",
-            "achieved": round(achieved, 3),
-            "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "TFLOP/s",
-            "frac": round(achieved / VALU_PEAK_TOPS, 4),
-            "traffic": BAND_TRAFFIC_BYTES,
-        },
-    }
+        "roofline": roofline(cells_per_step, float(kms[1]), kname),
+    })
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(batch, model, W, min(args.cpu_sample_reads, n))
+        idx = list(range(min(args.cpu_sample_reads, n)))
+        out["cpu_baseline"] = cpu_baseline(batch, model, W, idx, f"reads 0..{len(idx) - 1} of the same workload")
+    return out
+
+
+# ---------------------------------------------------------- persistent form
+
+
+def bench_persistent(args, wl):
+    import torch
+
+    from paper_2101_05012_amd import abea, autotune, synth
+
+    W, k = wl["W"], wl["k"]
+    dev = 0
+    torch.cuda.set_device(dev)
+    log(f"bench: generating workload {args.workload}")
+    t0 = time.perf_counter()
+    model = synth.pore_model(k)
+    ids = None
+    if args.max_reads > 0:
+        ids = range(min(args.max_reads, synth.CONFIGS[wl["config"]]["n_reads"]))
+    batch = synth.config_batch_parallel(wl["config"], k=k, read_ids=ids)
+    n = batch.n_reads
+    log(f"bench: generated {n} reads, {int(batch.kmer_offset[-1]) / 1e6:.1f} M k-mers in "
+        f"{time.perf_counter() - t0:.1f} s")
+    arena = int(args.trace_budget_gb * 1e9) if args.trace_budget_gb > 0 else 0
+
+    if args.tune:
+        log("bench: autotuning the launch form")
+        tuned = autotune.autotune(model, k, W, batch, dev, arena_bytes=arena, reps=1, log=log)
+        launch = tuned["best"]
+        tune_report = {"best": launch.as_dict(), "candidates": [
+            {**r["launch"], "ms": round(r["ms"], 2), "workers": r["workers"]} for r in tuned["table"]]}
+    else:
+        launch = autotune.Launch(cells_per_lane=args.cpl, waves_per_group=args.wpg,
+                                 waves_per_simd=args.wps, batches=args.nb)
+        tune_report = None
+
+    # persistent form: the job as nb captured graphs
+    job = autotune.Job(batch, launch.batches, dev)
+    al = autotune.make_aligner(model, k, W, launch, dev, arena)
+    run = autotune.GraphRun(al, job)
+    st = torch.cuda.Stream(dev)
+    log(f"bench: persistent {launch.as_dict()} workers {[i['workers'] for i in run.info]}")
+    autotune.time_passes(run.launch, st, max(1, args.warmup))
+    cells = int(sum(int(r.cells[: p.n_reads].sum().item()) for r, p in zip(run.results, job.parts)))
+    status = np.concatenate([r.status[: p.n_reads].cpu().numpy() for r, p in zip(run.results, job.parts)])
+    log(f"bench: timing {args.steps} passes")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run.launch(st)
+    st.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = run.info
+    run.close()
+    al.close()
+    del run
+    torch.cuda.empty_cache()
+
+    # kernel times of the first batch in the same form, eager, HIP events on
+    # the launch stream
+    log("bench: kernel times")
+    al_t = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True,
+                        arena_bytes=arena,
+                        workers=max(1, launch.waves_per_simd * autotune.resident_simds(dev)),
+                        waves_per_group=launch.waves_per_group, cells_per_lane=launch.cells_per_lane)
+    p0 = job.parts[0]
+    r0 = abea.DeviceResult.empty(p0, dev)
+    al_t.align_device(p0, r0, st)
+    kms0 = [float(x) for x in al_t.timings()]
+    cells0 = int(r0.cells[: p0.n_reads].sum().item())
+    al_t.close()
+    del r0
+    torch.cuda.empty_cache()
+
+    # plain per-batch form on the same reads: fused kernel, one wavefront per
+    # read, one launch per batch, batches one after the other
+    log("bench: plain per-batch form")
+    nbp = wl["plain_batches"]
+    jobp = autotune.Job(batch, nbp, dev) if nbp != launch.batches else job
+    alp = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
+    resp = [abea.DeviceResult.empty(p, dev) for p in jobp.parts]
+
+    def plain_pass(stream):
+        for p, r in zip(jobp.parts, resp):
+            alp.align_device(p, r, stream)
+
+    autotune.time_passes(plain_pass, st, 1)
+    plain_ms = autotune.time_passes(plain_pass, st, max(1, min(args.steps, 3)))
+    alp.close()
+    del resp
+    torch.cuda.empty_cache()
+
+    ms_step = dt / args.steps * 1e3
+    gcups = cells * args.steps / dt / 1e9
+    out = base_line(args, gcups, ms_step, args.workload, {
+        "n_reads": n,
+        "bandwidth": W,
+        "k": k,
+        "cells_per_step": cells,
+        "parallelism": "persistent pool of wavefronts, device work queue, HIP graphs",
+        "launch": launch.as_dict(),
+        "workers": [i["workers"] for i in info],
+        "trace_gb": round(sum(i["trace_bytes"] for i in info) / 1e9, 3),
+        "trace_budget_gb": args.trace_budget_gb,
+        "reads_used": "all" if args.max_reads <= 0 else f"first {n}",
+    })
+    out.update({
+        "reads_per_s": round(n * args.steps / dt, 1),
+        "reads_ok": int((status == 0).sum()),
+        "plain_per_batch": {
+            "batches": nbp,
+            "ms_per_step": round(plain_ms, 3),
+            "gcups": round(cells / (plain_ms / 1e3) / 1e9, 3),
+        },
+        "kernel_ms_batch0": {"prep": round(float(kms0[0]), 4), "align": round(float(kms0[1]), 4),
+                             "compact": round(float(kms0[3]), 4)},
+        "roofline": roofline(cells0, float(kms0[1]), "k_align"),
+    })
+    if tune_report:
+        out["autotune"] = tune_report
+    if args.backtrack_probe:
+        log("bench: backtrack probe")
+        out["backtrack"] = backtrack_probe(model, k, W, job, dev, st)
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        idx = sample_reads(batch, W, args.cpu_sample_gcells * 1e9)
+        stride = idx[1] - idx[0] if len(idx) > 1 else 1
+        out["cpu_baseline"] = cpu_baseline(batch, model, W, idx, f"every {stride}-th read of the same workload")
+    return out
+
+
+def backtrack_probe(model, k, W, job, dev, st):
+    """The backtrack alone (split kernels, first batch): path steps per second
+    and trace bytes walked per second."""
+    from paper_2101_05012_amd import abea
+
+    al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True,
+                      workers=abea.ABEA_WORKERS_SPLIT)
+    p0 = job.parts[0]
+    r0 = abea.DeviceResult.empty(p0, dev)
+    al.align_device(p0, r0, st)
+    ms = [float(x) for x in al.timings()]
+    info = al.plan_info()
+    steps = int(r0.pair_offset[-1].item())
+    al.close()
+    return {
+        "band_ms": round(float(ms[1]), 3),
+        "backtrack_ms": round(float(ms[2]), 3),
+        "path_steps": steps,
+        "msteps_per_s": round(steps / (ms[2] / 1e3) / 1e6, 2),
+        "trace_gb": round(info["trace_bytes"] / 1e9, 3),
+        "trace_gb_per_s": round(info["trace_bytes"] / (ms[2] / 1e3) / 1e9, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plain-4000-lognormal5kb", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-reads", type=int, default=1000)
+    ap.add_argument("--cpu-sample-gcells", type=float, default=20.0,
+                    help="persistent workloads: oracle sample size in Gcells")
+    ap.add_argument(
+        "--inflight",
+        type=int,
+        default=3,
+        help="plain workloads: batches in flight, each with its own context and stream, so one "
+        "batch's longest reads overlap the next batch's work (1 = one batch after the other)",
+    )
+    ap.add_argument(
+        "--workers",
+        type=int,
+        default=0,
+        help="plain workloads: -1 split band/backtrack kernels, 0 one fused wavefront per read, "
+        ">0 a persistent pool of that many wavefronts with a device work queue",
+    )
+    ap.add_argument("--wpg", type=int, default=1, help="wavefronts (reads) per workgroup of the fused kernel")
+    ap.add_argument("--tune", action="store_true", help="persistent workloads: autotune the launch form")
+    ap.add_argument("--cpl", type=int, default=0, help="persistent: cells per lane (0 = smallest)")
+    ap.add_argument("--wps", type=int, default=4, help="persistent: pool wavefronts per SIMD")
+    ap.add_argument("--nb", type=int, default=1, help="persistent: batches (graphs) per job")
+    ap.add_argument("--trace-budget-gb", type=float, default=0.0,
+                    help="persistent: traceback memory budget per batch (0 = unbounded)")
+    ap.add_argument("--max-reads", type=int, default=0,
+                    help="persistent: only the first N reads of the workload (quick runs; 0 = all)")
+    ap.add_argument("--backtrack-probe", action="store_true", help="persistent: time the backtrack alone")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(
+            f"bench.py runs on one GPU: the alignment of a read never spans devices and this build "
+            f"measures one GPU's share (asked for --gpus {args.gpus})",
+            file=sys.stderr,
+        )
+        sys.exit(2)
+    wl = WORKLOADS[args.workload]
+    if wl["kind"] == "plain":
+        out = bench_plain(args, wl)
+    else:
+        out = bench_persistent(args, wl)
     print(json.dumps(out), flush=True)
 
 

@@ -194,6 +194,11 @@ typedef struct {
 } abea_launch_t;
 int abea_set_launch(abea_ctx *ctx, const abea_launch_t *launch);
 
+/* The smallest cells_per_lane the band fill uses for a band width (what
+ * cells_per_lane = 0 selects), or 0 if the width is out of range.  Needs no
+ * device. */
+int abea_cells_per_lane(int32_t bandwidth);
+
 /* How a batch was planned: the context's last direct call, or a graph. */
 typedef struct {
   int32_t n_reads;

@@ -37,6 +37,7 @@ EXPORTED = (
     "abea_align_batch_device",
     "abea_get_timings",
     "abea_set_launch",
+    "abea_cells_per_lane",
     "abea_get_plan_info",
     "abea_graph_create",
     "abea_graph_launch",
@@ -151,6 +152,8 @@ def lib() -> ctypes.CDLL:
         L.abea_get_timings.restype = ctypes.c_int
         L.abea_set_launch.argtypes = [P, ctypes.POINTER(abea_launch_t)]
         L.abea_set_launch.restype = ctypes.c_int
+        L.abea_cells_per_lane.argtypes = [ctypes.c_int32]
+        L.abea_cells_per_lane.restype = ctypes.c_int
         L.abea_get_plan_info.argtypes = [P, ctypes.POINTER(abea_plan_info_t)]
         L.abea_get_plan_info.restype = ctypes.c_int
         L.abea_graph_create.argtypes = [P, ctypes.POINTER(abea_batch_t), ctypes.POINTER(abea_result_t), ctypes.POINTER(P)]
@@ -189,6 +192,14 @@ class HostResult:
 
     def read_pairs(self, r: int) -> np.ndarray:
         return self.pairs[int(self.pair_offset[r]) : int(self.pair_offset[r + 1])]
+
+
+def min_cells_per_lane(W: int) -> int:
+    """Band slots per lane the library uses for band width W."""
+    c = lib().abea_cells_per_lane(int(W))
+    if c <= 0:
+        raise ValueError(f"band width {W} out of range")
+    return c
 
 
 def pair_capacity(event_offset: np.ndarray, kmer_offset: np.ndarray) -> int:

@@ -459,6 +459,11 @@ void abea_destroy(abea_ctx *ctx) {
   delete ctx;
 }
 
+int abea_cells_per_lane(int32_t bandwidth) {
+  if (bandwidth < 2 || bandwidth > ABEA_MAX_BANDWIDTH) return 0;
+  return cells_per_lane(bandwidth);
+}
+
 int abea_set_launch(abea_ctx *ctx, const abea_launch_t *l) {
   if (!ctx) return ABEA_E_INVAL;
   if (!l) return fail(ctx, ABEA_E_INVAL, "null launch");

@@ -217,6 +217,95 @@ def config_batch(
     return make_batch([config_read(config_id, int(i), model) for i in read_ids])
 
 
+def _config_chunk(args):
+    """Generate reads ``ids`` of a workload into a shared-memory block of its
+    own (returned by name, so that the arrays need not be pickled)."""
+    from multiprocessing import shared_memory
+
+    config_id, ids, k = args
+    model = pore_model(k)
+    b = make_batch([config_read(config_id, int(i), model) for i in ids])
+    parts = [
+        b.events,
+        np.diff(b.event_offset).astype(np.uint64),
+        b.ranks,
+        np.diff(b.kmer_offset).astype(np.uint64),
+        b.scale,
+        b.shift,
+    ]
+    total = sum(p.nbytes for p in parts)
+    shm = shared_memory.SharedMemory(create=True, size=max(total, 1))
+    meta = []
+    off = 0
+    for p in parts:
+        dst = np.ndarray(p.shape, p.dtype, buffer=shm.buf, offset=off)
+        dst[...] = p
+        meta.append((p.shape, p.dtype.str, off))
+        off += p.nbytes
+    del dst
+    name = shm.name
+    # the parent unlinks the block; keep this process's resource tracker
+    # from removing it when the worker exits
+    from multiprocessing import resource_tracker
+
+    resource_tracker.unregister(shm._name, "shared_memory")
+    shm.close()
+    return name, meta
+
+
+def config_batch_parallel(
+    config_id: int,
+    k: Optional[int] = None,
+    read_ids: Optional[Sequence[int]] = None,
+    workers: Optional[int] = None,
+    chunk: int = 100,
+) -> Batch:
+    """config_batch over a process pool (same bytes: every read has its own
+    random stream); for the large workloads.  The pore model is the seeded
+    one of k (``pore_model(k)``)."""
+    import multiprocessing as mp
+    import os
+    from multiprocessing import shared_memory
+
+    cfg = CONFIGS[config_id]
+    k = cfg["k"] if k is None else k
+    ids = list(range(cfg["n_reads"]) if read_ids is None else read_ids)
+    workers = workers or min(16, os.cpu_count() or 1)
+    jobs = [(config_id, ids[j : j + chunk], k) for j in range(0, len(ids), chunk)]
+    with mp.get_context("fork").Pool(max(1, workers)) as pool:
+        results = pool.map(_config_chunk, jobs, chunksize=1)
+    blocks = []
+    try:
+        views = []
+        for name, meta in results:
+            shm = shared_memory.SharedMemory(name=name)
+            blocks.append(shm)
+            views.append([np.ndarray(s, np.dtype(d), buffer=shm.buf, offset=o) for s, d, o in meta])
+        n = len(ids)
+        ne = np.concatenate([v[1] for v in views]) if views else np.zeros(0, np.uint64)
+        nk = np.concatenate([v[3] for v in views]) if views else np.zeros(0, np.uint64)
+        eo = np.zeros(n + 1, np.uint64)
+        ko = np.zeros(n + 1, np.uint64)
+        np.cumsum(ne, out=eo[1:])
+        np.cumsum(nk, out=ko[1:])
+        ev = np.empty((int(eo[-1]), 3), np.float32)
+        rk = np.empty(int(ko[-1]), np.uint32)
+        e0 = k0 = 0
+        for v in views:
+            ev[e0 : e0 + v[0].shape[0]] = v[0]
+            rk[k0 : k0 + v[2].shape[0]] = v[2]
+            e0 += v[0].shape[0]
+            k0 += v[2].shape[0]
+        sc = np.concatenate([v[4] for v in views]) if views else np.zeros(0, np.float32)
+        sh = np.concatenate([v[5] for v in views]) if views else np.zeros(0, np.float32)
+        del views, v
+    finally:
+        for shm in blocks:
+            shm.close()
+            shm.unlink()
+    return Batch(ev, eo, rk, ko, sc, sh)
+
+
 def config_lengths(config_id: int, read_ids: Sequence[int]) -> np.ndarray:
     """Reference lengths only (cheap: draws the first number of each stream)."""
     kind = CONFIGS[config_id]["lengths"]
