@@ -21,6 +21,11 @@ Other workloads (``--workload``):
   ultralong-200-*: 200 reads of 200 kb..1 Mb (W = 100 or 250, k = 6 or 9).
       The persistent kernel under a trace budget, and the backtrack's
       throughput.
+  serving-512ch: reads arrive from 512 simulated channels (Poisson, 400
+      bases/s each, log-normal lengths with median 8 kb) into the library's
+      continuous-batching server.  The replay is sped up 1x..10000x; each
+      level reports p50/p99 per-read latency, reads/s and GCUPS.  The plain
+      batched kernel runs beside it on the same reads.
 
 Prints one JSON line.  ``value`` is whole-job GCUPS (DP cells filled inside
 the table per second, the same cell count as the CPU oracle's).  The line
@@ -61,7 +66,12 @@ WORKLOADS = {
     "ultralong-200-w100": dict(kind="persistent", config=4, W=100, k=6, plain_batches=1),
     "ultralong-200-w250": dict(kind="persistent", config=4, W=250, k=6, plain_batches=1),
     "ultralong-200-w250-k9": dict(kind="persistent", config=4, W=250, k=9, plain_batches=1),
+    "serving-512ch": dict(kind="serving", config=3, W=100, k=6),
 }
+
+# serving: (time compression, reads) per load level; x1 is real time for 512
+# channels at 400 bases/s each
+SERVING_LEVELS = [(1, 300), (10, 1000), (100, 4000), (1000, 20000), (3000, 30000), (10000, 30000)]
 
 # HBM traffic of one band-kernel launch on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a copy-kernel
@@ -382,6 +392,97 @@ def backtrack_probe(model, k, W, job, dev, st):
     }
 
 
+# ------------------------------------------------------------------ serving
+
+
+def bench_serving(args, wl):
+    import torch
+
+    from paper_2101_05012_amd import abea, serving, synth
+
+    W, k = wl["W"], wl["k"]
+    dev = 0
+    torch.cuda.set_device(dev)
+    levels = SERVING_LEVELS if not args.levels else [tuple(int(x) for x in s.split(":")) for s in args.levels.split(",")]
+    n_max = max(n for _, n in levels)
+    log(f"bench: generating {n_max} serving reads")
+    t0 = time.perf_counter()
+    model = synth.pore_model(k)
+    batch = synth.config_batch_parallel(wl["config"], k=k, read_ids=range(n_max))
+    # arrival times of the simulated sequencer (first n_max reads)
+    dur = 60.0
+    arr = synth.serving_arrivals(duration_s=dur)
+    while arr.shape[0] < n_max:
+        dur *= 2
+        arr = synth.serving_arrivals(duration_s=dur)
+    arr = arr[:n_max]
+    log(f"bench: generated in {time.perf_counter() - t0:.1f} s; real-time rate {n_max / arr[-1]:.1f} reads/s")
+    al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
+    budget = int(args.trace_budget_gb * 1e9) if args.trace_budget_gb > 0 else 8_000_000_000
+    out_levels = []
+    for comp, n in levels:
+        sub = batch.subset(range(n)) if n < batch.n_reads else batch
+        srv = abea.Server(al, slots=args.slots, max_batch_reads=args.batch_reads, trace_budget_bytes=budget)
+        log(f"bench: serving x{comp} {n} reads")
+        res = serving.run(srv, sub, arr[:n], compression=float(comp))
+        srv.close()
+        s = serving.summarize(res, sub, float(comp), arr[:n])
+        log(f"bench: {s}")
+        out_levels.append(s)
+    # the plain batched kernel on the same reads (largest level, inputs in HBM)
+    n = levels[-1][1]
+    sub = batch.subset(range(n)) if n < batch.n_reads else batch
+    db = abea.to_device(sub, dev)
+    dr = abea.DeviceResult.empty(db, dev)
+    st = torch.cuda.Stream(dev)
+    al.align_device(db, dr, st)
+    st.synchronize()
+    cells = int(dr.cells[:n].sum().item())
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        al.align_device(db, dr, st)
+    st.synchronize()
+    plain_s = (time.perf_counter() - t0) / reps
+    al.close()
+    best = max(out_levels, key=lambda s: s["gcups"])
+    out = base_line(args, best["gcups"], 1e3 * best["reads"] / best["reads_per_s"], args.workload, {
+        "reads_max": n_max,
+        "bandwidth": W,
+        "k": k,
+        "parallelism": "continuous batching: micro-batches on several streams, one wavefront per read",
+        "slots": args.slots,
+        "max_batch_reads": args.batch_reads,
+        "trace_budget_gb": budget / 1e9,
+        "value_is": "GCUPS of the load level with the highest throughput",
+    })
+    out.update({
+        "reads_per_s": best["reads_per_s"],
+        "latency_ms": best["latency_ms"],
+        "levels": out_levels,
+        "plain_batched": {"reads": n, "s": round(plain_s, 4), "gcups": round(cells / plain_s / 1e9, 3),
+                          "reads_per_s": round(n / plain_s, 1)},
+    })
+    return out
+
+
+def copy_calibration(mb: int) -> None:
+    """One plain device-to-device copy of `mb` MiB (a torch copy kernel), so
+    that a counter run of this program also measures what FETCH_SIZE and
+    WRITE_SIZE report for a known number of bytes."""
+    import torch
+
+    n = mb * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"bench: copy calibration {mb} MiB read + {mb} MiB written")
+    del src, dst
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -415,6 +516,11 @@ def main():
                     help="persistent: traceback memory budget per batch (0 = unbounded)")
     ap.add_argument("--max-reads", type=int, default=0,
                     help="persistent: only the first N reads of the workload (quick runs; 0 = all)")
+    ap.add_argument("--slots", type=int, default=4, help="serving: micro-batches on the device at once")
+    ap.add_argument("--batch-reads", type=int, default=1024, help="serving: reads per micro-batch")
+    ap.add_argument("--levels", default="", help="serving: compression:reads,... (default: the full sweep)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (HBM counter calibration)")
     ap.add_argument("--backtrack-probe", action="store_true", help="persistent: time the backtrack alone")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -425,8 +531,12 @@ def main():
         )
         sys.exit(2)
     wl = WORKLOADS[args.workload]
+    if args.copy_calibration_mb > 0:
+        copy_calibration(args.copy_calibration_mb)
     if wl["kind"] == "plain":
         out = bench_plain(args, wl)
+    elif wl["kind"] == "serving":
+        out = bench_serving(args, wl)
     else:
         out = bench_persistent(args, wl)
     print(json.dumps(out), flush=True)

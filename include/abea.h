@@ -231,6 +231,89 @@ int abea_graph_launch(abea_graph *graph, void *stream);
 int abea_graph_info(const abea_graph *graph, abea_plan_info_t *info);
 void abea_graph_destroy(abea_graph *graph);
 
+/* ---- serving loop (continuous batching) ------------------------------------
+ * A background thread of the library admits reads, as they arrive, into
+ * micro-batches and keeps up to `slots` micro-batches on the device at once,
+ * each on its own stream with its own buffers (all allocated by
+ * abea_server_create; admission allocates nothing).
+ *   - Reads wait in length classes (factor-2 bins of n_e + n_k); a free slot
+ *     takes, in arrival order, reads of the class whose first read has
+ *     waited longest, so a micro-batch lasts about as long as each of its
+ *     reads.
+ *   - Admission is by traceback bytes: a read needs
+ *     ceil((n_e + n_k - 1) / (32 / cells_per_lane)) * 512 bytes of trace tiles
+ *     and the reads on the device never need more than trace_budget_bytes
+ *     together (0 = no budget).  A read that arrives while others run joins
+ *     the next micro-batch as soon as a slot and trace memory are free.
+ *   - Each result is bit-identical to abea_align_batch on the read alone
+ *     (a read is aligned by its own wavefront whatever batch it is in).
+ * The server uses the context's model, band width and launch form; do not
+ * call abea_set_launch or destroy the context while a server exists.
+ * submit and poll may be called from different threads.
+ */
+typedef struct {
+  int32_t slots;              /* micro-batches on the device at once, 1..16 */
+  int32_t max_batch_reads;    /* reads per micro-batch */
+  uint64_t max_batch_events;  /* events per micro-batch (also the largest read) */
+  uint64_t max_batch_kmers;   /* k-mers per micro-batch (also the largest read) */
+  uint64_t trace_budget_bytes;/* traceback bytes of all reads on the device (0 = none) */
+} abea_server_config_t;
+
+/* One finished read.  Times are abea_server_now_ns() values: arrival (given
+ * at submission), admission into a micro-batch, and the moment its results
+ * were in host memory. */
+typedef struct {
+  uint64_t tag;
+  int32_t status;         /* ABEA_READ_* */
+  float log_likelihood;
+  uint64_t cells;
+  uint64_t pair_offset;   /* first pair in the caller's pairs buffer */
+  uint64_t n_pairs;
+  int64_t t_arrival_ns;
+  int64_t t_admit_ns;
+  int64_t t_done_ns;
+} abea_completion_t;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, pending;
+  uint64_t micro_batches;
+  uint64_t inflight_reads, max_inflight_reads;
+  uint64_t inflight_trace_bytes, max_inflight_trace_bytes;
+  int32_t error;          /* sticky ABEA_E_* of the background thread, 0 if none */
+  int32_t reserved;
+} abea_server_stats_t;
+
+typedef struct abea_server abea_server;
+
+/* Steady-clock time in nanoseconds (the clock of the completion times). */
+int64_t abea_server_now_ns(void);
+
+/* Create a server on ctx's device; *out receives it (free with
+ * abea_server_destroy).  Errors: ABEA_E_INVAL, ABEA_E_NOMEM, ABEA_E_HIP. */
+int abea_server_create(abea_ctx *ctx, const abea_server_config_t *cfg, abea_server **out);
+
+/* Queue reads (host pointers, layout of abea_batch_t; copied before the call
+ * returns).  tags[r] identifies read r in its completion; arrival_ns[r] is
+ * its arrival time (NULL = now).  Errors: ABEA_E_INVAL, ABEA_E_CAPACITY (a
+ * read larger than a micro-batch or than the trace budget; nothing queued),
+ * or the background thread's sticky error. */
+int abea_server_submit(abea_server *server, const abea_batch_t *reads, const uint64_t *tags,
+                       const int64_t *arrival_ns);
+
+/* Collect up to max_out finished reads, waiting up to timeout_us for the
+ * first; their pairs are copied into pairs[] (capacity pair_capacity), read
+ * i's at out[i].pair_offset.  *n_out receives the count (0 on timeout).
+ * Errors: ABEA_E_CAPACITY if the next result's pairs do not fit (nothing
+ * taken), or the background thread's sticky error. */
+int abea_server_poll(abea_server *server, abea_completion_t *out, int max_out, abea_pair_t *pairs,
+                     uint64_t pair_capacity, int32_t timeout_us, int *n_out);
+
+int abea_server_stats(abea_server *server, abea_server_stats_t *stats);
+
+/* Stop admitting, drop queued reads, wait for the device work in flight and
+ * free the server.  NULL is allowed. */
+void abea_server_destroy(abea_server *server);
+
 /* Free the context and all its device memory.  NULL is allowed. */
 void abea_destroy(abea_ctx *ctx);
 

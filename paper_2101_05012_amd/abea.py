@@ -43,6 +43,12 @@ EXPORTED = (
     "abea_graph_launch",
     "abea_graph_info",
     "abea_graph_destroy",
+    "abea_server_now_ns",
+    "abea_server_create",
+    "abea_server_submit",
+    "abea_server_poll",
+    "abea_server_stats",
+    "abea_server_destroy",
     "abea_destroy",
     "abea_strerror",
     "abea_last_error",
@@ -122,6 +128,64 @@ class abea_plan_info_t(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class abea_server_config_t(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_int32),
+        ("max_batch_reads", ctypes.c_int32),
+        ("max_batch_events", ctypes.c_uint64),
+        ("max_batch_kmers", ctypes.c_uint64),
+        ("trace_budget_bytes", ctypes.c_uint64),
+    ]
+
+
+class abea_completion_t(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("log_likelihood", ctypes.c_float),
+        ("cells", ctypes.c_uint64),
+        ("pair_offset", ctypes.c_uint64),
+        ("n_pairs", ctypes.c_uint64),
+        ("t_arrival_ns", ctypes.c_int64),
+        ("t_admit_ns", ctypes.c_int64),
+        ("t_done_ns", ctypes.c_int64),
+    ]
+
+
+COMPLETION_DTYPE = np.dtype(
+    [
+        ("tag", np.uint64),
+        ("status", np.int32),
+        ("log_likelihood", np.float32),
+        ("cells", np.uint64),
+        ("pair_offset", np.uint64),
+        ("n_pairs", np.uint64),
+        ("t_arrival_ns", np.int64),
+        ("t_admit_ns", np.int64),
+        ("t_done_ns", np.int64),
+    ]
+)
+
+
+class abea_server_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64),
+        ("admitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64),
+        ("pending", ctypes.c_uint64),
+        ("micro_batches", ctypes.c_uint64),
+        ("inflight_reads", ctypes.c_uint64),
+        ("max_inflight_reads", ctypes.c_uint64),
+        ("inflight_trace_bytes", ctypes.c_uint64),
+        ("max_inflight_trace_bytes", ctypes.c_uint64),
+        ("error", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+
+
 _lib = None
 
 
@@ -164,6 +228,19 @@ def lib() -> ctypes.CDLL:
         L.abea_graph_info.restype = ctypes.c_int
         L.abea_graph_destroy.argtypes = [P]
         L.abea_graph_destroy.restype = None
+        L.abea_server_now_ns.argtypes = []
+        L.abea_server_now_ns.restype = ctypes.c_int64
+        L.abea_server_create.argtypes = [P, ctypes.POINTER(abea_server_config_t), ctypes.POINTER(P)]
+        L.abea_server_create.restype = ctypes.c_int
+        L.abea_server_submit.argtypes = [P, ctypes.POINTER(abea_batch_t), P, P]
+        L.abea_server_submit.restype = ctypes.c_int
+        L.abea_server_poll.argtypes = [P, P, ctypes.c_int, P, ctypes.c_uint64, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int)]
+        L.abea_server_poll.restype = ctypes.c_int
+        L.abea_server_stats.argtypes = [P, ctypes.POINTER(abea_server_stats_t)]
+        L.abea_server_stats.restype = ctypes.c_int
+        L.abea_server_destroy.argtypes = [P]
+        L.abea_server_destroy.restype = None
         L.abea_destroy.argtypes = [P]
         L.abea_destroy.restype = None
         L.abea_strerror.argtypes = [ctypes.c_int]
@@ -427,3 +504,79 @@ class DeviceResult:
             self.status[:n].cpu().numpy(),
             self.cells[:n].cpu().numpy().view(np.uint64),
         )
+
+
+def now_ns() -> int:
+    """The serving loop's clock (steady, nanoseconds)."""
+    return int(lib().abea_server_now_ns())
+
+
+class Server:
+    """Continuous-batching serving loop of the library (abea_server_*)."""
+
+    def __init__(self, aligner: Aligner, slots: int = 4, max_batch_reads: int = 1024,
+                 max_batch_events: int = 1 << 24, max_batch_kmers: int = 1 << 23, trace_budget_bytes: int = 0):
+        self.aligner = aligner
+        cfg = abea_server_config_t(int(slots), int(max_batch_reads), int(max_batch_events), int(max_batch_kmers),
+                                   int(trace_budget_bytes))
+        h = ctypes.c_void_p()
+        aligner._check(lib().abea_server_create(aligner.handle, ctypes.byref(cfg), ctypes.byref(h)),
+                       "abea_server_create")
+        self.handle = h
+        self._out = np.zeros(0, COMPLETION_DTYPE)
+        self._pairs = np.zeros((0, 2), np.int32)
+
+    def submit(self, batch, lo: int, hi: int, tags, arrival_ns=None) -> None:
+        """Queue reads [lo, hi) of a host batch (``synth.Batch``-like)."""
+        eo = batch.event_offset
+        ko = batch.kmer_offset
+        e0, e1 = int(eo[lo]), int(eo[hi])
+        k0, k1 = int(ko[lo]), int(ko[hi])
+        ev = np.ascontiguousarray(batch.events[e0:e1], np.float32)
+        rk = np.ascontiguousarray(batch.ranks[k0:k1], np.uint32)
+        eor = np.ascontiguousarray(eo[lo : hi + 1] - eo[lo], np.uint64)
+        kor = np.ascontiguousarray(ko[lo : hi + 1] - ko[lo], np.uint64)
+        sc = np.ascontiguousarray(batch.scale[lo:hi], np.float32)
+        sh = np.ascontiguousarray(batch.shift[lo:hi], np.float32)
+        tg = np.ascontiguousarray(tags, np.uint64)
+        at = None if arrival_ns is None else np.ascontiguousarray(arrival_ns, np.int64)
+        b = abea_batch_t(hi - lo, _ptr(ev), _ptr(eor), _ptr(rk), _ptr(kor), _ptr(sc), _ptr(sh))
+        self.aligner._check(lib().abea_server_submit(self.handle, ctypes.byref(b), _ptr(tg), _ptr(at)),
+                            "abea_server_submit")
+
+    def poll(self, max_out: int = 4096, timeout_us: int = 1000, pair_capacity: int = 1 << 22, want_pairs: bool = True):
+        """Finished reads: (completions structured array, pairs int32 [total, 2]
+        or None when want_pairs is False)."""
+        if self._out.shape[0] < max_out:
+            self._out = np.zeros(max_out, COMPLETION_DTYPE)
+        if self._pairs.shape[0] < pair_capacity:
+            self._pairs = np.zeros((pair_capacity, 2), np.int32)
+        n = ctypes.c_int(0)
+        rc = lib().abea_server_poll(self.handle, _ptr(self._out), int(max_out), _ptr(self._pairs),
+                                    int(self._pairs.shape[0]), int(timeout_us), ctypes.byref(n))
+        if rc == ABEA_E_CAPACITY:  # the next result is larger: grow and retry
+            self._pairs = np.zeros((self._pairs.shape[0] * 4, 2), np.int32)
+            return self.poll(max_out, timeout_us, self._pairs.shape[0], want_pairs)
+        self.aligner._check(rc, "abea_server_poll")
+        k = n.value
+        comp = self._out[:k].copy()
+        if not want_pairs:
+            return comp, None
+        total = int((comp["n_pairs"]).sum()) if k else 0
+        return comp, self._pairs[:total].copy()
+
+    def stats(self) -> dict:
+        st = abea_server_stats_t()
+        self.aligner._check(lib().abea_server_stats(self.handle, ctypes.byref(st)), "abea_server_stats")
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().abea_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,7 +8,11 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabea.so")
-SOURCES = [os.path.join(CSRC, "abea_kernels.hip"), os.path.join(CSRC, "abea_host.cpp")]
+SOURCES = [
+    os.path.join(CSRC, "abea_kernels.hip"),
+    os.path.join(CSRC, "abea_host.cpp"),
+    os.path.join(CSRC, "abea_server.cpp"),
+]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -23,6 +27,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-command-line-argument",
+    "-pthread",
 ]
 
 

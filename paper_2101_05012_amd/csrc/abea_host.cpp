@@ -23,74 +23,19 @@
 
 #include "../../include/abea.h"
 #include "abea_internal.h"
+#include "abea_runtime.h"
 
 using namespace abea;
 
-namespace {
-
-struct DevBuf {
-  void *p = nullptr;
-  size_t cap = 0;
-};
-
-struct Plan {
-  int n = 0;
-  int workers = 0;        /* fused kernel: wavefronts (0 for the split kernels) */
-  int cpl = 2;            /* slots per lane the plan was made for */
-  int wpg = 1;            /* wavefronts per workgroup of the fused kernel */
-  uint64_t n_trace = 0;   /* uint2 words */
-  uint64_t n_scratch = 0; /* pair slots */
-  uint64_t n_events = 0;
-  uint64_t n_kmers = 0;
-  uint64_t pairs_needed = 0;
-  int32_t urgent_len = 0x7fffffff;
-};
-
-/* Device buffers and staging of one planned batch.  The context owns one for
- * its direct calls; every captured graph owns its own, so graphs can run
- * concurrently on different streams. */
-struct Work {
-  Plan plan;
-  std::vector<int> order;
-  DevBuf reads, rstat, queue, xmean, kparam, trace, scratch, path_len, path_src;
-  ReadDesc *h_reads = nullptr; /* pinned staging of the plan */
-  size_t h_cap = 0;
-  hipEvent_t staging_done = nullptr;
-  bool staging_pending = false;
-  hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  bool timed = false;
-  hipStream_t last_stream = nullptr;
-};
-
-}  // namespace
-
-struct abea_ctx {
-  int device = 0;
-  int W = 100;
-  uint32_t flags = 0;
-  uint32_t k = 6;
-  uint32_t n_model = 0;
-  uint64_t arena_bytes = 0; /* trace budget of one batch (0 = unbounded) */
-  int num_cus = 0;
-  abea_launch_t launch = {0, 1, 0, 0};
-  int cpl = 2; /* slots per lane in use */
-  DevBuf model;
-  hipStream_t own_stream = nullptr;
-  Work main;
-  /* host-API copies of inputs and outputs */
-  DevBuf events, ranks, scale, shift, pairs, pair_offset, ll, status, cells;
-  std::string err;
-};
-
 struct abea_graph {
   abea_ctx *ctx = nullptr;
-  Work work;
+  abea_rt::Work work;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
-namespace {
+namespace abea_rt {
 
 int fail(abea_ctx *ctx, int code, const char *fmt, ...) {
   if (ctx) {
@@ -104,13 +49,7 @@ int fail(abea_ctx *ctx, int code, const char *fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(ctx, expr)                                                                  \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail((ctx), e_ == hipErrorOutOfMemory ? ABEA_E_NOMEM : ABEA_E_HIP, "%s: %s", \
-                  #expr, hipGetErrorString(e_));                                            \
-  } while (0)
+
 
 int ensure(abea_ctx *ctx, Work *w, DevBuf &b, size_t bytes) {
   if (bytes == 0) bytes = 256;
@@ -278,17 +217,7 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
   return ABEA_OK;
 }
 
-struct DevIO {
-  const float *events;
-  const uint32_t *ranks;
-  const float *scale;
-  const float *shift;
-  int2 *pairs;
-  uint64_t *pair_offset;
-  float *ll;
-  int32_t *status;
-  uint64_t *cells;
-};
+
 
 int ensure_work(abea_ctx *ctx, Work &w) {
   const Plan &P = w.plan;
@@ -379,7 +308,9 @@ int check_batch(abea_ctx *ctx, const abea_batch_t *b, const abea_result_t *r) {
   return ABEA_OK;
 }
 
-}  // namespace
+}  // namespace abea_rt
+
+using namespace abea_rt;
 
 extern "C" {
 

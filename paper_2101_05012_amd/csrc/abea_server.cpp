@@ -1,0 +1,623 @@
+/*
+ * abea_server.cpp -- continuous-batching serving loop of libabea.so.
+ *
+ * Reads arrive one at a time (a simulated sequencer in the thesis's
+ * on-the-fly setting, Ch. 5 §5.5 and Ch. 6); a background thread admits
+ * them into micro-batches and keeps several micro-batches on the device at
+ * once, each on its own stream with its own buffers ("slots").
+ *   - Reads wait in length classes (factor-2 bins of n_e + n_k); a free slot
+ *     takes reads of the class whose first read has waited longest, so a
+ *     micro-batch is not held up by one long read and no read starves.
+ *   - Admission is by traceback bytes: a read needs
+ *     ceil((n_e + n_k - 1) / G) * 512 bytes of trace tiles; the reads on the
+ *     device never need more than trace_budget_bytes together.
+ *   - A read that arrives while others are on the device joins the next
+ *     micro-batch as soon as a slot and trace memory are free; its work
+ *     overlaps the running micro-batches on the device.
+ *   - Band state lives in the kernel's registers and the trace stays in
+ *     device memory; only inputs and results cross PCIe.
+ *   - A read's result does not depend on the micro-batch it ran in (each
+ *     read is aligned by its own wavefront).
+ * Each result carries its arrival, admission and completion times (steady
+ * clock), so the caller can report per-read latency.
+ */
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/abea.h"
+#include "abea_internal.h"
+#include "abea_runtime.h"
+
+using namespace abea;
+using namespace abea_rt;
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+/* Length classes of admission: class c holds reads with 2^c <= n_e + n_k <
+ * 2^(c+1); a micro-batch takes reads of one class, so its kernel lasts about
+ * as long as each of its reads. */
+constexpr int N_CLASSES = 40;
+
+int length_class(uint64_t len) {
+  int c = 0;
+  while (c < N_CLASSES - 1 && (len >> (c + 1)) != 0) ++c;
+  return c;
+}
+
+/* Host buffers recycled by size class (powers of two, at least 4 KB), so
+ * that a queued read does not allocate and fault in fresh pages; at most
+ * `keep` bytes stay pooled. */
+class BufPool {
+ public:
+  static int cls(size_t n) {
+    int c = 12;
+    while (c < 47 && ((size_t)1 << c) < n) ++c;
+    return c;
+  }
+  std::unique_ptr<uint8_t[]> get(size_t n, int *c_out) {
+    const int c = cls(n);
+    *c_out = c;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (!free_[c].empty()) {
+        std::unique_ptr<uint8_t[]> p = std::move(free_[c].back());
+        free_[c].pop_back();
+        pooled_ -= (size_t)1 << c;
+        return p;
+      }
+    }
+    return std::unique_ptr<uint8_t[]>(new (std::nothrow) uint8_t[(size_t)1 << c]);
+  }
+  void put(std::unique_ptr<uint8_t[]> p, int c) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    if (pooled_ + ((size_t)1 << c) > keep) return; /* freed here */
+    pooled_ += (size_t)1 << c;
+    free_[c].push_back(std::move(p));
+  }
+  size_t keep = (size_t)2 << 30;
+
+ private:
+  std::mutex mu_;
+  std::vector<std::unique_ptr<uint8_t[]>> free_[48];
+  size_t pooled_ = 0;
+};
+
+/* A queued read: events then k-mer ranks in one pooled buffer. */
+struct SrvRead {
+  uint64_t tag = 0;
+  int64_t t_arrival = 0;
+  int64_t t_admit = 0;
+  std::unique_ptr<uint8_t[]> buf;
+  int buf_cls = 0;
+  uint64_t ne = 0, nk = 0;
+  float scale = 1.f, shift = 0.f;
+  uint64_t trace_bytes = 0;
+  const abea_event_t *events() const { return reinterpret_cast<const abea_event_t *>(buf.get()); }
+  const uint32_t *ranks() const { return reinterpret_cast<const uint32_t *>(buf.get() + ne * sizeof(abea_event_t)); }
+};
+
+/* A finished read; its pairs are at [pos, pos + c.n_pairs) of the server's
+ * pair ring (results leave in the order they are queued). */
+struct Done {
+  abea_completion_t c;
+  uint64_t pos;
+};
+
+enum SlotState { FREE = 0, RUNNING = 1, COPYING = 2 };
+
+struct Slot {
+  hipStream_t st = nullptr;
+  hipEvent_t ev_meta = nullptr, ev_done = nullptr;
+  Work work;
+  /* pinned staging of inputs and results */
+  abea_event_t *h_ev = nullptr;
+  uint32_t *h_rk = nullptr;
+  float *h_sc = nullptr, *h_sh = nullptr;
+  uint64_t *h_eo = nullptr, *h_ko = nullptr;
+  abea_pair_t *h_pairs = nullptr;
+  uint64_t *h_po = nullptr, *h_cells = nullptr;
+  float *h_ll = nullptr;
+  int32_t *h_st = nullptr;
+  /* device inputs and results */
+  DevBuf d_ev, d_rk, d_sc, d_sh, d_pairs, d_po, d_ll, d_st, d_cells;
+  std::vector<SrvRead> reads;
+  uint64_t trace_bytes = 0;
+  int state = FREE;
+};
+
+}  // namespace
+
+struct abea_server {
+  abea_ctx *ctx = nullptr;
+  abea_server_config_t cfg{};
+  int G = 16;
+  std::vector<Slot> slots;
+  std::mutex mu;
+  std::condition_variable cv_work; /* new reads or stop */
+  std::condition_variable cv_done; /* new completions */
+  std::deque<SrvRead> pending[N_CLASSES]; /* arrival order within a class */
+  uint64_t n_pending = 0;
+  std::deque<Done> done;
+  std::vector<abea_pair_t> ring; /* pairs of the queued results: power-of-two ring */
+  uint64_t ring_head = 0, ring_tail = 0;
+  BufPool pool;
+  std::thread worker;
+  bool stop = false;
+  int error = ABEA_OK;
+  std::string err;
+  /* under mu */
+  uint64_t inflight_trace = 0;
+  uint64_t inflight_reads = 0;
+  abea_server_stats_t stats{};
+};
+
+namespace {
+
+uint64_t trace_bytes_of(int G, uint64_t ne, uint64_t nk) {
+  if (ne == 0 || nk == 0) return 0;
+  const uint64_t comp = ne + nk - 1;
+  return ((comp + G - 1) / G) * 64u * sizeof(uint2);
+}
+
+void slot_free(Slot &s) {
+  if (s.st) (void)hipStreamSynchronize(s.st);
+  work_free(s.work);
+  DevBuf *bufs[] = {&s.d_ev, &s.d_rk, &s.d_sc, &s.d_sh, &s.d_pairs, &s.d_po, &s.d_ll, &s.d_st, &s.d_cells};
+  for (DevBuf *b : bufs) free_buf(*b);
+  void *hosts[] = {s.h_ev, s.h_rk, s.h_sc, s.h_sh, s.h_eo, s.h_ko, s.h_pairs, s.h_po, s.h_cells, s.h_ll, s.h_st};
+  for (void *h : hosts)
+    if (h) (void)hipHostFree(h);
+  if (s.ev_meta) (void)hipEventDestroy(s.ev_meta);
+  if (s.ev_done) (void)hipEventDestroy(s.ev_done);
+  if (s.st) (void)hipStreamDestroy(s.st);
+  s = Slot();
+}
+
+template <typename T>
+int host_alloc(abea_ctx *ctx, T **p, uint64_t n) {
+  HIP_TRY(ctx, hipHostMalloc((void **)p, sizeof(T) * std::max<uint64_t>(n, 1), hipHostMallocDefault));
+  return ABEA_OK;
+}
+
+/* Buffers of one slot sized for the configured micro-batch capacity, so that
+ * admission never allocates. */
+int slot_init(abea_server *S, Slot &s) {
+  abea_ctx *ctx = S->ctx;
+  const abea_server_config_t &c = S->cfg;
+  const uint64_t nr = (uint64_t)c.max_batch_reads, ne = c.max_batch_events, nk = c.max_batch_kmers;
+  const uint64_t np = ne + nk; /* pair capacity: sum of n_e + n_k - 1 */
+  int rc;
+  HIP_TRY(ctx, hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
+  HIP_TRY(ctx, hipEventCreateWithFlags(&s.ev_meta, hipEventDisableTiming));
+  HIP_TRY(ctx, hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming));
+  if ((rc = work_init(ctx, s.work))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_ev, ne))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_rk, nk))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_sc, nr))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_sh, nr))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_eo, nr + 1))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_ko, nr + 1))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_pairs, np))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_po, nr + 1))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_cells, nr))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_ll, nr))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_st, nr))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_ev, sizeof(abea_event_t) * ne))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_rk, sizeof(uint32_t) * nk))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_sc, sizeof(float) * nr))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_sh, sizeof(float) * nr))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_pairs, sizeof(abea_pair_t) * np))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_po, sizeof(uint64_t) * (nr + 1)))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_ll, sizeof(float) * nr))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_st, sizeof(int32_t) * nr))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_cells, sizeof(uint64_t) * nr))) return rc;
+  /* the planned batch's own buffers at their largest */
+  Work &w = s.work;
+  const uint64_t trace_max = ((np + S->G - 1) / S->G + nr) * 64u * sizeof(uint2);
+  if ((rc = ensure(ctx, nullptr, w.reads, sizeof(ReadDesc) * nr))) return rc;
+  if ((rc = ensure(ctx, nullptr, w.rstat, sizeof(int32_t) * nr))) return rc;
+  if ((rc = ensure(ctx, nullptr, w.queue, sizeof(uint32_t)))) return rc;
+  if ((rc = ensure(ctx, nullptr, w.xmean, sizeof(float) * ne))) return rc;
+  if ((rc = ensure(ctx, nullptr, w.kparam, sizeof(KParam) * nk))) return rc;
+  if ((rc = ensure(ctx, nullptr, w.trace,
+                   c.trace_budget_bytes ? std::min<uint64_t>(c.trace_budget_bytes, trace_max) : trace_max)))
+    return rc;
+  if ((rc = ensure(ctx, nullptr, w.scratch, sizeof(int2) * np))) return rc;
+  if ((rc = ensure(ctx, nullptr, w.path_len, sizeof(uint64_t) * nr))) return rc;
+  if ((rc = ensure(ctx, nullptr, w.path_src, sizeof(uint64_t) * nr))) return rc;
+  if ((rc = host_alloc(ctx, &w.h_reads, nr))) return rc;
+  w.h_cap = nr;
+  return ABEA_OK;
+}
+
+/* Stage a micro-batch and enqueue it on the slot's stream. */
+int slot_launch(abea_server *S, Slot &s) {
+  abea_ctx *ctx = S->ctx;
+  const int n = (int)s.reads.size();
+  uint64_t eo = 0, ko = 0;
+  s.h_eo[0] = s.h_ko[0] = 0;
+  for (int r = 0; r < n; ++r) {
+    const SrvRead &R = s.reads[r];
+    if (R.ne) std::memcpy(s.h_ev + eo, R.events(), sizeof(abea_event_t) * R.ne);
+    if (R.nk) std::memcpy(s.h_rk + ko, R.ranks(), sizeof(uint32_t) * R.nk);
+    eo += R.ne;
+    ko += R.nk;
+    s.h_eo[r + 1] = eo;
+    s.h_ko[r + 1] = ko;
+    s.h_sc[r] = R.scale;
+    s.h_sh[r] = R.shift;
+  }
+  int rc;
+  if ((rc = plan_batch(ctx, s.work, n, s.h_eo, s.h_ko, eo + ko))) return rc;
+  if ((rc = ensure_work(ctx, s.work))) return rc;
+  hipStream_t st = s.st;
+  s.work.last_stream = st;
+  if (eo) HIP_TRY(ctx, hipMemcpyAsync(s.d_ev.p, s.h_ev, sizeof(abea_event_t) * eo, hipMemcpyHostToDevice, st));
+  if (ko) HIP_TRY(ctx, hipMemcpyAsync(s.d_rk.p, s.h_rk, sizeof(uint32_t) * ko, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(s.d_sc.p, s.h_sc, sizeof(float) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(s.d_sh.p, s.h_sh, sizeof(float) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(s.work.reads.p, s.work.h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipEventRecord(s.work.staging_done, st));
+  s.work.staging_pending = true;
+  DevIO io;
+  io.events = (const float *)s.d_ev.p;
+  io.ranks = (const uint32_t *)s.d_rk.p;
+  io.scale = (const float *)s.d_sc.p;
+  io.shift = (const float *)s.d_sh.p;
+  io.pairs = (int2 *)s.d_pairs.p;
+  io.pair_offset = (uint64_t *)s.d_po.p;
+  io.ll = (float *)s.d_ll.p;
+  io.status = (int32_t *)s.d_st.p;
+  io.cells = (uint64_t *)s.d_cells.p;
+  if ((rc = enqueue_kernels(ctx, s.work, io, st, false))) return rc;
+  HIP_TRY(ctx, hipMemcpyAsync(s.h_po, s.d_po.p, sizeof(uint64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(s.h_ll, s.d_ll.p, sizeof(float) * n, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(s.h_st, s.d_st.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(s.h_cells, s.d_cells.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipEventRecord(s.ev_meta, st));
+  /* the inputs are staged: recycle the host copies */
+  for (SrvRead &R : s.reads) S->pool.put(std::move(R.buf), R.buf_cls);
+  s.state = RUNNING;
+  return ABEA_OK;
+}
+
+/* Advance a slot whose work may have finished; true if anything changed. */
+bool slot_poll(abea_server *S, Slot &s, int *rc) {
+  abea_ctx *ctx = S->ctx;
+  *rc = ABEA_OK;
+  if (s.state == RUNNING) {
+    hipError_t q = hipEventQuery(s.ev_meta);
+    if (q == hipErrorNotReady) return false;
+    if (q != hipSuccess) {
+      *rc = fail(ctx, ABEA_E_HIP, "serving: %s", hipGetErrorString(q));
+      return false;
+    }
+    const int n = (int)s.reads.size();
+    const uint64_t total = s.h_po[n];
+    if (total) {
+      hipError_t e = hipMemcpyAsync(s.h_pairs, s.d_pairs.p, sizeof(abea_pair_t) * total, hipMemcpyDeviceToHost, s.st);
+      if (e != hipSuccess) {
+        *rc = fail(ctx, ABEA_E_HIP, "serving: %s", hipGetErrorString(e));
+        return false;
+      }
+    }
+    hipError_t e = hipEventRecord(s.ev_done, s.st);
+    if (e != hipSuccess) {
+      *rc = fail(ctx, ABEA_E_HIP, "serving: %s", hipGetErrorString(e));
+      return false;
+    }
+    s.state = COPYING;
+    return true;
+  }
+  if (s.state == COPYING) {
+    hipError_t q = hipEventQuery(s.ev_done);
+    if (q == hipErrorNotReady) return false;
+    if (q != hipSuccess) {
+      *rc = fail(ctx, ABEA_E_HIP, "serving: %s", hipGetErrorString(q));
+      return false;
+    }
+    const int64_t t = now_ns();
+    const int n = (int)s.reads.size();
+    const uint64_t total = s.h_po[n];
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      /* room in the pair ring (grows by doubling, keeping the queued pairs
+       * in order) */
+      uint64_t cap = S->ring.size();
+      if (S->ring_tail - S->ring_head + total > cap) {
+        uint64_t nc = std::max<uint64_t>(cap, 1u << 20);
+        while (S->ring_tail - S->ring_head + total > nc) nc *= 2;
+        std::vector<abea_pair_t> nr(nc);
+        for (uint64_t q = S->ring_head; q < S->ring_tail; ++q) nr[q & (nc - 1)] = S->ring[q & (cap - 1)];
+        S->ring.swap(nr);
+        cap = nc;
+      }
+      const uint64_t at = S->ring_tail & (cap - 1);
+      const uint64_t first = std::min<uint64_t>(total, cap - at);
+      if (first) std::memcpy(S->ring.data() + at, s.h_pairs, sizeof(abea_pair_t) * first);
+      if (total > first) std::memcpy(S->ring.data(), s.h_pairs + first, sizeof(abea_pair_t) * (total - first));
+      for (int r = 0; r < n; ++r) {
+        Done d;
+        const SrvRead &R = s.reads[r];
+        d.c.tag = R.tag;
+        d.c.status = s.h_st[r];
+        d.c.log_likelihood = s.h_ll[r];
+        d.c.cells = s.h_cells[r];
+        d.c.n_pairs = s.h_po[r + 1] - s.h_po[r];
+        d.c.pair_offset = 0;
+        d.c.t_arrival_ns = R.t_arrival;
+        d.c.t_admit_ns = R.t_admit;
+        d.c.t_done_ns = t;
+        d.pos = S->ring_tail + s.h_po[r];
+        S->done.push_back(d);
+      }
+      S->ring_tail += total;
+      S->inflight_trace -= s.trace_bytes;
+      S->inflight_reads -= (uint64_t)n;
+      S->stats.completed += (uint64_t)n;
+    }
+    S->cv_done.notify_all();
+    s.reads.clear();
+    s.trace_bytes = 0;
+    s.state = FREE;
+    return true;
+  }
+  return false;
+}
+
+/* Take pending reads for a free slot: from the length class whose first
+ * read has waited longest, in arrival order, within the slot's capacity and
+ * the trace budget (a read that alone exceeds the budget was refused at
+ * submission). */
+bool admit(abea_server *S, Slot &s) {
+  const abea_server_config_t &c = S->cfg;
+  std::lock_guard<std::mutex> lk(S->mu);
+  int cls = -1;
+  for (int q = 0; q < N_CLASSES; ++q)
+    if (!S->pending[q].empty() && (cls < 0 || S->pending[q].front().t_arrival < S->pending[cls].front().t_arrival))
+      cls = q;
+  if (cls < 0) return false;
+  std::deque<SrvRead> &P = S->pending[cls];
+  uint64_t ne = 0, nk = 0, tb = 0;
+  const int64_t t = now_ns();
+  while (!P.empty() && (int64_t)s.reads.size() < c.max_batch_reads) {
+    SrvRead &R = P.front();
+    if (ne + R.ne > c.max_batch_events || nk + R.nk > c.max_batch_kmers) break;
+    if (c.trace_budget_bytes && S->inflight_trace + tb + R.trace_bytes > c.trace_budget_bytes) break;
+    ne += R.ne;
+    nk += R.nk;
+    tb += R.trace_bytes;
+    R.t_admit = t;
+    s.reads.push_back(std::move(R));
+    P.pop_front();
+  }
+  if (s.reads.empty()) return false;
+  S->n_pending -= s.reads.size();
+  s.trace_bytes = tb;
+  S->inflight_trace += tb;
+  S->inflight_reads += s.reads.size();
+  S->stats.max_inflight_trace_bytes = std::max(S->stats.max_inflight_trace_bytes, S->inflight_trace);
+  S->stats.max_inflight_reads = std::max(S->stats.max_inflight_reads, S->inflight_reads);
+  S->stats.micro_batches += 1;
+  S->stats.admitted += s.reads.size();
+  return true;
+}
+
+void worker_main(abea_server *S) {
+  (void)hipSetDevice(S->ctx->device);
+  for (;;) {
+    bool progress = false;
+    int rc = ABEA_OK;
+    for (Slot &s : S->slots) {
+      if (slot_poll(S, s, &rc)) progress = true;
+      if (rc) break;
+    }
+    if (!rc) {
+      bool stopping;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        stopping = S->stop;
+      }
+      for (Slot &s : S->slots) {
+        if (stopping || s.state != FREE) continue;
+        if (!admit(S, s)) break;
+        if ((rc = slot_launch(S, s))) break;
+        progress = true;
+      }
+    }
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (rc) {
+      S->error = rc;
+      S->err = S->ctx->err;
+      S->cv_done.notify_all();
+      return;
+    }
+    bool idle = true;
+    for (Slot &s : S->slots) idle = idle && s.state == FREE;
+    if (S->stop && idle) return;
+    if (!progress) {
+      /* device work in flight: poll again soon; idle: sleep until a read
+       * arrives */
+      if (idle && S->n_pending == 0)
+        S->cv_work.wait_for(lk, std::chrono::milliseconds(10));
+      else
+        S->cv_work.wait_for(lk, std::chrono::microseconds(20));
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t abea_server_now_ns(void) { return now_ns(); }
+
+int abea_server_create(abea_ctx *ctx, const abea_server_config_t *cfg, abea_server **out) {
+  if (!ctx) return ABEA_E_INVAL;
+  if (!cfg || !out) return fail(ctx, ABEA_E_INVAL, "null argument");
+  *out = nullptr;
+  if (cfg->slots < 1 || cfg->slots > 16 || cfg->max_batch_reads < 1 || cfg->max_batch_events < 1 ||
+      cfg->max_batch_kmers < 1)
+    return fail(ctx, ABEA_E_INVAL, "serving config out of range");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  abea_server *S = new (std::nothrow) abea_server();
+  if (!S) return ABEA_E_NOMEM;
+  S->ctx = ctx;
+  S->cfg = *cfg;
+  S->G = bands_per_group(ctx->cpl);
+  S->slots.resize(cfg->slots);
+  int rc = ABEA_OK;
+  for (Slot &s : S->slots)
+    if ((rc = slot_init(S, s))) break;
+  if (rc) {
+    for (Slot &s : S->slots) slot_free(s);
+    delete S;
+    return rc;
+  }
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return ABEA_OK;
+}
+
+int abea_server_submit(abea_server *S, const abea_batch_t *b, const uint64_t *tags, const int64_t *arrival_ns) {
+  if (!S) return ABEA_E_INVAL;
+  abea_ctx *ctx = S->ctx;
+  if (!b || !tags) return fail(ctx, ABEA_E_INVAL, "null batch or tags");
+  if (b->n_reads < 0 || !b->event_offset || !b->kmer_offset) return fail(ctx, ABEA_E_INVAL, "bad batch");
+  const int n = b->n_reads;
+  if (n == 0) return ABEA_OK;
+  if (!b->scale || !b->shift) return fail(ctx, ABEA_E_INVAL, "null scale/shift");
+  const uint64_t *eo = b->event_offset, *ko = b->kmer_offset;
+  if (eo[0] != 0 || ko[0] != 0) return fail(ctx, ABEA_E_INVAL, "offsets must start at 0");
+  if (eo[n] > 0 && !b->events) return fail(ctx, ABEA_E_INVAL, "null events");
+  if (ko[n] > 0 && !b->kmer_rank) return fail(ctx, ABEA_E_INVAL, "null k-mer ranks");
+  const abea_server_config_t &c = S->cfg;
+  for (int r = 0; r < n; ++r) {
+    if (eo[r + 1] < eo[r] || ko[r + 1] < ko[r]) return fail(ctx, ABEA_E_INVAL, "offsets decrease at read %d", r);
+    const uint64_t ne = eo[r + 1] - eo[r], nk = ko[r + 1] - ko[r];
+    if (ne > c.max_batch_events || nk > c.max_batch_kmers || ne > 0x3fffffffull || nk > 0x3fffffffull)
+      return fail(ctx, ABEA_E_CAPACITY, "read %d (%llu events, %llu k-mers) exceeds a micro-batch", r,
+                  (unsigned long long)ne, (unsigned long long)nk);
+    if (c.trace_budget_bytes && trace_bytes_of(S->G, ne, nk) > c.trace_budget_bytes)
+      return fail(ctx, ABEA_E_CAPACITY, "read %d needs %llu trace bytes, over the budget", r,
+                  (unsigned long long)trace_bytes_of(S->G, ne, nk));
+  }
+  const int64_t t = now_ns();
+  std::vector<SrvRead> rs(n);
+  for (int r = 0; r < n; ++r) {
+    SrvRead &R = rs[r];
+    const uint64_t ne = eo[r + 1] - eo[r], nk = ko[r + 1] - ko[r];
+    R.tag = tags[r];
+    R.t_arrival = arrival_ns ? arrival_ns[r] : t;
+    R.ne = ne;
+    R.nk = nk;
+    R.buf = S->pool.get(ne * sizeof(abea_event_t) + nk * sizeof(uint32_t), &R.buf_cls);
+    if (!R.buf) return fail(ctx, ABEA_E_NOMEM, "host buffer for read %d", r);
+    if (ne) std::memcpy(R.buf.get(), b->events + eo[r], sizeof(abea_event_t) * ne);
+    if (nk) std::memcpy(R.buf.get() + ne * sizeof(abea_event_t), b->kmer_rank + ko[r], sizeof(uint32_t) * nk);
+    R.scale = b->scale[r];
+    R.shift = b->shift[r];
+    R.trace_bytes = trace_bytes_of(S->G, ne, nk);
+  }
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->error) return fail(ctx, S->error, "%s", S->err.c_str());
+    if (S->stop) return fail(ctx, ABEA_E_INVAL, "server is stopping");
+    for (SrvRead &R : rs) {
+      const int q = length_class(R.ne + R.nk);
+      S->pending[q].push_back(std::move(R));
+    }
+    S->n_pending += (uint64_t)n;
+    S->stats.submitted += (uint64_t)n;
+  }
+  S->cv_work.notify_one();
+  return ABEA_OK;
+}
+
+int abea_server_poll(abea_server *S, abea_completion_t *out, int max_out, abea_pair_t *pairs, uint64_t pair_capacity,
+                     int32_t timeout_us, int *n_out) {
+  if (!S) return ABEA_E_INVAL;
+  abea_ctx *ctx = S->ctx;
+  if (!n_out || (max_out > 0 && !out)) return fail(ctx, ABEA_E_INVAL, "null output");
+  *n_out = 0;
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (S->done.empty() && timeout_us > 0 && !S->error)
+    S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us),
+                        [&] { return !S->done.empty() || S->error; });
+  if (S->done.empty() && S->error) return fail(ctx, S->error, "%s", S->err.c_str());
+  uint64_t used = 0;
+  int k = 0;
+  while (k < max_out && !S->done.empty()) {
+    Done &d = S->done.front();
+    const uint64_t np = d.c.n_pairs;
+    if (used + np > pair_capacity) {
+      if (k == 0) {
+        *n_out = 0;
+        return fail(ctx, ABEA_E_CAPACITY, "next result has %llu pairs; pair capacity %llu",
+                    (unsigned long long)np, (unsigned long long)pair_capacity);
+      }
+      break;
+    }
+    const uint64_t cap = S->ring.size();
+    for (uint64_t q = 0; q < np;) { /* at most two pieces around the wrap */
+      const uint64_t at = (d.pos + q) & (cap - 1);
+      const uint64_t len = std::min<uint64_t>(np - q, cap - at);
+      std::memcpy(pairs + used + q, S->ring.data() + at, sizeof(abea_pair_t) * len);
+      q += len;
+    }
+    out[k] = d.c;
+    out[k].pair_offset = used;
+    used += np;
+    ++k;
+    S->ring_head = d.pos + np;
+    S->done.pop_front();
+  }
+  *n_out = k;
+  return ABEA_OK;
+}
+
+int abea_server_stats(abea_server *S, abea_server_stats_t *st) {
+  if (!S || !st) return ABEA_E_INVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  *st = S->stats;
+  st->pending = S->n_pending;
+  st->inflight_reads = S->inflight_reads;
+  st->inflight_trace_bytes = S->inflight_trace;
+  st->error = S->error;
+  return ABEA_OK;
+}
+
+void abea_server_destroy(abea_server *S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    for (auto &P : S->pending) P.clear();
+    S->n_pending = 0;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  (void)hipSetDevice(S->ctx->device);
+  for (Slot &s : S->slots) slot_free(s);
+  delete S;
+}
+
+}  // extern "C"

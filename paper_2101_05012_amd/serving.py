@@ -1,0 +1,104 @@
+"""Simulated sequencer driving the library's serving loop.
+
+Reads of a host batch arrive at given times (seconds from the start, sorted,
+read i at arrivals[i]), replayed ``compression`` times faster than real time.
+A submitter thread hands every read to the server at its arrival instant,
+stamped with that instant (so queueing in Python counts as latency).  The
+calling thread collects the results.  Latency = result in host memory -
+arrival.  All alignment runs in libabea.so; this module only paces
+submissions and does the book-keeping.
+"""
+
+from __future__ import annotations
+
+import threading
+import time
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import abea
+
+
+def run(server: abea.Server, batch, arrivals_s: np.ndarray, compression: float = 1.0,
+        keep_pairs: bool = False, tick_s: float = 0.0005, timeout_s: float = 600.0) -> Dict:
+    n = batch.n_reads
+    arrivals_s = np.asarray(arrivals_s, np.float64)
+    assert arrivals_s.shape[0] == n and np.all(np.diff(arrivals_s) >= 0)
+    t0 = abea.now_ns() + 2_000_000  # start 2 ms from now
+    target = t0 + (arrivals_s / compression * 1e9).astype(np.int64)
+    err = []
+
+    def submitter():
+        try:
+            i = 0
+            while i < n:
+                now = abea.now_ns()
+                if target[i] > now:
+                    wait = (target[i] - now) / 1e9
+                    time.sleep(min(wait, tick_s) if wait > tick_s else max(wait, 0.0))
+                    continue
+                j = int(np.searchsorted(target, now, side="right"))
+                j = max(j, i + 1)
+                server.submit(batch, i, j, np.arange(i, j, dtype=np.uint64), target[i:j])
+                i = j
+        except Exception as e:  # surfaced by the collector
+            err.append(e)
+
+    th = threading.Thread(target=submitter, daemon=True)
+    th.start()
+    comps = []
+    pairs: Optional[dict] = {} if keep_pairs else None
+    got = 0
+    deadline = time.monotonic() + timeout_s
+    while got < n:
+        if err:
+            raise err[0]
+        if time.monotonic() > deadline:
+            raise TimeoutError(f"serving: {got} of {n} reads finished")
+        c, p = server.poll(max_out=4096, timeout_us=2000, want_pairs=keep_pairs)
+        if c.shape[0] == 0:
+            continue
+        comps.append(c)
+        got += c.shape[0]
+        if keep_pairs:
+            for rec in c:
+                o = int(rec["pair_offset"])
+                pairs[int(rec["tag"])] = p[o : o + int(rec["n_pairs"])]
+    th.join()
+    if err:
+        raise err[0]
+    comp = np.concatenate(comps)
+    comp = comp[np.argsort(comp["tag"])]
+    return {"completions": comp, "pairs": pairs, "t0": t0, "stats": server.stats()}
+
+
+def summarize(res: Dict, batch, compression: float, arrivals_s: np.ndarray) -> Dict:
+    c = res["completions"]
+    n = c.shape[0]
+    lat_ms = (c["t_done_ns"] - c["t_arrival_ns"]) / 1e6
+    wait_ms = (c["t_admit_ns"] - c["t_arrival_ns"]) / 1e6
+    span_s = (c["t_done_ns"].max() - c["t_arrival_ns"].min()) / 1e9
+    cells = int(c["cells"].sum())
+    L = np.diff(batch.kmer_offset.astype(np.int64))
+    long = L > np.median(L)
+    bases = int(L.sum())
+    offered = n / (arrivals_s[-1] / compression) if arrivals_s[-1] > 0 else float("inf")
+    pct = lambda a, q: round(float(np.percentile(a, q)), 3) if a.size else None  # noqa: E731
+    st = res["stats"]
+    return {
+        "compression": compression,
+        "reads": n,
+        "offered_reads_per_s": round(offered, 1),
+        "offered_kbases_per_s": round(offered * bases / n / 1e3, 1),
+        "reads_per_s": round(n / span_s, 1),
+        "gcups": round(cells / span_s / 1e9, 3),
+        "latency_ms": {"p50": pct(lat_ms, 50), "p99": pct(lat_ms, 99), "max": round(float(lat_ms.max()), 3)},
+        "latency_ms_reads_below_median_length": {"p50": pct(lat_ms[~long], 50), "p99": pct(lat_ms[~long], 99)},
+        "latency_ms_reads_above_median_length": {"p50": pct(lat_ms[long], 50), "p99": pct(lat_ms[long], 99)},
+        "admission_wait_ms": {"p50": pct(wait_ms, 50), "p99": pct(wait_ms, 99)},
+        "micro_batches": st["micro_batches"],
+        "max_inflight_reads": st["max_inflight_reads"],
+        "max_inflight_trace_mb": round(st["max_inflight_trace_bytes"] / 1e6, 1),
+        "reads_ok": int((c["status"] == 0).sum()),
+    }
