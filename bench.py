@@ -73,10 +73,11 @@ WORKLOADS = {
 # channels at 400 bases/s each
 SERVING_LEVELS = [(1, 300), (10, 1000), (100, 4000), (1000, 20000), (3000, 30000), (10000, 30000)]
 
-# HBM traffic of one band-kernel launch on the default workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a copy-kernel
-# calibration; None until measured for the current kernel.
-BAND_TRAFFIC_BYTES = None
+# HBM bytes of one fused-kernel launch (k_align), from two rocprofv3 --pmc
+# runs (FETCH_SIZE x 1.99991, WRITE_SIZE x 1.0: the factors a 1 GiB device
+# copy needs to read its known size), by workload; a workload without a
+# measurement of the current kernel reports null.
+ALIGN_TRAFFIC_BYTES = {"plain-4000-lognormal5kb": 6.829e9}
 
 
 def log(*a):
@@ -111,7 +112,7 @@ def sample_reads(batch, W, target_cells: float):
     return list(range(0, n, stride))
 
 
-def roofline(cells, kernel_ms, kernel_name):
+def roofline(cells, kernel_ms, kernel_name, workload=None):
     achieved = cells * OPS_PER_CELL / (kernel_ms / 1e3) / 1e12
     return {
         "bound": "alu",
@@ -120,7 +121,7 @@ def roofline(cells, kernel_ms, kernel_name):
         "peak": round(VALU_PEAK_TOPS, 2),
         "unit": "TFLOP/s",
         "frac": round(achieved / VALU_PEAK_TOPS, 4),
-        "traffic": BAND_TRAFFIC_BYTES if kernel_name in ("k_band", "k_align") else None,
+        "traffic": ALIGN_TRAFFIC_BYTES.get(workload) if kernel_name == "k_align" else None,
     }
 
 
@@ -229,7 +230,7 @@ def bench_plain(args, wl):
             "compact": round(float(kms[3]), 4),
         },
         "reads_ok": int((status == 0).sum()),
-        "roofline": roofline(cells_per_step, float(kms[1]), kname),
+        "roofline": roofline(cells_per_step, float(kms[1]), kname, args.workload),
     })
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
