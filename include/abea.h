@@ -257,6 +257,8 @@ typedef struct {
   uint64_t max_batch_events;  /* events per micro-batch (also the largest read) */
   uint64_t max_batch_kmers;   /* k-mers per micro-batch (also the largest read) */
   uint64_t trace_budget_bytes;/* traceback bytes of all reads on the device (0 = none) */
+  uint64_t host_staging_bytes;/* pinned host arena for queued reads (0 = 1 GiB); reads beyond
+                                 it are queued in pageable memory and staged at launch */
 } abea_server_config_t;
 
 /* One finished read.  Times are abea_server_now_ns() values: arrival (given

@@ -135,6 +135,7 @@ class abea_server_config_t(ctypes.Structure):
         ("max_batch_events", ctypes.c_uint64),
         ("max_batch_kmers", ctypes.c_uint64),
         ("trace_budget_bytes", ctypes.c_uint64),
+        ("host_staging_bytes", ctypes.c_uint64),
     ]
 
 
@@ -515,10 +516,11 @@ class Server:
     """Continuous-batching serving loop of the library (abea_server_*)."""
 
     def __init__(self, aligner: Aligner, slots: int = 4, max_batch_reads: int = 1024,
-                 max_batch_events: int = 1 << 24, max_batch_kmers: int = 1 << 23, trace_budget_bytes: int = 0):
+                 max_batch_events: int = 1 << 24, max_batch_kmers: int = 1 << 23, trace_budget_bytes: int = 0,
+                 host_staging_bytes: int = 0):
         self.aligner = aligner
         cfg = abea_server_config_t(int(slots), int(max_batch_reads), int(max_batch_events), int(max_batch_kmers),
-                                   int(trace_budget_bytes))
+                                   int(trace_budget_bytes), int(host_staging_bytes))
         h = ctypes.c_void_p()
         aligner._check(lib().abea_server_create(aligner.handle, ctypes.byref(cfg), ctypes.byref(h)),
                        "abea_server_create")

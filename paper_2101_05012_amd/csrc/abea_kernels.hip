@@ -584,9 +584,13 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
   bool ok = true;
 
   for (;;) {
-    /* the cells of the current group: one dependent step per cell */
+    /* the cells of the current group: one dependent step per cell; the
+     * trace words of the lane the walk is in stay in SGPRs until it moves
+     * to another lane (every CPL k-mers) */
     const int lower = gcur << LG;
     int t = e + k;
+    int ln_cur = -1;
+    uint32_t wx = 0, wy = 0;
     for (;;) {
       e = __builtin_amdgcn_readfirstlane(e);
       k = __builtin_amdgcn_readfirstlane(k);
@@ -595,12 +599,18 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
       PK = writelane(k, qs, PK);
       ++qs;
       const int sl = k & (N - 1);
+      const int ln = sl >> LC;
+      if (ln != ln_cur) {
+        wx = rlane_u(T.x, ln);
+        wy = rlane_u(T.y, ln);
+        ln_cur = ln;
+      }
       const int bit = 31 - (((t & (G - 1)) << LC) + (sl & (CPL - 1)));
-      const int ub = (int)((rlane_u(T.x, sl >> LC) >> bit) & 1u);
-      const int lb = (int)((rlane_u(T.y, sl >> LC) >> bit) & 1u);
-      /* diagonal (0,0): e-1, k-1; up (1,0): e-1; left (x,1): k-1 */
-      e -= 1 - lb;
-      k -= 1 - (ub & (lb ^ 1));
+      /* code = up bit + 2 * left bit: 0 diagonal (e-1, k-1), 1 up (e-1),
+       * 2 or 3 left (k-1) */
+      const uint32_t code = ((wx >> bit) & 1u) | (((wy >> bit) & 1u) << 1);
+      e -= (int)((code >> 1) ^ 1u);
+      k -= (int)((0xDu >> code) & 1u);
       t = e + k;
       /* stop when 64 cells are gathered, or the walk left the table or the
        * group (each term < 0 means stop) */

@@ -61,9 +61,12 @@ int length_class(uint64_t len) {
   return c;
 }
 
-/* Host buffers recycled by size class (powers of two, at least 4 KB), so
- * that a queued read does not allocate and fault in fresh pages; at most
- * `keep` bytes stay pooled. */
+/* Host buffers of queued reads, by size class (powers of two, at least
+ * 4 KB).  Buffers are carved from one pinned arena allocated with the server
+ * and recycled per class, so a queued read is copied once, into pinned
+ * memory, and goes to the device by DMA from there; when the arena is used
+ * up a read gets a pageable buffer, copied through the slot's pinned staging
+ * at launch. */
 class BufPool {
  public:
   static int cls(size_t n) {
@@ -71,63 +74,106 @@ class BufPool {
     while (c < 47 && ((size_t)1 << c) < n) ++c;
     return c;
   }
-  std::unique_ptr<uint8_t[]> get(size_t n, int *c_out) {
+  int init(size_t bytes) {
+    size_ = bytes;
+    if (bytes == 0) return ABEA_OK;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      size_ = 0;
+      return ABEA_E_NOMEM;
+    }
+    arena_ = (uint8_t *)p;
+    return ABEA_OK;
+  }
+  uint8_t *get(size_t n, int *c_out, bool *pinned) {
     const int c = cls(n);
+    const size_t sz = (size_t)1 << c;
     *c_out = c;
     {
       std::lock_guard<std::mutex> lk(mu_);
       if (!free_[c].empty()) {
-        std::unique_ptr<uint8_t[]> p = std::move(free_[c].back());
+        uint8_t *p = free_[c].back();
         free_[c].pop_back();
-        pooled_ -= (size_t)1 << c;
+        *pinned = true;
+        return p;
+      }
+      if (bump_ + sz <= size_) {
+        uint8_t *p = arena_ + bump_;
+        bump_ += sz;
+        *pinned = true;
         return p;
       }
     }
-    return std::unique_ptr<uint8_t[]>(new (std::nothrow) uint8_t[(size_t)1 << c]);
+    *pinned = false;
+    return new (std::nothrow) uint8_t[sz];
   }
-  void put(std::unique_ptr<uint8_t[]> p, int c) {
+  void put(uint8_t *p, int c, bool pinned) {
     if (!p) return;
+    if (!pinned) {
+      delete[] p;
+      return;
+    }
     std::lock_guard<std::mutex> lk(mu_);
-    if (pooled_ + ((size_t)1 << c) > keep) return; /* freed here */
-    pooled_ += (size_t)1 << c;
-    free_[c].push_back(std::move(p));
+    free_[c].push_back(p);
   }
-  size_t keep = (size_t)2 << 30;
+  ~BufPool() {
+    if (arena_) (void)hipHostFree(arena_);
+  }
 
  private:
   std::mutex mu_;
-  std::vector<std::unique_ptr<uint8_t[]>> free_[48];
-  size_t pooled_ = 0;
+  std::vector<uint8_t *> free_[48];
+  uint8_t *arena_ = nullptr;
+  size_t size_ = 0, bump_ = 0;
 };
 
-/* A queued read: events then k-mer ranks in one pooled buffer. */
+/* A pointer that moves (the source forgets it); returned to the pool by
+ * hand. */
+struct Owned {
+  uint8_t *p = nullptr;
+  Owned() = default;
+  Owned(Owned &&o) noexcept : p(o.p) { o.p = nullptr; }
+  Owned &operator=(Owned &&o) noexcept {
+    p = o.p;
+    o.p = nullptr;
+    return *this;
+  }
+  Owned(const Owned &) = delete;
+  Owned &operator=(const Owned &) = delete;
+};
+
+/* A queued read: events then k-mer ranks in one pooled pinned buffer. */
 struct SrvRead {
   uint64_t tag = 0;
   int64_t t_arrival = 0;
   int64_t t_admit = 0;
-  std::unique_ptr<uint8_t[]> buf;
+  Owned buf;
   int buf_cls = 0;
+  bool pinned = false;
   uint64_t ne = 0, nk = 0;
   float scale = 1.f, shift = 0.f;
   uint64_t trace_bytes = 0;
-  const abea_event_t *events() const { return reinterpret_cast<const abea_event_t *>(buf.get()); }
-  const uint32_t *ranks() const { return reinterpret_cast<const uint32_t *>(buf.get() + ne * sizeof(abea_event_t)); }
+  const abea_event_t *events() const { return reinterpret_cast<const abea_event_t *>(buf.p); }
+  const uint32_t *ranks() const { return reinterpret_cast<const uint32_t *>(buf.p + ne * sizeof(abea_event_t)); }
 };
 
-/* A finished read; its pairs are at [pos, pos + c.n_pairs) of the server's
- * pair ring (results leave in the order they are queued). */
+/* A finished read; its pairs wait in its slot's pinned result buffer, which
+ * the slot keeps until every result of its micro-batch has been polled. */
 struct Done {
   abea_completion_t c;
-  uint64_t pos;
+  int slot;
+  uint64_t off;
 };
 
-enum SlotState { FREE = 0, RUNNING = 1, COPYING = 2 };
+enum SlotState { FREE = 0, RUNNING = 1, COPYING = 2, HARVESTED = 3 };
 
 struct Slot {
   hipStream_t st = nullptr;
   hipEvent_t ev_meta = nullptr, ev_done = nullptr;
   Work work;
-  /* pinned staging of inputs and results */
+  /* pinned staging of reads whose buffer is not pinned, of the small
+   * inputs and of the results */
   abea_event_t *h_ev = nullptr;
   uint32_t *h_rk = nullptr;
   float *h_sc = nullptr, *h_sh = nullptr;
@@ -140,7 +186,8 @@ struct Slot {
   DevBuf d_ev, d_rk, d_sc, d_sh, d_pairs, d_po, d_ll, d_st, d_cells;
   std::vector<SrvRead> reads;
   uint64_t trace_bytes = 0;
-  int state = FREE;
+  int state = FREE;         /* changed by the worker; HARVESTED -> FREE under the lock */
+  uint64_t outstanding = 0; /* harvested results not yet polled (under the lock) */
 };
 
 }  // namespace
@@ -151,13 +198,11 @@ struct abea_server {
   int G = 16;
   std::vector<Slot> slots;
   std::mutex mu;
-  std::condition_variable cv_work; /* new reads or stop */
+  std::condition_variable cv_work; /* new reads, polled results or stop */
   std::condition_variable cv_done; /* new completions */
   std::deque<SrvRead> pending[N_CLASSES]; /* arrival order within a class */
   uint64_t n_pending = 0;
   std::deque<Done> done;
-  std::vector<abea_pair_t> ring; /* pairs of the queued results: power-of-two ring */
-  uint64_t ring_head = 0, ring_tail = 0;
   BufPool pool;
   std::thread worker;
   bool stop = false;
@@ -177,8 +222,18 @@ uint64_t trace_bytes_of(int G, uint64_t ne, uint64_t nk) {
   return ((comp + G - 1) / G) * 64u * sizeof(uint2);
 }
 
-void slot_free(Slot &s) {
+void release_read(abea_server *S, SrvRead &R) {
+  S->pool.put(R.buf.p, R.buf_cls, R.pinned);
+  R.buf.p = nullptr;
+}
+
+void release_reads(abea_server *S, std::vector<SrvRead> &reads) {
+  for (SrvRead &R : reads) release_read(S, R);
+}
+
+void slot_free(abea_server *S, Slot &s) {
   if (s.st) (void)hipStreamSynchronize(s.st);
+  release_reads(S, s.reads);
   work_free(s.work);
   DevBuf *bufs[] = {&s.d_ev, &s.d_rk, &s.d_sc, &s.d_sh, &s.d_pairs, &s.d_po, &s.d_ll, &s.d_st, &s.d_cells};
   for (DevBuf *b : bufs) free_buf(*b);
@@ -198,7 +253,7 @@ int host_alloc(abea_ctx *ctx, T **p, uint64_t n) {
 }
 
 /* Buffers of one slot sized for the configured micro-batch capacity, so that
- * admission never allocates. */
+ * admission never allocates device memory. */
 int slot_init(abea_server *S, Slot &s) {
   abea_ctx *ctx = S->ctx;
   const abea_server_config_t &c = S->cfg;
@@ -248,16 +303,17 @@ int slot_init(abea_server *S, Slot &s) {
   return ABEA_OK;
 }
 
-/* Stage a micro-batch and enqueue it on the slot's stream. */
+/* Enqueue a micro-batch on the slot's stream: the reads' pinned buffers go
+ * to the device by DMA, then the kernels run, then the small per-read
+ * results come back. */
 int slot_launch(abea_server *S, Slot &s) {
   abea_ctx *ctx = S->ctx;
+  hipStream_t st = s.st;
   const int n = (int)s.reads.size();
   uint64_t eo = 0, ko = 0;
   s.h_eo[0] = s.h_ko[0] = 0;
   for (int r = 0; r < n; ++r) {
     const SrvRead &R = s.reads[r];
-    if (R.ne) std::memcpy(s.h_ev + eo, R.events(), sizeof(abea_event_t) * R.ne);
-    if (R.nk) std::memcpy(s.h_rk + ko, R.ranks(), sizeof(uint32_t) * R.nk);
     eo += R.ne;
     ko += R.nk;
     s.h_eo[r + 1] = eo;
@@ -268,10 +324,26 @@ int slot_launch(abea_server *S, Slot &s) {
   int rc;
   if ((rc = plan_batch(ctx, s.work, n, s.h_eo, s.h_ko, eo + ko))) return rc;
   if ((rc = ensure_work(ctx, s.work))) return rc;
-  hipStream_t st = s.st;
   s.work.last_stream = st;
-  if (eo) HIP_TRY(ctx, hipMemcpyAsync(s.d_ev.p, s.h_ev, sizeof(abea_event_t) * eo, hipMemcpyHostToDevice, st));
-  if (ko) HIP_TRY(ctx, hipMemcpyAsync(s.d_rk.p, s.h_rk, sizeof(uint32_t) * ko, hipMemcpyHostToDevice, st));
+  /* a read in a pinned buffer goes to the device by DMA from there; one in a
+   * pageable buffer is copied into the slot's pinned staging first */
+  for (int r = 0; r < n; ++r) {
+    const SrvRead &R = s.reads[r];
+    const abea_event_t *ev = R.events();
+    const uint32_t *rk = R.ranks();
+    if (!R.pinned) {
+      if (R.ne) std::memcpy(s.h_ev + s.h_eo[r], ev, sizeof(abea_event_t) * R.ne);
+      if (R.nk) std::memcpy(s.h_rk + s.h_ko[r], rk, sizeof(uint32_t) * R.nk);
+      ev = s.h_ev + s.h_eo[r];
+      rk = s.h_rk + s.h_ko[r];
+    }
+    if (R.ne)
+      HIP_TRY(ctx, hipMemcpyAsync((abea_event_t *)s.d_ev.p + s.h_eo[r], ev, sizeof(abea_event_t) * R.ne,
+                                  hipMemcpyHostToDevice, st));
+    if (R.nk)
+      HIP_TRY(ctx, hipMemcpyAsync((uint32_t *)s.d_rk.p + s.h_ko[r], rk, sizeof(uint32_t) * R.nk,
+                                  hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(ctx, hipMemcpyAsync(s.d_sc.p, s.h_sc, sizeof(float) * n, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(s.d_sh.p, s.h_sh, sizeof(float) * n, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(s.work.reads.p, s.work.h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice, st));
@@ -293,15 +365,14 @@ int slot_launch(abea_server *S, Slot &s) {
   HIP_TRY(ctx, hipMemcpyAsync(s.h_st, s.d_st.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipMemcpyAsync(s.h_cells, s.d_cells.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipEventRecord(s.ev_meta, st));
-  /* the inputs are staged: recycle the host copies */
-  for (SrvRead &R : s.reads) S->pool.put(std::move(R.buf), R.buf_cls);
   s.state = RUNNING;
   return ABEA_OK;
 }
 
 /* Advance a slot whose work may have finished; true if anything changed. */
-bool slot_poll(abea_server *S, Slot &s, int *rc) {
+bool slot_poll(abea_server *S, int si, int *rc) {
   abea_ctx *ctx = S->ctx;
+  Slot &s = S->slots[si];
   *rc = ABEA_OK;
   if (s.state == RUNNING) {
     hipError_t q = hipEventQuery(s.ev_meta);
@@ -310,6 +381,8 @@ bool slot_poll(abea_server *S, Slot &s, int *rc) {
       *rc = fail(ctx, ABEA_E_HIP, "serving: %s", hipGetErrorString(q));
       return false;
     }
+    /* the inputs are on the device: recycle their pinned buffers */
+    release_reads(S, s.reads);
     const int n = (int)s.reads.size();
     const uint64_t total = s.h_po[n];
     if (total) {
@@ -336,24 +409,8 @@ bool slot_poll(abea_server *S, Slot &s, int *rc) {
     }
     const int64_t t = now_ns();
     const int n = (int)s.reads.size();
-    const uint64_t total = s.h_po[n];
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      /* room in the pair ring (grows by doubling, keeping the queued pairs
-       * in order) */
-      uint64_t cap = S->ring.size();
-      if (S->ring_tail - S->ring_head + total > cap) {
-        uint64_t nc = std::max<uint64_t>(cap, 1u << 20);
-        while (S->ring_tail - S->ring_head + total > nc) nc *= 2;
-        std::vector<abea_pair_t> nr(nc);
-        for (uint64_t q = S->ring_head; q < S->ring_tail; ++q) nr[q & (nc - 1)] = S->ring[q & (cap - 1)];
-        S->ring.swap(nr);
-        cap = nc;
-      }
-      const uint64_t at = S->ring_tail & (cap - 1);
-      const uint64_t first = std::min<uint64_t>(total, cap - at);
-      if (first) std::memcpy(S->ring.data() + at, s.h_pairs, sizeof(abea_pair_t) * first);
-      if (total > first) std::memcpy(S->ring.data(), s.h_pairs + first, sizeof(abea_pair_t) * (total - first));
       for (int r = 0; r < n; ++r) {
         Done d;
         const SrvRead &R = s.reads[r];
@@ -366,19 +423,27 @@ bool slot_poll(abea_server *S, Slot &s, int *rc) {
         d.c.t_arrival_ns = R.t_arrival;
         d.c.t_admit_ns = R.t_admit;
         d.c.t_done_ns = t;
-        d.pos = S->ring_tail + s.h_po[r];
+        d.slot = si;
+        d.off = s.h_po[r];
         S->done.push_back(d);
       }
-      S->ring_tail += total;
+      s.outstanding = (uint64_t)n;
       S->inflight_trace -= s.trace_bytes;
       S->inflight_reads -= (uint64_t)n;
       S->stats.completed += (uint64_t)n;
+      s.state = n ? HARVESTED : FREE;
     }
     S->cv_done.notify_all();
     s.reads.clear();
     s.trace_bytes = 0;
-    s.state = FREE;
     return true;
+  }
+  if (s.state == HARVESTED) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (s.outstanding == 0) {
+      s.state = FREE;
+      return true;
+    }
   }
   return false;
 }
@@ -423,21 +488,21 @@ bool admit(abea_server *S, Slot &s) {
 
 void worker_main(abea_server *S) {
   (void)hipSetDevice(S->ctx->device);
+  const int ns = (int)S->slots.size();
   for (;;) {
     bool progress = false;
     int rc = ABEA_OK;
-    for (Slot &s : S->slots) {
-      if (slot_poll(S, s, &rc)) progress = true;
-      if (rc) break;
-    }
+    for (int si = 0; si < ns && !rc; ++si)
+      if (slot_poll(S, si, &rc)) progress = true;
     if (!rc) {
       bool stopping;
       {
         std::lock_guard<std::mutex> lk(S->mu);
         stopping = S->stop;
       }
-      for (Slot &s : S->slots) {
-        if (stopping || s.state != FREE) continue;
+      for (int si = 0; si < ns && !stopping; ++si) {
+        Slot &s = S->slots[si];
+        if (s.state != FREE) continue;
         if (!admit(S, s)) break;
         if ((rc = slot_launch(S, s))) break;
         progress = true;
@@ -450,12 +515,11 @@ void worker_main(abea_server *S) {
       S->cv_done.notify_all();
       return;
     }
+    /* idle: nothing on the device (results waiting to be polled may stay) */
     bool idle = true;
-    for (Slot &s : S->slots) idle = idle && s.state == FREE;
+    for (Slot &s : S->slots) idle = idle && (s.state == FREE || s.state == HARVESTED);
     if (S->stop && idle) return;
     if (!progress) {
-      /* device work in flight: poll again soon; idle: sleep until a read
-       * arrives */
       if (idle && S->n_pending == 0)
         S->cv_work.wait_for(lk, std::chrono::milliseconds(10));
       else
@@ -484,11 +548,14 @@ int abea_server_create(abea_ctx *ctx, const abea_server_config_t *cfg, abea_serv
   S->cfg = *cfg;
   S->G = bands_per_group(ctx->cpl);
   S->slots.resize(cfg->slots);
-  int rc = ABEA_OK;
-  for (Slot &s : S->slots)
-    if ((rc = slot_init(S, s))) break;
+  int rc = S->pool.init(cfg->host_staging_bytes ? cfg->host_staging_bytes : ((size_t)1 << 30));
+  if (rc) rc = fail(ctx, rc, "pinned host arena of %llu bytes", (unsigned long long)cfg->host_staging_bytes);
+  for (Slot &s : S->slots) {
+    if (rc) break;
+    rc = slot_init(S, s);
+  }
   if (rc) {
-    for (Slot &s : S->slots) slot_free(s);
+    for (Slot &s : S->slots) slot_free(S, s);
     delete S;
     return rc;
   }
@@ -529,18 +596,25 @@ int abea_server_submit(abea_server *S, const abea_batch_t *b, const uint64_t *ta
     R.t_arrival = arrival_ns ? arrival_ns[r] : t;
     R.ne = ne;
     R.nk = nk;
-    R.buf = S->pool.get(ne * sizeof(abea_event_t) + nk * sizeof(uint32_t), &R.buf_cls);
-    if (!R.buf) return fail(ctx, ABEA_E_NOMEM, "host buffer for read %d", r);
-    if (ne) std::memcpy(R.buf.get(), b->events + eo[r], sizeof(abea_event_t) * ne);
-    if (nk) std::memcpy(R.buf.get() + ne * sizeof(abea_event_t), b->kmer_rank + ko[r], sizeof(uint32_t) * nk);
+    R.buf.p = S->pool.get(ne * sizeof(abea_event_t) + nk * sizeof(uint32_t), &R.buf_cls, &R.pinned);
+    if (!R.buf.p) {
+      release_reads(S, rs);
+      return fail(ctx, ABEA_E_NOMEM, "pinned host buffer for read %d", r);
+    }
+    if (ne) std::memcpy(R.buf.p, b->events + eo[r], sizeof(abea_event_t) * ne);
+    if (nk) std::memcpy(R.buf.p + ne * sizeof(abea_event_t), b->kmer_rank + ko[r], sizeof(uint32_t) * nk);
     R.scale = b->scale[r];
     R.shift = b->shift[r];
     R.trace_bytes = trace_bytes_of(S->G, ne, nk);
   }
   {
     std::lock_guard<std::mutex> lk(S->mu);
-    if (S->error) return fail(ctx, S->error, "%s", S->err.c_str());
-    if (S->stop) return fail(ctx, ABEA_E_INVAL, "server is stopping");
+    if (S->error || S->stop) {
+      const int e = S->error ? S->error : ABEA_E_INVAL;
+      const std::string m = S->error ? S->err : std::string("server is stopping");
+      release_reads(S, rs);
+      return fail(ctx, e, "%s", m.c_str());
+    }
     for (SrvRead &R : rs) {
       const int q = length_class(R.ne + R.nk);
       S->pending[q].push_back(std::move(R));
@@ -565,6 +639,7 @@ int abea_server_poll(abea_server *S, abea_completion_t *out, int max_out, abea_p
   if (S->done.empty() && S->error) return fail(ctx, S->error, "%s", S->err.c_str());
   uint64_t used = 0;
   int k = 0;
+  bool freed = false; /* a slot's results are all taken: it can run again */
   while (k < max_out && !S->done.empty()) {
     Done &d = S->done.front();
     const uint64_t np = d.c.n_pairs;
@@ -576,21 +651,18 @@ int abea_server_poll(abea_server *S, abea_completion_t *out, int max_out, abea_p
       }
       break;
     }
-    const uint64_t cap = S->ring.size();
-    for (uint64_t q = 0; q < np;) { /* at most two pieces around the wrap */
-      const uint64_t at = (d.pos + q) & (cap - 1);
-      const uint64_t len = std::min<uint64_t>(np - q, cap - at);
-      std::memcpy(pairs + used + q, S->ring.data() + at, sizeof(abea_pair_t) * len);
-      q += len;
-    }
+    Slot &s = S->slots[d.slot];
+    if (np) std::memcpy(pairs + used, s.h_pairs + d.off, sizeof(abea_pair_t) * np);
     out[k] = d.c;
     out[k].pair_offset = used;
     used += np;
     ++k;
-    S->ring_head = d.pos + np;
+    if (--s.outstanding == 0) freed = true;
     S->done.pop_front();
   }
   *n_out = k;
+  lk.unlock();
+  if (freed) S->cv_work.notify_one();
   return ABEA_OK;
 }
 
@@ -610,13 +682,16 @@ void abea_server_destroy(abea_server *S) {
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
-    for (auto &P : S->pending) P.clear();
+    for (auto &P : S->pending) {
+      for (SrvRead &R : P) release_read(S, R);
+      P.clear();
+    }
     S->n_pending = 0;
   }
   S->cv_work.notify_all();
   if (S->worker.joinable()) S->worker.join();
   (void)hipSetDevice(S->ctx->device);
-  for (Slot &s : S->slots) slot_free(s);
+  for (Slot &s : S->slots) slot_free(S, s);
   delete S;
 }
 
