@@ -423,7 +423,8 @@ def bench_serving(args, wl):
     out_levels = []
     for comp, n in levels:
         sub = batch.subset(range(n)) if n < batch.n_reads else batch
-        srv = abea.Server(al, slots=args.slots, max_batch_reads=args.batch_reads, trace_budget_bytes=budget)
+        srv = abea.Server(al, slots=args.slots, max_batch_reads=args.batch_reads, trace_budget_bytes=budget,
+                          host_staging_bytes=int(args.host_staging_gb * (1 << 30)))
         log(f"bench: serving x{comp} {n} reads")
         res = serving.run(srv, sub, arr[:n], compression=float(comp))
         srv.close()
@@ -454,6 +455,8 @@ def bench_serving(args, wl):
         "parallelism": "continuous batching: micro-batches on several streams, one wavefront per read",
         "slots": args.slots,
         "max_batch_reads": args.batch_reads,
+        "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
+        "host_staging_gb": args.host_staging_gb,
         "trace_budget_gb": budget / 1e9,
         "value_is": "GCUPS of the load level with the highest throughput",
     })
@@ -517,8 +520,13 @@ def main():
                     help="persistent: traceback memory budget per batch (0 = unbounded)")
     ap.add_argument("--max-reads", type=int, default=0,
                     help="persistent: only the first N reads of the workload (quick runs; 0 = all)")
-    ap.add_argument("--slots", type=int, default=4, help="serving: micro-batches on the device at once")
-    ap.add_argument("--batch-reads", type=int, default=1024, help="serving: reads per micro-batch")
+    ap.add_argument("--slots", type=int, default=16, help="serving: micro-batches on the device at once")
+    ap.add_argument("--batch-reads", type=int, default=256, help="serving: reads per micro-batch")
+    ap.add_argument("--host-staging-gb", type=float, default=6.0,
+                    help="serving: pinned host arena for queued reads (GiB)")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="serving: hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32), so that "
+                    "the micro-batches of different slots run side by side")
     ap.add_argument("--levels", default="", help="serving: compression:reads,... (default: the full sweep)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
@@ -532,6 +540,9 @@ def main():
         )
         sys.exit(2)
     wl = WORKLOADS[args.workload]
+    if wl["kind"] == "serving" and 0 < args.hw_queues <= 32:
+        # read by the HIP runtime when it starts, i.e. before torch touches the GPU
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.copy_calibration_mb > 0:
         copy_calibration(args.copy_calibration_mb)
     if wl["kind"] == "plain":

@@ -283,6 +283,10 @@ typedef struct {
   uint64_t inflight_trace_bytes, max_inflight_trace_bytes;
   int32_t error;          /* sticky ABEA_E_* of the background thread, 0 if none */
   int32_t reserved;
+  /* where the background thread's time goes (nanoseconds, summed over
+   * micro-batches): enqueueing copies and kernels, from enqueue to results on
+   * the host, and turning finished micro-batches into results */
+  uint64_t enqueue_ns, device_ns, harvest_ns;
 } abea_server_stats_t;
 
 typedef struct abea_server abea_server;

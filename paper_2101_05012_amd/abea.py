@@ -181,6 +181,9 @@ class abea_server_stats_t(ctypes.Structure):
         ("max_inflight_trace_bytes", ctypes.c_uint64),
         ("error", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("enqueue_ns", ctypes.c_uint64),
+        ("device_ns", ctypes.c_uint64),
+        ("harvest_ns", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:

@@ -242,7 +242,7 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   const ReadDesc *reads = (const ReadDesc *)w.reads.p;
   int32_t *rstat = (int32_t *)w.rstat.p;
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[0], st));
-  HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ranks, io.scale, io.shift,
+  HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ranks, io.in_addr, io.scale, io.shift,
                            (const ModelEntry *)ctx->model.p, ctx->n_model, (float *)w.xmean.p,
                            (KParam *)w.kparam.p, rstat, (uint32_t *)w.queue.p, st));
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[1], st));

@@ -95,10 +95,13 @@ struct AlignArgs {
 };
 
 /* Kernel launchers (abea_kernels.hip). */
+/* in_addr: null, or per original read index r the device addresses of its
+ * events (in_addr[2r]) and ranks (in_addr[2r+1]), used instead of the batch
+ * arrays. */
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
-                       const uint32_t *ranks, const float *scale, const float *shift,
-                       const ModelEntry *model, uint32_t n_model, float *xmean, KParam *kparam,
-                       int32_t *rstat, uint32_t *queue, hipStream_t st);
+                       const uint32_t *ranks, const uint64_t *in_addr, const float *scale,
+                       const float *shift, const ModelEntry *model, uint32_t n_model, float *xmean,
+                       KParam *kparam, int32_t *rstat, uint32_t *queue, hipStream_t st);
 hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st);
 hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st);
 /* fused band + backtrack with a.n_workers wavefronts, wpg per workgroup */

@@ -56,8 +56,7 @@ struct Log2 {
 __device__ __forceinline__ float rot_up(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x13C,
                                                     0xF, 0xF, false));
-}
-__device__ __forceinline__ float rlane(float v, int lane) {
+}__device__ __forceinline__ float rlane(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 __device__ __forceinline__ uint32_t rlane_u(uint32_t v, int lane) {
@@ -133,6 +132,7 @@ __device__ __forceinline__ float read_slot(const float (&v)[CPL], int slot) {
 __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads,
                                               const float *__restrict__ events,
                                               const uint32_t *__restrict__ ranks,
+                                              const uint64_t *__restrict__ in_addr,
                                               const float *__restrict__ scale,
                                               const float *__restrict__ shift,
                                               const ModelEntry *__restrict__ model, uint32_t n_model,
@@ -147,11 +147,16 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
     if (threadIdx.x == 0) rstat[blockIdx.x] = READ_EMPTY;
     return;
   }
+  /* the read's events and ranks: in the batch arrays at its offsets, or
+   * (in_addr) at addresses of its own, e.g. in mapped host memory */
+  const float *ev = in_addr ? reinterpret_cast<const float *>(in_addr[2 * rd.orig]) : events + 3 * rd.ev_off;
+  const uint32_t *rk =
+      in_addr ? reinterpret_cast<const uint32_t *>(in_addr[2 * rd.orig + 1]) : ranks + rd.km_off;
   const float sc = scale[rd.orig];
   const float sh = shift[rd.orig];
   int bad = 0;
   for (int k = threadIdx.x; k < rd.n_k; k += blockDim.x) {
-    const uint32_t r = ranks[rd.km_off + k];
+    const uint32_t r = rk[k];
     KParam p;
     p.mu = p.c = p.h = p.pad = 0.0f;
     if (r < n_model) {
@@ -164,8 +169,7 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
     }
     kparam[rd.km_off + k] = p;
   }
-  for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x)
-    xmean[rd.ev_off + e] = events[3 * (rd.ev_off + e)];
+  for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) xmean[rd.ev_off + e] = ev[3 * e];
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) rstat[blockIdx.x] = bad ? READ_BAD_RANK : READ_OK;
 }
@@ -739,12 +743,12 @@ __global__ __launch_bounds__(256) void k_compact(const int2 *__restrict__ scratc
 /* ------------------------------------------------------------- launchers */
 
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
-                       const uint32_t *ranks, const float *scale, const float *shift,
-                       const ModelEntry *model, uint32_t n_model, float *xmean, KParam *kparam,
-                       int32_t *rstat, uint32_t *queue, hipStream_t st) {
+                       const uint32_t *ranks, const uint64_t *in_addr, const float *scale,
+                       const float *shift, const ModelEntry *model, uint32_t n_model, float *xmean,
+                       KParam *kparam, int32_t *rstat, uint32_t *queue, hipStream_t st) {
   if (n_planned <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(256), 0, st, reads, events, ranks, scale, shift,
-                     model, n_model, xmean, kparam, rstat, queue);
+  hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(256), 0, st, reads, events, ranks, in_addr, scale,
+                     shift, model, n_model, xmean, kparam, rstat, queue);
   return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ struct Work {
 struct DevIO {
   const float *events;
   const uint32_t *ranks;
+  const uint64_t *in_addr = nullptr; /* per-read input addresses (see launch_prep) */
   const float *scale;
   const float *shift;
   int2 *pairs;

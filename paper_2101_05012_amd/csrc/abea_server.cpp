@@ -77,15 +77,22 @@ class BufPool {
   int init(size_t bytes) {
     size_ = bytes;
     if (bytes == 0) return ABEA_OK;
-    void *p = nullptr;
-    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    void *p = nullptr, *d = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
       (void)hipGetLastError();
       size_ = 0;
       return ABEA_E_NOMEM;
     }
     arena_ = (uint8_t *)p;
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      return ABEA_E_HIP;
+    }
+    dev_ = (uint64_t)(uintptr_t)d;
     return ABEA_OK;
   }
+  /* device address of a pinned buffer from get() */
+  uint64_t dev_addr(const uint8_t *p) const { return dev_ + (uint64_t)(p - arena_); }
   uint8_t *get(size_t n, int *c_out, bool *pinned) {
     const int c = cls(n);
     const size_t sz = (size_t)1 << c;
@@ -125,6 +132,7 @@ class BufPool {
   std::mutex mu_;
   std::vector<uint8_t *> free_[48];
   uint8_t *arena_ = nullptr;
+  uint64_t dev_ = 0;
   size_t size_ = 0, bump_ = 0;
 };
 
@@ -172,10 +180,13 @@ struct Slot {
   hipStream_t st = nullptr;
   hipEvent_t ev_meta = nullptr, ev_done = nullptr;
   Work work;
-  /* pinned staging of reads whose buffer is not pinned, of the small
-   * inputs and of the results */
+  /* mapped pinned staging of reads whose buffer is not pinned (the prep
+   * kernel reads it in place), pinned staging of the small inputs and of the
+   * results */
   abea_event_t *h_ev = nullptr;
   uint32_t *h_rk = nullptr;
+  uint64_t dh_ev = 0, dh_rk = 0; /* their device addresses */
+  uint64_t *h_addr = nullptr;    /* per read: device addresses of its events, ranks */
   float *h_sc = nullptr, *h_sh = nullptr;
   uint64_t *h_eo = nullptr, *h_ko = nullptr;
   abea_pair_t *h_pairs = nullptr;
@@ -183,10 +194,11 @@ struct Slot {
   float *h_ll = nullptr;
   int32_t *h_st = nullptr;
   /* device inputs and results */
-  DevBuf d_ev, d_rk, d_sc, d_sh, d_pairs, d_po, d_ll, d_st, d_cells;
+  DevBuf d_addr, d_sc, d_sh, d_pairs, d_po, d_ll, d_st, d_cells;
   std::vector<SrvRead> reads;
   uint64_t trace_bytes = 0;
   int state = FREE;         /* changed by the worker; HARVESTED -> FREE under the lock */
+  int64_t t_launched = 0;   /* when the micro-batch was enqueued */
   uint64_t outstanding = 0; /* harvested results not yet polled (under the lock) */
 };
 
@@ -235,9 +247,10 @@ void slot_free(abea_server *S, Slot &s) {
   if (s.st) (void)hipStreamSynchronize(s.st);
   release_reads(S, s.reads);
   work_free(s.work);
-  DevBuf *bufs[] = {&s.d_ev, &s.d_rk, &s.d_sc, &s.d_sh, &s.d_pairs, &s.d_po, &s.d_ll, &s.d_st, &s.d_cells};
+  DevBuf *bufs[] = {&s.d_addr, &s.d_sc, &s.d_sh, &s.d_pairs, &s.d_po, &s.d_ll, &s.d_st, &s.d_cells};
   for (DevBuf *b : bufs) free_buf(*b);
-  void *hosts[] = {s.h_ev, s.h_rk, s.h_sc, s.h_sh, s.h_eo, s.h_ko, s.h_pairs, s.h_po, s.h_cells, s.h_ll, s.h_st};
+  void *hosts[] = {s.h_ev, s.h_rk, s.h_addr, s.h_sc, s.h_sh, s.h_eo, s.h_ko, s.h_pairs, s.h_po, s.h_cells,
+                   s.h_ll, s.h_st};
   for (void *h : hosts)
     if (h) (void)hipHostFree(h);
   if (s.ev_meta) (void)hipEventDestroy(s.ev_meta);
@@ -247,8 +260,18 @@ void slot_free(abea_server *S, Slot &s) {
 }
 
 template <typename T>
-int host_alloc(abea_ctx *ctx, T **p, uint64_t n) {
-  HIP_TRY(ctx, hipHostMalloc((void **)p, sizeof(T) * std::max<uint64_t>(n, 1), hipHostMallocDefault));
+int host_alloc(abea_ctx *ctx, T **p, uint64_t n, unsigned flags = hipHostMallocDefault) {
+  HIP_TRY(ctx, hipHostMalloc((void **)p, sizeof(T) * std::max<uint64_t>(n, 1), flags));
+  return ABEA_OK;
+}
+
+template <typename T>
+int mapped_alloc(abea_ctx *ctx, T **p, uint64_t n, uint64_t *dev) {
+  int rc = host_alloc(ctx, p, n, hipHostMallocMapped | hipHostMallocCoherent);
+  if (rc) return rc;
+  void *d = nullptr;
+  HIP_TRY(ctx, hipHostGetDevicePointer(&d, (void *)*p, 0));
+  *dev = (uint64_t)(uintptr_t)d;
   return ABEA_OK;
 }
 
@@ -264,8 +287,9 @@ int slot_init(abea_server *S, Slot &s) {
   HIP_TRY(ctx, hipEventCreateWithFlags(&s.ev_meta, hipEventDisableTiming));
   HIP_TRY(ctx, hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming));
   if ((rc = work_init(ctx, s.work))) return rc;
-  if ((rc = host_alloc(ctx, &s.h_ev, ne))) return rc;
-  if ((rc = host_alloc(ctx, &s.h_rk, nk))) return rc;
+  if ((rc = mapped_alloc(ctx, &s.h_ev, ne, &s.dh_ev))) return rc;
+  if ((rc = mapped_alloc(ctx, &s.h_rk, nk, &s.dh_rk))) return rc;
+  if ((rc = host_alloc(ctx, &s.h_addr, 2 * nr))) return rc;
   if ((rc = host_alloc(ctx, &s.h_sc, nr))) return rc;
   if ((rc = host_alloc(ctx, &s.h_sh, nr))) return rc;
   if ((rc = host_alloc(ctx, &s.h_eo, nr + 1))) return rc;
@@ -275,8 +299,7 @@ int slot_init(abea_server *S, Slot &s) {
   if ((rc = host_alloc(ctx, &s.h_cells, nr))) return rc;
   if ((rc = host_alloc(ctx, &s.h_ll, nr))) return rc;
   if ((rc = host_alloc(ctx, &s.h_st, nr))) return rc;
-  if ((rc = ensure(ctx, nullptr, s.d_ev, sizeof(abea_event_t) * ne))) return rc;
-  if ((rc = ensure(ctx, nullptr, s.d_rk, sizeof(uint32_t) * nk))) return rc;
+  if ((rc = ensure(ctx, nullptr, s.d_addr, sizeof(uint64_t) * 2 * nr))) return rc;
   if ((rc = ensure(ctx, nullptr, s.d_sc, sizeof(float) * nr))) return rc;
   if ((rc = ensure(ctx, nullptr, s.d_sh, sizeof(float) * nr))) return rc;
   if ((rc = ensure(ctx, nullptr, s.d_pairs, sizeof(abea_pair_t) * np))) return rc;
@@ -309,6 +332,7 @@ int slot_init(abea_server *S, Slot &s) {
 int slot_launch(abea_server *S, Slot &s) {
   abea_ctx *ctx = S->ctx;
   hipStream_t st = s.st;
+  const int64_t t_begin = now_ns();
   const int n = (int)s.reads.size();
   uint64_t eo = 0, ko = 0;
   s.h_eo[0] = s.h_ko[0] = 0;
@@ -325,33 +349,34 @@ int slot_launch(abea_server *S, Slot &s) {
   if ((rc = plan_batch(ctx, s.work, n, s.h_eo, s.h_ko, eo + ko))) return rc;
   if ((rc = ensure_work(ctx, s.work))) return rc;
   s.work.last_stream = st;
-  /* a read in a pinned buffer goes to the device by DMA from there; one in a
-   * pageable buffer is copied into the slot's pinned staging first */
+  /* the prep kernel reads every read's events and ranks in place from
+   * mapped pinned host memory: from the read's own buffer, or for a read
+   * queued in pageable memory from the slot's mapped staging */
   for (int r = 0; r < n; ++r) {
     const SrvRead &R = s.reads[r];
-    const abea_event_t *ev = R.events();
-    const uint32_t *rk = R.ranks();
-    if (!R.pinned) {
-      if (R.ne) std::memcpy(s.h_ev + s.h_eo[r], ev, sizeof(abea_event_t) * R.ne);
-      if (R.nk) std::memcpy(s.h_rk + s.h_ko[r], rk, sizeof(uint32_t) * R.nk);
-      ev = s.h_ev + s.h_eo[r];
-      rk = s.h_rk + s.h_ko[r];
+    uint64_t a_ev, a_rk;
+    if (R.pinned) {
+      a_ev = S->pool.dev_addr(R.buf.p);
+      a_rk = a_ev + R.ne * sizeof(abea_event_t);
+    } else {
+      if (R.ne) std::memcpy(s.h_ev + s.h_eo[r], R.events(), sizeof(abea_event_t) * R.ne);
+      if (R.nk) std::memcpy(s.h_rk + s.h_ko[r], R.ranks(), sizeof(uint32_t) * R.nk);
+      a_ev = s.dh_ev + s.h_eo[r] * sizeof(abea_event_t);
+      a_rk = s.dh_rk + s.h_ko[r] * sizeof(uint32_t);
     }
-    if (R.ne)
-      HIP_TRY(ctx, hipMemcpyAsync((abea_event_t *)s.d_ev.p + s.h_eo[r], ev, sizeof(abea_event_t) * R.ne,
-                                  hipMemcpyHostToDevice, st));
-    if (R.nk)
-      HIP_TRY(ctx, hipMemcpyAsync((uint32_t *)s.d_rk.p + s.h_ko[r], rk, sizeof(uint32_t) * R.nk,
-                                  hipMemcpyHostToDevice, st));
+    s.h_addr[2 * r] = a_ev;
+    s.h_addr[2 * r + 1] = a_rk;
   }
+  HIP_TRY(ctx, hipMemcpyAsync(s.d_addr.p, s.h_addr, sizeof(uint64_t) * 2 * n, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(s.d_sc.p, s.h_sc, sizeof(float) * n, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(s.d_sh.p, s.h_sh, sizeof(float) * n, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(s.work.reads.p, s.work.h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipEventRecord(s.work.staging_done, st));
   s.work.staging_pending = true;
   DevIO io;
-  io.events = (const float *)s.d_ev.p;
-  io.ranks = (const uint32_t *)s.d_rk.p;
+  io.events = nullptr;
+  io.ranks = nullptr;
+  io.in_addr = (const uint64_t *)s.d_addr.p;
   io.scale = (const float *)s.d_sc.p;
   io.shift = (const float *)s.d_sh.p;
   io.pairs = (int2 *)s.d_pairs.p;
@@ -366,6 +391,11 @@ int slot_launch(abea_server *S, Slot &s) {
   HIP_TRY(ctx, hipMemcpyAsync(s.h_cells, s.d_cells.p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipEventRecord(s.ev_meta, st));
   s.state = RUNNING;
+  s.t_launched = now_ns();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stats.enqueue_ns += (uint64_t)(s.t_launched - t_begin);
+  }
   return ABEA_OK;
 }
 
@@ -411,6 +441,7 @@ bool slot_poll(abea_server *S, int si, int *rc) {
     const int n = (int)s.reads.size();
     {
       std::lock_guard<std::mutex> lk(S->mu);
+      S->stats.device_ns += (uint64_t)(t - s.t_launched);
       for (int r = 0; r < n; ++r) {
         Done d;
         const SrvRead &R = s.reads[r];
@@ -432,6 +463,7 @@ bool slot_poll(abea_server *S, int si, int *rc) {
       S->inflight_reads -= (uint64_t)n;
       S->stats.completed += (uint64_t)n;
       s.state = n ? HARVESTED : FREE;
+      S->stats.harvest_ns += (uint64_t)(now_ns() - t);
     }
     S->cv_done.notify_all();
     s.reads.clear();

@@ -100,5 +100,8 @@ def summarize(res: Dict, batch, compression: float, arrivals_s: np.ndarray) -> D
         "micro_batches": st["micro_batches"],
         "max_inflight_reads": st["max_inflight_reads"],
         "max_inflight_trace_mb": round(st["max_inflight_trace_bytes"] / 1e6, 1),
+        "server_thread_s": {"enqueue": round(st["enqueue_ns"] / 1e9, 3), "device": round(st["device_ns"] / 1e9, 3),
+                            "harvest": round(st["harvest_ns"] / 1e9, 3)},
+        "span_s": round(span_s, 3),
         "reads_ok": int((c["status"] == 0).sum()),
     }
