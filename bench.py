@@ -419,7 +419,7 @@ def bench_serving(args, wl):
     arr = arr[:n_max]
     log(f"bench: generated in {time.perf_counter() - t0:.1f} s; real-time rate {n_max / arr[-1]:.1f} reads/s")
     al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
-    budget = int(args.trace_budget_gb * 1e9) if args.trace_budget_gb > 0 else 8_000_000_000
+    budget = int(args.trace_budget_gb * 1e9) if args.trace_budget_gb > 0 else 32_000_000_000
     out_levels = []
     for comp, n in levels:
         sub = batch.subset(range(n)) if n < batch.n_reads else batch

@@ -21,7 +21,8 @@ from . import abea
 
 
 def run(server: abea.Server, batch, arrivals_s: np.ndarray, compression: float = 1.0,
-        keep_pairs: bool = False, tick_s: float = 0.0005, timeout_s: float = 600.0) -> Dict:
+        keep_pairs: bool = False, tick_s: float = 0.0005, timeout_s: float = 600.0,
+        submitters: int = 4) -> Dict:
     n = batch.n_reads
     arrivals_s = np.asarray(arrivals_s, np.float64)
     assert arrivals_s.shape[0] == n and np.all(np.diff(arrivals_s) >= 0)
@@ -29,24 +30,45 @@ def run(server: abea.Server, batch, arrivals_s: np.ndarray, compression: float =
     target = t0 + (arrivals_s / compression * 1e9).astype(np.int64)
     err = []
 
-    def submitter():
+    def submitter(mine: np.ndarray):
+        """Hand reads `mine` (sorted) to the server at their arrival times;
+        several submitters share the copying of arriving reads."""
         try:
             i = 0
-            while i < n:
+            m = mine.shape[0]
+            tm = target[mine]
+            while i < m:
                 now = abea.now_ns()
-                if target[i] > now:
-                    wait = (target[i] - now) / 1e9
+                r = int(mine[i])
+                if target[r] > now:
+                    wait = (target[r] - now) / 1e9
                     time.sleep(min(wait, tick_s) if wait > tick_s else max(wait, 0.0))
                     continue
-                j = int(np.searchsorted(target, now, side="right"))
+                j = int(np.searchsorted(tm, now, side="right"))
                 j = max(j, i + 1)
-                server.submit(batch, i, j, np.arange(i, j, dtype=np.uint64), target[i:j])
-                i = j
+                # runs of consecutive read indices go in one call
+                while i < j:
+                    a = int(mine[i])
+                    b = i + 1
+                    while b < j and int(mine[b]) == int(mine[b - 1]) + 1:
+                        b += 1
+                    last = int(mine[b - 1])
+                    server.submit(batch, a, last + 1, np.arange(a, last + 1, dtype=np.uint64), target[a:last + 1])
+                    i = b
         except Exception as e:  # surfaced by the collector
             err.append(e)
 
-    th = threading.Thread(target=submitter, daemon=True)
-    th.start()
+    T = max(1, min(int(submitters), n))
+    if T == 1:
+        parts = [np.arange(n)]
+    else:
+        # contiguous blocks of 8 reads dealt round robin: each submitter keeps
+        # short consecutive runs
+        blk = np.arange(n) // 8
+        parts = [np.nonzero(blk % T == t)[0] for t in range(T)]
+    threads = [threading.Thread(target=submitter, args=(p,), daemon=True) for p in parts]
+    for th in threads:
+        th.start()
     comps = []
     pairs: Optional[dict] = {} if keep_pairs else None
     got = 0
@@ -65,7 +87,8 @@ def run(server: abea.Server, batch, arrivals_s: np.ndarray, compression: float =
             for rec in c:
                 o = int(rec["pair_offset"])
                 pairs[int(rec["tag"])] = p[o : o + int(rec["n_pairs"])]
-    th.join()
+    for th in threads:
+        th.join()
     if err:
         raise err[0]
     comp = np.concatenate(comps)

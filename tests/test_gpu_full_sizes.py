@@ -1,0 +1,95 @@
+"""Full-size workloads in the launch form the benchmark times, checked on
+sampled reads against the CPU oracle (bit-exact scores and pairs).
+
+* uneven-20000 (W = 100): the whole job as one captured graph of the
+  persistent kernel (pool of 4 wavefronts per SIMD, 4 reads per workgroup).
+* ultralong-200 (W = 250, k = 9): the persistent kernel under an 8 GB trace
+  budget (fewer workers than reads, so reads come from the work queue).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2101_05012_amd import abea, autotune, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sampled_parity(O, model, batch, W, res_by_read, idx):
+    om = O.Model(model.level_mean, model.level_stdv)
+    sub = batch.subset(idx)
+    o = O.align_batch(sub, om, W, n_threads=16)
+    for t, r in enumerate(idx):
+        status, ll, cells, pairs = res_by_read(r)
+        assert status == o.status[t], r
+        assert cells == int(o.cells[t]), r
+        if o.status[t] != 0:
+            continue
+        assert np.float32(ll) == o.score[t], (r, ll, o.score[t])
+        assert np.array_equal(pairs, o.read_pairs(t)), r
+
+
+def pick(batch, rng, n_long, n_short, n_rand):
+    L = np.diff(batch.kmer_offset.astype(np.int64))
+    order = np.argsort(-L, kind="stable")
+    idx = set(order[:n_long].tolist()) | set(order[-n_short:].tolist())
+    idx |= set(rng.choice(batch.n_reads, n_rand, replace=False).tolist())
+    return sorted(int(i) for i in idx)
+
+
+def test_uneven_20000_persistent_graph(oracle_mod):
+    import torch
+
+    model = synth.pore_model(6)
+    say("gpu: generating uneven-20000")
+    batch = synth.config_batch_parallel(2, k=6)
+    launch = autotune.Launch(cells_per_lane=2, waves_per_group=4, waves_per_simd=4, batches=1)
+    job = autotune.Job(batch, 1, 0)
+    al = autotune.make_aligner(model, 6, 100, launch, 0, 0)
+    run = autotune.GraphRun(al, job)
+    assert run.info[0]["workers"] < batch.n_reads
+    st = torch.cuda.Stream()
+    say("gpu: uneven-20000 graph replay")
+    run.launch(st)
+    st.synchronize()
+    h = run.results[0].to_host(batch.n_reads)
+    run.close()
+    al.close()
+    assert np.all(h.status == 0)
+    po = h.pair_offset.astype(np.int64)
+    assert po[0] == 0 and np.all(np.diff(po) > 0)
+    idx = pick(batch, np.random.default_rng(21), 3, 2, 10)
+    say(f"gpu: uneven-20000 oracle on {len(idx)} reads")
+    sampled_parity(oracle_mod, model, batch, 100,
+                   lambda r: (h.status[r], h.log_likelihood[r], int(h.cells[r]), h.read_pairs(r)), idx)
+
+
+def test_ultralong_w250_k9_under_trace_budget(oracle_mod):
+    import torch
+
+    model = synth.pore_model(9)
+    say("gpu: generating ultralong-200 k=9")
+    batch = synth.config_batch_parallel(4, k=9)
+    al = abea.Aligner(model.level_mean, model.level_stdv, 9, W=250, arena_bytes=8_000_000_000,
+                      workers=4 * autotune.resident_simds(0))
+    db = abea.to_device(batch)
+    dr = abea.DeviceResult.empty(db)
+    say("gpu: ultralong-200 W=250 k=9")
+    al.align_device(db, dr)
+    torch.cuda.synchronize()
+    info = al.plan_info()
+    assert 0 < info["workers"] < batch.n_reads and info["trace_bytes"] <= 8_000_000_000
+    h = dr.to_host(batch.n_reads)
+    al.close()
+    assert np.all(h.status == 0)
+    idx = pick(batch, np.random.default_rng(22), 1, 1, 1)
+    say(f"gpu: ultralong oracle on {len(idx)} reads")
+    sampled_parity(oracle_mod, model, batch, 250,
+                   lambda r: (h.status[r], h.log_likelihood[r], int(h.cells[r]), h.read_pairs(r)), idx)
