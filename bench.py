@@ -10,7 +10,9 @@ already resident in HBM:
 
 The default workload is the 4000-read log-normal batch (median 5 kb, clipped
 200 b..100 kb, W = 100, k = 6), aligned with one kernel launch per batch.
-`--inflight P` keeps P batches in flight on P streams.
+`--inflight P` keeps P batches in flight on P streams (default 6, on 16
+hardware queues: a batch lasts as long as its longest read, and 6 batches in
+flight overlap those tails best).
 
 Other workloads (``--workload``):
   uneven-20000-w100/w200: 20000 reads, 70% 500 b..5 kb and 30% 20..200 kb.
@@ -500,7 +502,7 @@ def main():
     ap.add_argument(
         "--inflight",
         type=int,
-        default=3,
+        default=6,
         help="plain workloads: batches in flight, each with its own context and stream, so one "
         "batch's longest reads overlap the next batch's work (1 = one batch after the other)",
     )
@@ -525,8 +527,8 @@ def main():
     ap.add_argument("--host-staging-gb", type=float, default=6.0,
                     help="serving: pinned host arena for queued reads (GiB)")
     ap.add_argument("--hw-queues", type=int, default=16,
-                    help="serving: hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32), so that "
-                    "the micro-batches of different slots run side by side")
+                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32) for the plain and "
+                    "serving workloads, so that batches or micro-batches on different streams run side by side")
     ap.add_argument("--levels", default="", help="serving: compression:reads,... (default: the full sweep)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
@@ -540,7 +542,7 @@ def main():
         )
         sys.exit(2)
     wl = WORKLOADS[args.workload]
-    if wl["kind"] == "serving" and 0 < args.hw_queues <= 32:
+    if wl["kind"] in ("serving", "plain") and 0 < args.hw_queues <= 32:
         # read by the HIP runtime when it starts, i.e. before torch touches the GPU
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.copy_calibration_mb > 0:
