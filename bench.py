@@ -79,7 +79,7 @@ SERVING_LEVELS = [(1, 300), (10, 1000), (100, 4000), (1000, 20000), (3000, 30000
 # runs (FETCH_SIZE x 1.99991, WRITE_SIZE x 1.0: the factors a 1 GiB device
 # copy needs to read its known size), by workload; a workload without a
 # measurement of the current kernel reports null.
-ALIGN_TRAFFIC_BYTES = {"plain-4000-lognormal5kb": 6.829e9}
+ALIGN_TRAFFIC_BYTES = {"plain-4000-lognormal5kb": 6.828e9}
 
 
 def log(*a):
@@ -492,8 +492,8 @@ def copy_calibration(mb: int) -> None:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--workload", default="plain-4000-lognormal5kb", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=1000)
