@@ -10,9 +10,11 @@ already resident in HBM:
 
 The default workload is the 4000-read log-normal batch (median 5 kb, clipped
 200 b..100 kb, W = 100, k = 6), aligned with one kernel launch per batch.
-`--inflight P` keeps P batches in flight on P streams (default 6, on 16
-hardware queues: a batch lasts as long as its longest read, and 6 batches in
-flight overlap those tails best).
+`--inflight P` keeps P batches in flight on P streams. The default is 16, on
+16 hardware queues: a batch lasts as long as its longest read, and 16
+batches in flight overlap those tails. Each launch runs a pool of 1024 fused
+wavefronts that take the batch's reads from a device work queue, leaving room
+on the chip for the other batches' long reads.
 
 Other workloads (``--workload``):
   uneven-20000-w100/w200: 20000 reads, 70% 500 b..5 kb and 30% 20..200 kb.
@@ -79,7 +81,7 @@ SERVING_LEVELS = [(1, 300), (10, 1000), (100, 4000), (1000, 20000), (3000, 30000
 # runs (FETCH_SIZE x 1.99991, WRITE_SIZE x 1.0: the factors a 1 GiB device
 # copy needs to read its known size), by workload; a workload without a
 # measurement of the current kernel reports null.
-ALIGN_TRAFFIC_BYTES = {"plain-4000-lognormal5kb": 6.828e9}
+ALIGN_TRAFFIC_BYTES = {"plain-4000-lognormal5kb": 6.804e9}
 
 
 def log(*a):
@@ -232,7 +234,10 @@ def bench_plain(args, wl):
             "compact": round(float(kms[3]), 4),
         },
         "reads_ok": int((status == 0).sum()),
-        "roofline": roofline(cells_per_step, float(kms[1]), kname, args.workload),
+        "roofline": {**roofline(cells_per_step, float(kms[1]), kname, args.workload),
+                     # the same work over the whole job's time (launches overlap)
+                     "achieved_job": round(gcups * OPS_PER_CELL / 1e3, 3),
+                     "frac_job": round(gcups * OPS_PER_CELL / 1e3 / VALU_PEAK_TOPS, 4)},
     })
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
@@ -492,8 +497,8 @@ def copy_calibration(mb: int) -> None:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
-    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=80)
+    ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="plain-4000-lognormal5kb", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=1000)
@@ -502,16 +507,17 @@ def main():
     ap.add_argument(
         "--inflight",
         type=int,
-        default=6,
+        default=16,
         help="plain workloads: batches in flight, each with its own context and stream, so one "
         "batch's longest reads overlap the next batch's work (1 = one batch after the other)",
     )
     ap.add_argument(
         "--workers",
         type=int,
-        default=0,
-        help="plain workloads: -1 split band/backtrack kernels, 0 one fused wavefront per read, "
-        ">0 a persistent pool of that many wavefronts with a device work queue",
+        default=1024,
+        help="plain workloads: wavefronts of each batch's launch: -1 split band/backtrack kernels, 0 one "
+        "fused wavefront per read, >0 a pool of that many fused wavefronts taking the batch's reads from "
+        "a device work queue (still one launch per batch)",
     )
     ap.add_argument("--wpg", type=int, default=1, help="wavefronts (reads) per workgroup of the fused kernel")
     ap.add_argument("--tune", action="store_true", help="persistent workloads: autotune the launch form")

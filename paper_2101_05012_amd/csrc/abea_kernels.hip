@@ -54,8 +54,7 @@ struct Log2 {
 
 /* lane l receives v of lane l-1, lane 0 receives lane 63 (DPP wave_ror:1) */
 __device__ __forceinline__ float rot_up(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x13C,
-                                                    0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x13C, 0xF, 0xF, false));
 }__device__ __forceinline__ float rlane(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -67,15 +66,6 @@ __device__ __forceinline__ float sel(float if_clear, float if_set, uint64_t mask
   float r;
   asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(mask));
   return r;
-}
-__device__ __forceinline__ int seli(int if_clear, int if_set, uint64_t mask) {
-  int r;
-  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(mask));
-  return r;
-}
-/* in place: lanes whose bit is set in `mask` take `val` (one v_cndmask) */
-__device__ __forceinline__ void put(float &dst, float val, uint64_t mask) {
-  asm("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(dst) : "v"(val), "s"(mask));
 }
 /* per lane: acc*2 + (bit of `mask`), one v_addc */
 __device__ __forceinline__ uint32_t shift_in(uint32_t acc, uint64_t mask) {
@@ -90,26 +80,6 @@ __device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_bal
 __device__ int writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
 #define ABEA_NINF_BITS ((int)0xff800000)
-
-/* Order-preserving key of the bits of a non-NaN float (-0 and +0 equal). */
-__device__ __forceinline__ int32_t fkey_bits(int32_t b) {
-  b = (b == (int32_t)0x80000000) ? 0 : b;
-  return b ^ ((b >> 31) & 0x7fffffff);
-}
-
-/* Bits of the value held by slot `slot` of a band, as a scalar. */
-template <int CPL>
-__device__ __forceinline__ int read_slot_bits(const float (&v)[CPL], int slot) {
-  const int ln = slot >> Log2<CPL>::v;
-  const int r = slot & (CPL - 1);
-  int t = __builtin_amdgcn_readlane(__float_as_int(v[0]), ln);
-#pragma unroll
-  for (int c = 1; c < CPL; ++c) {
-    const int u = __builtin_amdgcn_readlane(__float_as_int(v[c]), ln);
-    t = (r == c) ? u : t;
-  }
-  return t;
-}
 
 /* Value held by slot `slot` of a band, as a scalar. */
 template <int CPL>
@@ -177,26 +147,30 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
 /* ------------------------------------------------------------------ band */
 
 /* Band move of the Suzuki-Kasahara rule from the bits of the two end cells
- * of the previous band: 1 (k-mer move) if lo < hi, 0 (event move) otherwise,
- * and `par` (alternation) when both are -inf.  Float compare on the VALU, the
- * rest on the SALU; the result is an SGPR. */
-__device__ __forceinline__ int sk_move(int lo, int hi, int par) {
-  int m, t;
+ * of the previous band, as a wave-uniform mask: -1 (k-mer move) if lo < hi,
+ * else 0 (event move); when both are -inf the band parity decides, a k-mer
+ * move for odd bands.  For odd bands hi is first raised to at least -FLT_MAX
+ * (`nfm` holds -FLT_MAX in every lane): then lo < hi holds exactly when lo is
+ * -inf too (no finite lo is below -FLT_MAX), and every other outcome is
+ * unchanged.  The compare runs on the VALU with all lanes active, so its lane
+ * mask is all ones or all zeros and its low half is the result. */
+template <bool ODD>
+__device__ __forceinline__ int sk_move_mask(int lo, int hi, float nfm) {
   float tv;
   uint64_t cm;
-  asm volatile(
-      "v_mov_b32 %[tv], %[hi]\n\t"
-      "v_cmp_lt_f32_e64 %[cm], %[lo], %[tv]\n\t"
-      "s_and_b64 %[cm], %[cm], exec\n\t"
-      "s_cselect_b32 %[m], 1, 0\n\t"
-      "s_cmp_eq_u32 %[lo], %[hi]\n\t"
-      "s_cselect_b32 %[t], %[lo], 0\n\t"
-      "s_cmp_eq_u32 %[t], 0xff800000\n\t"
-      "s_cselect_b32 %[m], %[par], %[m]"
-      : [m] "=&s"(m), [t] "=&s"(t), [tv] "=&v"(tv), [cm] "=&s"(cm)
-      : [lo] "s"(lo), [hi] "s"(hi), [par] "s"(par)
-      : "scc");
-  return m;
+  if (ODD)
+    asm volatile(
+        "v_max_f32 %[tv], %[h], %[nfm]\n\t"
+        "v_cmp_lt_f32_e64 %[cm], %[lo], %[tv]"
+        : [tv] "=&v"(tv), [cm] "=s"(cm)
+        : [lo] "s"(lo), [h] "s"(hi), [nfm] "v"(nfm));
+  else
+    asm volatile(
+        "v_mov_b32 %[tv], %[h]\n\t"
+        "v_cmp_lt_f32_e64 %[cm], %[lo], %[tv]"
+        : [tv] "=&v"(tv), [cm] "=s"(cm)
+        : [lo] "s"(lo), [h] "s"(hi));
+  return (int)(uint32_t)cm;
 }
 
 /* The register of slot (.. % CPL == r) of every lane, as one VGPR. */
@@ -270,6 +244,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   const float4 *__restrict__ kp = reinterpret_cast<const float4 *>(a.kparam + rd.km_off);
   const int H = W / 2;
   const float NI = ABEA_NINF;
+  const float NFM = __int_as_float((int)0xff7fffff); /* -FLT_MAX */
 
   auto ldx = [&](int e) -> float {
     float v = 0.0f;
@@ -374,9 +349,10 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     const int sh = (K + W - 1) & (N - 1);
     const int lo = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(Sp, sf & (CPL - 1))), sf >> LC);
     const int hi = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(Sp, sh & (CPL - 1))), sh >> LC);
-    const int m = __builtin_amdgcn_readfirstlane(sk_move(lo, hi, b & 1));
-    K += m;
-    E += 1 - m;
+    const int mneg = __builtin_amdgcn_readfirstlane((b & 1) ? sk_move_mask<true>(lo, hi, NFM)
+                                                            : sk_move_mask<false>(lo, hi, NFM));
+    K -= mneg;
+    E += 1 + mneg;
 
     /* cells of band i inside the band and the table: k-mers kv with
      * wlo <= kv - K_r < wlo + wlen */
@@ -409,10 +385,10 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       const float s1 = sel(sd, su, mu);
       const uint64_t ml = ballot(sl > s1);
       const float sv = sel(s1, sl, ml);
-      /* trace planes: up bit (U beats D), left bit (L beats both); a set
-       * left bit means L whatever the up bit */
       const uint64_t valid = ballot((uint32_t)(dd[c] - wlo) < (uint32_t)wlen);
       nv[c] = sel(NI, sv, valid);
+      /* trace planes: up bit (U beats D), left bit (L beats both); a set
+       * left bit means L whatever the up bit */
       TU = shift_in(TU, mu);
       TL = shift_in(TL, ml);
     }
@@ -458,9 +434,11 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
    * interior test once per group, one trace word per lane per group. */
   int i = 2;
   uint64_t g = 0;
+  const bool gap_ok = N - W >= CPL; /* interior bands clear CPL slots outside the band */
   while (i + G - 1 <= last) {
     advance_rings();
-    const bool interior = (K >= 0) & (E >= W - 1) & (E + G <= n_e - 1) & (K + G + W - 1 <= n_k - 1);
+    const bool interior = gap_ok & (K >= 0) & (E >= W - 1) & (E + G <= n_e - 1) &
+                          (K + G + W - 1 <= n_k - 1);
     if (interior) {
       group(std::true_type(), i);
       cells += (uint64_t)W * G;
@@ -531,6 +509,32 @@ __global__ __launch_bounds__(64) void k_band(const AlignArgs a) {
 
 /* ------------------------------------------------------------- backtrack */
 
+/* Bit of trace cell (band t, slot k) in its lane's 32-bit word: 31 - ((t mod
+ * G) * CPL + k mod CPL), as (~((t << LC) + (k & (CPL - 1)))) & 31 in three
+ * SALU instructions (the compiler would rebuild the five-instruction form). */
+template <int CPL>
+__device__ __forceinline__ int trace_bit(int t, int k) {
+  int b;
+  if constexpr (CPL == 1) {
+    asm("s_andn2_b32 %0, 31, %1" : "=s"(b) : "s"(t));
+  } else {
+    int m;
+    if constexpr (CPL == 2)
+      asm("s_and_b32 %1, %3, 1\n\ts_lshl1_add_u32 %0, %2, %1\n\ts_andn2_b32 %0, 31, %0"
+          : "=&s"(b), "=&s"(m) : "s"(t), "s"(k) : "scc");
+    else if constexpr (CPL == 4)
+      asm("s_and_b32 %1, %3, 3\n\ts_lshl2_add_u32 %0, %2, %1\n\ts_andn2_b32 %0, 31, %0"
+          : "=&s"(b), "=&s"(m) : "s"(t), "s"(k) : "scc");
+    else if constexpr (CPL == 8)
+      asm("s_and_b32 %1, %3, 7\n\ts_lshl3_add_u32 %0, %2, %1\n\ts_andn2_b32 %0, 31, %0"
+          : "=&s"(b), "=&s"(m) : "s"(t), "s"(k) : "scc");
+    else
+      asm("s_and_b32 %1, %3, 15\n\ts_lshl4_add_u32 %0, %2, %1\n\ts_andn2_b32 %0, 31, %0"
+          : "=&s"(b), "=&s"(m) : "s"(t), "s"(k) : "scc");
+  }
+  return b;
+}
+
 /* Backtrack of one read (Alg. 5.1, after the band loop) by the calling
  * wavefront, from its trace tiles: writes the path's pairs backwards into
  * the read's scratch slots, its length and first slot, and its final status
@@ -541,7 +545,6 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
                                                uint2 *__restrict__ ring) {
   constexpr int N = 64 * CPL;
   constexpr int LC = Log2<CPL>::v;
-  constexpr int G = 32 / CPL;
   constexpr int LG = 5 - LC;           /* log2(G) */
   constexpr int RG = BT_RING_GROUPS;   /* tile groups in the LDS ring */
   constexpr int QG = RG / 4;           /* groups per refill quarter */
@@ -582,7 +585,11 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
 
   int PE = 0, PK = 0;
   uint64_t q = 0; /* cells emitted and stored */
-  int qs = 0;     /* cells gathered in the lanes, not stored yet */
+  /* cells gathered in the lanes, not stored yet, in the low 6 bits over a
+   * base that makes the count negative once all 64 lanes hold one: the same
+   * register is the writelane lane (which takes bits 5:0) and the stop test */
+  constexpr uint32_t QBASE = 0x7fffffc0u;
+  uint32_t qc = QBASE;
   const uint64_t res_end = rd.pr_off + (uint64_t)(n_e + n_k - 1);
   int2 *__restrict__ out = a.scratch;
   bool ok = true;
@@ -594,36 +601,37 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
     const int lower = gcur << LG;
     int t = e + k;
     int ln_cur = -1;
-    uint32_t wx = 0, wy = 0;
+    uint64_t wxy = 0; /* the lane's up-bit word (low half) and left-bit word (high half) */
     for (;;) {
       e = __builtin_amdgcn_readfirstlane(e);
       k = __builtin_amdgcn_readfirstlane(k);
       /* emit the cell; every 64 cells go out in one coalesced store */
-      PE = writelane(e, qs, PE);
-      PK = writelane(k, qs, PK);
-      ++qs;
+      PE = writelane(e, (int)qc, PE);
+      PK = writelane(k, (int)qc, PK);
+      ++qc;
       const int sl = k & (N - 1);
       const int ln = sl >> LC;
       if (ln != ln_cur) {
-        wx = rlane_u(T.x, ln);
-        wy = rlane_u(T.y, ln);
+        wxy = (uint64_t)rlane_u(T.x, ln) | ((uint64_t)rlane_u(T.y, ln) << 32);
         ln_cur = ln;
       }
-      const int bit = 31 - (((t & (G - 1)) << LC) + (sl & (CPL - 1)));
-      /* code = up bit + 2 * left bit: 0 diagonal (e-1, k-1), 1 up (e-1),
-       * 2 or 3 left (k-1) */
-      const uint32_t code = ((wx >> bit) & 1u) | (((wy >> bit) & 1u) << 1);
-      e -= (int)((code >> 1) ^ 1u);
-      k -= (int)((0xDu >> code) & 1u);
+      const int bit = trace_bit<CPL>(t, k);
+      const uint64_t b2 = wxy >> bit; /* up bit at 0, left bit at 32 */
+      const uint32_t ub = (uint32_t)b2 & 1u;
+      const uint32_t lb = (uint32_t)(b2 >> 32) & 1u;
+      /* diagonal (0,0): e-1, k-1; up (1,0): e-1; left (x,1): k-1 */
+      e -= (int)(lb ^ 1u);
+      k -= (int)((~ub | lb) & 1u);
       t = e + k;
-      /* stop when 64 cells are gathered, or the walk left the table or the
-       * group (each term < 0 means stop) */
-      if (((63 - qs) | e | k | (t - lower)) < 0) break;
+      /* stop when 64 cells are gathered or the walk left the group (t falls
+       * by 1 or 2 per step, so this also ends a walk that leaves the table;
+       * the caller checks that it ended at the origin) */
+      if (((int)qc | (t - lower)) < 0) break;
     }
-    if (qs == 64) {
+    if ((int)qc < 0) {
       q += 64;
       out[res_end - q + (63 - lane)] = make_int2(PE, PK);
-      qs = 0;
+      qc = QBASE;
     }
     if ((e | k) < 0) break;
     const int gi = t >> LG;
@@ -640,6 +648,7 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
       Tn = ring[((gcur - 1) & (RG - 1)) * 64 + lane];
     }
   }
+  const int qs = (int)(qc - QBASE);
   q += qs;
   if (ok && !(e == -1 && k == -1)) ok = false;
   /* the last qs cells: lane l holds cell q - qs + l counted from the end */
@@ -704,40 +713,50 @@ __global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
 
 /* ------------------------------------------------------- scan + compact */
 
-__global__ __launch_bounds__(1024) void k_scan(const uint64_t *__restrict__ len, int n,
-                                               uint64_t *__restrict__ off) {
-  __shared__ uint64_t part[1024];
-  const int tid = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int lo = min(n, tid * per);
+/* Both kernels run as single-wavefront workgroups: while other batches'
+ * alignment waves hold the chip, a one-wave group takes the first free wave
+ * slot, where a multi-wave group would wait for a CU with that many free
+ * slots at once. */
+__global__ __launch_bounds__(64) void k_scan(const uint64_t *__restrict__ len, int n,
+                                             uint64_t *__restrict__ off) {
+  const int lane = threadIdx.x;
+  const int per = (n + 63) >> 6;
+  const int lo = min(n, lane * per);
   const int hi = min(n, lo + per);
   uint64_t sum = 0;
   for (int r = lo; r < hi; ++r) sum += len[r];
-  part[tid] = sum;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const uint64_t v = tid >= d ? part[tid - d] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  uint64_t inc = sum; /* inclusive scan of the 64 lane sums */
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t v = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += v;
   }
-  uint64_t run = part[tid] - sum;
+  uint64_t run = inc - sum;
   for (int r = lo; r < hi; ++r) {
     off[r] = run;
     run += len[r];
   }
-  if (tid == 1023) off[n] = part[1023];
+  if (lane == 63) off[n] = inc;
 }
 
-__global__ __launch_bounds__(256) void k_compact(const int2 *__restrict__ scratch,
-                                                 const uint64_t *__restrict__ src,
-                                                 const uint64_t *__restrict__ off,
-                                                 int2 *__restrict__ pairs) {
+__global__ __launch_bounds__(64) void k_compact(const int2 *__restrict__ scratch,
+                                                const uint64_t *__restrict__ src,
+                                                const uint64_t *__restrict__ off,
+                                                int2 *__restrict__ pairs) {
   const int r = blockIdx.x;
   const uint64_t o = off[r];
   const uint64_t n = off[r + 1] - o;
-  const uint64_t s0 = src[r];
-  for (uint64_t t = threadIdx.x; t < n; t += blockDim.x) pairs[o + t] = scratch[s0 + t];
+  const int2 *__restrict__ in = scratch + src[r];
+  int2 *__restrict__ out = pairs + o;
+  uint64_t t = threadIdx.x;
+  /* four loads in flight per lane */
+  for (; t + 192 < n; t += 256) {
+    const int2 a = in[t], b = in[t + 64], c = in[t + 128], d = in[t + 192];
+    out[t] = a;
+    out[t + 64] = b;
+    out[t + 128] = c;
+    out[t + 192] = d;
+  }
+  for (; t < n; t += 64) out[t] = in[t];
 }
 
 /* ------------------------------------------------------------- launchers */
@@ -830,14 +849,14 @@ int align_groups_per_cu(int cpl, int rpg, int wpg) {
 }
 
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, len, n, offset);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, len, n, offset);
   return hipGetLastError();
 }
 
 hipError_t launch_compact(const int2 *scratch, const uint64_t *path_src, const uint64_t *offset,
                           int n, int2 *pairs, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact, dim3(n), dim3(256), 0, st, scratch, path_src, offset, pairs);
+  hipLaunchKernelGGL(k_compact, dim3(n), dim3(64), 0, st, scratch, path_src, offset, pairs);
   return hipGetLastError();
 }
 
