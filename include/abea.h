@@ -159,9 +159,12 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *batch,
  * Device time in milliseconds of each stage of the last direct call
  * (abea_align_batch or abea_align_batch_device), when the context was
  * created with ABEA_F_TIMING: out[0] k-mer parameter preparation, out[1] band
- * fill (split kernels) or band fill + backtrack (fused kernel), out[2]
- * backtrack (split kernels; 0 for the fused kernel), out[3] compaction.
- * Synchronises the stream of the last call.  n is the length of out.
+ * fill (split kernels) or band fill + backtrack (fused kernel), from the start
+ * to the end of that kernel's dispatch (time spent waiting for free compute
+ * units behind other work on the device is not counted), out[2] backtrack
+ * (split kernels; 0 for the fused kernel), out[3] path-length scan and
+ * compaction.  Synchronises the stream of the last call.  n is the length of
+ * out.
  */
 int abea_get_timings(abea_ctx *ctx, float *out, int n);
 

@@ -264,20 +264,26 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   a.n_workers = P.workers;
   a.W = ctx->W;
   a.urgent_len = P.urgent_len;
+  /* the band or fused kernel's own start and end: with other batches in
+   * flight its dispatch may wait for free CUs, which these do not count */
+  hipEvent_t k0 = timed ? w.tev[2] : nullptr, k1 = timed ? w.tev[3] : nullptr;
+  const bool launched = n > 0 && (P.workers == 0 || (P.workers > 0 && P.workers <= n));
   if (P.workers == 0) {
-    HIP_TRY(ctx, launch_band(a, P.cpl, refills_per_group(ctx->W, P.cpl), st));
-    if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[2], st));
-    HIP_TRY(ctx, launch_backtrack(a, P.cpl, st));
+    HIP_TRY(ctx, launch_band(a, P.cpl, refills_per_group(ctx->W, P.cpl), st, k0, k1));
   } else {
-    HIP_TRY(ctx, launch_align(a, P.cpl, refills_per_group(ctx->W, P.cpl), P.wpg, st));
-    if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[2], st));
+    HIP_TRY(ctx, launch_align(a, P.cpl, refills_per_group(ctx->W, P.cpl), P.wpg, st, k0, k1));
   }
-  if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[3], st));
+  if (timed && !launched) { /* nothing dispatched: an empty interval */
+    HIP_TRY(ctx, hipEventRecord(w.tev[2], st));
+    HIP_TRY(ctx, hipEventRecord(w.tev[3], st));
+  }
+  if (P.workers == 0) HIP_TRY(ctx, launch_backtrack(a, P.cpl, st));
+  if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[4], st));
 
   HIP_TRY(ctx, launch_scan((const uint64_t *)w.path_len.p, n, io.pair_offset, st));
   HIP_TRY(ctx, launch_compact((const int2 *)w.scratch.p, (const uint64_t *)w.path_src.p,
                               io.pair_offset, n, io.pairs, st));
-  if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[4], st));
+  if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[5], st));
   w.timed = timed;
   return ABEA_OK;
 }
@@ -513,10 +519,12 @@ int abea_get_timings(abea_ctx *ctx, float *out, int n) {
   if (!ctx || !out || n < 0) return ABEA_E_INVAL;
   Work &w = ctx->main;
   if (!w.timed) return fail(ctx, ABEA_E_UNSUPPORTED, "context not created with ABEA_F_TIMING");
-  HIP_TRY(ctx, hipEventSynchronize(w.tev[4]));
+  HIP_TRY(ctx, hipEventSynchronize(w.tev[5]));
+  /* prep, band or fused kernel, backtrack, scan + compaction */
+  static const int from[4] = {0, 2, 3, 4}, to[4] = {1, 3, 4, 5};
   for (int q = 0; q < n && q < 4; ++q) {
     float ms = 0.f;
-    HIP_TRY(ctx, hipEventElapsedTime(&ms, w.tev[q], w.tev[q + 1]));
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, w.tev[from[q]], w.tev[to[q]]));
     out[q] = ms;
   }
   return ABEA_OK;

@@ -102,10 +102,14 @@ hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events
                        const uint32_t *ranks, const uint64_t *in_addr, const float *scale,
                        const float *shift, const ModelEntry *model, uint32_t n_model, float *xmean,
                        KParam *kparam, int32_t *rstat, uint32_t *queue, hipStream_t st);
-hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st);
+/* t0, t1: null, or events that take the start and end time of the kernel's
+ * own dispatch */
+hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st, hipEvent_t t0 = nullptr,
+                       hipEvent_t t1 = nullptr);
 hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st);
 /* fused band + backtrack with a.n_workers wavefronts, wpg per workgroup */
-hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, hipStream_t st);
+hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, hipStream_t st,
+                        hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 /* resident workgroups of the fused kernel per CU (occupancy) */
 int align_groups_per_cu(int cpl, int rpg, int wpg);
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st);

@@ -39,6 +39,8 @@
  */
 #include "abea_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #pragma clang fp contract(off)
@@ -783,12 +785,13 @@ hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events
   if (cpl == 8 && rpg == 2) CALL(8, 2);  \
   if (cpl == 16 && rpg == 1) CALL(16, 1);
 
-hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st) {
+hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st, hipEvent_t t0,
+                       hipEvent_t t1) {
   if (a.n_reads <= 0) return hipSuccess;
-#define ABEA_L(C, R)                                                                    \
-  {                                                                                     \
-    hipLaunchKernelGGL((k_band<C, R>), dim3(a.n_reads), dim3(64), 0, st, a);            \
-    return hipGetLastError();                                                           \
+#define ABEA_L(C, R)                                                                       \
+  {                                                                                        \
+    hipExtLaunchKernelGGL((k_band<C, R>), dim3(a.n_reads), dim3(64), 0, st, t0, t1, 0, a); \
+    return hipGetLastError();                                                              \
   }
   ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
@@ -809,21 +812,23 @@ hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st) {
 }
 
 template <int CPL, int RPG>
-static hipError_t launch_align_c(const AlignArgs &a, int wpg, hipStream_t st) {
+static hipError_t launch_align_c(const AlignArgs &a, int wpg, hipStream_t st, hipEvent_t t0,
+                                 hipEvent_t t1) {
   const dim3 grid((a.n_workers + wpg - 1) / wpg);
   switch (wpg) {
-    case 1: hipLaunchKernelGGL((k_align<CPL, RPG, 1>), grid, dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_align<CPL, RPG, 2>), grid, dim3(128), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_align<CPL, RPG, 4>), grid, dim3(256), 0, st, a); break;
+    case 1: hipExtLaunchKernelGGL((k_align<CPL, RPG, 1>), grid, dim3(64), 0, st, t0, t1, 0, a); break;
+    case 2: hipExtLaunchKernelGGL((k_align<CPL, RPG, 2>), grid, dim3(128), 0, st, t0, t1, 0, a); break;
+    case 4: hipExtLaunchKernelGGL((k_align<CPL, RPG, 4>), grid, dim3(256), 0, st, t0, t1, 0, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, hipStream_t st) {
+hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, hipStream_t st,
+                        hipEvent_t t0, hipEvent_t t1) {
   if (a.n_reads <= 0 || a.n_workers <= 0) return hipSuccess;
   if (a.n_workers > a.n_reads) return hipErrorInvalidValue;
-#define ABEA_L(C, R) return launch_align_c<C, R>(a, wpg, st)
+#define ABEA_L(C, R) return launch_align_c<C, R>(a, wpg, st, t0, t1)
   ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
   return hipErrorInvalidValue;

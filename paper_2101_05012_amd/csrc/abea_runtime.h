@@ -47,7 +47,10 @@ struct Work {
   size_t h_cap = 0;
   hipEvent_t staging_done = nullptr;
   bool staging_pending = false;
-  hipEvent_t tev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  /* timing (ABEA_F_TIMING): before and after k_prep; start and end of the
+   * band or fused kernel, taken from its dispatch (no wait for free CUs
+   * counted); after the backtrack; after the compaction */
+  hipEvent_t tev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
   hipStream_t last_stream = nullptr;
 };
