@@ -8,7 +8,9 @@
  *   - Alg. 5.2 "... cell score computation" (transition constants, the three
  *     moves and the arg-max),
  *   - Alg. 5.3 "... log probability computation" (Gaussian log-emission), with
- *     the read-model scaling paragraph that follows it (mu*scale + shift).
+ *     the per-read scaling paragraph that follows it: the model scaled to the
+ *     events (mu*scale + shift), or, as an option, the events scaled to the
+ *     model ((x - shift)/scale).
  * Where the text is silent or garbled the readings used are listed in the
  * design notes of the repository (band-move direction, initial lower-left,
  * tie-breaks, epsilon = 1e-10, inclusive band limits, global alignment).
@@ -111,11 +113,29 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
   oracle_transitions(n_e, n_k, lp);
   const float lp_skip = lp[0], lp_stay = lp[1], lp_step = lp[2];
 
-  /* Scaled model level of every k-mer of the read (read-model scaling:
-   * mu = level_mean*scale + shift, one rounding; sigma is not scaled). */
+  /* Per-read scaling (paragraph after Alg. 5.3), sigma never scaled:
+   * by default the model level of every k-mer of the read is scaled,
+   * mu = level_mean*scale + shift with one rounding, and the events are used
+   * as they are; with ORACLE_SCALE_EVENTS every event is scaled to the model,
+   * x' = (x - shift)/scale, and the model levels are used as they are. */
   float *mu = (float *)malloc(sizeof(float) * (size_t)n_k);
-  if (!mu) return ORACLE_E_NOMEM;
-  for (int64_t k = 0; k < n_k; ++k) mu[k] = fmaf(level_mean[rank[k]], scale, shift);
+  float *xs = (float *)malloc(sizeof(float) * (size_t)n_e);
+  if (!mu || !xs) {
+    free(mu); free(xs);
+    return ORACLE_E_NOMEM;
+  }
+  const int scale_events = (flags & ORACLE_SCALE_EVENTS) != 0;
+  for (int64_t k = 0; k < n_k; ++k)
+    mu[k] = scale_events ? level_mean[rank[k]] : fmaf(level_mean[rank[k]], scale, shift);
+  for (int64_t e = 0; e < n_e; ++e) {
+    const float x = event_mean[e * event_stride];
+    if (scale_events) {
+      const float d = x - shift;
+      xs[e] = d / scale;
+    } else {
+      xs[e] = x;
+    }
+  }
 
   const int64_t last = n_e + n_k; /* bands 0..last; the last holds (n_e-1, n_k-1) */
   const int64_t nb = last + 1;
@@ -124,7 +144,7 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
   int64_t *E = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
   int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
   if (!S || !T || !E || !K) {
-    free(mu); free(S); free(T); free(E); free(K);
+    free(mu); free(xs); free(S); free(T); free(E); free(K);
     return ORACLE_E_NOMEM;
   }
   st.n_bands = nb;
@@ -183,8 +203,7 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
       const float diag = band_get(S, i - 2, k - 1 - K[i - 2], W);
       const int64_t e_em = (flags & ORACLE_PLANT_EVENT_OFF_BY_ONE) ? (e > 0 ? e - 1 : 0) : e;
       const uint32_t r = rank[k];
-      const float em = oracle_emission(event_mean[e_em * event_stride], mu[k], level_stdv[r],
-                                       c[r], h[r], flags);
+      const float em = oracle_emission(xs[e_em], mu[k], level_stdv[r], c[r], h[r], flags);
       const float score_d = (diag + lp_step) + em;
       const float score_u = (flags & ORACLE_PLANT_DROP_UP_EMISSION) ? (up + lp_stay)
                                                                     : (up + lp_stay) + em;
@@ -220,8 +239,8 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
         const float left = band_get(S, i - 1, k - 1 - K[i - 1], W);
         const float diag = band_get(S, i - 2, k - 1 - K[i - 2], W);
         const uint32_t r = rank[k];
-        const float em = oracle_emission(event_mean[e * event_stride], mu[k], level_stdv[r],
-                                         c[r], h[r], flags & ORACLE_FORM_LITERAL);
+        const float em = oracle_emission(xs[e], mu[k], level_stdv[r], c[r], h[r],
+                                         flags & ORACLE_FORM_LITERAL);
         double cand[3] = {(double)((diag + lp_step) + em), (double)((up + lp_stay) + em),
                           (double)(left + lp_skip)};
         double best = cand[d - 1], second = -INFINITY;
@@ -261,7 +280,7 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
       ll_out[2 * i + 1] = K[i];
     }
   if (stats) *stats = st;
-  free(mu); free(S); free(T); free(E); free(K);
+  free(mu); free(xs); free(S); free(T); free(E); free(K);
   return status;
 }
 

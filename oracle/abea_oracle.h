@@ -39,7 +39,13 @@ enum {
   ORACLE_PLANT_DROP_UP_EMISSION = 4u,
   /* PLANTED MISTAKE for tests only: uses the event index of the diagonal
    * neighbour (e-1) in the emission. */
-  ORACLE_PLANT_EVENT_OFF_BY_ONE = 8u
+  ORACLE_PLANT_EVENT_OFF_BY_ONE = 8u,
+  /* Events scaled to the model instead of the model to the events (the
+   * per-read scaling paragraph after Alg. 5.3 allows either): every event
+   * mean becomes x' = (x - shift) / scale (float32 subtract, then IEEE
+   * float32 divide), and the model levels are used unscaled.  sigma is not
+   * scaled in either mode. */
+  ORACLE_SCALE_EVENTS = 16u
 };
 
 typedef struct {

@@ -27,6 +27,7 @@ FORM_LITERAL = 1
 PLANT_SK_REVERSED = 2
 PLANT_DROP_UP_EMISSION = 4
 PLANT_EVENT_OFF_BY_ONE = 8
+SCALE_EVENTS = 16  # events scaled to the model: x' = (x - shift) / scale, model levels unscaled
 
 GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-pthread"]
 

@@ -483,3 +483,78 @@ def test_batch_driver_matches_single_read_calls(oracle_mod, model6):
         r = oracle_mod.align(rd.events, rd.ranks, model6, rd.scale, rd.shift, 100)
         assert rb.status[i] == r.status and rb.score[i] == r.score and rb.cells[i] == r.cells
         assert np.array_equal(rb.read_pairs(i), r.pairs)
+
+
+# ---------------------------------------------------------------- P9 events scaled to the model
+
+def scaled_events_f32(x, sc, sh):
+    """x' = (x - shift) / scale, each operation rounded to float32 (numpy's
+    float32 arithmetic is IEEE round-to-nearest-even)."""
+    x = np.asarray(x, np.float32)
+    return (x - F32(sh)) / F32(sc)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_scale_events_single_cell_is_gaussian_of_scaled_event(oracle_mod, model6, seed):
+    """Paragraph after Alg. 5.3, events scaled to the model: a one-event,
+    one-k-mer read scores lp_step + ln N((x - shift)/scale; mu, sigma) with the
+    model level unscaled.  Reference in double precision from scipy; a shift
+    added instead of subtracted, a product instead of a quotient, or a model
+    level still scaled moves the score far outside the tolerance."""
+    rng = np.random.default_rng(500 + seed)
+    lp_step = float(oracle_mod.transitions(1, 1)[2])
+    for _ in range(300):
+        r = int(rng.integers(0, model6.n))
+        sc = F32(rng.uniform(0.8, 1.25))
+        sh = F32(rng.choice([-1, 1]) * rng.uniform(1.0, 5.0))
+        mu = float(model6.level_mean[r])
+        sigma = float(model6.level_stdv[r])
+        x = F32((mu + rng.normal(0, 2 * sigma)) * float(sc) + float(sh))
+        res = oracle_mod.align(np.array([x], np.float32), np.array([r], np.uint32), model6, sc, sh, 100,
+                               flags=oracle_mod.SCALE_EVENTS)
+        assert res.status == 0 and res.pairs.tolist() == [[0, 0]]
+        xp = (float(x) - float(sh)) / float(sc)
+        ref = lp_step + stats.norm.logpdf(xp, mu, sigma)
+        # float32 rounding of x', of the emission's four operations and of the two adds
+        tol = 8 * float(np.spacing(F32(max(1.0, abs(ref))))) + abs(xp - mu) / sigma ** 2 * abs(xp) * 2.0 ** -22
+        assert abs(float(res.score) - ref) <= tol, (x, sc, sh, r, res.score, ref)
+
+
+@pytest.mark.parametrize("shift", [0.0, 3.0, -4.5])
+def test_scale_events_at_unit_scale_equals_model_scaling_exactly(oracle_mod, shift):
+    """With scale 1 both modes compare x - (m + shift) and (x - shift) - m.
+    On inputs where both are exact (model levels and events on a 1/64 grid)
+    they are the same number, so the two modes give identical alignments."""
+    rng = np.random.default_rng(77)
+    n_model = 4 ** 4
+    lm = (rng.integers(60 * 64, 130 * 64, n_model) / 64.0).astype(np.float32)
+    ls = rng.uniform(1.0, 3.0, n_model).astype(np.float32)
+    M = oracle_mod.Model(lm, ls)
+    for _ in range(6):
+        n_k = int(rng.integers(50, 200))
+        ranks = rng.integers(0, n_model, n_k).astype(np.uint32)
+        owner = np.sort(rng.integers(0, n_k, int(1.7 * n_k)))
+        x = (lm[ranks[owner]] + rng.integers(-3 * 64, 3 * 64, owner.size) / 64.0 + shift).astype(np.float32)
+        a = oracle_mod.align(x, ranks, M, 1.0, shift, 100)
+        b = oracle_mod.align(x, ranks, M, 1.0, shift, 100, flags=oracle_mod.SCALE_EVENTS)
+        assert a.status == b.status == 0
+        assert a.score == b.score and np.array_equal(a.pairs, b.pairs) and a.cells == b.cells
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_scale_events_banded_score_equals_best_path_by_brute_force(oracle_mod, model2, seed):
+    """The max-plus recurrence over scaled events: with a band covering the
+    table the oracle's score is the best float32 path sum over every path,
+    and its path is one of the best."""
+    rng = np.random.default_rng(900 + seed)
+    n_e = int(rng.integers(1, 8))
+    n_k = int(rng.integers(1, 6))
+    x, ranks, sc, sh = tiny_read(rng, n_e, n_k, model2)
+    W = 2 * (n_e + n_k) + 4
+    res = oracle_mod.align(x, ranks, model2, sc, sh, W, flags=oracle_mod.SCALE_EVENTS)
+    lp = lp_consts(oracle_mod, n_e, n_k)
+    # scaled events against the unscaled model: scale 1 and shift 0 in the helper
+    best, paths = brute_force(scaled_events_f32(x, sc, sh), ranks, model2, 1.0, 0.0, lp)
+    assert res.status == 0
+    assert res.score == best
+    assert [tuple(p) for p in res.pairs.tolist()] in [list(map(tuple, p)) for p in paths]
