@@ -65,6 +65,8 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 WORKLOADS = {
     "plain-4000-lognormal5kb": dict(kind="plain", config=1, W=100, k=6),
     "plain-64x1kb": dict(kind="plain", config=0, W=100, k=6),
+    # the same 4000 reads with the events scaled to the model instead
+    "plain-4000-lognormal5kb-scale-events": dict(kind="plain", config=1, W=100, k=6, scale_events=True),
     "uneven-20000-w100": dict(kind="persistent", config=2, W=100, k=6, plain_batches=5),
     "uneven-20000-w200": dict(kind="persistent", config=2, W=200, k=6, plain_batches=5),
     "ultralong-200-w100": dict(kind="persistent", config=4, W=100, k=6, plain_batches=1),
@@ -88,7 +90,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(batch, model, W, idx, what):
+def cpu_baseline(batch, model, W, idx, what, scale_events=False):
     """The oracle on the host's cores (up to 16 threads) over reads idx."""
     from oracle import oracle as O
 
@@ -96,7 +98,7 @@ def cpu_baseline(batch, model, W, idx, what):
     sub = batch.subset(idx)
     om = O.Model(model.level_mean, model.level_stdv)
     t0 = time.perf_counter()
-    res = O.align_batch(sub, om, W, n_threads=cores)
+    res = O.align_batch(sub, om, W, n_threads=cores, flags=O.SCALE_EVENTS if scale_events else 0)
     dt = time.perf_counter() - t0
     cells = int(res.cells.sum())
     return {
@@ -167,7 +169,8 @@ def bench_plain(args, wl):
     slots = []
     for _ in range(P):
         al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True,
-                          workers=args.workers, waves_per_group=args.wpg)
+                          workers=args.workers, waves_per_group=args.wpg,
+                          scale_events=wl.get("scale_events", False))
         slots.append((al, abea.DeviceResult.empty(db, dev), torch.cuda.Stream(dev)))
     torch.cuda.synchronize()
 
@@ -223,6 +226,7 @@ def bench_plain(args, wl):
         "parallelism": "one wavefront per read",
         "launch": "fused band+backtrack, one launch per batch" if fused else "band and backtrack kernels",
         "batches_in_flight": P,
+        "per_read_scaling": "events to the model" if wl.get("scale_events") else "model to the events",
     })
     out.update({
         "reads_per_s": round(n * args.steps / dt, 1),
@@ -242,7 +246,8 @@ def bench_plain(args, wl):
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         idx = list(range(min(args.cpu_sample_reads, n)))
-        out["cpu_baseline"] = cpu_baseline(batch, model, W, idx, f"reads 0..{len(idx) - 1} of the same workload")
+        out["cpu_baseline"] = cpu_baseline(batch, model, W, idx, f"reads 0..{len(idx) - 1} of the same workload",
+                                           scale_events=wl.get("scale_events", False))
     return out
 
 

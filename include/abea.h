@@ -52,6 +52,15 @@ extern "C" {
 
 /* ---- config flags -------------------------------------------------------- */
 #define ABEA_F_TIMING 1u /* record device time of every kernel of each call (abea_get_timings) */
+/* Scale the events to the model instead of the model to the events (the
+ * per-read scaling paragraph after Alg. 5.3 allows either side; the thesis's
+ * CLI calls it --scale-events): every event mean becomes
+ * x' = (x - shift[r]) / scale[r] (float32 subtract, then correctly rounded
+ * float32 divide) and the model levels are used unscaled.  Without the flag
+ * the model is scaled: mu' = fmaf(level_mean, scale[r], shift[r]).  sigma is
+ * unscaled in both modes.  scale[r] must be finite and non-zero. */
+#define ABEA_F_SCALE_EVENTS 2u
+#define ABEA_F_ALL (ABEA_F_TIMING | ABEA_F_SCALE_EVENTS)
 
 /* One event of the event table (Alg. 5.1 input "events[]": mean, stdv, n).
  * 12 bytes; only .mean is read (Alg. 5.3). */

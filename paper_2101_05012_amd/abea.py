@@ -29,6 +29,7 @@ READ_OK, READ_EMPTY, READ_BAND_LOST, READ_BAD_RANK = 0, 1, 2, 3
 ABEA_MAX_BANDWIDTH = 512
 ABEA_MAX_K = 12
 ABEA_F_TIMING = 1
+ABEA_F_SCALE_EVENTS = 2  # events scaled to the model: (x - shift) / scale
 ABEA_WORKERS_SPLIT = -1
 
 EXPORTED = (
@@ -304,10 +305,12 @@ class Aligner:
         workers: int = 0,
         waves_per_group: int = 1,
         cells_per_lane: int = 0,
+        scale_events: bool = False,
     ):
         self._lm = np.ascontiguousarray(level_mean, np.float32)
         self._ls = np.ascontiguousarray(level_stdv, np.float32)
-        cfg = abea_config_t(W, device, int(arena_bytes), ABEA_F_TIMING if timing else 0)
+        flags = (ABEA_F_TIMING if timing else 0) | (ABEA_F_SCALE_EVENTS if scale_events else 0)
+        cfg = abea_config_t(W, device, int(arena_bytes), flags)
         mdl = abea_model_t(k, self._lm.ctypes.data, self._ls.ctypes.data)
         h = ctypes.c_void_p()
         rc = lib().abea_create(ctypes.byref(cfg), ctypes.byref(mdl), ctypes.byref(h))

@@ -243,7 +243,8 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   int32_t *rstat = (int32_t *)w.rstat.p;
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[0], st));
   HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ranks, io.in_addr, io.scale, io.shift,
-                           (const ModelEntry *)ctx->model.p, ctx->n_model, (float *)w.xmean.p,
+                           (const ModelEntry *)ctx->model.p, ctx->n_model,
+                           (ctx->flags & ABEA_F_SCALE_EVENTS) != 0, (float *)w.xmean.p,
                            (KParam *)w.kparam.p, rstat, (uint32_t *)w.queue.p, st));
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[1], st));
 
@@ -339,6 +340,7 @@ int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **
   *out = nullptr;
   if (cfg->bandwidth < 2 || cfg->bandwidth > ABEA_MAX_BANDWIDTH) return ABEA_E_INVAL;
   if (model->k < 1 || model->k > ABEA_MAX_K) return ABEA_E_INVAL;
+  if (cfg->flags & ~ABEA_F_ALL) return ABEA_E_INVAL;
   if (!model->level_mean || !model->level_stdv) return ABEA_E_INVAL;
   const uint32_t n_model = 1u << (2 * model->k);
   std::vector<ModelEntry> me(n_model);

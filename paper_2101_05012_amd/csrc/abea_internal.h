@@ -98,10 +98,13 @@ struct AlignArgs {
 /* in_addr: null, or per original read index r the device addresses of its
  * events (in_addr[2r]) and ranks (in_addr[2r+1]), used instead of the batch
  * arrays. */
+/* scale_events: event means become (x - shift)/scale and the model levels
+ * stay unscaled, instead of mu' = fmaf(level, scale, shift) */
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
                        const uint32_t *ranks, const uint64_t *in_addr, const float *scale,
-                       const float *shift, const ModelEntry *model, uint32_t n_model, float *xmean,
-                       KParam *kparam, int32_t *rstat, uint32_t *queue, hipStream_t st);
+                       const float *shift, const ModelEntry *model, uint32_t n_model,
+                       bool scale_events, float *xmean, KParam *kparam, int32_t *rstat,
+                       uint32_t *queue, hipStream_t st);
 /* t0, t1: null, or events that take the start and end time of the kernel's
  * own dispatch */
 hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st, hipEvent_t t0 = nullptr,

@@ -108,6 +108,7 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
                                               const float *__restrict__ scale,
                                               const float *__restrict__ shift,
                                               const ModelEntry *__restrict__ model, uint32_t n_model,
+                                              int scale_events,
                                               float *__restrict__ xmean,
                                               KParam *__restrict__ kparam,
                                               int32_t *__restrict__ rstat,
@@ -133,7 +134,9 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
     p.mu = p.c = p.h = p.pad = 0.0f;
     if (r < n_model) {
       const ModelEntry me = model[r];
-      p.mu = __builtin_fmaf(me.mean, sc, sh);
+      /* per-read scaling (paragraph after Alg. 5.3): the model to the
+       * events with one rounding, or, scaling the events instead, unscaled */
+      p.mu = scale_events ? me.mean : __builtin_fmaf(me.mean, sc, sh);
       p.c = me.c;
       p.h = me.h;
     } else {
@@ -141,7 +144,15 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
     }
     kparam[rd.km_off + k] = p;
   }
-  for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) xmean[rd.ev_off + e] = ev[3 * e];
+  if (scale_events) {
+    /* x' = (x - shift) / scale: float32 subtract, correctly rounded divide */
+    for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) {
+      const float d = ev[3 * e] - sh;
+      xmean[rd.ev_off + e] = d / sc;
+    }
+  } else {
+    for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) xmean[rd.ev_off + e] = ev[3 * e];
+  }
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) rstat[blockIdx.x] = bad ? READ_BAD_RANK : READ_OK;
 }
@@ -765,11 +776,12 @@ __global__ __launch_bounds__(64) void k_compact(const int2 *__restrict__ scratch
 
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
                        const uint32_t *ranks, const uint64_t *in_addr, const float *scale,
-                       const float *shift, const ModelEntry *model, uint32_t n_model, float *xmean,
-                       KParam *kparam, int32_t *rstat, uint32_t *queue, hipStream_t st) {
+                       const float *shift, const ModelEntry *model, uint32_t n_model,
+                       bool scale_events, float *xmean, KParam *kparam, int32_t *rstat,
+                       uint32_t *queue, hipStream_t st) {
   if (n_planned <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(256), 0, st, reads, events, ranks, in_addr, scale,
-                     shift, model, n_model, xmean, kparam, rstat, queue);
+                     shift, model, n_model, (int)scale_events, xmean, kparam, rstat, queue);
   return hipGetLastError();
 }
 
