@@ -438,7 +438,7 @@ def bench_serving(args, wl):
         srv = abea.Server(al, slots=args.slots, max_batch_reads=args.batch_reads, trace_budget_bytes=budget,
                           host_staging_bytes=int(args.host_staging_gb * (1 << 30)))
         log(f"bench: serving x{comp} {n} reads")
-        res = serving.run(srv, sub, arr[:n], compression=float(comp))
+        res = serving.run(srv, sub, arr[:n], compression=float(comp), submitters=args.submitters)
         srv.close()
         s = serving.summarize(res, sub, float(comp), arr[:n])
         log(f"bench: {s}")
@@ -467,6 +467,7 @@ def bench_serving(args, wl):
         "parallelism": "continuous batching: micro-batches on several streams, one wavefront per read",
         "slots": args.slots,
         "max_batch_reads": args.batch_reads,
+        "submitters": args.submitters,
         "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
         "host_staging_gb": args.host_staging_gb,
         "trace_budget_gb": budget / 1e9,
@@ -535,6 +536,7 @@ def main():
                     help="persistent: only the first N reads of the workload (quick runs; 0 = all)")
     ap.add_argument("--slots", type=int, default=16, help="serving: micro-batches on the device at once")
     ap.add_argument("--batch-reads", type=int, default=256, help="serving: reads per micro-batch")
+    ap.add_argument("--submitters", type=int, default=4, help="serving: sequencer threads handing reads to the server")
     ap.add_argument("--host-staging-gb", type=float, default=6.0,
                     help="serving: pinned host arena for queued reads (GiB)")
     ap.add_argument("--hw-queues", type=int, default=16,

@@ -299,6 +299,11 @@ typedef struct {
    * micro-batches): enqueueing copies and kernels, from enqueue to results on
    * the host, and turning finished micro-batches into results */
   uint64_t enqueue_ns, device_ns, harvest_ns;
+  /* time spent inside abea_server_submit, summed over calls and threads,
+   * and the part of it spent taking host buffers and copying reads in */
+  uint64_t submit_ns, submit_copy_ns;
+  /* reads that found the pinned arena full and took a pageable buffer */
+  uint64_t pageable_reads;
 } abea_server_stats_t;
 
 typedef struct abea_server abea_server;
@@ -320,7 +325,9 @@ int abea_server_submit(abea_server *server, const abea_batch_t *reads, const uin
 
 /* Collect up to max_out finished reads, waiting up to timeout_us for the
  * first; their pairs are copied into pairs[] (capacity pair_capacity), read
- * i's at out[i].pair_offset.  *n_out receives the count (0 on timeout).
+ * i's at out[i].pair_offset.  pairs = NULL takes the results without their
+ * pairs (out[i].n_pairs still counts them; pair_capacity is ignored).
+ * *n_out receives the count (0 on timeout).  Several threads may poll.
  * Errors: ABEA_E_CAPACITY if the next result's pairs do not fit (nothing
  * taken), or the background thread's sticky error. */
 int abea_server_poll(abea_server *server, abea_completion_t *out, int max_out, abea_pair_t *pairs,

@@ -185,6 +185,9 @@ class abea_server_stats_t(ctypes.Structure):
         ("enqueue_ns", ctypes.c_uint64),
         ("device_ns", ctypes.c_uint64),
         ("harvest_ns", ctypes.c_uint64),
+        ("submit_ns", ctypes.c_uint64),
+        ("submit_copy_ns", ctypes.c_uint64),
+        ("pageable_reads", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -557,11 +560,12 @@ class Server:
         or None when want_pairs is False)."""
         if self._out.shape[0] < max_out:
             self._out = np.zeros(max_out, COMPLETION_DTYPE)
-        if self._pairs.shape[0] < pair_capacity:
+        if want_pairs and self._pairs.shape[0] < pair_capacity:
             self._pairs = np.zeros((pair_capacity, 2), np.int32)
         n = ctypes.c_int(0)
-        rc = lib().abea_server_poll(self.handle, _ptr(self._out), int(max_out), _ptr(self._pairs),
-                                    int(self._pairs.shape[0]), int(timeout_us), ctypes.byref(n))
+        pp, cap = (_ptr(self._pairs), int(self._pairs.shape[0])) if want_pairs else (None, 0)
+        rc = lib().abea_server_poll(self.handle, _ptr(self._out), int(max_out), pp, cap, int(timeout_us),
+                                    ctypes.byref(n))
         if rc == ABEA_E_CAPACITY:  # the next result is larger: grow and retry
             self._pairs = np.zeros((self._pairs.shape[0] * 4, 2), np.int32)
             return self.poll(max_out, timeout_us, self._pairs.shape[0], want_pairs)

@@ -96,8 +96,8 @@ struct AlignArgs {
 
 /* Kernel launchers (abea_kernels.hip). */
 /* in_addr: null, or per original read index r the device addresses of its
- * events (in_addr[2r]) and ranks (in_addr[2r+1]), used instead of the batch
- * arrays. */
+ * event means (in_addr[2r], one float per event) and ranks (in_addr[2r+1]),
+ * used instead of the batch arrays. */
 /* scale_events: event means become (x - shift)/scale and the model levels
  * stay unscaled, instead of mu' = fmaf(level, scale, shift) */
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,

@@ -120,9 +120,11 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
     if (threadIdx.x == 0) rstat[blockIdx.x] = READ_EMPTY;
     return;
   }
-  /* the read's events and ranks: in the batch arrays at its offsets, or
-   * (in_addr) at addresses of its own, e.g. in mapped host memory */
+  /* the read's events and ranks: in the batch arrays at its offsets (12-byte
+   * events, the mean first), or (in_addr) at addresses of its own, e.g. in
+   * mapped host memory, where only the event means are stored */
   const float *ev = in_addr ? reinterpret_cast<const float *>(in_addr[2 * rd.orig]) : events + 3 * rd.ev_off;
+  const int ev_stride = in_addr ? 1 : 3;
   const uint32_t *rk =
       in_addr ? reinterpret_cast<const uint32_t *>(in_addr[2 * rd.orig + 1]) : ranks + rd.km_off;
   const float sc = scale[rd.orig];
@@ -147,11 +149,11 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
   if (scale_events) {
     /* x' = (x - shift) / scale: float32 subtract, correctly rounded divide */
     for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) {
-      const float d = ev[3 * e] - sh;
+      const float d = ev[ev_stride * e] - sh;
       xmean[rd.ev_off + e] = d / sc;
     }
   } else {
-    for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) xmean[rd.ev_off + e] = ev[3 * e];
+    for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) xmean[rd.ev_off + e] = ev[ev_stride * e];
   }
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) rstat[blockIdx.x] = bad ? READ_BAD_RANK : READ_OK;

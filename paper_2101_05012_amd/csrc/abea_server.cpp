@@ -151,7 +151,8 @@ struct Owned {
   Owned &operator=(const Owned &) = delete;
 };
 
-/* A queued read: events then k-mer ranks in one pooled pinned buffer. */
+/* A queued read: its event means (the only event field the alignment
+ * reads) then its k-mer ranks, in one pooled pinned buffer. */
 struct SrvRead {
   uint64_t tag = 0;
   int64_t t_arrival = 0;
@@ -162,8 +163,8 @@ struct SrvRead {
   uint64_t ne = 0, nk = 0;
   float scale = 1.f, shift = 0.f;
   uint64_t trace_bytes = 0;
-  const abea_event_t *events() const { return reinterpret_cast<const abea_event_t *>(buf.p); }
-  const uint32_t *ranks() const { return reinterpret_cast<const uint32_t *>(buf.p + ne * sizeof(abea_event_t)); }
+  const float *means() const { return reinterpret_cast<const float *>(buf.p); }
+  const uint32_t *ranks() const { return reinterpret_cast<const uint32_t *>(buf.p + ne * sizeof(float)); }
 };
 
 /* A finished read; its pairs wait in its slot's pinned result buffer, which
@@ -183,7 +184,7 @@ struct Slot {
   /* mapped pinned staging of reads whose buffer is not pinned (the prep
    * kernel reads it in place), pinned staging of the small inputs and of the
    * results */
-  abea_event_t *h_ev = nullptr;
+  float *h_ev = nullptr; /* event means */
   uint32_t *h_rk = nullptr;
   uint64_t dh_ev = 0, dh_rk = 0; /* their device addresses */
   uint64_t *h_addr = nullptr;    /* per read: device addresses of its events, ranks */
@@ -357,11 +358,11 @@ int slot_launch(abea_server *S, Slot &s) {
     uint64_t a_ev, a_rk;
     if (R.pinned) {
       a_ev = S->pool.dev_addr(R.buf.p);
-      a_rk = a_ev + R.ne * sizeof(abea_event_t);
+      a_rk = a_ev + R.ne * sizeof(float);
     } else {
-      if (R.ne) std::memcpy(s.h_ev + s.h_eo[r], R.events(), sizeof(abea_event_t) * R.ne);
+      if (R.ne) std::memcpy(s.h_ev + s.h_eo[r], R.means(), sizeof(float) * R.ne);
       if (R.nk) std::memcpy(s.h_rk + s.h_ko[r], R.ranks(), sizeof(uint32_t) * R.nk);
-      a_ev = s.dh_ev + s.h_eo[r] * sizeof(abea_event_t);
+      a_ev = s.dh_ev + s.h_eo[r] * sizeof(float);
       a_rk = s.dh_rk + s.h_ko[r] * sizeof(uint32_t);
     }
     s.h_addr[2 * r] = a_ev;
@@ -603,6 +604,7 @@ int abea_server_submit(abea_server *S, const abea_batch_t *b, const uint64_t *ta
   if (b->n_reads < 0 || !b->event_offset || !b->kmer_offset) return fail(ctx, ABEA_E_INVAL, "bad batch");
   const int n = b->n_reads;
   if (n == 0) return ABEA_OK;
+  const int64_t t_entry = now_ns();
   if (!b->scale || !b->shift) return fail(ctx, ABEA_E_INVAL, "null scale/shift");
   const uint64_t *eo = b->event_offset, *ko = b->kmer_offset;
   if (eo[0] != 0 || ko[0] != 0) return fail(ctx, ABEA_E_INVAL, "offsets must start at 0");
@@ -620,6 +622,7 @@ int abea_server_submit(abea_server *S, const abea_batch_t *b, const uint64_t *ta
                   (unsigned long long)trace_bytes_of(S->G, ne, nk));
   }
   const int64_t t = now_ns();
+  uint64_t n_pageable = 0;
   std::vector<SrvRead> rs(n);
   for (int r = 0; r < n; ++r) {
     SrvRead &R = rs[r];
@@ -628,17 +631,24 @@ int abea_server_submit(abea_server *S, const abea_batch_t *b, const uint64_t *ta
     R.t_arrival = arrival_ns ? arrival_ns[r] : t;
     R.ne = ne;
     R.nk = nk;
-    R.buf.p = S->pool.get(ne * sizeof(abea_event_t) + nk * sizeof(uint32_t), &R.buf_cls, &R.pinned);
+    R.buf.p = S->pool.get(ne * sizeof(float) + nk * sizeof(uint32_t), &R.buf_cls, &R.pinned);
     if (!R.buf.p) {
       release_reads(S, rs);
       return fail(ctx, ABEA_E_NOMEM, "pinned host buffer for read %d", r);
     }
-    if (ne) std::memcpy(R.buf.p, b->events + eo[r], sizeof(abea_event_t) * ne);
-    if (nk) std::memcpy(R.buf.p + ne * sizeof(abea_event_t), b->kmer_rank + ko[r], sizeof(uint32_t) * nk);
+    {
+      /* only the event means are kept: 4 of the event's 12 bytes */
+      float *dst = reinterpret_cast<float *>(R.buf.p);
+      const abea_event_t *src = b->events + eo[r];
+      for (uint64_t e = 0; e < ne; ++e) dst[e] = src[e].mean;
+    }
+    if (nk) std::memcpy(R.buf.p + ne * sizeof(float), b->kmer_rank + ko[r], sizeof(uint32_t) * nk);
     R.scale = b->scale[r];
     R.shift = b->shift[r];
     R.trace_bytes = trace_bytes_of(S->G, ne, nk);
+    n_pageable += R.pinned ? 0 : 1;
   }
+  const int64_t t_copied = now_ns();
   {
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->error || S->stop) {
@@ -653,6 +663,9 @@ int abea_server_submit(abea_server *S, const abea_batch_t *b, const uint64_t *ta
     }
     S->n_pending += (uint64_t)n;
     S->stats.submitted += (uint64_t)n;
+    S->stats.submit_ns += (uint64_t)(now_ns() - t_entry);
+    S->stats.submit_copy_ns += (uint64_t)(t_copied - t);
+    S->stats.pageable_reads += n_pageable;
   }
   S->cv_work.notify_one();
   return ABEA_OK;
@@ -664,36 +677,46 @@ int abea_server_poll(abea_server *S, abea_completion_t *out, int max_out, abea_p
   abea_ctx *ctx = S->ctx;
   if (!n_out || (max_out > 0 && !out)) return fail(ctx, ABEA_E_INVAL, "null output");
   *n_out = 0;
-  std::unique_lock<std::mutex> lk(S->mu);
-  if (S->done.empty() && timeout_us > 0 && !S->error)
-    S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us),
-                        [&] { return !S->done.empty() || S->error; });
-  if (S->done.empty() && S->error) return fail(ctx, S->error, "%s", S->err.c_str());
-  uint64_t used = 0;
-  int k = 0;
-  bool freed = false; /* a slot's results are all taken: it can run again */
-  while (k < max_out && !S->done.empty()) {
-    Done &d = S->done.front();
-    const uint64_t np = d.c.n_pairs;
-    if (used + np > pair_capacity) {
-      if (k == 0) {
-        *n_out = 0;
-        return fail(ctx, ABEA_E_CAPACITY, "next result has %llu pairs; pair capacity %llu",
-                    (unsigned long long)np, (unsigned long long)pair_capacity);
+  /* take the results under the lock; copy their pairs after releasing it
+   * (a slot is not reused while results of it are outstanding, so its
+   * buffers stay valid), then count them off */
+  std::vector<Done> taken;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->done.empty() && timeout_us > 0 && !S->error)
+      S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us),
+                          [&] { return !S->done.empty() || S->error; });
+    if (S->done.empty() && S->error) return fail(ctx, S->error, "%s", S->err.c_str());
+    uint64_t used = 0;
+    while ((int)taken.size() < max_out && !S->done.empty()) {
+      Done &d = S->done.front();
+      const uint64_t np = d.c.n_pairs;
+      if (pairs && used + np > pair_capacity) {
+        if (taken.empty())
+          return fail(ctx, ABEA_E_CAPACITY, "next result has %llu pairs; pair capacity %llu",
+                      (unsigned long long)np, (unsigned long long)pair_capacity);
+        break;
       }
-      break;
+      d.c.pair_offset = pairs ? used : 0;
+      used += pairs ? np : 0;
+      taken.push_back(d);
+      S->done.pop_front();
     }
-    Slot &s = S->slots[d.slot];
-    if (np) std::memcpy(pairs + used, s.h_pairs + d.off, sizeof(abea_pair_t) * np);
-    out[k] = d.c;
-    out[k].pair_offset = used;
-    used += np;
-    ++k;
-    if (--s.outstanding == 0) freed = true;
-    S->done.pop_front();
+  }
+  const int k = (int)taken.size();
+  for (int i = 0; i < k; ++i) {
+    const Done &d = taken[i];
+    if (pairs && d.c.n_pairs)
+      std::memcpy(pairs + d.c.pair_offset, S->slots[d.slot].h_pairs + d.off, sizeof(abea_pair_t) * d.c.n_pairs);
+    out[i] = d.c;
+  }
+  bool freed = false; /* a slot's results are all taken: it can run again */
+  if (k) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (const Done &d : taken)
+      if (--S->slots[d.slot].outstanding == 0) freed = true;
   }
   *n_out = k;
-  lk.unlock();
   if (freed) S->cv_work.notify_one();
   return ABEA_OK;
 }

@@ -28,11 +28,14 @@ def run(server: abea.Server, batch, arrivals_s: np.ndarray, compression: float =
     assert arrivals_s.shape[0] == n and np.all(np.diff(arrivals_s) >= 0)
     t0 = abea.now_ns() + 2_000_000  # start 2 ms from now
     target = t0 + (arrivals_s / compression * 1e9).astype(np.int64)
+    submitted = np.zeros(n, np.int64)  # when each read's submit call returned
+    call_ns = []  # per submitter: time spent inside submit calls
     err = []
 
     def submitter(mine: np.ndarray):
         """Hand reads `mine` (sorted) to the server at their arrival times;
         several submitters share the copying of arriving reads."""
+        spent = 0
         try:
             i = 0
             m = mine.shape[0]
@@ -53,18 +56,23 @@ def run(server: abea.Server, batch, arrivals_s: np.ndarray, compression: float =
                     while b < j and int(mine[b]) == int(mine[b - 1]) + 1:
                         b += 1
                     last = int(mine[b - 1])
+                    c0 = abea.now_ns()
                     server.submit(batch, a, last + 1, np.arange(a, last + 1, dtype=np.uint64), target[a:last + 1])
+                    c1 = abea.now_ns()
+                    spent += c1 - c0
+                    submitted[a : last + 1] = c1
                     i = b
         except Exception as e:  # surfaced by the collector
             err.append(e)
+        call_ns.append(spent)
 
     T = max(1, min(int(submitters), n))
     if T == 1:
         parts = [np.arange(n)]
     else:
-        # contiguous blocks of 8 reads dealt round robin: each submitter keeps
-        # short consecutive runs
-        blk = np.arange(n) // 8
+        # contiguous blocks of 64 reads dealt round robin: a submitter that
+        # is behind hands a whole run of due reads over in one call
+        blk = np.arange(n) // 64
         parts = [np.nonzero(blk % T == t)[0] for t in range(T)]
     threads = [threading.Thread(target=submitter, args=(p,), daemon=True) for p in parts]
     for th in threads:
@@ -93,7 +101,8 @@ def run(server: abea.Server, batch, arrivals_s: np.ndarray, compression: float =
         raise err[0]
     comp = np.concatenate(comps)
     comp = comp[np.argsort(comp["tag"])]
-    return {"completions": comp, "pairs": pairs, "t0": t0, "stats": server.stats()}
+    return {"completions": comp, "pairs": pairs, "t0": t0, "stats": server.stats(),
+            "submit_lag_ns": submitted - target, "submit_call_ns": call_ns}
 
 
 def summarize(res: Dict, batch, compression: float, arrivals_s: np.ndarray) -> Dict:
@@ -120,6 +129,12 @@ def summarize(res: Dict, batch, compression: float, arrivals_s: np.ndarray) -> D
         "latency_ms_reads_below_median_length": {"p50": pct(lat_ms[~long], 50), "p99": pct(lat_ms[~long], 99)},
         "latency_ms_reads_above_median_length": {"p50": pct(lat_ms[long], 50), "p99": pct(lat_ms[long], 99)},
         "admission_wait_ms": {"p50": pct(wait_ms, 50), "p99": pct(wait_ms, 99)},
+        # arrival -> the submit call returned (the simulated sequencer's own lag)
+        "submit_lag_ms": {"p50": pct(res["submit_lag_ns"] / 1e6, 50), "p99": pct(res["submit_lag_ns"] / 1e6, 99)},
+        "submit_calls_s": round(sum(res["submit_call_ns"]) / 1e9, 3),
+        "submit_in_library_s": round(st["submit_ns"] / 1e9, 3),
+        "submit_copy_s": round(st["submit_copy_ns"] / 1e9, 3),
+        "pageable_reads": st["pageable_reads"],
         "micro_batches": st["micro_batches"],
         "max_inflight_reads": st["max_inflight_reads"],
         "max_inflight_trace_mb": round(st["max_inflight_trace_bytes"] / 1e6, 1),
