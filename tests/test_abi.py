@@ -61,3 +61,23 @@ def test_create_rejects_bad_config_without_touching_the_gpu():
     for flags in (4, 8, 1 << 31):  # bits no ABEA_F_* defines
         cfg_f = abea.abea_config_t(100, 0, 0, flags)
         assert lib.abea_create(ctypes.byref(cfg_f), ctypes.byref(mdl), ctypes.byref(h)) == abea.ABEA_E_INVAL
+
+
+def test_cells_per_lane_rule_for_every_band_width():
+    """Host planning without a device: the band fill's slots per lane is the
+    smallest power of two whose 64*c slots hold the band plus the slot-refill
+    interval (32/c bands per trace group, refilled once or twice per group,
+    at least every 2 bands), and 0 outside 2 <= W <= ABEA_MAX_BANDWIDTH."""
+    lib = abea.lib()
+
+    def fits(W, c):
+        return any((32 // c) // rpg >= 2 and 64 * c - W >= (32 // c) // rpg for rpg in (1, 2))
+
+    for W in range(2, 513):
+        c = lib.abea_cells_per_lane(W)
+        assert c in (1, 2, 4, 8, 16), (W, c)
+        assert fits(W, c), (W, c)
+        assert c == 1 or not fits(W, c // 2), (W, c)
+    assert [lib.abea_cells_per_lane(W) for W in (100, 200, 250, 512)] == [2, 4, 4, 16]
+    for W in (-1, 0, 1, 513, 1 << 20):
+        assert lib.abea_cells_per_lane(W) == 0
