@@ -110,6 +110,50 @@ def cpu_baseline(batch, model, W, idx, what, scale_events=False):
     }
 
 
+def band_slots(batch, W) -> int:
+    """W x computed bands (2 .. n_e + n_k) over the batch: the band-slot count
+    (cells of every band whether inside the table or not)."""
+    ne = np.diff(batch.event_offset.astype(np.int64))
+    nk = np.diff(batch.kmer_offset.astype(np.int64))
+    ok = (ne > 0) & (nk > 0)
+    return int(W * (ne[ok] + nk[ok] - 1).sum())
+
+
+def host_api_rate(al, batch, cells, reps=3):
+    """abea_align_batch with inputs and outputs in host memory (copies over
+    PCIe both ways inside the call), result buffers allocated once."""
+    import ctypes
+
+    from paper_2101_05012_amd import abea
+
+    n = batch.n_reads
+    ev = np.ascontiguousarray(batch.events, np.float32)
+    eo = np.ascontiguousarray(batch.event_offset, np.uint64)
+    ko = np.ascontiguousarray(batch.kmer_offset, np.uint64)
+    rk = np.ascontiguousarray(batch.ranks, np.uint32)
+    sc = np.ascontiguousarray(batch.scale, np.float32)
+    sh = np.ascontiguousarray(batch.shift, np.float32)
+    cap = abea.pair_capacity(eo, ko)
+    pairs = np.ones((max(cap, 1), 2), np.int32)  # touched: no page faults inside the timed calls
+    po = np.zeros(n + 1, np.uint64)
+    ll = np.zeros(n, np.float32)
+    st = np.zeros(n, np.int32)
+    ce = np.zeros(n, np.uint64)
+    b = abea.abea_batch_t(n, ev.ctypes.data, eo.ctypes.data, rk.ctypes.data, ko.ctypes.data, sc.ctypes.data,
+                          sh.ctypes.data)
+    r = abea.abea_result_t(pairs.ctypes.data, cap, po.ctypes.data, ll.ctypes.data, st.ctypes.data, ce.ctypes.data)
+    call = lambda: al._check(abea.lib().abea_align_batch(al.handle, ctypes.byref(b), ctypes.byref(r)),  # noqa: E731
+                             "abea_align_batch")
+    call()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    dt = (time.perf_counter() - t0) / reps
+    return {"gcups": round(cells / dt / 1e9, 3), "ms_per_batch": round(dt * 1e3, 3),
+            "reads_per_s": round(n / dt, 1), "calls": reps,
+            "what": "abea_align_batch, host buffers, PCIe both ways, one batch at a time"}
+
+
 def sample_reads(batch, W, target_cells: float):
     """Every s-th read, s chosen so that the sample has about target_cells."""
     n = batch.n_reads
@@ -210,6 +254,7 @@ def bench_plain(args, wl):
     dt = time.perf_counter() - t0
     log("bench: timed region done")
     plan = slots[0][0].plan_info()
+    host = host_api_rate(slots[0][0], batch, cells_per_step) if args.host_api else None
     for al, _, _ in slots:
         al.close()
 
@@ -230,6 +275,7 @@ def bench_plain(args, wl):
     })
     out.update({
         "reads_per_s": round(n * args.steps / dt, 1),
+        "band_slot_gcups": round(band_slots(batch, W) * args.steps / dt / 1e9, 3),
         "kernel_gcups": round(cells_per_step / (kms.sum() / 1e3) / 1e9, 3),
         "kernel_ms": {
             "prep": round(float(kms[0]), 4),
@@ -238,6 +284,7 @@ def bench_plain(args, wl):
             "compact": round(float(kms[3]), 4),
         },
         "reads_ok": int((status == 0).sum()),
+        **({"host_api": host} if host else {}),
         "roofline": {**roofline(cells_per_step, float(kms[1]), kname, args.workload),
                      # the same work over the whole job's time (launches overlap)
                      "achieved_job": round(gcups * OPS_PER_CELL / 1e3, 3),
@@ -358,6 +405,7 @@ def bench_persistent(args, wl):
     })
     out.update({
         "reads_per_s": round(n * args.steps / dt, 1),
+        "band_slot_gcups": round(band_slots(batch, W) * args.steps / dt / 1e9, 3),
         "reads_ok": int((status == 0).sum()),
         "plain_per_batch": {
             "batches": nbp,
@@ -543,6 +591,8 @@ def main():
                     help="hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32) for the plain and "
                     "serving workloads, so that batches or micro-batches on different streams run side by side")
     ap.add_argument("--levels", default="", help="serving: compression:reads,... (default: the full sweep)")
+    ap.add_argument("--host-api", action="store_true",
+                    help="plain: also time abea_align_batch on host buffers (PCIe both ways), after the timed region")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     ap.add_argument("--backtrack-probe", action="store_true", help="persistent: time the backtrack alone")
