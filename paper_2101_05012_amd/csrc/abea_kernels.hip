@@ -259,6 +259,8 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   const float4 *__restrict__ kp = reinterpret_cast<const float4 *>(a.kparam + rd.km_off);
   const int H = W / 2;
   const float NI = ABEA_NINF;
+  /* all ones when the band's two end slots sit in different registers */
+  const uint64_t wflip = (((W - 1) & (CPL - 1)) != 0) ? ~0ull : 0ull;
   const float NFM = __int_as_float((int)0xff7fffff); /* -FLT_MAX */
 
   auto ldx = [&](int e) -> float {
@@ -284,6 +286,9 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
    * latest band, E the event of its first cell. */
   int K = -H;
   int E = H - 1;
+  /* bits of the end cells of the latest band, for the next band's move:
+   * band 1 is all -inf */
+  int lo_c = ABEA_NINF_BITS, hi_c = ABEA_NINF_BITS;
   float Spp[CPL], Sp[CPL], PM[CPL], PC[CPL], PH[CPL];
   int dd[CPL]; /* kv(slot) - K_r */
   int xb[CPL]; /* ring index of the slot's event at band b = 0 of the group */
@@ -358,12 +363,10 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     /* the band position is wave-uniform: keep it in SGPRs */
     K = __builtin_amdgcn_readfirstlane(K);
     E = __builtin_amdgcn_readfirstlane(E);
-    /* Suzuki-Kasahara placement from the two end cells of band i-1; i0 is
-     * even, so i is odd when b is */
-    const int sf = K & (N - 1);
-    const int sh = (K + W - 1) & (N - 1);
-    const int lo = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(Sp, sf & (CPL - 1))), sf >> LC);
-    const int hi = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(Sp, sh & (CPL - 1))), sh >> LC);
+    /* Suzuki-Kasahara placement from the two end cells of band i-1 (taken
+     * at the end of that band, into lo_c and hi_c); i0 is even, so i is odd
+     * when b is */
+    const int lo = lo_c, hi = hi_c;
     const int mneg = __builtin_amdgcn_readfirstlane((b & 1) ? sk_move_mask<true>(lo, hi, NFM)
                                                             : sk_move_mask<false>(lo, hi, NFM));
     K -= mneg;
@@ -382,6 +385,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     const float lf0 = rot_up(Sp[CPL - 1]);  /* left  (e, k-1): band i-1, slot s-1 */
     const float dg0 = rot_up(Spp[CPL - 1]); /* diag (e-1, k-1): band i-2, slot s-1 */
     float nv[CPL]; /* band i; band i-2 is still read below */
+    float sv[CPL]; /* band i before the window mask */
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
       const float x = X[c];
@@ -399,13 +403,39 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       const uint64_t mu = ballot(su > sd);
       const float s1 = sel(sd, su, mu);
       const uint64_t ml = ballot(sl > s1);
-      const float sv = sel(s1, sl, ml);
+      sv[c] = sel(s1, sl, ml);
       const uint64_t valid = ballot((uint32_t)(dd[c] - wlo) < (uint32_t)wlen);
-      nv[c] = sel(NI, sv, valid);
+      nv[c] = sel(NI, sv[c], valid);
       /* trace planes: up bit (U beats D), left bit (L beats both); a set
        * left bit means L whatever the up bit */
       TU = shift_in(TU, mu);
       TL = shift_in(TL, ml);
+    }
+    /* the end cells of this band for the next band's move.  Both lie in the
+     * band; inside the table they are never masked, so they are read from
+     * the unmasked scores, which keeps the window mask off the chain from
+     * one band's move to the next */
+    {
+      const float(&src)[CPL] = INTERIOR ? sv : nv;
+      const int sf = K & (N - 1);
+      const int sh = (K + W - 1) & (N - 1);
+      if constexpr (CPL == 2) {
+        /* register of the first slot from the parity of K, as a wave mask
+         * made on the SALU; the last slot's register differs exactly when W
+         * is even */
+        uint64_t mlo;
+        asm("s_bitcmp1_b32 %1, 0\n\t"
+            "s_cselect_b64 %0, -1, 0"
+            : "=s"(mlo)
+            : "s"(K)
+            : "scc");
+        const uint64_t mhi = mlo ^ wflip;
+        lo_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], mlo)), sf >> LC);
+        hi_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], mhi)), sh >> LC);
+      } else {
+        lo_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sf & (CPL - 1))), sf >> LC);
+        hi_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sh & (CPL - 1))), sh >> LC);
+      }
     }
 #pragma unroll
     for (int c = 0; c < CPL; ++c) Spp[c] = nv[c];
