@@ -197,6 +197,23 @@ __device__ __forceinline__ float pick(const float (&v)[CPL], int r) {
   return t;
 }
 
+/* Bits of the value held by slot `slot` of a band at four slots per lane,
+ * as a scalar: the register is chosen by the slot's two low bits in two
+ * levels of selects, whose wave masks are made on the SALU. */
+__device__ __forceinline__ int end_cell_bits4(const float (&v)[4], int slot) {
+  uint64_t m0, m1;
+  asm("s_bitcmp1_b32 %2, 0\n\t"
+      "s_cselect_b64 %0, -1, 0\n\t"
+      "s_bitcmp1_b32 %2, 1\n\t"
+      "s_cselect_b64 %1, -1, 0"
+      : "=&s"(m0), "=s"(m1)
+      : "s"(slot)
+      : "scc");
+  const float a = sel(v[0], v[1], m0);
+  const float b = sel(v[2], v[3], m0);
+  return __builtin_amdgcn_readlane(__float_as_int(sel(a, b, m1)), slot >> 2);
+}
+
 /* Sizes of the band fill for CPL slots per lane.
  *   N   slots of the wave (64*CPL >= W + 2)
  *   G   bands per trace word (32/CPL, even)
@@ -432,6 +449,9 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
         const uint64_t mhi = mlo ^ wflip;
         lo_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], mlo)), sf >> LC);
         hi_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], mhi)), sh >> LC);
+      } else if constexpr (CPL == 4) {
+        lo_c = end_cell_bits4(src, sf);
+        hi_c = end_cell_bits4(src, sh);
       } else {
         lo_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sf & (CPL - 1))), sf >> LC);
         hi_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sh & (CPL - 1))), sh >> LC);
