@@ -69,6 +69,12 @@ __device__ __forceinline__ float sel(float if_clear, float if_set, uint64_t mask
   asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(mask));
   return r;
 }
+/* per lane: the larger of a and b (one v_max_f32, no canonicalisation) */
+__device__ __forceinline__ float vmax(float a, float b) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 /* per lane: acc*2 + (bit of `mask`), one v_addc */
 __device__ __forceinline__ uint32_t shift_in(uint32_t acc, uint64_t mask) {
   uint32_t r;
@@ -417,10 +423,14 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       const float sd = (diag + lp_step) + em;
       const float su = (up + lp_stay) + em;
       const float sl = left + lp_skip;
+      /* first maximum in the order D, U, L.  The value is the plain maximum
+       * (scores are finite or -inf, never NaN or -0, so v_max gives the
+       * bits the selects would); the compares only set the trace bits and
+       * stay off the chain from one band to the next */
       const uint64_t mu = ballot(su > sd);
-      const float s1 = sel(sd, su, mu);
+      const float s1 = vmax(sd, su);
       const uint64_t ml = ballot(sl > s1);
-      sv[c] = sel(s1, sl, ml);
+      sv[c] = vmax(s1, sl);
       const uint64_t valid = ballot((uint32_t)(dd[c] - wlo) < (uint32_t)wlen);
       nv[c] = sel(NI, sv[c], valid);
       /* trace planes: up bit (U beats D), left bit (L beats both); a set
