@@ -584,7 +584,7 @@ def main():
                     help="persistent: only the first N reads of the workload (quick runs; 0 = all)")
     ap.add_argument("--slots", type=int, default=16, help="serving: micro-batches on the device at once")
     ap.add_argument("--batch-reads", type=int, default=256, help="serving: reads per micro-batch")
-    ap.add_argument("--submitters", type=int, default=4, help="serving: sequencer threads handing reads to the server")
+    ap.add_argument("--submitters", type=int, default=8, help="serving: sequencer threads handing reads to the server")
     ap.add_argument("--host-staging-gb", type=float, default=6.0,
                     help="serving: pinned host arena for queued reads (GiB)")
     ap.add_argument("--hw-queues", type=int, default=16,
