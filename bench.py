@@ -63,16 +63,16 @@ OPS_PER_CELL = 11
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 WORKLOADS = {
-    "plain-4000-lognormal5kb": dict(kind="plain", config=1, W=100, k=6),
-    "plain-64x1kb": dict(kind="plain", config=0, W=100, k=6),
+    "plain-4000-lognormal5kb": dict(kind="plain", source="plain-4000-lognormal5kb", W=100, k=6),
+    "plain-64x1kb": dict(kind="plain", source="plain-64x1kb", W=100, k=6),
     # the same 4000 reads with the events scaled to the model instead
-    "plain-4000-lognormal5kb-scale-events": dict(kind="plain", config=1, W=100, k=6, scale_events=True),
-    "uneven-20000-w100": dict(kind="persistent", config=2, W=100, k=6, plain_batches=5),
-    "uneven-20000-w200": dict(kind="persistent", config=2, W=200, k=6, plain_batches=5),
-    "ultralong-200-w100": dict(kind="persistent", config=4, W=100, k=6, plain_batches=1),
-    "ultralong-200-w250": dict(kind="persistent", config=4, W=250, k=6, plain_batches=1),
-    "ultralong-200-w250-k9": dict(kind="persistent", config=4, W=250, k=9, plain_batches=1),
-    "serving-512ch": dict(kind="serving", config=3, W=100, k=6),
+    "plain-4000-lognormal5kb-scale-events": dict(kind="plain", source="plain-4000-lognormal5kb", W=100, k=6, scale_events=True),
+    "uneven-20000-w100": dict(kind="persistent", source="uneven-20000", W=100, k=6, plain_batches=5),
+    "uneven-20000-w200": dict(kind="persistent", source="uneven-20000", W=200, k=6, plain_batches=5),
+    "ultralong-200-w100": dict(kind="persistent", source="ultralong-200", W=100, k=6, plain_batches=1),
+    "ultralong-200-w250": dict(kind="persistent", source="ultralong-200", W=250, k=6, plain_batches=1),
+    "ultralong-200-w250-k9": dict(kind="persistent", source="ultralong-200", W=250, k=9, plain_batches=1),
+    "serving-512ch": dict(kind="serving", source="serving-lognormal8kb", W=100, k=6),
 }
 
 # serving: (time compression, reads) per load level; x1 is real time for 512
@@ -204,7 +204,7 @@ def bench_plain(args, wl):
     W, k = wl["W"], wl["k"]
     log(f"bench: generating workload {args.workload}")
     model = synth.pore_model(k)
-    batch = synth.config_batch(wl["config"], model)
+    batch = synth.workload_batch(wl["source"], model)
     n = batch.n_reads
     dev = 0
     torch.cuda.set_device(dev)
@@ -314,8 +314,8 @@ def bench_persistent(args, wl):
     model = synth.pore_model(k)
     ids = None
     if args.max_reads > 0:
-        ids = range(min(args.max_reads, synth.CONFIGS[wl["config"]]["n_reads"]))
-    batch = synth.config_batch_parallel(wl["config"], k=k, read_ids=ids)
+        ids = range(min(args.max_reads, synth.WORKLOADS[wl["source"]]["n_reads"]))
+    batch = synth.workload_batch_parallel(wl["source"], k=k, read_ids=ids)
     n = batch.n_reads
     log(f"bench: generated {n} reads, {int(batch.kmer_offset[-1]) / 1e6:.1f} M k-mers in "
         f"{time.perf_counter() - t0:.1f} s")
@@ -469,7 +469,7 @@ def bench_serving(args, wl):
     log(f"bench: generating {n_max} serving reads")
     t0 = time.perf_counter()
     model = synth.pore_model(k)
-    batch = synth.config_batch_parallel(wl["config"], k=k, read_ids=range(n_max))
+    batch = synth.workload_batch_parallel(wl["source"], k=k, read_ids=range(n_max))
     # arrival times of the simulated sequencer (first n_max reads)
     dur = 60.0
     arr = synth.serving_arrivals(duration_s=dur)

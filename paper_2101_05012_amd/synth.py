@@ -22,7 +22,7 @@ D_rapid), which are not available here.  What is drawn, and why:
   level_stdv), stdv ~ U(0.5, 3), duration ~ Exp(mean 2.5 ms), all float32.
   Only the mean is read by the alignment (Alg. 5.3).
 
-Every read draws from its own stream ``default_rng([config_seed, read_id])``,
+Every read draws from its own stream ``default_rng([workload_seed, read_id])``,
 so a read's bytes do not depend on which batch it is in or where.
 """
 
@@ -35,18 +35,18 @@ from typing import Optional, Sequence
 import numpy as np
 
 MODEL_SEED_BASE = 1000
-CONFIG_SEED_BASE = 2026_0000
+WORKLOAD_SEED_BASE = 2026_0000
 
 SKIP_PROB = 0.05
 EVENTS_PER_KMER_MEAN = 1.8
 
 # Workload shapes.  W is the band width, k the k-mer length.
-CONFIGS = {
-    0: dict(name="plain-64x1kb", n_reads=64, W=100, k=6, lengths="fixed1000"),
-    1: dict(name="plain-4000-lognormal5kb", n_reads=4000, W=100, k=6, lengths="lognormal5k"),
-    2: dict(name="uneven-20000", n_reads=20000, W=100, k=6, lengths="mixed"),
-    3: dict(name="serving-lognormal8kb", n_reads=None, W=100, k=6, lengths="lognormal8k"),
-    4: dict(name="ultralong-200", n_reads=200, W=100, k=6, lengths="ultralong"),
+WORKLOADS = {
+    "plain-64x1kb": dict(seed_index=0, n_reads=64, W=100, k=6, lengths="fixed1000"),
+    "plain-4000-lognormal5kb": dict(seed_index=1, n_reads=4000, W=100, k=6, lengths="lognormal5k"),
+    "uneven-20000": dict(seed_index=2, n_reads=20000, W=100, k=6, lengths="mixed"),
+    "serving-lognormal8kb": dict(seed_index=3, n_reads=None, W=100, k=6, lengths="lognormal8k"),
+    "ultralong-200": dict(seed_index=4, n_reads=200, W=100, k=6, lengths="ultralong"),
 }
 
 
@@ -189,42 +189,42 @@ def make_batch(reads: Sequence[Read]) -> Batch:
     )
 
 
-def config_seed(config_id: int) -> int:
-    return CONFIG_SEED_BASE + config_id
+def workload_seed(workload: str) -> int:
+    return WORKLOAD_SEED_BASE + WORKLOADS[workload]["seed_index"]
 
 
-def read_rng(config_id: int, read_id: int) -> np.random.Generator:
-    return np.random.default_rng([config_seed(config_id), read_id])
+def read_rng(workload: str, read_id: int) -> np.random.Generator:
+    return np.random.default_rng([workload_seed(workload), read_id])
 
 
-def config_read(config_id: int, read_id: int, model: PoreModel) -> Read:
+def workload_read(workload: str, read_id: int, model: PoreModel) -> Read:
     """Read ``read_id`` of a workload; identical whatever batch it is in."""
-    rng = read_rng(config_id, read_id)
-    L = draw_length(rng, CONFIGS[config_id]["lengths"])
+    rng = read_rng(workload, read_id)
+    L = draw_length(rng, WORKLOADS[workload]["lengths"])
     return gen_read(rng, L, model)
 
 
-def config_batch(
-    config_id: int,
+def workload_batch(
+    workload: str,
     model: Optional[PoreModel] = None,
     read_ids: Optional[Sequence[int]] = None,
 ) -> Batch:
-    cfg = CONFIGS[config_id]
+    cfg = WORKLOADS[workload]
     if model is None:
         model = pore_model(cfg["k"])
     if read_ids is None:
         read_ids = range(cfg["n_reads"])
-    return make_batch([config_read(config_id, int(i), model) for i in read_ids])
+    return make_batch([workload_read(workload, int(i), model) for i in read_ids])
 
 
-def _config_chunk(args):
+def _workload_chunk(args):
     """Generate reads ``ids`` of a workload into a shared-memory block of its
     own (returned by name, so that the arrays need not be pickled)."""
     from multiprocessing import shared_memory
 
-    config_id, ids, k = args
+    workload, ids, k = args
     model = pore_model(k)
-    b = make_batch([config_read(config_id, int(i), model) for i in ids])
+    b = make_batch([workload_read(workload, int(i), model) for i in ids])
     parts = [
         b.events,
         np.diff(b.event_offset).astype(np.uint64),
@@ -253,27 +253,27 @@ def _config_chunk(args):
     return name, meta
 
 
-def config_batch_parallel(
-    config_id: int,
+def workload_batch_parallel(
+    workload: str,
     k: Optional[int] = None,
     read_ids: Optional[Sequence[int]] = None,
     workers: Optional[int] = None,
     chunk: int = 100,
 ) -> Batch:
-    """config_batch over a process pool (same bytes: every read has its own
+    """workload_batch over a process pool (same bytes: every read has its own
     random stream); for the large workloads.  The pore model is the seeded
     one of k (``pore_model(k)``)."""
     import multiprocessing as mp
     import os
     from multiprocessing import shared_memory
 
-    cfg = CONFIGS[config_id]
+    cfg = WORKLOADS[workload]
     k = cfg["k"] if k is None else k
     ids = list(range(cfg["n_reads"]) if read_ids is None else read_ids)
     workers = workers or min(16, os.cpu_count() or 1)
-    jobs = [(config_id, ids[j : j + chunk], k) for j in range(0, len(ids), chunk)]
+    jobs = [(workload, ids[j : j + chunk], k) for j in range(0, len(ids), chunk)]
     with mp.get_context("fork").Pool(max(1, workers)) as pool:
-        results = pool.map(_config_chunk, jobs, chunksize=1)
+        results = pool.map(_workload_chunk, jobs, chunksize=1)
     blocks = []
     try:
         views = []
@@ -306,10 +306,10 @@ def config_batch_parallel(
     return Batch(ev, eo, rk, ko, sc, sh)
 
 
-def config_lengths(config_id: int, read_ids: Sequence[int]) -> np.ndarray:
+def workload_lengths(workload: str, read_ids: Sequence[int]) -> np.ndarray:
     """Reference lengths only (cheap: draws the first number of each stream)."""
-    kind = CONFIGS[config_id]["lengths"]
-    return np.array([draw_length(read_rng(config_id, int(i)), kind) for i in read_ids], np.int64)
+    kind = WORKLOADS[workload]["lengths"]
+    return np.array([draw_length(read_rng(workload, int(i)), kind) for i in read_ids], np.int64)
 
 
 def noiseless_batch(n_reads: int, L: int, model: PoreModel, seed: int = 7) -> Batch:
@@ -323,7 +323,7 @@ def serving_arrivals(
     bases_per_s: float = 400.0,
     duration_s: float = 10.0,
     mean_len: Optional[float] = None,
-    seed: int = CONFIG_SEED_BASE + 3,
+    seed: int = WORKLOAD_SEED_BASE + WORKLOADS["serving-lognormal8kb"]["seed_index"],
 ) -> np.ndarray:
     """Arrival times (s) of reads from ``n_channels`` independent Poisson
     channels, each delivering ``bases_per_s`` on average (a simulated

@@ -64,7 +64,7 @@ def test_forms_identical_on_mixed_batch(oracle_mod, m6, om6):
     split kernels, the fused kernel and persistent pools of 1, 7 and 64
     workers agree bit for bit, and with the oracle."""
     rng = np.random.default_rng(77)
-    main = synth.config_batch(1, m6, read_ids=range(200, 400))
+    main = synth.workload_batch("plain-4000-lognormal5kb", m6, read_ids=range(200, 400))
     edge = _edge_reads(m6, rng)
     reads = [main.read(i) for i in range(main.n_reads)] + [edge.read(i) for i in range(edge.n_reads)]
     order = rng.permutation(len(reads))
@@ -96,7 +96,7 @@ def test_forms_identical_on_mixed_batch(oracle_mod, m6, om6):
 @pytest.mark.parametrize("wpg,cpl", [(2, 0), (4, 0), (1, 4), (2, 8)])
 def test_group_shapes_and_slot_counts(m6, wpg, cpl):
     """Waves per workgroup and slots per lane change the schedule only."""
-    b = synth.config_batch(1, m6, read_ids=range(1000, 1096))
+    b = synth.workload_batch("plain-4000-lognormal5kb", m6, read_ids=range(1000, 1096))
     ref = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100).align(b)
     say(f"gpu: wpg={wpg} cpl={cpl}")
     for workers in (0, 16):
@@ -110,7 +110,7 @@ def test_trace_admission_limits_workers(m6):
     """A trace budget smaller than the batch's trace admits fewer workers; the
     results do not change; a budget below the longest read's trace is an
     error that names it."""
-    b = synth.config_batch(1, m6, read_ids=range(0, 128))
+    b = synth.workload_batch("plain-4000-lognormal5kb", m6, read_ids=range(0, 128))
     full = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100)
     ref = full.align(b)
     total = full.plan_info()["trace_bytes"]
@@ -139,7 +139,7 @@ def test_graph_replays_match_eager(m6, workers):
     synchronisation between replays: every replay equals the eager call."""
     import torch
 
-    b = synth.config_batch(1, m6, read_ids=range(2000, 2160))
+    b = synth.workload_batch("plain-4000-lognormal5kb", m6, read_ids=range(2000, 2160))
     al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, workers=workers)
     db = abea.to_device(b)
     dr_e = abea.DeviceResult.empty(db)
@@ -173,7 +173,7 @@ def test_two_graphs_concurrently(m6):
     import torch
 
     al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, workers=32)
-    parts = [synth.config_batch(1, m6, read_ids=range(3000 + 80 * j, 3080 + 80 * j)) for j in range(2)]
+    parts = [synth.workload_batch("plain-4000-lognormal5kb", m6, read_ids=range(3000 + 80 * j, 3080 + 80 * j)) for j in range(2)]
     eager = [al.align(p) for p in parts]
     dbs = [abea.to_device(p) for p in parts]
     drs = [abea.DeviceResult.empty(d) for d in dbs]

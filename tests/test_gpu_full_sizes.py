@@ -49,7 +49,7 @@ def test_uneven_20000_persistent_graph(oracle_mod):
 
     model = synth.pore_model(6)
     say("gpu: generating uneven-20000")
-    batch = synth.config_batch_parallel(2, k=6)
+    batch = synth.workload_batch_parallel("uneven-20000", k=6)
     launch = autotune.Launch(cells_per_lane=2, waves_per_group=4, waves_per_simd=4, batches=1)
     job = autotune.Job(batch, 1, 0)
     al = autotune.make_aligner(model, 6, 100, launch, 0, 0)
@@ -76,7 +76,7 @@ def test_ultralong_w250_k9_under_trace_budget(oracle_mod):
 
     model = synth.pore_model(9)
     say("gpu: generating ultralong-200 k=9")
-    batch = synth.config_batch_parallel(4, k=9)
+    batch = synth.workload_batch_parallel("ultralong-200", k=9)
     al = abea.Aligner(model.level_mean, model.level_stdv, 9, W=250, arena_bytes=8_000_000_000,
                       workers=4 * autotune.resident_simds(0))
     db = abea.to_device(batch)

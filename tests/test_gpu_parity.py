@@ -66,9 +66,9 @@ def check_parity(batch, gres, O, om, W, idx=None, flags=0, threads=8):
     assert rel_bad == 0
 
 
-def test_config0_all_reads_bit_exact(oracle_mod, m6, om6):
-    b = synth.config_batch(0, m6)
-    say("gpu: config0 64 reads W=100 host API")
+def test_64x1kb_all_reads_bit_exact(oracle_mod, m6, om6):
+    b = synth.workload_batch("plain-64x1kb", m6)
+    say("gpu: 64 reads of 1 kb W=100 host API")
     g = aligner(m6, 100).align(b)
     check_parity(b, g, oracle_mod, om6, 100)
     assert np.all(g.status == 0)
@@ -77,7 +77,7 @@ def test_config0_all_reads_bit_exact(oracle_mod, m6, om6):
 def test_device_api_matches_host_api(m6):
     import torch
 
-    b = synth.config_batch(0, m6, read_ids=range(64, 128))
+    b = synth.workload_batch("plain-64x1kb", m6, read_ids=range(64, 128))
     al = aligner(m6, 100)
     h = al.align(b)
     say("gpu: device API 64 reads")
@@ -92,13 +92,13 @@ def test_device_api_matches_host_api(m6):
     assert np.array_equal(h.status, d.status) and np.array_equal(h.cells, d.cells)
 
 
-def test_config1_full_batch_sampled_reads(oracle_mod, m6, om6):
+def test_4000_lognormal_full_batch_sampled_reads(oracle_mod, m6, om6):
     """The 4000-read log-normal workload in one launch (device API, the bench
     configuration); the oracle checks the 12 longest reads and 52 others."""
     import torch
 
-    b = synth.config_batch(1, m6)
-    say("gpu: config1 4000 reads device API")
+    b = synth.workload_batch("plain-4000-lognormal5kb", m6)
+    say("gpu: 4000 log-normal reads device API")
     db = abea.to_device(b)
     dr = abea.DeviceResult.empty(db)
     al = aligner(m6, 100)
@@ -153,7 +153,7 @@ def test_noiseless_reads_align_on_diagonal(m6):
 
 
 def test_read_result_same_alone_and_in_batch(m6):
-    b = synth.config_batch(1, m6, read_ids=range(100, 164))
+    b = synth.workload_batch("plain-4000-lognormal5kb", m6, read_ids=range(100, 164))
     al = aligner(m6, 100)
     say("gpu: alone vs in batch")
     whole = al.align(b)
@@ -177,7 +177,7 @@ def test_k9_model_and_wide_band(oracle_mod):
 def test_capacity_error_writes_nothing(m6):
     import ctypes
 
-    b = synth.config_batch(0, m6, read_ids=range(4))
+    b = synth.workload_batch("plain-64x1kb", m6, read_ids=range(4))
     al = aligner(m6, 100)
     ev = np.ascontiguousarray(b.events)
     cap = abea.pair_capacity(b.event_offset, b.kmer_offset)

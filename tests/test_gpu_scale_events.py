@@ -29,9 +29,9 @@ def om6(oracle_mod, m6):
     return oracle_mod.Model(m6.level_mean, m6.level_stdv)
 
 
-def test_config0_scaled_events_bit_exact(oracle_mod, m6, om6):
-    b = synth.config_batch(0, m6)
-    say("gpu: scale-events config0 64 reads W=100")
+def test_64x1kb_scaled_events_bit_exact(oracle_mod, m6, om6):
+    b = synth.workload_batch("plain-64x1kb", m6)
+    say("gpu: scale-events 64 reads of 1 kb W=100")
     al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, scale_events=True)
     g = al.align(b)
     al.close()
@@ -55,13 +55,13 @@ def test_edge_cases_scaled_events_every_form(oracle_mod, m6, om6, W, workers):
     assert g.status[0] == abea.READ_EMPTY and g.status[3] == abea.READ_BAD_RANK
 
 
-def test_config1_scaled_events_device_api_sampled(oracle_mod, m6, om6):
+def test_4000_lognormal_scaled_events_device_api_sampled(oracle_mod, m6, om6):
     """The 4000-read workload in the benchmark's launch form (device API,
     1024-wavefront pool); the oracle checks the 8 longest reads and 24 others."""
     import torch
 
-    b = synth.config_batch(1, m6)
-    say("gpu: scale-events config1 4000 reads device API, 1024 workers")
+    b = synth.workload_batch("plain-4000-lognormal5kb", m6)
+    say("gpu: scale-events 4000 log-normal reads device API, 1024 workers")
     al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, scale_events=True, workers=1024)
     db = abea.to_device(b)
     dr = abea.DeviceResult.empty(db)
@@ -78,7 +78,7 @@ def test_config1_scaled_events_device_api_sampled(oracle_mod, m6, om6):
 
 
 def test_serving_scaled_events_matches_oracle(oracle_mod, m6, om6):
-    b = synth.config_batch(3, m6, read_ids=range(40))
+    b = synth.workload_batch("serving-lognormal8kb", m6, read_ids=range(40))
     al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, scale_events=True)
     srv = abea.Server(al, slots=4, max_batch_reads=16)
     say("gpu: scale-events serving 40 reads")

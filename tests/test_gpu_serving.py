@@ -25,7 +25,7 @@ def m6():
 
 @pytest.fixture(scope="module")
 def reads(m6):
-    return synth.config_batch(3, m6, read_ids=range(160))
+    return synth.workload_batch("serving-lognormal8kb", m6, read_ids=range(160))
 
 
 @pytest.fixture(scope="module")

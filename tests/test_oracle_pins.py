@@ -374,8 +374,8 @@ def rescore(pairs, x, ranks, M, sc, sh, lp, dtype):
     return acc
 
 
-def test_path_invariants_config0(oracle_mod, model6):
-    b = synth.config_batch(0, synth.pore_model(6), read_ids=range(16))
+def test_path_invariants_64x1kb(oracle_mod, model6):
+    b = synth.workload_batch("plain-64x1kb", synth.pore_model(6), read_ids=range(16))
     for i in range(b.n_reads):
         rd = b.read(i)
         x = rd.events[:, 0]
@@ -405,7 +405,7 @@ def test_model_scaling_is_a_single_rounding_fma(oracle_mod, model6):
     """Read-model scaling (paragraph after Alg. 5.3): mu = mean*scale + shift
     with one rounding.  Aligning with (scale, shift) equals aligning against a
     model whose means were scaled exactly here, with scale 1 and shift 0."""
-    b = synth.config_batch(0, synth.pore_model(6), read_ids=range(3))
+    b = synth.workload_batch("plain-64x1kb", synth.pore_model(6), read_ids=range(3))
     for i in range(b.n_reads):
         rd = b.read(i)
         used = np.unique(rd.ranks)
@@ -463,7 +463,7 @@ def test_literal_and_canonical_emission_forms_agree(oracle_mod, model6):
     ulp; alignments agree except on reads whose decisions hinge on an exact
     float32 tie, and scores agree to 1e-5 relative."""
     m = synth.pore_model(6)
-    b = synth.config_batch(0, m, read_ids=range(64, 464))
+    b = synth.workload_batch("plain-64x1kb", m, read_ids=range(64, 464))
     nt = max(1, min(8, os.cpu_count() or 1))
     r0 = oracle_mod.align_batch(b, model6, 100, n_threads=nt, flags=0)
     r1 = oracle_mod.align_batch(b, model6, 100, n_threads=nt, flags=oracle_mod.FORM_LITERAL)
@@ -476,7 +476,7 @@ def test_literal_and_canonical_emission_forms_agree(oracle_mod, model6):
 
 
 def test_batch_driver_matches_single_read_calls(oracle_mod, model6):
-    b = synth.config_batch(0, synth.pore_model(6), read_ids=range(8))
+    b = synth.workload_batch("plain-64x1kb", synth.pore_model(6), read_ids=range(8))
     rb = oracle_mod.align_batch(b, model6, 100, n_threads=3)
     for i in range(b.n_reads):
         rd = b.read(i)

@@ -22,16 +22,16 @@ def test_kmer_ranks_base4():
 
 def test_read_is_independent_of_batch_position():
     m = synth.pore_model(6)
-    a = synth.config_batch(1, m, read_ids=[5, 6, 7])
-    b = synth.config_batch(1, m, read_ids=[7, 99, 5])
+    a = synth.workload_batch("plain-4000-lognormal5kb", m, read_ids=[5, 6, 7])
+    b = synth.workload_batch("plain-4000-lognormal5kb", m, read_ids=[7, 99, 5])
     ra, rb = a.read(2), b.read(0)
     assert np.array_equal(ra.events, rb.events) and np.array_equal(ra.ranks, rb.ranks)
     assert a.read(0).scale == b.read(2).scale
 
 
-def test_event_moments_config0():
+def test_event_moments_64x1kb():
     m = synth.pore_model(6)
-    b = synth.config_batch(0, m)
+    b = synth.workload_batch("plain-64x1kb", m)
     ne = np.diff(b.event_offset).astype(np.float64)
     nk = np.diff(b.kmer_offset).astype(np.float64)
     assert np.all(nk == 995)
@@ -43,14 +43,14 @@ def test_event_moments_config0():
 
 
 def test_length_distributions():
-    L1 = synth.config_lengths(1, range(4000))
+    L1 = synth.workload_lengths("plain-4000-lognormal5kb", range(4000))
     assert L1.min() >= 200 and L1.max() <= 100_000
     assert 4500 < np.median(L1) < 5500
-    L2 = synth.config_lengths(2, range(4000))
+    L2 = synth.workload_lengths("uneven-20000", range(4000))
     long = L2 >= 20_000
     assert 0.27 < long.mean() < 0.33
     assert L2[~long].min() >= 500 and L2[~long].max() <= 5000
-    L4 = synth.config_lengths(4, range(200))
+    L4 = synth.workload_lengths("ultralong-200", range(200))
     assert L4.min() >= 200_000 and L4.max() <= 1_000_000
 
 
