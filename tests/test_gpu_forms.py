@@ -189,3 +189,39 @@ def test_two_graphs_concurrently(m6):
     for g in gs:
         g.close()
     al.close()
+
+
+@pytest.mark.parametrize("workers", [-1, 0])
+def test_kernel_timings(m6, workers):
+    """abea_get_timings: every stage of the last call has a device time; the
+    band (split) or fused kernel's interval lies inside the call's wall time;
+    the fused form has no separate backtrack; a context made without
+    ABEA_F_TIMING refuses."""
+    import time
+
+    import torch
+
+    b = synth.workload_batch("plain-4000-lognormal5kb", m6, read_ids=range(0, 400))
+    al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, timing=True, workers=workers)
+    db = abea.to_device(b)
+    dr = abea.DeviceResult.empty(db)
+    say(f"gpu: timings workers={workers}")
+    al.align_device(db, dr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    al.align_device(db, dr)
+    ms = al.timings()
+    wall = (time.perf_counter() - t0) * 1e3
+    al.close()
+    assert ms.shape == (4,) and np.all(np.isfinite(ms)) and np.all(ms >= 0)
+    assert ms[0] > 0 and ms[1] > 0 and ms[3] > 0
+    assert ms[1] <= wall
+    if workers == -1:
+        assert ms[2] > 0  # the split backtrack kernel
+    else:
+        assert ms[2] < 0.5 * ms[1]  # nothing between the fused kernel's end and the next event
+    plain = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100)
+    plain.align(b.subset(range(4)))
+    with pytest.raises(abea.AbeaError):
+        plain.timings()
+    plain.close()
