@@ -551,8 +551,10 @@ def copy_calibration(mb: int) -> None:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=80)
-    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 200 batches for the plain workloads, 3 passes for the persistent ones)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default: 16 batches for the plain workloads, 1 pass for the persistent ones)")
     ap.add_argument("--workload", default="plain-4000-lognormal5kb", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=1000)
@@ -599,12 +601,18 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(
-            f"bench.py runs on one GPU: the alignment of a read never spans devices and this build "
+            f"bench.py runs on one GPU: the alignment of a read never spans devices, so the benchmark "
             f"measures one GPU's share (asked for --gpus {args.gpus})",
             file=sys.stderr,
         )
         sys.exit(2)
     wl = WORKLOADS[args.workload]
+    # plain: enough batches that the drain of the last ones in flight is a
+    # small part of the timed region; persistent: whole passes of the job
+    if args.steps is None:
+        args.steps = 200 if wl["kind"] == "plain" else 3
+    if args.warmup is None:
+        args.warmup = 16 if wl["kind"] == "plain" else 1
     if wl["kind"] in ("serving", "plain") and 0 < args.hw_queues <= 32:
         # read by the HIP runtime when it starts, i.e. before torch touches the GPU
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
