@@ -101,13 +101,43 @@ def cpu_baseline(batch, model, W, idx, what, scale_events=False):
     res = O.align_batch(sub, om, W, n_threads=cores, flags=O.SCALE_EVENTS if scale_events else 0)
     dt = time.perf_counter() - t0
     cells = int(res.cells.sum())
+    # one thread on the first reads of the same sample (about 0.25 G cells)
+    per = np.cumsum(res.cells.astype(np.int64))
+    n1 = max(1, int(np.searchsorted(per, min(250_000_000, int(per[-1]) if per.size else 0)) + 1))
+    n1 = min(n1, len(idx))
+    sub1 = batch.subset(list(idx)[:n1])
+    t1 = time.perf_counter()
+    r1 = O.align_batch(sub1, om, W, n_threads=1, flags=O.SCALE_EVENTS if scale_events else 0)
+    dt1 = time.perf_counter() - t1
+    c1 = int(r1.cells.sum())
     return {
         "value": round(cells / dt / 1e9, 4),
         "unit": "GCUPS",
         "cores": cores,
         "kind": "oracle",
         "sample": f"{what}: {len(idx)} reads, {cells / 1e9:.2f} Gcells, {dt:.2f} s",
+        "one_thread": {"value": round(c1 / dt1 / 1e9, 4), "unit": "GCUPS",
+                       "sample": f"the first {n1} reads of that sample, {c1 / 1e9:.2f} Gcells, {dt1:.2f} s"},
+        "host_cpu": host_cpu(),
     }
+
+
+def host_cpu() -> str:
+    """Model name of the host CPU and the logical CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return f"{model}, {n} logical CPUs available"
 
 
 def band_slots(batch, W) -> int:

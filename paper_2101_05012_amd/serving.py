@@ -114,6 +114,9 @@ def summarize(res: Dict, batch, compression: float, arrivals_s: np.ndarray) -> D
     cells = int(c["cells"].sum())
     L = np.diff(batch.kmer_offset.astype(np.int64))
     long = L > np.median(L)
+    # completions are sorted by tag = read index, so L lines up with them
+    Lr = L[c["tag"].astype(np.int64)]
+    dec = np.minimum(9, (np.argsort(np.argsort(Lr, kind="stable"), kind="stable") * 10) // max(1, n))
     bases = int(L.sum())
     offered = n / (arrivals_s[-1] / compression) if arrivals_s[-1] > 0 else float("inf")
     pct = lambda a, q: round(float(np.percentile(a, q)), 3) if a.size else None  # noqa: E731
@@ -128,6 +131,12 @@ def summarize(res: Dict, batch, compression: float, arrivals_s: np.ndarray) -> D
         "latency_ms": {"p50": pct(lat_ms, 50), "p99": pct(lat_ms, 99), "max": round(float(lat_ms.max()), 3)},
         "latency_ms_reads_below_median_length": {"p50": pct(lat_ms[~long], 50), "p99": pct(lat_ms[~long], 99)},
         "latency_ms_reads_above_median_length": {"p50": pct(lat_ms[long], 50), "p99": pct(lat_ms[long], 99)},
+        # by decile of read length (shortest tenth first)
+        "latency_ms_by_length_decile": [
+            {"p50": pct(lat_ms[m], 50), "p99": pct(lat_ms[m], 99),
+             "kb": [round(float(Lr[m].min()) / 1e3, 1), round(float(Lr[m].max()) / 1e3, 1)]}
+            for m in (dec == q for q in range(10)) if m.any()
+        ],
         "admission_wait_ms": {"p50": pct(wait_ms, 50), "p99": pct(wait_ms, 99)},
         # arrival -> the submit call returned (the simulated sequencer's own lag)
         "submit_lag_ms": {"p50": pct(res["submit_lag_ns"] / 1e6, 50), "p99": pct(res["submit_lag_ns"] / 1e6, 99)},
