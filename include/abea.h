@@ -194,15 +194,30 @@ int abea_get_timings(abea_ctx *ctx, float *out, int n);
  * waves_per_group: wavefronts (reads) per workgroup of the fused kernel, 1, 2
  * or 4.  cells_per_lane: band slots per lane, 0 = the smallest power of two
  * with 64*c >= W + 2, else a power of two at least that and at most 16.
+ * band_clear: which band slots the band fill resets to -inf after each band
+ * whose cells all lie inside the DP table (every form gives the same
+ * results; only the speed differs):
+ *   ABEA_CLEAR_WINDOW : every slot outside the band's cells;
+ *   ABEA_CLEAR_EDGES  : only the two slots beside the band (k-mers K-1 and
+ *       K+W), the only ones the next two bands read; fewer vector and more
+ *       scalar instructions per band, faster when the SIMDs hold several
+ *       wavefronts, slower for a lone one; needs 2 or 4 cells_per_lane;
+ *   ABEA_CLEAR_AUTO (0): edges at 4 cells_per_lane, and at 2 when the launch
+ *       has at least two wavefronts per SIMD of the device (reads, or pool
+ *       workers), else window.
+ * Bands with cells outside the table always clear every slot outside them.
  * Applies to later calls and graphs; waits for the context's queued work.
  * Errors: ABEA_E_INVAL.
  */
 #define ABEA_WORKERS_SPLIT (-1)
+#define ABEA_CLEAR_AUTO 0
+#define ABEA_CLEAR_WINDOW 1
+#define ABEA_CLEAR_EDGES 2
 typedef struct {
   int32_t workers;
   int32_t waves_per_group;
   int32_t cells_per_lane;
-  int32_t reserved; /* 0 */
+  int32_t band_clear; /* ABEA_CLEAR_* */
 } abea_launch_t;
 int abea_set_launch(abea_ctx *ctx, const abea_launch_t *launch);
 
@@ -219,6 +234,8 @@ typedef struct {
   int32_t waves_per_group;
   uint64_t trace_bytes;    /* device trace memory of the batch */
   uint64_t scratch_bytes;  /* device pair scratch of the batch */
+  int32_t band_clear;      /* ABEA_CLEAR_WINDOW or ABEA_CLEAR_EDGES, as resolved */
+  int32_t reserved;        /* 0 */
 } abea_plan_info_t;
 int abea_get_plan_info(const abea_ctx *ctx, abea_plan_info_t *info);
 

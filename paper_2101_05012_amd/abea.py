@@ -31,6 +31,9 @@ ABEA_MAX_K = 12
 ABEA_F_TIMING = 1
 ABEA_F_SCALE_EVENTS = 2  # events scaled to the model: (x - shift) / scale
 ABEA_WORKERS_SPLIT = -1
+ABEA_CLEAR_AUTO = 0  # band_clear: the library chooses
+ABEA_CLEAR_WINDOW = 1  # every slot outside the band's cells, every band
+ABEA_CLEAR_EDGES = 2  # interior bands: only the two slots beside the band
 
 EXPORTED = (
     "abea_create",
@@ -111,7 +114,7 @@ class abea_launch_t(ctypes.Structure):
         ("workers", ctypes.c_int32),
         ("waves_per_group", ctypes.c_int32),
         ("cells_per_lane", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("band_clear", ctypes.c_int32),
     ]
 
 
@@ -123,10 +126,12 @@ class abea_plan_info_t(ctypes.Structure):
         ("waves_per_group", ctypes.c_int32),
         ("trace_bytes", ctypes.c_uint64),
         ("scratch_bytes", ctypes.c_uint64),
+        ("band_clear", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
 
 
 class abea_server_config_t(ctypes.Structure):
@@ -309,6 +314,7 @@ class Aligner:
         waves_per_group: int = 1,
         cells_per_lane: int = 0,
         scale_events: bool = False,
+        band_clear: int = ABEA_CLEAR_AUTO,
     ):
         self._lm = np.ascontiguousarray(level_mean, np.float32)
         self._ls = np.ascontiguousarray(level_stdv, np.float32)
@@ -323,13 +329,15 @@ class Aligner:
         self.W = W
         self.k = k
         self.device = device
-        if (workers, waves_per_group, cells_per_lane) != (0, 1, 0):
-            self.set_launch(workers, waves_per_group, cells_per_lane)
+        if (workers, waves_per_group, cells_per_lane, band_clear) != (0, 1, 0, ABEA_CLEAR_AUTO):
+            self.set_launch(workers, waves_per_group, cells_per_lane, band_clear)
 
-    def set_launch(self, workers: int = 0, waves_per_group: int = 1, cells_per_lane: int = 0) -> None:
+    def set_launch(self, workers: int = 0, waves_per_group: int = 1, cells_per_lane: int = 0,
+                   band_clear: int = ABEA_CLEAR_AUTO) -> None:
         """Launch form (abea_set_launch): workers -1 split kernels, 0 one fused
-        wavefront per read, > 0 a persistent pool with a device work queue."""
-        L = abea_launch_t(int(workers), int(waves_per_group), int(cells_per_lane), 0)
+        wavefront per read, > 0 a persistent pool with a device work queue;
+        band_clear one of ABEA_CLEAR_*."""
+        L = abea_launch_t(int(workers), int(waves_per_group), int(cells_per_lane), int(band_clear))
         self._check(lib().abea_set_launch(self.handle, ctypes.byref(L)), "abea_set_launch")
 
     def plan_info(self) -> dict:

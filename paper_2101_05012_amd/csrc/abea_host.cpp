@@ -113,9 +113,26 @@ void transitions(int64_t n_events, int64_t n_kmers, float *skip, float *stay, fl
 bool split_kernels(const abea_ctx *ctx) { return ctx->launch.workers == ABEA_WORKERS_SPLIT; }
 
 /* Wavefronts of the fused kernel that are resident at once on the device. */
-int resident_workers(abea_ctx *ctx) {
-  const int gpc = align_groups_per_cu(ctx->cpl, refills_per_group(ctx->W, ctx->cpl), ctx->launch.waves_per_group);
+int resident_workers(abea_ctx *ctx, bool edge) {
+  const int gpc =
+      align_groups_per_cu(ctx->cpl, refills_per_group(ctx->W, ctx->cpl), ctx->launch.waves_per_group, edge);
   return std::max(1, gpc * ctx->num_cus * ctx->launch.waves_per_group);
+}
+
+/* Slot clearing of interior bands for a launch of `waves` wavefronts.  Edge
+ * clearing trades per-band VALU work (every slot's window test) for scalar
+ * work (two wave masks that follow the band); the scalar instructions cost a
+ * lone wavefront more issue time than the vector ones they replace, and cost
+ * nothing when other wavefronts on the SIMD keep the VALU busy.  At four slots
+ * per lane it saves twice the vector work and wins either way; at two it
+ * wins once the launch alone holds two wavefronts per SIMD. */
+bool edge_clearing(const abea_ctx *ctx, int waves) {
+  if (ctx->cpl != 2 && ctx->cpl != 4) return false;
+  switch (ctx->launch.band_clear) {
+    case ABEA_CLEAR_WINDOW: return false;
+    case ABEA_CLEAR_EDGES: return true;
+    default: return ctx->cpl == 4 || waves >= 2 * 4 * ctx->num_cus;
+  }
 }
 
 /* Plan a batch from host offsets.
@@ -155,8 +172,9 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
   const int G = bands_per_group(ctx->cpl);
   auto words = [&](int s) -> uint64_t { return ((comp[w.order[s]] + G - 1) / G) * 64u; };
   int workers = n;
-  if (!split_kernels(ctx) && ctx->launch.workers > 0)
-    workers = std::min(n, std::min(ctx->launch.workers, resident_workers(ctx)));
+  const bool pool = !split_kernels(ctx) && ctx->launch.workers > 0;
+  P.edge = edge_clearing(ctx, pool ? std::min(n, ctx->launch.workers) : n);
+  if (pool) workers = std::min(n, std::min(ctx->launch.workers, resident_workers(ctx, P.edge)));
   if (ctx->arena_bytes > 0) {
     uint64_t sum = 0;
     int fit = 0;
@@ -270,9 +288,9 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   hipEvent_t k0 = timed ? w.tev[2] : nullptr, k1 = timed ? w.tev[3] : nullptr;
   const bool launched = n > 0 && (P.workers == 0 || (P.workers > 0 && P.workers <= n));
   if (P.workers == 0) {
-    HIP_TRY(ctx, launch_band(a, P.cpl, refills_per_group(ctx->W, P.cpl), st, k0, k1));
+    HIP_TRY(ctx, launch_band(a, P.cpl, refills_per_group(ctx->W, P.cpl), P.edge, st, k0, k1));
   } else {
-    HIP_TRY(ctx, launch_align(a, P.cpl, refills_per_group(ctx->W, P.cpl), P.wpg, st, k0, k1));
+    HIP_TRY(ctx, launch_align(a, P.cpl, refills_per_group(ctx->W, P.cpl), P.wpg, P.edge, st, k0, k1));
   }
   if (timed && !launched) { /* nothing dispatched: an empty interval */
     HIP_TRY(ctx, hipEventRecord(w.tev[2], st));
@@ -414,6 +432,10 @@ int abea_set_launch(abea_ctx *ctx, const abea_launch_t *l) {
   if (c < minc || c > 16 || (c & (c - 1)) != 0)
     return fail(ctx, ABEA_E_INVAL, "cells_per_lane %d: need a power of two in [%d, 16]", l->cells_per_lane, minc);
   if (refills_per_group(ctx->W, c) == 0) return fail(ctx, ABEA_E_INVAL, "cells_per_lane %d too small", c);
+  if (l->band_clear != ABEA_CLEAR_AUTO && l->band_clear != ABEA_CLEAR_WINDOW && l->band_clear != ABEA_CLEAR_EDGES)
+    return fail(ctx, ABEA_E_INVAL, "band_clear %d: need 0, 1 or 2", l->band_clear);
+  if (l->band_clear == ABEA_CLEAR_EDGES && c != 2 && c != 4)
+    return fail(ctx, ABEA_E_INVAL, "band_clear ABEA_CLEAR_EDGES needs 2 or 4 cells_per_lane, not %d", c);
   /* buffers of an earlier call may still be in use by queued kernels */
   if (ctx->main.last_stream) HIP_TRY(ctx, hipStreamSynchronize(ctx->main.last_stream));
   ctx->launch = *l;
@@ -428,6 +450,8 @@ int abea_get_plan_info(const abea_ctx *ctx, abea_plan_info_t *info) {
   info->workers = P.workers;
   info->cells_per_lane = P.cpl;
   info->waves_per_group = P.wpg;
+  info->band_clear = P.edge ? ABEA_CLEAR_EDGES : ABEA_CLEAR_WINDOW;
+  info->reserved = 0;
   info->trace_bytes = P.n_trace * sizeof(uint2);
   info->scratch_bytes = P.n_scratch * sizeof(int2);
   return ABEA_OK;
@@ -607,6 +631,8 @@ int abea_graph_info(const abea_graph *g, abea_plan_info_t *info) {
   info->workers = P.workers;
   info->cells_per_lane = P.cpl;
   info->waves_per_group = P.wpg;
+  info->band_clear = P.edge ? ABEA_CLEAR_EDGES : ABEA_CLEAR_WINDOW;
+  info->reserved = 0;
   info->trace_bytes = P.n_trace * sizeof(uint2);
   info->scratch_bytes = P.n_scratch * sizeof(int2);
   return ABEA_OK;

@@ -106,15 +106,16 @@ hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events
                        bool scale_events, float *xmean, KParam *kparam, int32_t *rstat,
                        uint32_t *queue, hipStream_t st);
 /* t0, t1: null, or events that take the start and end time of the kernel's
- * own dispatch */
-hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st, hipEvent_t t0 = nullptr,
-                       hipEvent_t t1 = nullptr);
+ * own dispatch.  edge: interior bands clear only the two slots beside the
+ * band (cpl 2 or 4), else every slot outside the band's cells */
+hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, bool edge, hipStream_t st,
+                       hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st);
 /* fused band + backtrack with a.n_workers wavefronts, wpg per workgroup */
-hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, hipStream_t st,
+hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, bool edge, hipStream_t st,
                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 /* resident workgroups of the fused kernel per CU (occupancy) */
-int align_groups_per_cu(int cpl, int rpg, int wpg);
+int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge);
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st);
 hipError_t launch_compact(const int2 *scratch, const uint64_t *path_src, const uint64_t *offset,
                           int n, int2 *pairs, hipStream_t st);

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
 /* ------------------------------------------------------------------ band */
 
 /* Band move of the Suzuki-Kasahara rule from the bits of the two end cells
- * of the previous band, as a wave-uniform mask: -1 (k-mer move) if lo < hi,
+ * of the previous band, as a wave mask: all ones (k-mer move) if lo < hi,
  * else 0 (event move); when both are -inf the band parity decides, a k-mer
  * move for odd bands.  For odd bands hi is first raised to at least -FLT_MAX
  * (`nfm` holds -FLT_MAX in every lane): then lo < hi holds exactly when lo is
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
  * unchanged.  The compare runs on the VALU with all lanes active, so its lane
  * mask is all ones or all zeros and its low half is the result. */
 template <bool ODD>
-__device__ __forceinline__ int sk_move_mask(int lo, int hi, float nfm) {
+__device__ __forceinline__ uint64_t sk_move_mask(int lo, int hi, float nfm) {
   float tv;
   uint64_t cm;
   if (ODD)
@@ -191,7 +191,7 @@ __device__ __forceinline__ int sk_move_mask(int lo, int hi, float nfm) {
         "v_cmp_lt_f32_e64 %[cm], %[lo], %[tv]"
         : [tv] "=&v"(tv), [cm] "=s"(cm)
         : [lo] "s"(lo), [h] "s"(hi));
-  return (int)(uint32_t)cm;
+  return cm;
 }
 
 /* The register of slot (.. % CPL == r) of every lane, as one VGPR. */
@@ -218,6 +218,50 @@ __device__ __forceinline__ int end_cell_bits4(const float (&v)[4], int slot) {
   const float a = sel(v[0], v[1], m0);
   const float b = sel(v[2], v[3], m0);
   return __builtin_amdgcn_readlane(__float_as_int(sel(a, b, m1)), slot >> 2);
+}
+
+/* Wave masks, one per register, of the two slots beside a band of W cells
+ * whose first k-mer is K: k-mers K - 1 and K + W. */
+template <int CPL>
+__device__ __forceinline__ void edge_init(uint64_t (&m)[CPL], int K, int W) {
+  constexpr int N = 64 * CPL;
+  constexpr int LC = Log2<CPL>::v;
+  const int sa = (K - 1) & (N - 1), sb = (K + W) & (N - 1);
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+    m[c] = (((sa & (CPL - 1)) == c) ? (1ull << (sa >> LC)) : 0ull) |
+           (((sb & (CPL - 1)) == c) ? (1ull << (sb >> LC)) : 0ull);
+}
+
+/* The same masks after the band move `mneg` (-1: k-mer move, the band and
+ * both slots one k-mer higher; 0: unchanged).  One slot higher is the next
+ * register of the same lane, or register 0 of the next lane (lane 63 wraps to
+ * lane 0); the shifted copy does not depend on the move, so only the selects
+ * wait for it. */
+template <int CPL>
+__device__ __forceinline__ void edge_move(uint64_t (&m)[CPL], int mneg) {
+  const uint64_t top = m[CPL - 1];
+  uint64_t n[1];
+  n[0] = (top << 1) | (top >> 63);
+  /* 64-bit selects on one compare (the compiler would split each in two) */
+  if constexpr (CPL == 2) {
+    asm("s_cmp_lg_u32 %[mn], 0\n\t"
+        "s_cselect_b64 %[m1], %[m0], %[m1]\n\t"
+        "s_cselect_b64 %[m0], %[n0], %[m0]"
+        : [m0] "+&s"(m[0]), [m1] "+&s"(m[1])
+        : [n0] "s"(n[0]), [mn] "s"(mneg)
+        : "scc");
+  } else {
+    static_assert(CPL == 4, "edge masks are kept for two or four slots per lane");
+    asm("s_cmp_lg_u32 %[mn], 0\n\t"
+        "s_cselect_b64 %[m3], %[m2], %[m3]\n\t"
+        "s_cselect_b64 %[m2], %[m1], %[m2]\n\t"
+        "s_cselect_b64 %[m1], %[m0], %[m1]\n\t"
+        "s_cselect_b64 %[m0], %[n0], %[m0]"
+        : [m0] "+&s"(m[0]), [m1] "+&s"(m[1]), [m2] "+&s"(m[2]), [m3] "+&s"(m[3])
+        : [n0] "s"(n[0]), [mn] "s"(mneg)
+        : "scc");
+  }
 }
 
 /* Sizes of the band fill for CPL slots per lane.
@@ -256,13 +300,25 @@ struct WaveLds {
  *
  * Slot s (lane s / CPL, register s % CPL) holds k-mer kv(s) = K_r + ((s -
  * K_r) mod N), fixed from one refill to the next (every RF bands, RF <= N - W
- * and RF <= G): a k-mer that leaves the band keeps its slot, masked, until
+ * and RF <= G): a k-mer that leaves the band keeps its slot until
  * the next refill relabels the slot as the k-mer N higher, which cannot enter
  * the band before then.  At a refill the wavefront loads each slot's k-mer
  * parameters (mu', c, h) from the k-mer ring and the LDS address of its event
  * at the refill band; band b after it reads the event of the slot from that
- * address + b (the event of a cell (e, k) in band i is i - 2 - k). */
-template <int CPL, int RPG>
+ * address + b (the event of a cell (e, k) in band i is i - 2 - k).
+ *
+ * Every slot computes a score each band; the slots outside the band must read
+ * as -inf wherever a later cell of the band takes them as a neighbour.  Edge
+ * bands (some cell outside the DP table) clear every slot outside the cells
+ * of the band in the table, and so do interior bands unless CLEAR_EDGES.
+ * With CLEAR_EDGES (two or four slots per lane) interior bands clear only
+ * k-mers K - 1 and K + W: the cells of the next band read band i at
+ * k-mers K' - 1 .. K' + W - 1 and band i - 1 at K' - 1 .. K' + W - 2, with K'
+ * = K or K + 1, so no other slot outside a band is ever read by a cell in one,
+ * and what those slots hold (scores of k-mers outside the band, or NaN from
+ * stale ring entries) never reaches the band, its end cells or the trace bits
+ * of its cells. */
+template <int CPL, int RPG, bool CLEAR_EDGES>
 __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd, uint2 *trace,
                                          float *__restrict__ lx, float4 *__restrict__ lk) {
   constexpr int N = Geom<CPL>::N;
@@ -282,8 +338,6 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   const float4 *__restrict__ kp = reinterpret_cast<const float4 *>(a.kparam + rd.km_off);
   const int H = W / 2;
   const float NI = ABEA_NINF;
-  /* all ones when the band's two end slots sit in different registers */
-  const uint64_t wflip = (((W - 1) & (CPL - 1)) != 0) ? ~0ull : 0ull;
   const float NFM = __int_as_float((int)0xff7fffff); /* -FLT_MAX */
 
   auto ldx = [&](int e) -> float {
@@ -312,6 +366,16 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   /* bits of the end cells of the latest band, for the next band's move:
    * band 1 is all -inf */
   int lo_c = ABEA_NINF_BITS, hi_c = ABEA_NINF_BITS;
+  /* CLEAR_EDGES: interior bands clear only the two slots beside the band,
+   * whose wave masks follow every band move on the SALU */
+  static_assert(!CLEAR_EDGES || CPL == 2 || CPL == 4, "edge clearing needs two or four slots per lane");
+  constexpr bool EDGE_MASKS = CLEAR_EDGES;
+  uint64_t edge[CPL];
+  if constexpr (EDGE_MASKS) edge_init<CPL>(edge, K, W);
+  /* at two slots per lane: all ones when the first (last) slot of the latest
+   * band is odd, i.e. in register 1 */
+  uint64_t plo = (K & 1) ? ~0ull : 0ull;
+  uint64_t phi = ((K + W - 1) & 1) ? ~0ull : 0ull;
   float Spp[CPL], Sp[CPL], PM[CPL], PC[CPL], PH[CPL];
   int dd[CPL]; /* kv(slot) - K_r */
   int xb[CPL]; /* ring index of the slot's event at band b = 0 of the group */
@@ -383,22 +447,28 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   auto band = [&](auto interior_tag, float(&Spp)[CPL], const float(&Sp)[CPL], int i, int b,
                   const float(&X)[CPL]) {
     constexpr bool INTERIOR = decltype(interior_tag)::value;
+    constexpr bool EDGE = INTERIOR && EDGE_MASKS;
     /* the band position is wave-uniform: keep it in SGPRs */
     K = __builtin_amdgcn_readfirstlane(K);
-    E = __builtin_amdgcn_readfirstlane(E);
     /* Suzuki-Kasahara placement from the two end cells of band i-1 (taken
      * at the end of that band, into lo_c and hi_c); i0 is even, so i is odd
-     * when b is */
+     * when b is.  The event of the first cell follows from K: e + k = i - 2
+     * in band i. */
     const int lo = lo_c, hi = hi_c;
-    const int mneg = __builtin_amdgcn_readfirstlane((b & 1) ? sk_move_mask<true>(lo, hi, NFM)
-                                                            : sk_move_mask<false>(lo, hi, NFM));
+    const uint64_t mv = (b & 1) ? sk_move_mask<true>(lo, hi, NFM) : sk_move_mask<false>(lo, hi, NFM);
+    const int mneg = __builtin_amdgcn_readfirstlane((int)(uint32_t)mv);
     K -= mneg;
-    E += 1 + mneg;
+    if constexpr (EDGE_MASKS) edge_move<CPL>(edge, mneg);
+    if constexpr (CPL == 2) {
+      /* a k-mer move changes the parity of both end slots */
+      plo ^= mv;
+      phi ^= mv;
+    }
 
     /* cells of band i inside the band and the table: k-mers kv with
      * wlo <= kv - K_r < wlo + wlen */
     int wlo = K - Kr, wlen = W;
-    if (!INTERIOR) {
+    if constexpr (!INTERIOR) {
       const int klo = max(K, max(0, i - 1 - n_e));
       const int khi = min(K + W - 1, min(n_k - 1, i - 2));
       wlen = max(0, khi - klo + 1);
@@ -431,8 +501,15 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       const float s1 = vmax(sd, su);
       const uint64_t ml = ballot(sl > s1);
       sv[c] = vmax(s1, sl);
-      const uint64_t valid = ballot((uint32_t)(dd[c] - wlo) < (uint32_t)wlen);
-      nv[c] = sel(NI, sv[c], valid);
+      if constexpr (EDGE) {
+        /* only the two slots beside the band are cleared: the next two bands
+         * read no other slot outside this band (the others may hold any
+         * value, the scores of k-mers outside the band) */
+        nv[c] = sel(sv[c], NI, edge[c]);
+      } else {
+        const uint64_t valid = ballot((uint32_t)(dd[c] - wlo) < (uint32_t)wlen);
+        nv[c] = sel(NI, sv[c], valid);
+      }
       /* trace planes: up bit (U beats D), left bit (L beats both); a set
        * left bit means L whatever the up bit */
       TU = shift_in(TU, mu);
@@ -447,18 +524,10 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       const int sf = K & (N - 1);
       const int sh = (K + W - 1) & (N - 1);
       if constexpr (CPL == 2) {
-        /* register of the first slot from the parity of K, as a wave mask
-         * made on the SALU; the last slot's register differs exactly when W
-         * is even */
-        uint64_t mlo;
-        asm("s_bitcmp1_b32 %1, 0\n\t"
-            "s_cselect_b64 %0, -1, 0"
-            : "=s"(mlo)
-            : "s"(K)
-            : "scc");
-        const uint64_t mhi = mlo ^ wflip;
-        lo_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], mlo)), sf >> LC);
-        hi_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], mhi)), sh >> LC);
+        /* register of each end slot from its parity, as wave masks kept on
+         * the SALU */
+        lo_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], plo)), sf >> LC);
+        hi_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], phi)), sh >> LC);
       } else if constexpr (CPL == 4) {
         lo_c = end_cell_bits4(src, sf);
         hi_c = end_cell_bits4(src, sh);
@@ -511,6 +580,8 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   uint64_t g = 0;
   const bool gap_ok = N - W >= CPL; /* interior bands clear CPL slots outside the band */
   while (i + G - 1 <= last) {
+    K = __builtin_amdgcn_readfirstlane(K);
+    E = i - 3 - K; /* band i - 1 is the latest */
     advance_rings();
     const bool interior = gap_ok & (K >= 0) & (E >= W - 1) & (E + G <= n_e - 1) &
                           (K + G + W - 1 <= n_k - 1);
@@ -526,6 +597,8 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   }
   /* the last, partial group */
   if (i <= last) {
+    K = __builtin_amdgcn_readfirstlane(K);
+    E = i - 3 - K;
     advance_rings();
     const int gb = last - i + 1;
     for (int b = 0;; b += 2) {
@@ -565,7 +638,7 @@ __device__ __forceinline__ void band_skipped(const AlignArgs &a, const ReadDesc 
 }
 
 /* Band fill alone, one wavefront per planned read. */
-template <int CPL, int RPG>
+template <int CPL, int RPG, bool EDGE>
 __global__ __launch_bounds__(64) void k_band(const AlignArgs a) {
   __shared__ WaveLds<CPL> lds;
   const int s = blockIdx.x;
@@ -577,7 +650,7 @@ __global__ __launch_bounds__(64) void k_band(const AlignArgs a) {
   /* the longest reads set the kernel's duration: let them issue first */
   const bool urgent = rd.n_e + rd.n_k >= a.urgent_len;
   if (urgent) __builtin_amdgcn_s_setprio(2);
-  const int st = band_read<CPL, RPG>(a, rd, a.trace + rd.tr_off, lds.band.lx, lds.band.lk);
+  const int st = band_read<CPL, RPG, EDGE>(a, rd, a.trace + rd.tr_off, lds.band.lx, lds.band.lk);
   if (urgent) __builtin_amdgcn_s_setprio(0);
   if (threadIdx.x == 0) a.rstat[s] = st;
 }
@@ -755,7 +828,7 @@ __global__ __launch_bounds__(64) void k_backtrack(const AlignArgs a) {
  * keeps read w's trace region for all its reads.  n_workers = n_reads is the
  * plain one-launch form; fewer workers bound the trace memory (admission by
  * traceback bytes) and let the longest reads of the batch overlap the rest. */
-template <int CPL, int RPG, int WPG>
+template <int CPL, int RPG, int WPG, bool EDGE>
 __global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
   __shared__ WaveLds<CPL> lds[WPG];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -770,7 +843,7 @@ __global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
     const bool urgent = rd.n_e + rd.n_k >= a.urgent_len;
     if (urgent) __builtin_amdgcn_s_setprio(2);
     if (st == READ_OK)
-      st = band_read<CPL, RPG>(a, rd, slab, lds[wv].band.lx, lds[wv].band.lk);
+      st = band_read<CPL, RPG, EDGE>(a, rd, slab, lds[wv].band.lx, lds[wv].band.lk);
     else
       band_skipped(a, rd);
     /* the walk reads back what this wavefront's lanes just stored (each lane
@@ -847,25 +920,29 @@ hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events
   return hipGetLastError();
 }
 
-/* Kernel variant for (cells per lane, refills per group). */
-#define ABEA_VARIANTS(CALL)              \
-  if (cpl == 1 && rpg == 1) CALL(1, 1);  \
-  if (cpl == 1 && rpg == 2) CALL(1, 2);  \
-  if (cpl == 2 && rpg == 1) CALL(2, 1);  \
-  if (cpl == 2 && rpg == 2) CALL(2, 2);  \
-  if (cpl == 4 && rpg == 1) CALL(4, 1);  \
-  if (cpl == 4 && rpg == 2) CALL(4, 2);  \
-  if (cpl == 8 && rpg == 1) CALL(8, 1);  \
-  if (cpl == 8 && rpg == 2) CALL(8, 2);  \
-  if (cpl == 16 && rpg == 1) CALL(16, 1);
+/* Kernel variant for (cells per lane, refills per group, edge clearing). */
+#define ABEA_VARIANTS(CALL)                                  \
+  if (cpl == 1 && rpg == 1 && !edge) CALL(1, 1, false);      \
+  if (cpl == 1 && rpg == 2 && !edge) CALL(1, 2, false);      \
+  if (cpl == 2 && rpg == 1 && !edge) CALL(2, 1, false);      \
+  if (cpl == 2 && rpg == 2 && !edge) CALL(2, 2, false);      \
+  if (cpl == 2 && rpg == 1 && edge) CALL(2, 1, true);        \
+  if (cpl == 2 && rpg == 2 && edge) CALL(2, 2, true);        \
+  if (cpl == 4 && rpg == 1 && !edge) CALL(4, 1, false);      \
+  if (cpl == 4 && rpg == 2 && !edge) CALL(4, 2, false);      \
+  if (cpl == 4 && rpg == 1 && edge) CALL(4, 1, true);        \
+  if (cpl == 4 && rpg == 2 && edge) CALL(4, 2, true);        \
+  if (cpl == 8 && rpg == 1 && !edge) CALL(8, 1, false);      \
+  if (cpl == 8 && rpg == 2 && !edge) CALL(8, 2, false);      \
+  if (cpl == 16 && rpg == 1 && !edge) CALL(16, 1, false);
 
-hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, hipStream_t st, hipEvent_t t0,
+hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, bool edge, hipStream_t st, hipEvent_t t0,
                        hipEvent_t t1) {
   if (a.n_reads <= 0) return hipSuccess;
-#define ABEA_L(C, R)                                                                       \
-  {                                                                                        \
-    hipExtLaunchKernelGGL((k_band<C, R>), dim3(a.n_reads), dim3(64), 0, st, t0, t1, 0, a); \
-    return hipGetLastError();                                                              \
+#define ABEA_L(C, R, E)                                                                       \
+  {                                                                                           \
+    hipExtLaunchKernelGGL((k_band<C, R, E>), dim3(a.n_reads), dim3(64), 0, st, t0, t1, 0, a); \
+    return hipGetLastError();                                                                 \
   }
   ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
@@ -885,43 +962,43 @@ hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int CPL, int RPG>
+template <int CPL, int RPG, bool EDGE>
 static hipError_t launch_align_c(const AlignArgs &a, int wpg, hipStream_t st, hipEvent_t t0,
                                  hipEvent_t t1) {
   const dim3 grid((a.n_workers + wpg - 1) / wpg);
   switch (wpg) {
-    case 1: hipExtLaunchKernelGGL((k_align<CPL, RPG, 1>), grid, dim3(64), 0, st, t0, t1, 0, a); break;
-    case 2: hipExtLaunchKernelGGL((k_align<CPL, RPG, 2>), grid, dim3(128), 0, st, t0, t1, 0, a); break;
-    case 4: hipExtLaunchKernelGGL((k_align<CPL, RPG, 4>), grid, dim3(256), 0, st, t0, t1, 0, a); break;
+    case 1: hipExtLaunchKernelGGL((k_align<CPL, RPG, 1, EDGE>), grid, dim3(64), 0, st, t0, t1, 0, a); break;
+    case 2: hipExtLaunchKernelGGL((k_align<CPL, RPG, 2, EDGE>), grid, dim3(128), 0, st, t0, t1, 0, a); break;
+    case 4: hipExtLaunchKernelGGL((k_align<CPL, RPG, 4, EDGE>), grid, dim3(256), 0, st, t0, t1, 0, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, hipStream_t st,
+hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, bool edge, hipStream_t st,
                         hipEvent_t t0, hipEvent_t t1) {
   if (a.n_reads <= 0 || a.n_workers <= 0) return hipSuccess;
   if (a.n_workers > a.n_reads) return hipErrorInvalidValue;
-#define ABEA_L(C, R) return launch_align_c<C, R>(a, wpg, st, t0, t1)
+#define ABEA_L(C, R, E) return launch_align_c<C, R, E>(a, wpg, st, t0, t1)
   ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
   return hipErrorInvalidValue;
 }
 
-template <int CPL, int RPG>
+template <int CPL, int RPG, bool EDGE>
 static int groups_per_cu_c(int wpg) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (wpg) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 1>, 64, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 2>, 128, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 4>, 256, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 1, EDGE>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 2, EDGE>, 128, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 4, EDGE>, 256, 0); break;
   }
   return e == hipSuccess ? n : 0;
 }
 
-int align_groups_per_cu(int cpl, int rpg, int wpg) {
-#define ABEA_L(C, R) return groups_per_cu_c<C, R>(wpg)
+int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge) {
+#define ABEA_L(C, R, E) return groups_per_cu_c<C, R, E>(wpg)
   ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
   return 0;

@@ -28,6 +28,7 @@ struct Plan {
   int workers = 0;        /* fused kernel: wavefronts (0 for the split kernels) */
   int cpl = 2;            /* slots per lane the plan was made for */
   int wpg = 1;            /* wavefronts per workgroup of the fused kernel */
+  bool edge = false;      /* interior bands clear only the two slots beside the band */
   uint64_t n_trace = 0;   /* uint2 words */
   uint64_t n_scratch = 0; /* pair slots */
   uint64_t n_events = 0;

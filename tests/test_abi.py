@@ -81,3 +81,25 @@ def test_cells_per_lane_rule_for_every_band_width():
     assert [lib.abea_cells_per_lane(W) for W in (100, 200, 250, 512)] == [2, 4, 4, 16]
     for W in (-1, 0, 1, 513, 1 << 20):
         assert lib.abea_cells_per_lane(W) == 0
+
+
+def test_binding_constants_and_structs_match_the_header():
+    """Every integer #define of the header has the binding's value, and the
+    binding's launch and plan-info structures have the header's fields in
+    order."""
+    src = open(os.path.join(ROOT, "include", "abea.h")).read()
+    defs = dict(re.findall(r"#define\s+(ABEA_[A-Z0-9_]+)\s+\(?(-?\d+)u?\)?\s", src))
+    checked = 0
+    for name, val in defs.items():
+        if hasattr(abea, name):
+            assert int(getattr(abea, name)) == int(val), name
+            checked += 1
+    for name in ("ABEA_CLEAR_AUTO", "ABEA_CLEAR_WINDOW", "ABEA_CLEAR_EDGES", "ABEA_WORKERS_SPLIT"):
+        assert name in defs and hasattr(abea, name), name
+    assert checked >= 8
+    body = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    for cname, cls in (("abea_launch_t", abea.abea_launch_t), ("abea_plan_info_t", abea.abea_plan_info_t)):
+        m = re.search(r"typedef struct \{([^}]*)\}\s*" + cname + ";", body)
+        assert m, cname
+        fields = re.findall(r"\b([a-z_]+);", m.group(1))
+        assert fields == [f for f, _ in cls._fields_], cname
