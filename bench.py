@@ -243,7 +243,7 @@ def bench_plain(args, wl):
     slots = []
     for _ in range(P):
         al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True,
-                          workers=args.workers, waves_per_group=args.wpg,
+                          workers=args.workers, waves_per_group=args.wpg, band_clear=args.band_clear,
                           scale_events=wl.get("scale_events", False))
         slots.append((al, abea.DeviceResult.empty(db, dev), torch.cuda.Stream(dev)))
     torch.cuda.synchronize()
@@ -301,6 +301,7 @@ def bench_plain(args, wl):
         "parallelism": "one wavefront per read",
         "launch": "fused band+backtrack, one launch per batch" if fused else "band and backtrack kernels",
         "batches_in_flight": P,
+        "band_clear": {1: "window", 2: "edges"}.get(plan.get("band_clear"), "?"),
         "per_read_scaling": "events to the model" if wl.get("scale_events") else "model to the events",
     })
     out.update({
@@ -606,6 +607,9 @@ def main():
         "a device work queue (still one launch per batch)",
     )
     ap.add_argument("--wpg", type=int, default=1, help="wavefronts (reads) per workgroup of the fused kernel")
+    ap.add_argument("--band-clear", type=int, default=2, choices=(0, 1, 2),
+                    help="plain workloads: slot clearing of interior bands, 0 auto, 1 window, 2 edges "
+                         "(default edges: the batches in flight together fill every SIMD)")
     ap.add_argument("--tune", action="store_true", help="persistent workloads: autotune the launch form")
     ap.add_argument("--cpl", type=int, default=0, help="persistent: cells per lane (0 = smallest)")
     ap.add_argument("--wps", type=int, default=4, help="persistent: pool wavefronts per SIMD")

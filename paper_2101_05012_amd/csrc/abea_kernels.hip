@@ -694,6 +694,7 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
   constexpr int N = 64 * CPL;
   constexpr int LC = Log2<CPL>::v;
   constexpr int LG = 5 - LC;           /* log2(G) */
+  constexpr int G = 1 << LG;           /* bands per trace group */
   constexpr int RG = BT_RING_GROUPS;   /* tile groups in the LDS ring */
   constexpr int QG = RG / 4;           /* groups per refill quarter */
 
@@ -732,36 +733,39 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
   uint2 Tn = ring[((gcur - 1) & (RG - 1)) * 64 + lane];
 
   int PE = 0, PK = 0;
-  uint64_t q = 0; /* cells emitted and stored */
-  /* cells gathered in the lanes, not stored yet, in the low 6 bits over a
-   * base that makes the count negative once all 64 lanes hold one: the same
-   * register is the writelane lane (which takes bits 5:0) and the stop test */
-  constexpr uint32_t QBASE = 0x7fffffc0u;
-  uint32_t qc = QBASE;
+  uint64_t q = 0;  /* cells stored */
+  uint32_t qn = 0; /* cells gathered in lanes 0 .. qn-1, not stored yet */
   const uint64_t res_end = rd.pr_off + (uint64_t)(n_e + n_k - 1);
   int2 *__restrict__ out = a.scratch;
   bool ok = true;
+  /* store the gathered cells in one coalesced store: lane l holds cell q + l
+   * counted from the end of the read's slots */
+  auto flush = [&]() {
+    if (lane < (int)qn) out[res_end - 1 - (q + lane)] = make_int2(PE, PK);
+    q += qn;
+    qn = 0;
+  };
 
   for (;;) {
-    /* the cells of the current group: one dependent step per cell; the
-     * trace words of the lane the walk is in stay in SGPRs until it moves
-     * to another lane (every CPL k-mers) */
+    /* the cells of the current group: one dependent step per cell, at most G
+     * of them (t falls at every step), so the lanes are emptied before a
+     * group that might not fit; the trace words of the lane the walk is in
+     * stay in SGPRs until k leaves that lane's CPL k-mers */
+    if (qn + G > 64) flush();
     const int lower = gcur << LG;
     int t = e + k;
-    int ln_cur = -1;
-    uint64_t wxy = 0; /* the lane's up-bit word (low half) and left-bit word (high half) */
+    int klo = 0x7fffffff; /* first k-mer of the loaded lane (none yet) */
+    uint64_t wxy = 0;     /* the lane's up-bit word (low half) and left-bit word (high half) */
     for (;;) {
       e = __builtin_amdgcn_readfirstlane(e);
       k = __builtin_amdgcn_readfirstlane(k);
-      /* emit the cell; every 64 cells go out in one coalesced store */
-      PE = writelane(e, (int)qc, PE);
-      PK = writelane(k, (int)qc, PK);
-      ++qc;
-      const int sl = k & (N - 1);
-      const int ln = sl >> LC;
-      if (ln != ln_cur) {
+      PE = writelane(e, (int)qn, PE);
+      PK = writelane(k, (int)qn, PK);
+      ++qn;
+      if (k < klo) {
+        const int ln = (k & (N - 1)) >> LC;
         wxy = (uint64_t)rlane_u(T.x, ln) | ((uint64_t)rlane_u(T.y, ln) << 32);
-        ln_cur = ln;
+        klo = k & ~(CPL - 1);
       }
       const int bit = trace_bit<CPL>(t, k);
       const uint64_t b2 = wxy >> bit; /* up bit at 0, left bit at 32 */
@@ -771,15 +775,10 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
       e -= (int)(lb ^ 1u);
       k -= (int)((~ub | lb) & 1u);
       t = e + k;
-      /* stop when 64 cells are gathered or the walk left the group (t falls
-       * by 1 or 2 per step, so this also ends a walk that leaves the table;
-       * the caller checks that it ended at the origin) */
-      if (((int)qc | (t - lower)) < 0) break;
-    }
-    if ((int)qc < 0) {
-      q += 64;
-      out[res_end - q + (63 - lane)] = make_int2(PE, PK);
-      qc = QBASE;
+      /* stop when the walk left the group (t falls by 1 or 2 per step, so
+       * this also ends a walk that leaves the table; the caller checks that
+       * it ended at the origin) */
+      if (t < lower) break;
     }
     if ((e | k) < 0) break;
     const int gi = t >> LG;
@@ -796,11 +795,8 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
       Tn = ring[((gcur - 1) & (RG - 1)) * 64 + lane];
     }
   }
-  const int qs = (int)(qc - QBASE);
-  q += qs;
+  flush();
   if (ok && !(e == -1 && k == -1)) ok = false;
-  /* the last qs cells: lane l holds cell q - qs + l counted from the end */
-  if (lane < qs) out[res_end - 1 - (q - qs + lane)] = make_int2(PE, PK);
   if (lane == 0) {
     a.path_len[orig] = ok ? q : 0;
     a.path_src[orig] = res_end - q;
