@@ -377,7 +377,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   uint64_t plo = (K & 1) ? ~0ull : 0ull;
   uint64_t phi = ((K + W - 1) & 1) ? ~0ull : 0ull;
   float Spp[CPL], Sp[CPL], PM[CPL], PC[CPL], PH[CPL];
-  int dd[CPL]; /* kv(slot) - K_r */
+  int kvs[CPL]; /* kv(slot), the k-mer the slot holds */
   int xb[CPL]; /* ring index of the slot's event at band b = 0 of the group */
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
@@ -385,10 +385,9 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     Spp[c] = (kv == -1) ? 0.0f : NI; /* band 0: the origin, k-mer -1 */
     Sp[c] = NI;
     PM[c] = PC[c] = PH[c] = 0.0f;
-    dd[c] = 0;
+    kvs[c] = kv;
     xb[c] = 0;
   }
-  int Kr = K;
 
   /* Rings: event e at lx[e mod RX], k-mer k at lk[k mod RK], written a
    * quarter (64 entries) at a time; the quarter after the top one waits in
@@ -418,12 +417,11 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
    * its group, i = i0 + b. */
   auto refill = [&](int i, int b) {
     K = __builtin_amdgcn_readfirstlane(K);
-    Kr = K;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
       const int d = (lane * CPL + c - K) & (N - 1);
       const int kv = K + d;
-      dd[c] = d;
+      kvs[c] = kv;
       const float4 p = lk[kv & (RK - 1)];
       PM[c] = p.x;
       PC[c] = p.y;
@@ -466,13 +464,13 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     }
 
     /* cells of band i inside the band and the table: k-mers kv with
-     * wlo <= kv - K_r < wlo + wlen */
-    int wlo = K - Kr, wlen = W;
+     * wlo <= kv < wlo + wlen (one unsigned compare against the SGPR wlo) */
+    int wlo = K, wlen = W;
     if constexpr (!INTERIOR) {
       const int klo = max(K, max(0, i - 1 - n_e));
       const int khi = min(K + W - 1, min(n_k - 1, i - 2));
       wlen = max(0, khi - klo + 1);
-      wlo = klo - Kr;
+      wlo = klo;
       cells += (uint64_t)wlen;
     }
     const float lf0 = rot_up(Sp[CPL - 1]);  /* left  (e, k-1): band i-1, slot s-1 */
@@ -507,7 +505,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
          * value, the scores of k-mers outside the band) */
         nv[c] = sel(sv[c], NI, edge[c]);
       } else {
-        const uint64_t valid = ballot((uint32_t)(dd[c] - wlo) < (uint32_t)wlen);
+        const uint64_t valid = ballot((uint32_t)(kvs[c] - wlo) < (uint32_t)wlen);
         nv[c] = sel(NI, sv[c], valid);
       }
       /* trace planes: up bit (U beats D), left bit (L beats both); a set
