@@ -12,9 +12,10 @@ The default workload is the 4000-read log-normal batch (median 5 kb, clipped
 200 b..100 kb, W = 100, k = 6), aligned with one kernel launch per batch.
 `--inflight P` keeps P batches in flight on P streams. The default is 16, on
 16 hardware queues: a batch lasts as long as its longest read, and 16
-batches in flight overlap those tails. Each launch runs a pool of 1024 fused
-wavefronts that take the batch's reads from a device work queue, leaving room
-on the chip for the other batches' long reads.
+batches in flight overlap those tails. Each launch runs a pool of 320 fused
+wavefronts that take the batch's reads from a device work queue. The 16
+pools together ask for the chip's 5120 resident wave slots (5 per SIMD at
+the kernel's register use, 1024 SIMDs), no more.
 
 Other workloads (``--workload``):
   uneven-20000-w100/w200: 20000 reads, 70% 500 b..5 kb and 30% 20..200 kb.
@@ -83,7 +84,7 @@ SERVING_LEVELS = [(1, 300), (10, 1000), (100, 4000), (1000, 20000), (3000, 30000
 # runs (FETCH_SIZE x 1.99991, WRITE_SIZE x 1.0: the factors a 1 GiB device
 # copy needs to read its known size), by workload; a workload without a
 # measurement of the current kernel reports null.
-ALIGN_TRAFFIC_BYTES = {"plain-4000-lognormal5kb": 6.806e9}
+ALIGN_TRAFFIC_BYTES = {"plain-4000-lognormal5kb": 6.734e9}
 
 
 def log(*a):
@@ -601,10 +602,11 @@ def main():
     ap.add_argument(
         "--workers",
         type=int,
-        default=1024,
+        default=320,
         help="plain workloads: wavefronts of each batch's launch: -1 split band/backtrack kernels, 0 one "
         "fused wavefront per read, >0 a pool of that many fused wavefronts taking the batch's reads from "
-        "a device work queue (still one launch per batch)",
+        "a device work queue (still one launch per batch); the default 320 x 16 batches in flight fills "
+        "the 5120 resident wave slots",
     )
     ap.add_argument("--wpg", type=int, default=1, help="wavefronts (reads) per workgroup of the fused kernel")
     ap.add_argument("--band-clear", type=int, default=2, choices=(0, 1, 2),

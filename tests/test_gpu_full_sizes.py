@@ -97,7 +97,7 @@ def test_ultralong_w250_k9_under_trace_budget(oracle_mod):
 
 def test_plain_4000_bench_launch_in_flight(oracle_mod):
     """plain-4000-lognormal5kb (W = 100) in the launch form the default bench
-    times: a pool of 1024 wavefronts per batch with edge clearing, several
+    times: a pool of 320 wavefronts per batch with edge clearing, several
     batches in flight on their own streams over one device-resident batch.
     Every context's result equals the window-clearing form's bit for bit; 10
     longest, 10 shortest and 40 other reads match the oracle."""
@@ -106,7 +106,7 @@ def test_plain_4000_bench_launch_in_flight(oracle_mod):
     model = synth.pore_model(6)
     b = synth.workload_batch("plain-4000-lognormal5kb", model)
     db = abea.to_device(b, 0)
-    ref_al = abea.Aligner(model.level_mean, model.level_stdv, 6, W=100, workers=1024,
+    ref_al = abea.Aligner(model.level_mean, model.level_stdv, 6, W=100, workers=320,
                           band_clear=abea.ABEA_CLEAR_WINDOW)
     ref_dr = abea.DeviceResult.empty(db, 0)
     ref_al.align_device(db, ref_dr)
@@ -115,7 +115,7 @@ def test_plain_4000_bench_launch_in_flight(oracle_mod):
     assert np.all(ref.status == 0)
     slots = []
     for j in range(4):
-        al = abea.Aligner(model.level_mean, model.level_stdv, 6, W=100, workers=1024,
+        al = abea.Aligner(model.level_mean, model.level_stdv, 6, W=100, workers=320,
                           band_clear=abea.ABEA_CLEAR_EDGES)
         slots.append((al, abea.DeviceResult.empty(db, 0), torch.cuda.Stream(0)))
     say("gpu: plain-4000 bench launch, 4 contexts in flight, edges vs window")
@@ -125,7 +125,7 @@ def test_plain_4000_bench_launch_in_flight(oracle_mod):
     torch.cuda.synchronize()
     for al, dr, _ in slots:
         info = al.plan_info()
-        assert info["workers"] == 1024 and info["band_clear"] == abea.ABEA_CLEAR_EDGES
+        assert info["workers"] == 320 and info["band_clear"] == abea.ABEA_CLEAR_EDGES
         g = dr.to_host(b.n_reads)
         assert np.array_equal(g.status, ref.status)
         assert np.array_equal(g.cells, ref.cells)
