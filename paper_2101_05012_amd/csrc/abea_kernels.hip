@@ -241,15 +241,14 @@ __device__ __forceinline__ void edge_init(uint64_t (&m)[CPL], int K, int W) {
 template <int CPL>
 __device__ __forceinline__ void edge_move(uint64_t (&m)[CPL], int mneg) {
   const uint64_t top = m[CPL - 1];
-  uint64_t n[1];
-  n[0] = (top << 1) | (top >> 63);
+  const uint64_t n0 = (top << 1) | (top >> 63); /* the top register, one slot higher */
   /* 64-bit selects on one compare (the compiler would split each in two) */
   if constexpr (CPL == 2) {
     asm("s_cmp_lg_u32 %[mn], 0\n\t"
         "s_cselect_b64 %[m1], %[m0], %[m1]\n\t"
         "s_cselect_b64 %[m0], %[n0], %[m0]"
         : [m0] "+&s"(m[0]), [m1] "+&s"(m[1])
-        : [n0] "s"(n[0]), [mn] "s"(mneg)
+        : [n0] "s"(n0), [mn] "s"(mneg)
         : "scc");
   } else {
     static_assert(CPL == 4, "edge masks are kept for two or four slots per lane");
@@ -259,7 +258,7 @@ __device__ __forceinline__ void edge_move(uint64_t (&m)[CPL], int mneg) {
         "s_cselect_b64 %[m1], %[m0], %[m1]\n\t"
         "s_cselect_b64 %[m0], %[n0], %[m0]"
         : [m0] "+&s"(m[0]), [m1] "+&s"(m[1]), [m2] "+&s"(m[2]), [m3] "+&s"(m[3])
-        : [n0] "s"(n[0]), [mn] "s"(mneg)
+        : [n0] "s"(n0), [mn] "s"(mneg)
         : "scc");
   }
 }
