@@ -240,11 +240,15 @@ def bench_plain(args, wl):
     dev = 0
     torch.cuda.set_device(dev)
     P = max(1, args.inflight)
+    # edge clearing exists at 2 and 4 slots per lane; other widths take the automatic choice
+    band_clear = args.band_clear
+    if band_clear == abea.ABEA_CLEAR_EDGES and abea.min_cells_per_lane(W) not in (2, 4):
+        band_clear = abea.ABEA_CLEAR_AUTO
     db = abea.to_device(batch, dev)  # inputs resident in HBM, shared by all slots
     slots = []
     for _ in range(P):
         al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True,
-                          workers=args.workers, waves_per_group=args.wpg, band_clear=args.band_clear,
+                          workers=args.workers, waves_per_group=args.wpg, band_clear=band_clear,
                           scale_events=wl.get("scale_events", False))
         slots.append((al, abea.DeviceResult.empty(db, dev), torch.cuda.Stream(dev)))
     torch.cuda.synchronize()
