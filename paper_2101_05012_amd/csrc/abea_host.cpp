@@ -123,9 +123,9 @@ int resident_workers(abea_ctx *ctx, bool edge) {
  * clearing trades per-band VALU work (every slot's window test) for scalar
  * work (two wave masks that follow the band); the scalar instructions cost a
  * lone wavefront more issue time than the vector ones they replace, and cost
- * nothing when other wavefronts on the SIMD keep the VALU busy.  At four slots
- * per lane it saves twice the vector work and wins either way; at two it
- * wins once the launch alone holds two wavefronts per SIMD. */
+ * less than them when other wavefronts on the SIMD keep the VALU busy.  At
+ * four slots per lane it saves twice the vector work and wins either way; at
+ * two it wins once the launch alone holds two wavefronts per SIMD. */
 bool edge_clearing(const abea_ctx *ctx, int waves) {
   if (ctx->cpl != 2 && ctx->cpl != 4) return false;
   switch (ctx->launch.band_clear) {
