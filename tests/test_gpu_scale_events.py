@@ -57,17 +57,20 @@ def test_edge_cases_scaled_events_every_form(oracle_mod, m6, om6, W, workers):
 
 def test_4000_lognormal_scaled_events_device_api_sampled(oracle_mod, m6, om6):
     """The 4000-read workload in the benchmark's launch form (device API,
-    1024-wavefront pool); the oracle checks the 8 longest reads and 24 others."""
+    320-wavefront pool, edge clearing); the oracle checks the 8 longest reads
+    and 24 others."""
     import torch
 
     b = synth.workload_batch("plain-4000-lognormal5kb", m6)
-    say("gpu: scale-events 4000 log-normal reads device API, 1024 workers")
-    al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, scale_events=True, workers=1024)
+    say("gpu: scale-events 4000 log-normal reads device API, 320 workers, edge clearing")
+    al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, scale_events=True, workers=320,
+                      band_clear=abea.ABEA_CLEAR_EDGES)
     db = abea.to_device(b)
     dr = abea.DeviceResult.empty(db)
     al.align_device(db, dr)
     torch.cuda.synchronize()
     g = dr.to_host(b.n_reads)
+    assert al.plan_info()["band_clear"] == abea.ABEA_CLEAR_EDGES
     al.close()
     assert np.all(g.status == 0)
     L = np.diff(b.kmer_offset)
