@@ -194,6 +194,26 @@ __device__ __forceinline__ uint64_t sk_move_mask(int lo, int hi, float nfm) {
   return cm;
 }
 
+/* The same decision with the last end cell left in its register: one compare
+ * of lo against every lane's value of that register (raised to -FLT_MAX for
+ * odd bands), whose bit for the end cell's lane is the answer.  No readlane
+ * and no move of the last end cell into a VGPR; two scalar instructions read
+ * the bit. */
+template <bool ODD>
+__device__ __forceinline__ uint64_t sk_move_mask_lane(int lo, float hv, int hl, float nfm) {
+  float tv;
+  uint64_t cm;
+  if (ODD)
+    asm volatile(
+        "v_max_f32 %[tv], %[h], %[nfm]\n\t"
+        "v_cmp_lt_f32_e64 %[cm], %[lo], %[tv]"
+        : [tv] "=&v"(tv), [cm] "=s"(cm)
+        : [lo] "s"(lo), [h] "v"(hv), [nfm] "v"(nfm));
+  else
+    asm volatile("v_cmp_lt_f32_e64 %[cm], %[lo], %[h]" : [cm] "=s"(cm) : [lo] "s"(lo), [h] "v"(hv));
+  return ((cm >> (hl & 63)) & 1ull) ? ~0ull : 0ull;
+}
+
 /* The register of slot (.. % CPL == r) of every lane, as one VGPR. */
 template <int CPL>
 __device__ __forceinline__ float pick(const float (&v)[CPL], int r) {
@@ -203,10 +223,10 @@ __device__ __forceinline__ float pick(const float (&v)[CPL], int r) {
   return t;
 }
 
-/* Bits of the value held by slot `slot` of a band at four slots per lane,
- * as a scalar: the register is chosen by the slot's two low bits in two
- * levels of selects, whose wave masks are made on the SALU. */
-__device__ __forceinline__ int end_cell_bits4(const float (&v)[4], int slot) {
+/* The register holding slot `slot` of a band at four slots per lane, as one
+ * VGPR: the register is chosen by the slot's two low bits in two levels of
+ * selects, whose wave masks are made on the SALU. */
+__device__ __forceinline__ float end_cell_reg4(const float (&v)[4], int slot) {
   uint64_t m0, m1;
   asm("s_bitcmp1_b32 %2, 0\n\t"
       "s_cselect_b64 %0, -1, 0\n\t"
@@ -217,7 +237,11 @@ __device__ __forceinline__ int end_cell_bits4(const float (&v)[4], int slot) {
       : "scc");
   const float a = sel(v[0], v[1], m0);
   const float b = sel(v[2], v[3], m0);
-  return __builtin_amdgcn_readlane(__float_as_int(sel(a, b, m1)), slot >> 2);
+  return sel(a, b, m1);
+}
+/* Bits of the value held by slot `slot` at four slots per lane, as a scalar. */
+__device__ __forceinline__ int end_cell_bits4(const float (&v)[4], int slot) {
+  return __builtin_amdgcn_readlane(__float_as_int(end_cell_reg4(v, slot)), slot >> 2);
 }
 
 /* Wave masks, one per register, of the two slots beside a band of W cells
@@ -365,6 +389,10 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   /* bits of the end cells of the latest band, for the next band's move:
    * band 1 is all -inf */
   int lo_c = ABEA_NINF_BITS, hi_c = ABEA_NINF_BITS;
+  /* edge kernels keep the last end cell in its register (hv, lane hl) and
+   * decide the move by one compare against every lane */
+  float hv = NI;
+  int hl = 0;
   /* CLEAR_EDGES: interior bands clear only the two slots beside the band,
    * whose wave masks follow every band move on the SALU */
   static_assert(!CLEAR_EDGES || CPL == 2 || CPL == 4, "edge clearing needs two or four slots per lane");
@@ -452,7 +480,11 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
      * when b is.  The event of the first cell follows from K: e + k = i - 2
      * in band i. */
     const int lo = lo_c, hi = hi_c;
-    const uint64_t mv = (b & 1) ? sk_move_mask<true>(lo, hi, NFM) : sk_move_mask<false>(lo, hi, NFM);
+    uint64_t mv;
+    if constexpr (EDGE_MASKS)
+      mv = (b & 1) ? sk_move_mask_lane<true>(lo, hv, hl, NFM) : sk_move_mask_lane<false>(lo, hv, hl, NFM);
+    else
+      mv = (b & 1) ? sk_move_mask<true>(lo, hi, NFM) : sk_move_mask<false>(lo, hi, NFM);
     const int mneg = __builtin_amdgcn_readfirstlane((int)(uint32_t)mv);
     K -= mneg;
     if constexpr (EDGE_MASKS) edge_move<CPL>(edge, mneg);
@@ -524,10 +556,20 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
         /* register of each end slot from its parity, as wave masks kept on
          * the SALU */
         lo_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], plo)), sf >> LC);
-        hi_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], phi)), sh >> LC);
+        if constexpr (EDGE_MASKS) {
+          hv = sel(src[0], src[1], phi);
+          hl = sh >> LC;
+        } else {
+          hi_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], phi)), sh >> LC);
+        }
       } else if constexpr (CPL == 4) {
         lo_c = end_cell_bits4(src, sf);
-        hi_c = end_cell_bits4(src, sh);
+        if constexpr (EDGE_MASKS) {
+          hv = end_cell_reg4(src, sh);
+          hl = sh >> 2;
+        } else {
+          hi_c = end_cell_bits4(src, sh);
+        }
       } else {
         lo_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sf & (CPL - 1))), sf >> LC);
         hi_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sh & (CPL - 1))), sh >> LC);
