@@ -389,8 +389,11 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   /* bits of the end cells of the latest band, for the next band's move:
    * band 1 is all -inf */
   int lo_c = ABEA_NINF_BITS, hi_c = ABEA_NINF_BITS;
-  /* edge kernels keep the last end cell in its register (hv, lane hl) and
-   * decide the move by one compare against every lane */
+  /* edge kernels at two slots per lane keep the last end cell in its
+   * register (hv, lane hl) and decide the move by one compare against every
+   * lane; at four slots per lane (three or fewer wavefronts per SIMD) the
+   * longer scalar chain of that form did not pay */
+  constexpr bool LANE_MOVE = CLEAR_EDGES && CPL == 2;
   float hv = NI;
   int hl = 0;
   /* CLEAR_EDGES: interior bands clear only the two slots beside the band,
@@ -481,7 +484,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
      * in band i. */
     const int lo = lo_c, hi = hi_c;
     uint64_t mv;
-    if constexpr (EDGE_MASKS)
+    if constexpr (LANE_MOVE)
       mv = (b & 1) ? sk_move_mask_lane<true>(lo, hv, hl, NFM) : sk_move_mask_lane<false>(lo, hv, hl, NFM);
     else
       mv = (b & 1) ? sk_move_mask<true>(lo, hi, NFM) : sk_move_mask<false>(lo, hi, NFM);
@@ -556,7 +559,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
         /* register of each end slot from its parity, as wave masks kept on
          * the SALU */
         lo_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], plo)), sf >> LC);
-        if constexpr (EDGE_MASKS) {
+        if constexpr (LANE_MOVE) {
           hv = sel(src[0], src[1], phi);
           hl = sh >> LC;
         } else {
@@ -564,12 +567,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
         }
       } else if constexpr (CPL == 4) {
         lo_c = end_cell_bits4(src, sf);
-        if constexpr (EDGE_MASKS) {
-          hv = end_cell_reg4(src, sh);
-          hl = sh >> 2;
-        } else {
-          hi_c = end_cell_bits4(src, sh);
-        }
+        hi_c = end_cell_bits4(src, sh);
       } else {
         lo_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sf & (CPL - 1))), sf >> LC);
         hi_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sh & (CPL - 1))), sh >> LC);
