@@ -143,3 +143,31 @@ def test_invalid_choices_refused(m6):
     with pytest.raises(abea.AbeaError):
         narrow.set_launch(band_clear=EDGES)
     narrow.close()
+
+
+@pytest.mark.parametrize("clear", [WINDOW, EDGES])
+def test_graph_keeps_the_clearing_form(m6, clear):
+    """A captured batch records the clearing form it was planned with
+    (abea_graph_info) and its replays equal the eager call of the other form."""
+    import torch
+
+    b = synth.workload_batch("plain-4000-lognormal5kb", m6, read_ids=range(3000, 3096))
+    other = EDGES if clear == WINDOW else WINDOW
+    ref_al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, workers=16, band_clear=other)
+    ref = ref_al.align(b)
+    ref_al.close()
+    al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, workers=16, band_clear=clear)
+    db = abea.to_device(b)
+    dr = abea.DeviceResult.empty(db)
+    say(f"gpu: graph with band_clear={clear}")
+    g = al.graph(db, dr)
+    assert g.info()["band_clear"] == clear
+    st = torch.cuda.Stream()
+    for _ in range(3):
+        dr.log_likelihood.fill_(0.0)
+        dr.pairs.fill_(-1)
+        g.launch(st)
+        st.synchronize()
+        same(ref, dr.to_host(b.n_reads))
+    g.close()
+    al.close()
