@@ -17,18 +17,23 @@
  *              W; slot s is lane s / CPL, register s % CPL), so a cell's up
  *              neighbour is the same slot of the previous band and its left
  *              and diagonal neighbours are slot s-1 of the two previous bands:
- *              one DPP wave_ror:1 per band each.  The k-mer parameters of a
- *              slot never move; only the slot a k-mer step frees is refilled.
- *              The event window rotates one slot per band.  The band move
- *              (Suzuki-Kasahara rule) is a wave-uniform scalar decision.
- *              Entering events and k-mer parameters stream through per-wave
- *              LDS rings refilled a quarter ahead.  Only two trace bits per
- *              slot reach HBM (two bit planes, 32/CPL bands per 32-bit word).
+ *              one DPP wave_ror:1 per band (the diagonal reuses the previous
+ *              band's).  The slots keep their k-mers and are relabelled every
+ *              few bands from a per-wave LDS k-mer ring; each band reads its
+ *              events from an LDS event ring.  The band move (Suzuki-Kasahara
+ *              rule) is a wave-uniform scalar decision.  Slots outside the band
+ *              are cleared to -inf each band: every one of them, or (interior
+ *              bands of launches that fill the SIMDs) only the two beside the
+ *              band.  Only two trace bits per slot reach HBM (two bit planes,
+ *              32/CPL bands per 32-bit word).
  *  k_backtrack one wavefront per read walks the path with wave-uniform scalar
  *              state: the trace bits of cell (e, k) are in group (e+k)/G, lane
  *              (k mod N)/CPL, so no band positions are needed.  Trace tiles
- *              stream through an LDS ring; pairs are gathered 64 at a time in
- *              lanes and stored coalesced.
+ *              stream through an LDS ring; pairs are gathered in lanes, up to
+ *              64 at a time, and stored coalesced.
+ *  k_align     the fused form: each wavefront fills a read's bands and then
+ *              walks it, one read per wavefront or a persistent pool taking
+ *              reads from a device work queue.
  *  k_scan/k_compact turn per-read path lengths into the caller's compact
  *              pair layout.
  *
