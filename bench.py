@@ -241,7 +241,14 @@ def bench_plain(args, wl):
     torch.cuda.set_device(dev)
     P = max(1, args.inflight)
     # edge clearing exists at 2 and 4 slots per lane; other widths take the automatic choice
+    # slot clearing: by default edges when the batches in flight together hold
+    # at least two wavefronts per SIMD (the library sees one launch at a time),
+    # else the library's own choice; edges exist at 2 and 4 slots per lane
     band_clear = args.band_clear
+    if band_clear < 0:
+        simds = 4 * torch.cuda.get_device_properties(dev).multi_processor_count
+        per_launch = n if args.workers <= 0 else min(n, args.workers)
+        band_clear = abea.ABEA_CLEAR_EDGES if P * per_launch >= 2 * simds else abea.ABEA_CLEAR_AUTO
     if band_clear == abea.ABEA_CLEAR_EDGES and abea.min_cells_per_lane(W) not in (2, 4):
         band_clear = abea.ABEA_CLEAR_AUTO
     db = abea.to_device(batch, dev)  # inputs resident in HBM, shared by all slots
@@ -613,9 +620,10 @@ def main():
         "the 5120 resident wave slots",
     )
     ap.add_argument("--wpg", type=int, default=1, help="wavefronts (reads) per workgroup of the fused kernel")
-    ap.add_argument("--band-clear", type=int, default=2, choices=(0, 1, 2),
-                    help="plain workloads: slot clearing of interior bands, 0 auto, 1 window, 2 edges "
-                         "(default edges: the batches in flight together fill every SIMD)")
+    ap.add_argument("--band-clear", type=int, default=-1, choices=(-1, 0, 1, 2),
+                    help="plain workloads: slot clearing of interior bands, 0 the library's choice, 1 window, "
+                         "2 edges; -1 (default) edges when the batches in flight hold two wavefronts per SIMD, "
+                         "else the library's choice")
     ap.add_argument("--tune", action="store_true", help="persistent workloads: autotune the launch form")
     ap.add_argument("--cpl", type=int, default=0, help="persistent: cells per lane (0 = smallest)")
     ap.add_argument("--wps", type=int, default=4, help="persistent: pool wavefronts per SIMD")
