@@ -85,12 +85,23 @@ typedef struct {
   const float *level_stdv;
 } abea_model_t;
 
+/* arena_bytes values: ABEA_ARENA_AUTO takes a fraction of the device memory
+ * free when the context is created (the thesis's GPU memory fraction, its
+ * CLI's --cuda-mem-frac, 0.9 by default; §5.4.2.2 sizes its pre-allocation
+ * from free memory); ABEA_ARENA_UNBOUNDED sets no budget. */
+#define ABEA_ARENA_AUTO 0ull
+#define ABEA_ARENA_UNBOUNDED UINT64_MAX
+#define ABEA_ARENA_AUTO_FRACTION 0.9
+
 typedef struct {
   int32_t bandwidth;    /* W, the band width (thesis: typically 100) */
   int32_t device;       /* HIP device ordinal */
-  uint64_t arena_bytes; /* traceback budget of one batch in bytes (0 = unbounded): the fused
-                           kernel runs only as many reads at once as their trace fits in it
-                           (admission by traceback bytes); see abea_launch_t */
+  uint64_t arena_bytes; /* traceback budget of one batch in bytes (admission by traceback
+                           bytes): the fused kernel runs only as many reads at once as their
+                           trace fits in it, and the split kernels run the batch in parts
+                           whose traces fit it; a read whose own trace exceeds it fails the
+                           call with ABEA_E_NOMEM.  ABEA_ARENA_AUTO or ABEA_ARENA_UNBOUNDED,
+                           or a byte count; see abea_launch_t */
   uint32_t flags;       /* ABEA_F_* */
 } abea_config_t;
 
@@ -141,10 +152,16 @@ int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **
  * Align a batch held in host memory; synchronous.  Every pointer in *batch
  * and *res is a host pointer; the call copies the inputs to the device, runs
  * the alignment and copies the results back before returning, and keeps no
- * reference to the caller's buffers.  A context is not thread-safe.
+ * reference to the caller's buffers.  Copies go through a pinned staging ring
+ * the context owns (two chunks of ABEA_HOST_STAGING_CHUNK bytes, allocated at
+ * the first call): the event means (the only event field read, Alg. 5.3) are
+ * gathered into it by host threads while the previous chunk is in flight,
+ * and the pairs come back through it the same way.  A context is not
+ * thread-safe.
  * Errors: ABEA_E_INVAL, ABEA_E_CAPACITY (nothing written), ABEA_E_NOMEM,
  * ABEA_E_HIP.
  */
+#define ABEA_HOST_STAGING_CHUNK (32ull << 20)
 int abea_align_batch(abea_ctx *ctx, const abea_batch_t *batch, abea_result_t *res);
 
 /*
@@ -168,7 +185,8 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *batch,
  * Device time in milliseconds of each stage of the last direct call
  * (abea_align_batch or abea_align_batch_device), when the context was
  * created with ABEA_F_TIMING: out[0] k-mer parameter preparation, out[1] band
- * fill (split kernels) or band fill + backtrack (fused kernel), from the start
+ * fill (split kernels; in several parts, from the first part's band fill to
+ * the last part's) or band fill + backtrack (fused kernel), from the start
  * to the end of that kernel's dispatch (time spent waiting for free compute
  * units behind other work on the device is not counted), out[2] backtrack
  * (split kernels; 0 for the fused kernel), out[3] path-length scan and
@@ -184,7 +202,8 @@ int abea_get_timings(abea_ctx *ctx, float *out, int n);
  * §5.4.1) and pre-allocates memory for a batch with a CPU fall-back for reads
  * that do not fit (§5.4.2.2, §5.4.3); here:
  *   workers == ABEA_WORKERS_SPLIT : one wavefront per read, band fill and
- *       backtrack as two kernels (every read's trace is in memory at once);
+ *       backtrack as two kernels (every read's trace is in memory at once,
+ *       or, under a trace budget, the reads of one part at a time);
  *   workers == 0 : one fused kernel, one wavefront per read that fills the
  *       bands and then backtracks (the default; one launch per batch);
  *   workers  > 0 : the fused kernel as a persistent pool of that many
@@ -235,7 +254,9 @@ typedef struct {
   uint64_t trace_bytes;    /* device trace memory of the batch */
   uint64_t scratch_bytes;  /* device pair scratch of the batch */
   int32_t band_clear;      /* ABEA_CLEAR_WINDOW or ABEA_CLEAR_EDGES, as resolved */
-  int32_t reserved;        /* 0 */
+  int32_t parts;           /* split kernels: parts the batch runs in under the trace budget;
+                              fused kernel: 1 */
+  uint64_t trace_budget;   /* the context's trace budget in bytes (0: none) */
 } abea_plan_info_t;
 int abea_get_plan_info(const abea_ctx *ctx, abea_plan_info_t *info);
 

@@ -34,6 +34,9 @@ ABEA_WORKERS_SPLIT = -1
 ABEA_CLEAR_AUTO = 0  # band_clear: the library chooses
 ABEA_CLEAR_WINDOW = 1  # every slot outside the band's cells, every band
 ABEA_CLEAR_EDGES = 2  # interior bands: only the two slots beside the band
+ABEA_ARENA_AUTO = 0  # arena_bytes: 0.9 of the device memory free at abea_create
+ABEA_ARENA_UNBOUNDED = (1 << 64) - 1  # arena_bytes: no trace budget
+ABEA_HOST_STAGING_CHUNK = 32 << 20
 
 EXPORTED = (
     "abea_create",
@@ -127,11 +130,12 @@ class abea_plan_info_t(ctypes.Structure):
         ("trace_bytes", ctypes.c_uint64),
         ("scratch_bytes", ctypes.c_uint64),
         ("band_clear", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("parts", ctypes.c_int32),
+        ("trace_budget", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class abea_server_config_t(ctypes.Structure):

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/abea.h"
@@ -49,49 +50,101 @@ int fail(abea_ctx *ctx, int code, const char *fmt, ...) {
   return code;
 }
 
-
-
-int ensure(abea_ctx *ctx, Work *w, DevBuf &b, size_t bytes) {
+int ensure(abea_ctx *ctx, Work *w, DevBuf &b, size_t bytes, hipStream_t st) {
   if (bytes == 0) bytes = 256;
   if (bytes <= b.cap) return ABEA_OK;
-  /* kernels queued by earlier calls may still use the old buffer */
-  if (w && w->last_stream) HIP_TRY(ctx, hipStreamSynchronize(w->last_stream));
-  HIP_TRY(ctx, hipDeviceSynchronize());
-  if (b.p) HIP_TRY(ctx, hipFree(b.p));
-  b.p = nullptr;
-  b.cap = 0;
   const size_t rounded = (bytes + (2u << 20) - 1) & ~size_t((2u << 20) - 1);
-  hipError_t e = hipMalloc(&b.p, rounded);
+  hipError_t e;
+  if (w && ctx->pools) {
+    /* stream-ordered growth: the old buffer is released on `st` once w's last
+     * batch is done with it (same stream: stream order; another stream: a
+     * device-side wait on that batch's event), and the new one is allocated
+     * on `st` */
+    if (b.p) {
+      if (w->done_pending && w->last_stream != st) HIP_TRY(ctx, hipStreamWaitEvent(st, w->done, 0));
+      if (b.pooled) {
+        HIP_TRY(ctx, hipFreeAsync(b.p, st));
+      } else {
+        const int rc = work_wait(ctx, *w);
+        if (rc) return rc;
+        HIP_TRY(ctx, hipFree(b.p));
+      }
+      b.p = nullptr;
+      b.cap = 0;
+    }
+    e = hipMallocAsync(&b.p, rounded, st);
+    b.pooled = true;
+  } else {
+    /* a set-up buffer (no queued work uses it), or a device without memory
+     * pools: wait for w's own last batch only */
+    if (w && b.p) {
+      const int rc = work_wait(ctx, *w);
+      if (rc) return rc;
+    }
+    if (b.p) HIP_TRY(ctx, hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+    e = hipMalloc(&b.p, rounded);
+    b.pooled = false;
+  }
   if (e != hipSuccess) {
     b.p = nullptr;
     (void)hipGetLastError();
-    return fail(ctx, ABEA_E_NOMEM, "hipMalloc(%zu bytes) failed: %s", rounded, hipGetErrorString(e));
+    return fail(ctx, ABEA_E_NOMEM, "device allocation of %zu bytes failed: %s", rounded, hipGetErrorString(e));
   }
   b.cap = rounded;
   return ABEA_OK;
 }
 
-void free_buf(DevBuf &b) {
-  if (b.p) (void)hipFree(b.p);
+void free_buf(DevBuf &b, hipStream_t st) {
+  if (b.p) {
+    if (b.pooled)
+      (void)hipFreeAsync(b.p, st);
+    else
+      (void)hipFree(b.p);
+  }
   b.p = nullptr;
   b.cap = 0;
+  b.pooled = false;
 }
 
 int work_init(abea_ctx *ctx, Work &w) {
   HIP_TRY(ctx, hipEventCreateWithFlags(&w.staging_done, hipEventDisableTiming));
+  HIP_TRY(ctx, hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
   for (auto &ev : w.tev) HIP_TRY(ctx, hipEventCreate(&ev));
   return ABEA_OK;
 }
 
-void work_free(Work &w) {
+int work_wait(abea_ctx *ctx, Work &w) {
+  if (w.done_pending) HIP_TRY(ctx, hipEventSynchronize(w.done));
+  w.done_pending = false;
+  return ABEA_OK;
+}
+
+int work_mark(abea_ctx *ctx, Work &w, hipStream_t st) {
+  HIP_TRY(ctx, hipEventRecord(w.done, st));
+  w.last_stream = st;
+  w.done_pending = true;
+  return ABEA_OK;
+}
+
+void work_free(Work &w, hipStream_t st) {
+  if (w.done_pending && w.done) (void)hipEventSynchronize(w.done);
+  w.done_pending = false;
   DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.xmean, &w.kparam,
                     &w.trace, &w.scratch, &w.path_len, &w.path_src};
-  for (DevBuf *b : bufs) free_buf(*b);
+  for (DevBuf *b : bufs) free_buf(*b, st);
+  if (w.staging_pending && w.staging_done) (void)hipEventSynchronize(w.staging_done);
+  w.staging_pending = false;
   if (w.h_reads) (void)hipHostFree(w.h_reads);
   w.h_reads = nullptr;
   w.h_cap = 0;
+  for (void *h : w.retired_host) (void)hipHostFree(h);
+  w.retired_host.clear();
   if (w.staging_done) (void)hipEventDestroy(w.staging_done);
   w.staging_done = nullptr;
+  if (w.done) (void)hipEventDestroy(w.done);
+  w.done = nullptr;
   for (auto &ev : w.tev) {
     if (ev) (void)hipEventDestroy(ev);
     ev = nullptr;
@@ -140,10 +193,14 @@ bool edge_clearing(const abea_ctx *ctx, int waves) {
  *    longest first, so the longest band chains start first and every read
  *    fits the trace region of any read planned before it.
  *  - Pair scratch: n_e + n_k - 1 slots per read (a path never has more).
- *  - Trace: fused kernel with P workers: read s < P gets its own region and
+ *  - Trace, fused kernel with P workers: read s < P gets its own region and
  *    worker s reuses it for every later read it takes; P is the requested
  *    worker count, capped by residency and by the trace budget (admission by
- *    traceback bytes).  Split kernels: every read gets its own region. */
+ *    traceback bytes).
+ *  - Trace, split kernels: every read of a part has its own region; the reads
+ *    are cut into consecutive parts whose traces fit the budget, run one
+ *    part after the other.
+ * Only a read whose own trace exceeds the budget is refused (ABEA_E_NOMEM). */
 int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t *ko,
                uint64_t pair_capacity) {
   Plan &P = w.plan;
@@ -171,44 +228,51 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
   /* trace words of planned read s, and the worker count */
   const int G = bands_per_group(ctx->cpl);
   auto words = [&](int s) -> uint64_t { return ((comp[w.order[s]] + G - 1) / G) * 64u; };
+  const uint64_t budget = ctx->trace_budget;
+  const bool split = split_kernels(ctx);
+  if (n > 0 && budget > 0 && words(0) * sizeof(uint2) > budget)
+    return fail(ctx, ABEA_E_NOMEM, "the trace of the longest read (%llu bytes) exceeds the trace budget %llu",
+                (unsigned long long)(words(0) * sizeof(uint2)), (unsigned long long)budget);
   int workers = n;
-  const bool pool = !split_kernels(ctx) && ctx->launch.workers > 0;
+  const bool pool = !split && ctx->launch.workers > 0;
   P.edge = edge_clearing(ctx, pool ? std::min(n, ctx->launch.workers) : n);
   if (pool) workers = std::min(n, std::min(ctx->launch.workers, resident_workers(ctx, P.edge)));
-  if (ctx->arena_bytes > 0) {
+  if (!split && budget > 0) {
     uint64_t sum = 0;
     int fit = 0;
-    while (fit < workers && (sum + words(fit)) * sizeof(uint2) <= ctx->arena_bytes) sum += words(fit++);
-    if (fit < workers) {
-      if (split_kernels(ctx) || fit == 0)
-        return fail(ctx, ABEA_E_NOMEM, "trace of %s needs more than arena_bytes = %llu",
-                    fit == 0 ? "the longest read" : "the batch", (unsigned long long)ctx->arena_bytes);
-      workers = fit;
-    }
+    while (fit < workers && (sum + words(fit)) * sizeof(uint2) <= budget) sum += words(fit++);
+    workers = fit; /* at least the longest read, which fits (checked above) */
   }
-  P.workers = split_kernels(ctx) ? 0 : workers;
+  P.workers = split ? 0 : workers;
   P.cpl = ctx->cpl;
   P.wpg = ctx->launch.waves_per_group;
 
   if ((size_t)n > w.h_cap) {
-    if (w.staging_pending) HIP_TRY(ctx, hipEventSynchronize(w.staging_done));
-    w.staging_pending = false;
-    if (w.h_reads) (void)hipHostFree(w.h_reads);
-    w.h_reads = nullptr;
-    w.h_cap = 0;
-    const size_t cap = std::max<size_t>(n, 1024);
-    HIP_TRY(ctx, hipHostMalloc((void **)&w.h_reads, cap * sizeof(ReadDesc), hipHostMallocDefault));
+    /* a larger pinned staging buffer; the old one may still feed a queued
+     * upload and is freed with the Work (freeing pinned memory here would
+     * wait for the whole device) */
+    const size_t cap = std::max<size_t>({(size_t)n, 2 * w.h_cap, 1024});
+    ReadDesc *h = nullptr;
+    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap * sizeof(ReadDesc), hipHostMallocDefault));
+    if (w.h_reads) w.retired_host.push_back(w.h_reads);
+    w.h_reads = h;
     w.h_cap = cap;
+    w.staging_pending = false;
   }
   /* the previous call's upload must have left the staging buffer */
   if (w.staging_pending) HIP_TRY(ctx, hipEventSynchronize(w.staging_done));
   w.staging_pending = false;
 
-  uint64_t tr = 0, pr = 0;
+  P.parts.assign(1, 0);
+  uint64_t tr = 0, tr_max = 0, pr = 0;
   for (int s = 0; s < n; ++s) {
     const int r = w.order[s];
     ReadDesc &d = w.h_reads[s];
     const uint64_t ne = eo[r + 1] - eo[r], nk = ko[r + 1] - ko[r];
+    if (split && budget > 0 && comp[r] > 0 && (tr + words(s)) * sizeof(uint2) > budget) {
+      P.parts.push_back(s); /* the next part reuses the trace buffer from 0 */
+      tr = 0;
+    }
     d.ev_off = eo[r];
     d.km_off = ko[r];
     d.n_e = (int32_t)ne;
@@ -221,9 +285,11 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
     if (comp[r] == 0) continue;
     transitions((int64_t)ne, (int64_t)nk, &d.lp_skip, &d.lp_stay, &d.lp_step);
     if (s < workers) tr += words(s);
+    tr_max = std::max(tr_max, tr);
     pr += comp[r];
   }
-  P.n_trace = tr;
+  P.parts.push_back(n);
+  P.n_trace = tr_max;
   P.n_scratch = pr;
   /* the 256 longest reads (about one per CU) issue at raised priority */
   {
@@ -235,21 +301,19 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
   return ABEA_OK;
 }
 
-
-
-int ensure_work(abea_ctx *ctx, Work &w) {
+int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st) {
   const Plan &P = w.plan;
   const size_t n = (size_t)std::max(P.n, 1);
   int rc;
-  if ((rc = ensure(ctx, &w, w.reads, sizeof(ReadDesc) * n))) return rc;
-  if ((rc = ensure(ctx, &w, w.rstat, sizeof(int32_t) * n))) return rc;
-  if ((rc = ensure(ctx, &w, w.queue, sizeof(uint32_t)))) return rc;
-  if ((rc = ensure(ctx, &w, w.xmean, sizeof(float) * (size_t)P.n_events))) return rc;
-  if ((rc = ensure(ctx, &w, w.kparam, sizeof(KParam) * (size_t)P.n_kmers))) return rc;
-  if ((rc = ensure(ctx, &w, w.trace, sizeof(uint2) * (size_t)P.n_trace))) return rc;
-  if ((rc = ensure(ctx, &w, w.scratch, sizeof(int2) * (size_t)P.n_scratch))) return rc;
-  if ((rc = ensure(ctx, &w, w.path_len, sizeof(uint64_t) * n))) return rc;
-  if ((rc = ensure(ctx, &w, w.path_src, sizeof(uint64_t) * n))) return rc;
+  if ((rc = ensure(ctx, &w, w.reads, sizeof(ReadDesc) * n, st))) return rc;
+  if ((rc = ensure(ctx, &w, w.rstat, sizeof(int32_t) * n, st))) return rc;
+  if ((rc = ensure(ctx, &w, w.queue, sizeof(uint32_t), st))) return rc;
+  if ((rc = ensure(ctx, &w, w.xmean, sizeof(float) * (size_t)P.n_events, st))) return rc;
+  if ((rc = ensure(ctx, &w, w.kparam, sizeof(KParam) * (size_t)P.n_kmers, st))) return rc;
+  if ((rc = ensure(ctx, &w, w.trace, sizeof(uint2) * (size_t)P.n_trace, st))) return rc;
+  if ((rc = ensure(ctx, &w, w.scratch, sizeof(int2) * (size_t)P.n_scratch, st))) return rc;
+  if ((rc = ensure(ctx, &w, w.path_len, sizeof(uint64_t) * n, st))) return rc;
+  if ((rc = ensure(ctx, &w, w.path_src, sizeof(uint64_t) * n, st))) return rc;
   return ABEA_OK;
 }
 
@@ -260,7 +324,7 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   const ReadDesc *reads = (const ReadDesc *)w.reads.p;
   int32_t *rstat = (int32_t *)w.rstat.p;
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[0], st));
-  HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ranks, io.in_addr, io.scale, io.shift,
+  HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ev_stride, io.ranks, io.in_addr, io.scale, io.shift,
                            (const ModelEntry *)ctx->model.p, ctx->n_model,
                            (ctx->flags & ABEA_F_SCALE_EVENTS) != 0, (float *)w.xmean.p,
                            (KParam *)w.kparam.p, rstat, (uint32_t *)w.queue.p, st));
@@ -288,7 +352,19 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   hipEvent_t k0 = timed ? w.tev[2] : nullptr, k1 = timed ? w.tev[3] : nullptr;
   const bool launched = n > 0 && (P.workers == 0 || (P.workers > 0 && P.workers <= n));
   if (P.workers == 0) {
-    HIP_TRY(ctx, launch_band(a, P.cpl, refills_per_group(ctx->W, P.cpl), P.edge, st, k0, k1));
+    /* split kernels, part after part over the same trace buffer (with more
+     * than one part the band interval runs from the first part's band fill
+     * to the last part's) */
+    const int np = (int)P.parts.size() - 1;
+    for (int p = 0; p < np; ++p) {
+      AlignArgs ap = a;
+      ap.reads = reads + P.parts[p];
+      ap.rstat = rstat + P.parts[p];
+      ap.n_reads = P.parts[p + 1] - P.parts[p];
+      HIP_TRY(ctx, launch_band(ap, P.cpl, refills_per_group(ctx->W, P.cpl), P.edge, st, p == 0 ? k0 : nullptr,
+                               p == np - 1 ? k1 : nullptr));
+      if (p < np - 1) HIP_TRY(ctx, launch_backtrack(ap, P.cpl, st));
+    }
   } else {
     HIP_TRY(ctx, launch_align(a, P.cpl, refills_per_group(ctx->W, P.cpl), P.wpg, P.edge, st, k0, k1));
   }
@@ -296,7 +372,14 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
     HIP_TRY(ctx, hipEventRecord(w.tev[2], st));
     HIP_TRY(ctx, hipEventRecord(w.tev[3], st));
   }
-  if (P.workers == 0) HIP_TRY(ctx, launch_backtrack(a, P.cpl, st));
+  if (P.workers == 0 && P.parts.size() >= 2) {
+    AlignArgs ap = a;
+    const int lp = (int)P.parts.size() - 2;
+    ap.reads = reads + P.parts[lp];
+    ap.rstat = rstat + P.parts[lp];
+    ap.n_reads = P.parts[lp + 1] - P.parts[lp];
+    HIP_TRY(ctx, launch_backtrack(ap, P.cpl, st));
+  }
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[4], st));
 
   HIP_TRY(ctx, launch_scan((const uint64_t *)w.path_len.p, n, io.pair_offset, st));
@@ -310,12 +393,115 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
 /* Upload the plan and enqueue the batch on `st`. */
 int run_planned(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st) {
   int rc;
-  if ((rc = ensure_work(ctx, w))) return rc;
-  w.last_stream = st;
+  if ((rc = ensure_work(ctx, w, st))) return rc;
   HIP_TRY(ctx, hipMemcpyAsync(w.reads.p, w.h_reads, sizeof(ReadDesc) * w.plan.n, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipEventRecord(w.staging_done, st));
   w.staging_pending = true;
-  return enqueue_kernels(ctx, w, io, st, (ctx->flags & ABEA_F_TIMING) != 0);
+  if ((rc = enqueue_kernels(ctx, w, io, st, (ctx->flags & ABEA_F_TIMING) != 0))) return rc;
+  return work_mark(ctx, w, st);
+}
+
+/* ---- host-API staging ---------------------------------------------------- */
+
+/* fn(lo, hi) over [0, n) on up to eight host threads, about `grain` items or
+ * more each; the calling thread takes the first range, and any range whose
+ * thread cannot start runs on it too. */
+template <typename F>
+void parallel_for(size_t n, size_t grain, F fn) {
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t T = std::min<size_t>({8, hw, std::max<size_t>(1, n / std::max<size_t>(grain, 1))});
+  if (T <= 1) {
+    fn(0, n);
+    return;
+  }
+  const size_t per = (n + T - 1) / T;
+  std::vector<std::thread> th;
+  th.reserve(T - 1);
+  for (size_t t = 1; t < T; ++t) {
+    const size_t lo = std::min(n, t * per), hi = std::min(n, lo + per);
+    if (lo >= hi) break;
+    try {
+      th.emplace_back(fn, lo, hi);
+    } catch (...) {
+      fn(lo, hi);
+    }
+  }
+  fn(0, std::min(n, per));
+  for (auto &x : th) x.join();
+}
+
+/* The pinned staging ring of the host API (two chunks), at the first call. */
+int stage_init(abea_ctx *ctx) {
+  for (int i = 0; i < 2; ++i) {
+    if (!ctx->h_stage[i]) HIP_TRY(ctx, hipHostMalloc(&ctx->h_stage[i], ABEA_HOST_STAGING_CHUNK, hipHostMallocDefault));
+    if (!ctx->stage_ev[i]) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->stage_ev[i], hipEventDisableTiming));
+  }
+  return ABEA_OK;
+}
+
+/* The next ring chunk, once the copy that last used it is done. */
+int stage_take(abea_ctx *ctx, int *slot) {
+  const int sl = ctx->stage_next;
+  ctx->stage_next ^= 1;
+  if (ctx->stage_pending[sl]) HIP_TRY(ctx, hipEventSynchronize(ctx->stage_ev[sl]));
+  ctx->stage_pending[sl] = false;
+  *slot = sl;
+  return ABEA_OK;
+}
+
+/* dst[0, bytes) on the device from fill(off, len, chunk), chunk by chunk on
+ * the context's stream: the host fills one chunk while the other is in
+ * flight. */
+template <typename Fill>
+int stage_up(abea_ctx *ctx, void *dst, size_t bytes, Fill fill) {
+  const size_t C = ABEA_HOST_STAGING_CHUNK;
+  for (size_t off = 0; off < bytes; off += C) {
+    int sl, rc;
+    if ((rc = stage_take(ctx, &sl))) return rc;
+    const size_t len = std::min(C, bytes - off);
+    fill(off, len, (char *)ctx->h_stage[sl]);
+    HIP_TRY(ctx, hipMemcpyAsync((char *)dst + off, ctx->h_stage[sl], len, hipMemcpyHostToDevice, ctx->own_stream));
+    HIP_TRY(ctx, hipEventRecord(ctx->stage_ev[sl], ctx->own_stream));
+    ctx->stage_pending[sl] = true;
+  }
+  return ABEA_OK;
+}
+
+int stage_copy_up(abea_ctx *ctx, void *dst, const void *src, size_t bytes) {
+  const char *s = (const char *)src;
+  return stage_up(ctx, dst, bytes, [s](size_t off, size_t len, char *d) {
+    parallel_for(len, 1u << 20, [d, s, off](size_t lo, size_t hi) { std::memcpy(d + lo, s + off + lo, hi - lo); });
+  });
+}
+
+/* src[0, bytes) on the device to drain(off, len, chunk), chunk by chunk:
+ * the next chunk's copy is in flight while the host drains the last one. */
+template <typename Drain>
+int stage_down(abea_ctx *ctx, const void *src, size_t bytes, Drain drain) {
+  const size_t C = ABEA_HOST_STAGING_CHUNK;
+  int prev = -1;
+  size_t prev_off = 0, prev_len = 0;
+  for (size_t off = 0;; off += C) {
+    int sl = -1, rc;
+    if (off < bytes) {
+      if ((rc = stage_take(ctx, &sl))) return rc;
+      const size_t len = std::min(C, bytes - off);
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->h_stage[sl], (const char *)src + off, len, hipMemcpyDeviceToHost,
+                                  ctx->own_stream));
+      HIP_TRY(ctx, hipEventRecord(ctx->stage_ev[sl], ctx->own_stream));
+      ctx->stage_pending[sl] = true;
+    }
+    if (prev >= 0) {
+      HIP_TRY(ctx, hipEventSynchronize(ctx->stage_ev[prev]));
+      ctx->stage_pending[prev] = false;
+      drain(prev_off, prev_len, (const char *)ctx->h_stage[prev]);
+    }
+    if (off >= bytes) break;
+    prev = sl;
+    prev_off = off;
+    prev_len = std::min(C, bytes - off);
+  }
+  return ABEA_OK;
 }
 
 int check_batch(abea_ctx *ctx, const abea_batch_t *b, const abea_result_t *r) {
@@ -382,13 +568,25 @@ int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **
   ctx->flags = cfg->flags;
   ctx->k = model->k;
   ctx->n_model = n_model;
-  ctx->arena_bytes = cfg->arena_bytes;
+  ctx->trace_budget = cfg->arena_bytes == ABEA_ARENA_UNBOUNDED ? 0 : cfg->arena_bytes;
   int rc = ABEA_OK;
   do {
     hipError_t e = hipSetDevice(cfg->device);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "hipSetDevice: %s", hipGetErrorString(e)); break; }
     e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "device attribute: %s", hipGetErrorString(e)); break; }
+    int pools = 0;
+    e = hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, cfg->device);
+    ctx->pools = (e == hipSuccess && pools != 0);
+    (void)hipGetLastError();
+    if (cfg->arena_bytes == ABEA_ARENA_AUTO) {
+      /* a fraction of the device memory free now (the thesis's GPU memory
+       * fraction, 0.9 by default) */
+      size_t fr = 0, tot = 0;
+      e = hipMemGetInfo(&fr, &tot);
+      if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "hipMemGetInfo: %s", hipGetErrorString(e)); break; }
+      ctx->trace_budget = std::max<uint64_t>((uint64_t)((double)fr * ABEA_ARENA_AUTO_FRACTION), 1);
+    }
     if ((rc = ensure(ctx, nullptr, ctx->model, sizeof(ModelEntry) * n_model))) break;
     e = hipMemcpy(ctx->model.p, me.data(), sizeof(ModelEntry) * n_model, hipMemcpyHostToDevice);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "model upload: %s", hipGetErrorString(e)); break; }
@@ -407,12 +605,23 @@ int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **
 void abea_destroy(abea_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
-  (void)hipDeviceSynchronize();
-  work_free(ctx->main);
+  /* wait for this context's own work only (its last batch, and the host
+   * API's copies on its stream), then release in order on its stream */
+  (void)work_wait(ctx, ctx->main);
+  hipStream_t st = ctx->own_stream;
+  if (st) (void)hipStreamSynchronize(st);
+  work_free(ctx->main, st);
   DevBuf *bufs[] = {&ctx->model, &ctx->events, &ctx->ranks, &ctx->scale, &ctx->shift,
                     &ctx->pairs, &ctx->pair_offset, &ctx->ll, &ctx->status, &ctx->cells};
-  for (DevBuf *b : bufs) free_buf(*b);
-  if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+  for (DevBuf *b : bufs) free_buf(*b, st);
+  if (st) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (ctx->h_stage[i]) (void)hipHostFree(ctx->h_stage[i]);
+    if (ctx->stage_ev[i]) (void)hipEventDestroy(ctx->stage_ev[i]);
+  }
   delete ctx;
 }
 
@@ -423,6 +632,7 @@ int abea_cells_per_lane(int32_t bandwidth) {
 
 int abea_set_launch(abea_ctx *ctx, const abea_launch_t *l) {
   if (!ctx) return ABEA_E_INVAL;
+  int rc;
   if (!l) return fail(ctx, ABEA_E_INVAL, "null launch");
   if (l->workers < ABEA_WORKERS_SPLIT) return fail(ctx, ABEA_E_INVAL, "workers < -1");
   if (l->waves_per_group != 1 && l->waves_per_group != 2 && l->waves_per_group != 4)
@@ -436,8 +646,8 @@ int abea_set_launch(abea_ctx *ctx, const abea_launch_t *l) {
     return fail(ctx, ABEA_E_INVAL, "band_clear %d: need 0, 1 or 2", l->band_clear);
   if (l->band_clear == ABEA_CLEAR_EDGES && c != 2 && c != 4)
     return fail(ctx, ABEA_E_INVAL, "band_clear ABEA_CLEAR_EDGES needs 2 or 4 cells_per_lane, not %d", c);
-  /* buffers of an earlier call may still be in use by queued kernels */
-  if (ctx->main.last_stream) HIP_TRY(ctx, hipStreamSynchronize(ctx->main.last_stream));
+  /* the context's queued batch was planned with the old form */
+  if ((rc = work_wait(ctx, ctx->main))) return rc;
   ctx->launch = *l;
   ctx->cpl = c;
   return ABEA_OK;
@@ -451,9 +661,10 @@ int abea_get_plan_info(const abea_ctx *ctx, abea_plan_info_t *info) {
   info->cells_per_lane = P.cpl;
   info->waves_per_group = P.wpg;
   info->band_clear = P.edge ? ABEA_CLEAR_EDGES : ABEA_CLEAR_WINDOW;
-  info->reserved = 0;
+  info->parts = std::max(1, (int)P.parts.size() - 1);
   info->trace_bytes = P.n_trace * sizeof(uint2);
   info->scratch_bytes = P.n_scratch * sizeof(int2);
+  info->trace_budget = ctx->trace_budget;
   return ABEA_OK;
 }
 
@@ -498,25 +709,33 @@ int abea_align_batch(abea_ctx *ctx, const abea_batch_t *b, abea_result_t *r) {
   if (P.pairs_needed > 0 && !r->pairs) return fail(ctx, ABEA_E_INVAL, "null pairs");
   hipStream_t st = ctx->own_stream;
   Work *w = &ctx->main;
-  if ((rc = ensure(ctx, w, ctx->events, sizeof(abea_event_t) * (size_t)P.n_events))) return rc;
-  if ((rc = ensure(ctx, w, ctx->ranks, sizeof(uint32_t) * (size_t)P.n_kmers))) return rc;
-  if ((rc = ensure(ctx, w, ctx->scale, sizeof(float) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, w, ctx->shift, sizeof(float) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, w, ctx->pairs, sizeof(abea_pair_t) * (size_t)P.pairs_needed))) return rc;
-  if ((rc = ensure(ctx, w, ctx->pair_offset, sizeof(uint64_t) * (size_t)(n + 1)))) return rc;
-  if ((rc = ensure(ctx, w, ctx->ll, sizeof(float) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, w, ctx->status, sizeof(int32_t) * (size_t)n))) return rc;
-  if ((rc = ensure(ctx, w, ctx->cells, sizeof(uint64_t) * (size_t)n))) return rc;
-  if (P.n_events)
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->events.p, b->events, sizeof(abea_event_t) * P.n_events,
-                                hipMemcpyHostToDevice, st));
-  if (P.n_kmers)
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->ranks.p, b->kmer_rank, sizeof(uint32_t) * P.n_kmers,
-                                hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->scale.p, b->scale, sizeof(float) * n, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->shift.p, b->shift, sizeof(float) * n, hipMemcpyHostToDevice, st));
+  if ((rc = stage_init(ctx))) return rc;
+  if ((rc = ensure(ctx, w, ctx->events, sizeof(float) * (size_t)P.n_events, st))) return rc;
+  if ((rc = ensure(ctx, w, ctx->ranks, sizeof(uint32_t) * (size_t)P.n_kmers, st))) return rc;
+  if ((rc = ensure(ctx, w, ctx->scale, sizeof(float) * (size_t)n, st))) return rc;
+  if ((rc = ensure(ctx, w, ctx->shift, sizeof(float) * (size_t)n, st))) return rc;
+  if ((rc = ensure(ctx, w, ctx->pairs, sizeof(abea_pair_t) * (size_t)P.pairs_needed, st))) return rc;
+  if ((rc = ensure(ctx, w, ctx->pair_offset, sizeof(uint64_t) * (size_t)(n + 1), st))) return rc;
+  if ((rc = ensure(ctx, w, ctx->ll, sizeof(float) * (size_t)n, st))) return rc;
+  if ((rc = ensure(ctx, w, ctx->status, sizeof(int32_t) * (size_t)n, st))) return rc;
+  if ((rc = ensure(ctx, w, ctx->cells, sizeof(uint64_t) * (size_t)n, st))) return rc;
+  /* inputs through the pinned ring: the event means gathered out of the
+   * 12-byte records, then the ranks, scales and shifts */
+  const abea_event_t *ev = b->events;
+  rc = stage_up(ctx, ctx->events.p, sizeof(float) * (size_t)P.n_events, [ev](size_t off, size_t len, char *dst) {
+    float *d = (float *)dst;
+    const abea_event_t *src = ev + off / sizeof(float);
+    parallel_for(len / sizeof(float), 1u << 16, [d, src](size_t lo, size_t hi) {
+      for (size_t i = lo; i < hi; ++i) d[i] = src[i].mean;
+    });
+  });
+  if (rc) return rc;
+  if ((rc = stage_copy_up(ctx, ctx->ranks.p, b->kmer_rank, sizeof(uint32_t) * (size_t)P.n_kmers))) return rc;
+  if ((rc = stage_copy_up(ctx, ctx->scale.p, b->scale, sizeof(float) * (size_t)n))) return rc;
+  if ((rc = stage_copy_up(ctx, ctx->shift.p, b->shift, sizeof(float) * (size_t)n))) return rc;
   DevIO io;
   io.events = (const float *)ctx->events.p;
+  io.ev_stride = 1;
   io.ranks = (const uint32_t *)ctx->ranks.p;
   io.scale = (const float *)ctx->scale.p;
   io.shift = (const float *)ctx->shift.p;
@@ -526,6 +745,7 @@ int abea_align_batch(abea_ctx *ctx, const abea_batch_t *b, abea_result_t *r) {
   io.status = (int32_t *)ctx->status.p;
   io.cells = (uint64_t *)ctx->cells.p;
   if ((rc = run_planned(ctx, ctx->main, io, st))) return rc;
+  /* the per-read results (small), then the pairs through the ring */
   HIP_TRY(ctx, hipMemcpyAsync(r->pair_offset, io.pair_offset, sizeof(uint64_t) * (n + 1),
                               hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipMemcpyAsync(r->log_likelihood, io.ll, sizeof(float) * n, hipMemcpyDeviceToHost, st));
@@ -536,8 +756,11 @@ int abea_align_batch(abea_ctx *ctx, const abea_batch_t *b, abea_result_t *r) {
   const uint64_t total = r->pair_offset[n];
   if (total > r->pair_capacity) return fail(ctx, ABEA_E_HIP, "internal: %llu pairs exceed capacity",
                                             (unsigned long long)total);
-  if (total)
-    HIP_TRY(ctx, hipMemcpy(r->pairs, io.pairs, sizeof(abea_pair_t) * total, hipMemcpyDeviceToHost));
+  char *dst = (char *)r->pairs;
+  rc = stage_down(ctx, io.pairs, sizeof(abea_pair_t) * total, [dst](size_t off, size_t len, const char *src) {
+    parallel_for(len, 1u << 20, [dst, off, src](size_t lo, size_t hi) { std::memcpy(dst + off + lo, src + lo, hi - lo); });
+  });
+  if (rc) return rc;
   return ABEA_OK;
 }
 
@@ -573,15 +796,17 @@ int abea_graph_create(abea_ctx *ctx, const abea_batch_t *b, const abea_result_t 
   hipError_t e;
   do {
     if ((rc = work_init(ctx, w))) break;
-    if ((rc = plan_batch(ctx, w, n, b->event_offset, b->kmer_offset, r->pair_capacity))) break;
-    if ((rc = ensure_work(ctx, w))) break;
-    /* the plan goes to the device once; replays do not copy */
-    if (n > 0) {
-      e = hipMemcpy(w.reads.p, w.h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice);
-      if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "plan upload: %s", hipGetErrorString(e)); break; }
-    }
     e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "stream: %s", hipGetErrorString(e)); break; }
+    if ((rc = plan_batch(ctx, w, n, b->event_offset, b->kmer_offset, r->pair_capacity))) break;
+    if ((rc = ensure_work(ctx, w, g->cap_stream))) break;
+    /* the plan goes to the device once; replays do not copy */
+    if (n > 0) {
+      e = hipMemcpyAsync(w.reads.p, w.h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice, g->cap_stream);
+      if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "plan upload: %s", hipGetErrorString(e)); break; }
+    }
+    e = hipStreamSynchronize(g->cap_stream);
+    if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "plan upload: %s", hipGetErrorString(e)); break; }
     e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "begin capture: %s", hipGetErrorString(e)); break; }
     int erc = ABEA_OK;
@@ -619,9 +844,8 @@ int abea_graph_launch(abea_graph *g, void *stream) {
   if (!g || !g->exec) return ABEA_E_INVAL;
   abea_ctx *ctx = g->ctx;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  g->work.last_stream = (hipStream_t)stream;
   HIP_TRY(ctx, hipGraphLaunch(g->exec, (hipStream_t)stream));
-  return ABEA_OK;
+  return work_mark(ctx, g->work, (hipStream_t)stream);
 }
 
 int abea_graph_info(const abea_graph *g, abea_plan_info_t *info) {
@@ -632,20 +856,26 @@ int abea_graph_info(const abea_graph *g, abea_plan_info_t *info) {
   info->cells_per_lane = P.cpl;
   info->waves_per_group = P.wpg;
   info->band_clear = P.edge ? ABEA_CLEAR_EDGES : ABEA_CLEAR_WINDOW;
-  info->reserved = 0;
+  info->parts = std::max(1, (int)P.parts.size() - 1);
   info->trace_bytes = P.n_trace * sizeof(uint2);
   info->scratch_bytes = P.n_scratch * sizeof(int2);
+  info->trace_budget = g->ctx->trace_budget;
   return ABEA_OK;
 }
 
 void abea_graph_destroy(abea_graph *g) {
   if (!g) return;
   (void)hipSetDevice(g->ctx->device);
-  (void)hipDeviceSynchronize();
+  /* wait for the graph's last replay only, then release its buffers in
+   * order on its own stream */
+  (void)work_wait(g->ctx, g->work);
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
-  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
-  work_free(g->work);
+  work_free(g->work, g->cap_stream);
+  if (g->cap_stream) {
+    (void)hipStreamSynchronize(g->cap_stream);
+    (void)hipStreamDestroy(g->cap_stream);
+  }
   delete g;
 }
 

@@ -100,7 +100,9 @@ struct AlignArgs {
  * used instead of the batch arrays. */
 /* scale_events: event means become (x - shift)/scale and the model levels
  * stay unscaled, instead of mu' = fmaf(level, scale, shift) */
-hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
+/* ev_stride: floats from one event mean to the next in `events` (3 for the
+ * 12-byte event records, 1 for a compact array of means) */
+hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events, int ev_stride,
                        const uint32_t *ranks, const uint64_t *in_addr, const float *scale,
                        const float *shift, const ModelEntry *model, uint32_t n_model,
                        bool scale_events, float *xmean, KParam *kparam, int32_t *rstat,

@@ -113,7 +113,7 @@ __device__ __forceinline__ float read_slot(const float (&v)[CPL], int slot) {
 /* ------------------------------------------------------------------ prep */
 
 __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads,
-                                              const float *__restrict__ events,
+                                              const float *__restrict__ events, int events_stride,
                                               const uint32_t *__restrict__ ranks,
                                               const uint64_t *__restrict__ in_addr,
                                               const float *__restrict__ scale,
@@ -132,10 +132,12 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
     return;
   }
   /* the read's events and ranks: in the batch arrays at its offsets (12-byte
-   * events, the mean first), or (in_addr) at addresses of its own, e.g. in
-   * mapped host memory, where only the event means are stored */
-  const float *ev = in_addr ? reinterpret_cast<const float *>(in_addr[2 * rd.orig]) : events + 3 * rd.ev_off;
-  const int ev_stride = in_addr ? 1 : 3;
+   * events with the mean first, or the means alone), or (in_addr) at
+   * addresses of its own, e.g. in mapped host memory, where only the event
+   * means are stored */
+  const int ev_stride = in_addr ? 1 : events_stride;
+  const float *ev =
+      in_addr ? reinterpret_cast<const float *>(in_addr[2 * rd.orig]) : events + (uint64_t)ev_stride * rd.ev_off;
   const uint32_t *rk =
       in_addr ? reinterpret_cast<const uint32_t *>(in_addr[2 * rd.orig + 1]) : ranks + rd.km_off;
   const float sc = scale[rd.orig];
@@ -160,11 +162,11 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
   if (scale_events) {
     /* x' = (x - shift) / scale: float32 subtract, correctly rounded divide */
     for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) {
-      const float d = ev[ev_stride * e] - sh;
+      const float d = ev[(int64_t)ev_stride * e] - sh;
       xmean[rd.ev_off + e] = d / sc;
     }
   } else {
-    for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) xmean[rd.ev_off + e] = ev[ev_stride * e];
+    for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) xmean[rd.ev_off + e] = ev[(int64_t)ev_stride * e];
   }
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) rstat[blockIdx.x] = bad ? READ_BAD_RANK : READ_OK;
@@ -947,14 +949,14 @@ __global__ __launch_bounds__(64) void k_compact(const int2 *__restrict__ scratch
 
 /* ------------------------------------------------------------- launchers */
 
-hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events,
+hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events, int ev_stride,
                        const uint32_t *ranks, const uint64_t *in_addr, const float *scale,
                        const float *shift, const ModelEntry *model, uint32_t n_model,
                        bool scale_events, float *xmean, KParam *kparam, int32_t *rstat,
                        uint32_t *queue, hipStream_t st) {
   if (n_planned <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(256), 0, st, reads, events, ranks, in_addr, scale,
-                     shift, model, n_model, (int)scale_events, xmean, kparam, rstat, queue);
+  hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(256), 0, st, reads, events, ev_stride, ranks, in_addr,
+                     scale, shift, model, n_model, (int)scale_events, xmean, kparam, rstat, queue);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ using namespace abea;
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
+  bool pooled = false; /* from the stream-ordered allocator (hipMallocAsync) */
 };
 
 struct Plan {
@@ -35,6 +36,10 @@ struct Plan {
   uint64_t n_kmers = 0;
   uint64_t pairs_needed = 0;
   int32_t urgent_len = 0x7fffffff;
+  /* split kernels under a trace budget: planned reads [parts[p], parts[p+1])
+   * form part p, whose traces fit the budget together; the parts run one
+   * after the other over the same trace buffer */
+  std::vector<int> parts;
 };
 
 /* Device buffers and staging of one planned batch.  The context owns one for
@@ -53,11 +58,20 @@ struct Work {
    * counted); after the backtrack; after the compaction */
   hipEvent_t tev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
+  /* the stream of the last enqueued batch, and an event recorded after it:
+   * later work that must wait for it (a buffer's release, a new launch
+   * form) waits for the event, never for the device */
   hipStream_t last_stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool done_pending = false;
+  /* pinned plan staging outgrown by a larger batch: freed with the Work (a
+   * pinned free on the call path would wait for the whole device) */
+  std::vector<void *> retired_host;
 };
 
 struct DevIO {
   const float *events;
+  int ev_stride = 3; /* floats from one event mean to the next: 3 (abea_event_t) or 1 (means only) */
   const uint32_t *ranks;
   const uint64_t *in_addr = nullptr; /* per-read input addresses (see launch_prep) */
   const float *scale;
@@ -77,15 +91,22 @@ struct abea_ctx {
   uint32_t flags = 0;
   uint32_t k = 6;
   uint32_t n_model = 0;
-  uint64_t arena_bytes = 0; /* trace budget of one batch (0 = unbounded) */
+  uint64_t trace_budget = 0; /* trace bytes of one batch (0 = unbounded) */
   int num_cus = 0;
+  bool pools = false; /* the device supports the stream-ordered allocator */
   abea_launch_t launch = {0, 1, 0, 0};
   int cpl = 2; /* slots per lane in use */
   abea_rt::DevBuf model;
   hipStream_t own_stream = nullptr;
   abea_rt::Work main;
-  /* host-API copies of inputs and outputs */
+  /* host-API copies of inputs (the event means only) and outputs */
   abea_rt::DevBuf events, ranks, scale, shift, pairs, pair_offset, ll, status, cells;
+  /* host-API pinned staging ring: two chunks, each with the event of the
+   * copy that last used it */
+  void *h_stage[2] = {nullptr, nullptr};
+  hipEvent_t stage_ev[2] = {nullptr, nullptr};
+  bool stage_pending[2] = {false, false};
+  int stage_next = 0;
   std::string err;
 };
 
@@ -100,15 +121,26 @@ int fail(abea_ctx *ctx, int code, const char *fmt, ...);
                   #expr, hipGetErrorString(e_));                                            \
   } while (0)
 
-/* Grow a device buffer to at least `bytes` (waits for queued work first). */
-int ensure(abea_ctx *ctx, Work *w, DevBuf &b, size_t bytes);
-void free_buf(DevBuf &b);
+/* Grow a device buffer to at least `bytes`.  w == nullptr: a set-up buffer
+ * that no queued work uses yet (plain hipMalloc).  Otherwise a buffer of w's
+ * batches, grown in stream order on `st`: the old buffer is released on `st`
+ * after w's last batch, the new one allocated on `st`; no other stream, and
+ * not the host, waits. */
+int ensure(abea_ctx *ctx, Work *w, DevBuf &b, size_t bytes, hipStream_t st = nullptr);
+/* Release a buffer; a pooled one in stream order on `st`, which must be
+ * ordered after every use of the buffer. */
+void free_buf(DevBuf &b, hipStream_t st = nullptr);
 int work_init(abea_ctx *ctx, Work &w);
-void work_free(Work &w);
+/* Wait (host) for w's last enqueued batch. */
+int work_wait(abea_ctx *ctx, Work &w);
+/* Release w's buffers on `st` (ordered after w's last batch). */
+void work_free(Work &w, hipStream_t st = nullptr);
+/* Record w.done on `st` after a batch was enqueued there. */
+int work_mark(abea_ctx *ctx, Work &w, hipStream_t st);
 /* Plan a batch from host offsets into w (see the definition). */
 int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t *ko, uint64_t pair_capacity);
-/* Device buffers of a planned batch. */
-int ensure_work(abea_ctx *ctx, Work &w);
+/* Device buffers of a planned batch, grown in stream order on `st`. */
+int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st);
 /* Kernels of a planned batch whose plan is on the device. */
 int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, bool timed);
 

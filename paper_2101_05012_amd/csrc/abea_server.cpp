@@ -247,9 +247,10 @@ void release_reads(abea_server *S, std::vector<SrvRead> &reads) {
 void slot_free(abea_server *S, Slot &s) {
   if (s.st) (void)hipStreamSynchronize(s.st);
   release_reads(S, s.reads);
-  work_free(s.work);
+  work_free(s.work, s.st);
   DevBuf *bufs[] = {&s.d_addr, &s.d_sc, &s.d_sh, &s.d_pairs, &s.d_po, &s.d_ll, &s.d_st, &s.d_cells};
-  for (DevBuf *b : bufs) free_buf(*b);
+  for (DevBuf *b : bufs) free_buf(*b, s.st);
+  if (s.st) (void)hipStreamSynchronize(s.st);
   void *hosts[] = {s.h_ev, s.h_rk, s.h_addr, s.h_sc, s.h_sh, s.h_eo, s.h_ko, s.h_pairs, s.h_po, s.h_cells,
                    s.h_ll, s.h_st};
   for (void *h : hosts)
@@ -348,8 +349,7 @@ int slot_launch(abea_server *S, Slot &s) {
   }
   int rc;
   if ((rc = plan_batch(ctx, s.work, n, s.h_eo, s.h_ko, eo + ko))) return rc;
-  if ((rc = ensure_work(ctx, s.work))) return rc;
-  s.work.last_stream = st;
+  if ((rc = ensure_work(ctx, s.work, st))) return rc;
   /* the prep kernel reads every read's events and ranks in place from
    * mapped pinned host memory: from the read's own buffer, or for a read
    * queued in pageable memory from the slot's mapped staging */
@@ -386,6 +386,7 @@ int slot_launch(abea_server *S, Slot &s) {
   io.status = (int32_t *)s.d_st.p;
   io.cells = (uint64_t *)s.d_cells.p;
   if ((rc = enqueue_kernels(ctx, s.work, io, st, false))) return rc;
+  if ((rc = work_mark(ctx, s.work, st))) return rc;
   HIP_TRY(ctx, hipMemcpyAsync(s.h_po, s.d_po.p, sizeof(uint64_t) * (n + 1), hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipMemcpyAsync(s.h_ll, s.d_ll.p, sizeof(float) * n, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipMemcpyAsync(s.h_st, s.d_st.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
