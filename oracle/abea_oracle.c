@@ -302,6 +302,7 @@ typedef struct {
   float *score;
   int32_t *status;
   int64_t *cells;
+  double *min_margin;
   const int32_t *order;
   int32_t next;
   int32_t error;
@@ -329,6 +330,7 @@ static void *batch_worker(void *arg) {
     J->score[r] = sc;
     J->path_len[r] = st.path_len;
     J->cells[r] = st.cells;
+    if (J->min_margin) J->min_margin[r] = st.min_margin;
   }
   return NULL;
 }
@@ -347,7 +349,8 @@ int oracle_align_batch(int32_t n_reads, const float *events, int64_t event_strid
                        const float *c, const float *h, int64_t n_model,
                        int32_t W, uint32_t flags, int32_t n_threads,
                        const uint64_t *pair_slot, int32_t *pairs,
-                       int64_t *path_len, float *score, int32_t *status, int64_t *cells) {
+                       int64_t *path_len, float *score, int32_t *status, int64_t *cells,
+                       double *min_margin) {
   if (n_reads < 0 || n_threads < 1 || W < 2) return ORACLE_E_INVAL;
   int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_reads + 1));
   uint64_t *len = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n_reads + 1));
@@ -364,7 +367,7 @@ int oracle_align_batch(int32_t n_reads, const float *events, int64_t event_strid
   qsort(order, (size_t)n_reads, sizeof(int32_t), cmp_len_desc);
   batch_job_t J = {n_reads, events, event_stride, event_offset, kmer_offset, rank,
                    scale, shift, level_mean, level_stdv, c, h, n_model, W, flags,
-                   pair_slot, pairs, path_len, score, status, cells, order, 0, 0};
+                   pair_slot, pairs, path_len, score, status, cells, min_margin, order, 0, 0};
   int32_t started = 0;
   for (int32_t t = 0; t < n_threads; ++t) {
     if (pthread_create(&th[t], NULL, batch_worker, &J) != 0) break;

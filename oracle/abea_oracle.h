@@ -97,7 +97,8 @@ void oracle_band_limits(int64_t E, int64_t K, int64_t n_e, int64_t n_k, int32_t 
  * Align a whole batch with `n_threads` POSIX threads, one read per task,
  * longest first (the CPU baseline).  Pairs of read r go to
  * pairs[2*pair_slot[r] ...]; pair_slot must give each read room for
- * n_e+n_k pairs.  Per-read outputs are indexed by read.
+ * n_e+n_k pairs.  Per-read outputs are indexed by read; min_margin (may be
+ * NULL) receives each read's oracle_stats_t.min_margin.
  */
 int oracle_align_batch(int32_t n_reads, const float *events, int64_t event_stride,
                        const uint64_t *event_offset, const uint32_t *rank,
@@ -106,7 +107,8 @@ int oracle_align_batch(int32_t n_reads, const float *events, int64_t event_strid
                        const float *c, const float *h, int64_t n_model,
                        int32_t W, uint32_t flags, int32_t n_threads,
                        const uint64_t *pair_slot, int32_t *pairs,
-                       int64_t *path_len, float *score, int32_t *status, int64_t *cells);
+                       int64_t *path_len, float *score, int32_t *status, int64_t *cells,
+                       double *min_margin);
 
 #ifdef __cplusplus
 }

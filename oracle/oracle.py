@@ -75,7 +75,7 @@ def lib():
                                    P, P, P, P, P]
         L.oracle_align.restype = ctypes.c_int
         L.oracle_align_batch.argtypes = [i32, P, i64, P, P, P, P, P, P, P, P, P, i64, i32, u32, i32,
-                                         P, P, P, P, P, P]
+                                         P, P, P, P, P, P, P]
         L.oracle_align_batch.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -182,6 +182,7 @@ class BatchResult:
     cells: np.ndarray
     pair_slot: np.ndarray
     pairs: np.ndarray  # int32 [capacity, 2]
+    min_margin: np.ndarray  # float64 [n]: smallest band-move or path-cell decision margin
 
     def read_pairs(self, r: int) -> np.ndarray:
         s = int(self.pair_slot[r])
@@ -201,6 +202,7 @@ def align_batch(batch, model: Model, W: int, n_threads: int = 1, flags: int = 0)
     score = np.zeros(n, np.float32)
     status = np.zeros(n, np.int32)
     cells = np.zeros(n, np.int64)
+    margin = np.zeros(n, np.float64)
     eo = np.ascontiguousarray(batch.event_offset, np.uint64)
     ko = np.ascontiguousarray(batch.kmer_offset, np.uint64)
     rk = np.ascontiguousarray(batch.ranks, np.uint32)
@@ -210,7 +212,8 @@ def align_batch(batch, model: Model, W: int, n_threads: int = 1, flags: int = 0)
         n, _p(ev), 3, _p(eo), _p(rk), _p(ko), _p(sc), _p(sh),
         _p(model.level_mean), _p(model.level_stdv), _p(model.c), _p(model.h), model.n,
         W, flags, n_threads, _p(slot), _p(pairs), _p(path_len), _p(score), _p(status), _p(cells),
+        _p(margin),
     )
     if err < 0:
         raise RuntimeError(f"oracle_align_batch error {err}")
-    return BatchResult(status, score, path_len, cells, slot[:-1], pairs)
+    return BatchResult(status, score, path_len, cells, slot[:-1], pairs, margin)

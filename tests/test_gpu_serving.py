@@ -29,10 +29,23 @@ def reads(m6):
 
 
 @pytest.fixture(scope="module")
-def alone(m6, reads):
+def alone(m6, reads, oracle_mod):
+    """Each read aligned alone by the library, and those results checked
+    against the oracle (acceptance rule), so that the mix is compared with
+    oracle-checked results."""
+    import parity_util
+
     al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100)
     out = [al.align(reads.subset([i])) for i in range(reads.n_reads)]
     al.close()
+    om = oracle_mod.Model(m6.level_mean, m6.level_stdv)
+    ores = oracle_mod.align_batch(reads, om, 100, n_threads=16)
+    po = np.zeros(reads.n_reads + 1, np.uint64)
+    po[1:] = np.cumsum([len(a.pairs) for a in out])
+    got = parity_util.result_digests(np.concatenate([a.pairs for a in out]), po,
+                                     np.array([a.status[0] for a in out]), np.array([a.cells[0] for a in out]),
+                                     np.array([a.log_likelihood[0] for a in out], np.float32))
+    parity_util.check_acceptance("serving-lognormal8kb alone", got, parity_util.oracle_result_digests(ores), say)
     return out
 
 
