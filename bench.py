@@ -8,21 +8,28 @@ already resident in HBM:
   * backtrack;
   * pair compaction.
 
-The default workload is the 4000-read log-normal batch (median 5 kb, clipped
-200 b..100 kb, W = 100, k = 6), aligned with one kernel launch per batch.
-`--inflight P` keeps P batches in flight on P streams. The default is 16, on
-16 hardware queues: a batch lasts as long as its longest read, and 16
-batches in flight overlap those tails. Each launch runs a pool of 320 fused
-wavefronts that take the batch's reads from a device work queue. The 16
-pools together ask for the chip's 5120 resident wave slots (5 per SIMD at
-the kernel's register use, 1024 SIMDs), no more.
+The default workload is the largest single-GPU job, uneven-20000-w100:
+20000 reads, 70% 500 b..5 kb and 30% 20..200 kb (W = 100, k = 6), run as a
+captured graph of the persistent kernel (device work queue, admission by
+traceback bytes) in the launch form the autotuner chose for it.  Beside it,
+in the same line:
+  * the plain per-batch kernel on the same reads (5 batches of 4000, one
+    launch each, one wavefront per read);
+  * a short serving level (reads of the 512-channel sequencer replayed 1000x
+    faster than real time) with p50/p99 latency;
+  * abea_align_batch on host buffers (the first 4000 reads of the job);
+  * the oracle on the host's cores.
 
 Other workloads (``--workload``):
-  uneven-20000-w100/w200: 20000 reads, 70% 500 b..5 kb and 30% 20..200 kb.
-      Run as captured graphs of the persistent kernel (device work queue,
-      admission by traceback bytes), with the launch form autotuned
-      (``--tune``).  The plain per-batch kernel runs beside it on the same
-      reads (5 batches of 4000, one launch each).
+  uneven-20000-w200: the same reads at W = 200 (``--tune`` autotunes the
+      launch form of either width).
+  plain-4000-lognormal5kb: 4000 log-normal reads (median 5 kb, clipped
+      200 b..100 kb, W = 100), one kernel launch per batch.  `--inflight P`
+      keeps P batches in flight on P streams (default 16, on 16 hardware
+      queues): a batch lasts as long as its longest read, and the batches in
+      flight overlap those tails.  Each launch runs a pool of 320 fused
+      wavefronts that take the batch's reads from a device work queue; the
+      16 pools together ask for the chip's 5120 resident wave slots.
   ultralong-200-*: 200 reads of 200 kb..1 Mb (W = 100 or 250, k = 6 or 9).
       The persistent kernel under a trace budget, and the backtrack's
       throughput.
@@ -60,19 +67,30 @@ METRIC = "ABEA GCUPS + reads/s on 1 MI355X; p50/p99 per-read latency in serving 
 # mul, mul, sub), three moves 5 adds, arg-max 2 compare/selects.
 OPS_PER_CELL = 11
 # Plain (non-packed, non-fused) FP32 VALU peak of MI355X: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz.
+# 16 lanes x 2.4 GHz.  The cell's arithmetic cannot use FMA (its rounding
+# order is fixed) nor packed FP32, so this is its issue ceiling.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak (counts an FMA as two flops and packed
+# FP32 as two lanes).
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
     "plain-4000-lognormal5kb": dict(kind="plain", source="plain-4000-lognormal5kb", W=100, k=6),
     "plain-64x1kb": dict(kind="plain", source="plain-64x1kb", W=100, k=6),
     # the same 4000 reads with the events scaled to the model instead
     "plain-4000-lognormal5kb-scale-events": dict(kind="plain", source="plain-4000-lognormal5kb", W=100, k=6, scale_events=True),
-    "uneven-20000-w100": dict(kind="persistent", source="uneven-20000", W=100, k=6, plain_batches=5),
-    "uneven-20000-w200": dict(kind="persistent", source="uneven-20000", W=200, k=6, plain_batches=5),
-    "ultralong-200-w100": dict(kind="persistent", source="ultralong-200", W=100, k=6, plain_batches=1),
-    "ultralong-200-w250": dict(kind="persistent", source="ultralong-200", W=250, k=6, plain_batches=1),
-    "ultralong-200-w250-k9": dict(kind="persistent", source="ultralong-200", W=250, k=9, plain_batches=1),
+    # launch: the autotuner's choice (cells per lane, reads per workgroup,
+    # pool wavefronts per SIMD, batches per job)
+    "uneven-20000-w100": dict(kind="persistent", source="uneven-20000", W=100, k=6, plain_batches=5,
+                              launch=(2, 4, 4, 1), extras=True),
+    "uneven-20000-w200": dict(kind="persistent", source="uneven-20000", W=200, k=6, plain_batches=5,
+                              launch=(4, 4, 3, 1)),
+    "ultralong-200-w100": dict(kind="persistent", source="ultralong-200", W=100, k=6, plain_batches=1,
+                               launch=(2, 1, 4, 1)),
+    "ultralong-200-w250": dict(kind="persistent", source="ultralong-200", W=250, k=6, plain_batches=1,
+                               launch=(4, 1, 4, 1)),
+    "ultralong-200-w250-k9": dict(kind="persistent", source="ultralong-200", W=250, k=9, plain_batches=1,
+                                  launch=(4, 1, 4, 1)),
     "serving-512ch": dict(kind="serving", source="serving-lognormal8kb", W=100, k=6),
 }
 
@@ -193,9 +211,13 @@ def sample_reads(batch, W, target_cells: float):
     return list(range(0, n, stride))
 
 
-def roofline(cells, kernel_ms, kernel_name, workload=None):
+def roofline(cells, kernel_ms, kernel_name, workload=None, job_gcups=None):
+    """The kernel's algorithmic FP32 work (11 ops per cell) over its average
+    launch duration, against the FP32 issue ceiling of non-fused, non-packed
+    lane operations (``peak``) and against the published FP32 vector peak;
+    with ``job_gcups``, the same over the whole job's wall time."""
     achieved = cells * OPS_PER_CELL / (kernel_ms / 1e3) / 1e12
-    return {
+    out = {
         "bound": "alu",
         "kernel": kernel_name,
         "achieved": round(achieved, 3),
@@ -203,7 +225,14 @@ def roofline(cells, kernel_ms, kernel_name, workload=None):
         "unit": "TFLOP/s",
         "frac": round(achieved / VALU_PEAK_TOPS, 4),
         "traffic": ALIGN_TRAFFIC_BYTES.get(workload) if kernel_name == "k_align" else None,
+        "fp32_vector_peak": FP32_VECTOR_PEAK_TFLOPS,
+        "frac_of_fp32_vector_peak": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
     }
+    if job_gcups is not None:
+        job = job_gcups * OPS_PER_CELL / 1e3
+        out.update({"achieved_job": round(job, 3), "frac_job": round(job / VALU_PEAK_TOPS, 4),
+                    "frac_job_of_fp32_vector_peak": round(job / FP32_VECTOR_PEAK_TFLOPS, 4)})
+    return out
 
 
 def base_line(args, value, ms_step, workload, cfg_extra):
@@ -280,8 +309,11 @@ def bench_plain(args, wl):
                 if kt is not None:
                     kt += ms
 
-    log(f"bench: warmup {args.warmup}")
-    run(args.warmup)
+    # every context makes its first call (buffer allocation, staging) before
+    # the timed region, whatever --warmup says
+    warm = max(args.warmup, P)
+    log(f"bench: warmup {warm} batches ({P} contexts)")
+    run(warm)
     torch.cuda.synchronize()
     dr0 = slots[0][1]
     cells_per_step = int(dr0.cells[:n].sum().item())
@@ -313,6 +345,7 @@ def bench_plain(args, wl):
         "parallelism": "one wavefront per read",
         "launch": "fused band+backtrack, one launch per batch" if fused else "band and backtrack kernels",
         "batches_in_flight": P,
+        "warmup_batches": warm,
         "band_clear": {1: "window", 2: "edges"}.get(plan.get("band_clear"), "?"),
         "per_read_scaling": "events to the model" if wl.get("scale_events") else "model to the events",
     })
@@ -328,10 +361,8 @@ def bench_plain(args, wl):
         },
         "reads_ok": int((status == 0).sum()),
         **({"host_api": host} if host else {}),
-        "roofline": {**roofline(cells_per_step, float(kms[1]), kname, args.workload),
-                     # the same work over the whole job's time (launches overlap)
-                     "achieved_job": round(gcups * OPS_PER_CELL / 1e3, 3),
-                     "frac_job": round(gcups * OPS_PER_CELL / 1e3 / VALU_PEAK_TOPS, 4)},
+        # per launch (launches overlap), and over the whole job's time
+        "roofline": roofline(cells_per_step, float(kms[1]), kname, args.workload, job_gcups=gcups),
     })
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
@@ -371,8 +402,11 @@ def bench_persistent(args, wl):
         tune_report = {"best": launch.as_dict(), "candidates": [
             {**r["launch"], "ms": round(r["ms"], 2), "workers": r["workers"]} for r in tuned["table"]]}
     else:
-        launch = autotune.Launch(cells_per_lane=args.cpl, waves_per_group=args.wpg,
-                                 waves_per_simd=args.wps, batches=args.nb)
+        dc, dw, dp, db_ = wl["launch"]
+        launch = autotune.Launch(cells_per_lane=args.cpl if args.cpl >= 0 else dc,
+                                 waves_per_group=args.wpg if args.wpg > 0 else dw,
+                                 waves_per_simd=args.wps if args.wps > 0 else dp,
+                                 batches=args.nb if args.nb > 0 else db_)
         tune_report = None
 
     # persistent form: the job as nb captured graphs
@@ -457,8 +491,21 @@ def bench_persistent(args, wl):
         },
         "kernel_ms_batch0": {"prep": round(float(kms0[0]), 4), "align": round(float(kms0[1]), 4),
                              "compact": round(float(kms0[3]), 4)},
-        "roofline": roofline(cells0, float(kms0[1]), "k_align"),
+        # per launch: batch 0 run eagerly in the same form; job: the timed passes
+        "roofline": roofline(cells0, float(kms0[1]), "k_align", args.workload,
+                             job_gcups=gcups if launch.batches == 1 else None),
     })
+    if wl.get("extras") and not args.no_extras:
+        log("bench: host-buffer API on the first 4000 reads")
+        sub = batch.subset(range(min(4000, n)))
+        alh = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
+        sub_cells = int(alh.align(sub).cells.sum())
+        out["host_api"] = {**host_api_rate(alh, sub, sub_cells),
+                           "reads": sub.n_reads, "what": "abea_align_batch on the first 4000 reads of the job: "
+                           "host buffers through the pinned staging ring, PCIe both ways, one batch at a time"}
+        alh.close()
+        del sub
+        out["serving"] = serving_level(args, dev)
     if tune_report:
         out["autotune"] = tune_report
     if args.backtrack_probe:
@@ -497,6 +544,49 @@ def backtrack_probe(model, k, W, job, dev, st):
 
 
 # ------------------------------------------------------------------ serving
+
+
+def serving_level(args, dev):
+    """One load level of the serving loop (reads of the 512-channel
+    sequencer, replayed `compression` times faster than real time), beside
+    the plain batched kernel on the same reads."""
+    import torch
+
+    from paper_2101_05012_amd import abea, serving, synth
+
+    comp, n = (int(x) for x in args.serving_level.split(":"))
+    W, k = 100, 6
+    model = synth.pore_model(k)
+    batch = synth.workload_batch_parallel("serving-lognormal8kb", k=k, read_ids=range(n))
+    arr = synth.serving_arrivals(duration_s=60.0)
+    while arr.shape[0] < n:
+        arr = synth.serving_arrivals(duration_s=2 * arr[-1])
+    arr = arr[:n]
+    al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
+    srv = abea.Server(al, slots=args.slots, max_batch_reads=args.batch_reads, trace_budget_bytes=32_000_000_000,
+                      host_staging_bytes=int(args.host_staging_gb * (1 << 30)))
+    log(f"bench: serving x{comp} {n} reads")
+    res = serving.run(srv, batch, arr, compression=float(comp), submitters=args.submitters)
+    srv.close()
+    s = serving.summarize(res, batch, float(comp), arr)
+    db = abea.to_device(batch, dev)
+    dr = abea.DeviceResult.empty(db, dev)
+    st = torch.cuda.Stream(dev)
+    al.align_device(db, dr, st)
+    st.synchronize()
+    cells = int(dr.cells[:n].sum().item())
+    t0 = time.perf_counter()
+    for _ in range(3):
+        al.align_device(db, dr, st)
+    st.synchronize()
+    plain_s = (time.perf_counter() - t0) / 3
+    al.close()
+    keep = ("compression", "reads", "offered_reads_per_s", "reads_per_s", "gcups", "latency_ms",
+            "admission_wait_ms", "micro_batches", "span_s", "reads_ok")
+    return {"workload": "serving-512ch", "slots": args.slots, "max_batch_reads": args.batch_reads,
+            **{key: s[key] for key in keep},
+            "plain_batched_same_reads": {"s": round(plain_s, 4), "gcups": round(cells / plain_s / 1e9, 3),
+                                         "reads_per_s": round(n / plain_s, 1)}}
 
 
 def bench_serving(args, wl):
@@ -595,10 +685,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 200 batches for the plain workloads, 3 passes for the persistent ones)")
+                    help="timed steps (default: 200 batches for the plain workloads, 10 passes for the persistent ones)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps first (default: 16 batches for the plain workloads, 1 pass for the persistent ones)")
-    ap.add_argument("--workload", default="plain-4000-lognormal5kb", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="uneven-20000-w100", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-reads", type=int, default=1000)
     ap.add_argument("--cpu-sample-gcells", type=float, default=20.0,
@@ -619,17 +709,25 @@ def main():
         "a device work queue (still one launch per batch); the default 320 x 16 batches in flight fills "
         "the 5120 resident wave slots",
     )
-    ap.add_argument("--wpg", type=int, default=1, help="wavefronts (reads) per workgroup of the fused kernel")
+    ap.add_argument("--wpg", type=int, default=0,
+                    help="wavefronts (reads) per workgroup of the fused kernel (default: 1 for the plain "
+                         "workloads, the tuned form for the persistent ones)")
     ap.add_argument("--band-clear", type=int, default=-1, choices=(-1, 0, 1, 2),
                     help="plain workloads: slot clearing of interior bands, 0 the library's choice, 1 window, "
                          "2 edges; -1 (default) edges when the batches in flight hold two wavefronts per SIMD, "
                          "else the library's choice")
     ap.add_argument("--tune", action="store_true", help="persistent workloads: autotune the launch form")
-    ap.add_argument("--cpl", type=int, default=0, help="persistent: cells per lane (0 = smallest)")
-    ap.add_argument("--wps", type=int, default=4, help="persistent: pool wavefronts per SIMD")
-    ap.add_argument("--nb", type=int, default=1, help="persistent: batches (graphs) per job")
+    ap.add_argument("--cpl", type=int, default=-1,
+                    help="persistent: cells per lane (0 = smallest; default: the workload's tuned form)")
+    ap.add_argument("--wps", type=int, default=0, help="persistent: pool wavefronts per SIMD (default: tuned)")
+    ap.add_argument("--nb", type=int, default=0, help="persistent: batches (graphs) per job (default: tuned)")
     ap.add_argument("--trace-budget-gb", type=float, default=0.0,
-                    help="persistent: traceback memory budget per batch (0 = unbounded)")
+                    help="persistent: traceback memory budget per batch (0 = the library's default, 0.9 of "
+                         "the device memory free when the context is created)")
+    ap.add_argument("--serving-level", default="1000:5000",
+                    help="default workload: the serving load level in the line, compression:reads")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: leave out the serving level and the host-buffer rate")
     ap.add_argument("--max-reads", type=int, default=0,
                     help="persistent: only the first N reads of the workload (quick runs; 0 = all)")
     ap.add_argument("--slots", type=int, default=16, help="serving: micro-batches on the device at once")
@@ -638,8 +736,8 @@ def main():
     ap.add_argument("--host-staging-gb", type=float, default=6.0,
                     help="serving: pinned host arena for queued reads (GiB)")
     ap.add_argument("--hw-queues", type=int, default=16,
-                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32) for the plain and "
-                    "serving workloads, so that batches or micro-batches on different streams run side by side")
+                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32), so that batches or "
+                    "serving micro-batches on different streams run side by side")
     ap.add_argument("--levels", default="", help="serving: compression:reads,... (default: the full sweep)")
     ap.add_argument("--host-api", action="store_true",
                     help="plain: also time abea_align_batch on host buffers (PCIe both ways), after the timed region")
@@ -658,10 +756,12 @@ def main():
     # plain: enough batches that the drain of the last ones in flight is a
     # small part of the timed region; persistent: whole passes of the job
     if args.steps is None:
-        args.steps = 200 if wl["kind"] == "plain" else 3
+        args.steps = 200 if wl["kind"] == "plain" else 10
     if args.warmup is None:
         args.warmup = 16 if wl["kind"] == "plain" else 1
-    if wl["kind"] in ("serving", "plain") and 0 < args.hw_queues <= 32:
+    if args.wpg <= 0 and wl["kind"] != "persistent":
+        args.wpg = 1
+    if 0 < args.hw_queues <= 32:
         # read by the HIP runtime when it starts, i.e. before torch touches the GPU
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.copy_calibration_mb > 0:
