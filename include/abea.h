@@ -182,6 +182,39 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *batch,
                             const abea_result_t *res, void *stream);
 
 /*
+ * No-allocation variant of abea_align_batch_device, for callers that cannot
+ * allocate memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  Same arguments, semantics (device
+ * inputs and outputs, host offsets, asynchronous on `stream`) and results,
+ * bit for bit, but the call allocates nothing:
+ *   - every device buffer beyond the caller's inputs and outputs (plan,
+ *     k-mer parameters, event means, trace tiles, pair scratch, per-read
+ *     lengths) lies in one fixed array of ABEA_NOALLOC_SCRATCH_BYTES that the
+ *     library holds on each device it runs on until the process ends;
+ *   - the plan is staged through pinned host memory that abea_create set
+ *     aside for ABEA_NOALLOC_MAX_READS reads.
+ * It always runs the fused kernel (band fill and backtrack by one wavefront
+ * per read) with the context's worker count (0: one per read), capped by how
+ * many of the longest reads' traces fit in what the other buffers leave of
+ * the array (admission by traceback bytes).
+ * Limits: n_reads <= ABEA_NOALLOC_MAX_READS, and 4 B per event, 16 B per
+ * k-mer, 8 B per path slot (sum of n_e + n_k - 1), 96 B per read and the
+ * trace of at least the longest read (ceil((n_e + n_k - 1) / (32 /
+ * cells_per_lane)) * 512 B) must fit in ABEA_NOALLOC_SCRATCH_BYTES; a batch
+ * beyond them fails with ABEA_E_NOMEM and nothing is enqueued.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the kernels write whatever they read of it first, so
+ * nothing needs clearing): calls that overlap on one device race, whichever
+ * contexts make them; order them on one stream.  abea_get_timings and
+ * abea_get_plan_info do not report these calls.
+ * Errors: as abea_align_batch_device, plus ABEA_E_NOMEM beyond the limits.
+ */
+#define ABEA_NOALLOC_SCRATCH_BYTES (256ull << 20)
+#define ABEA_NOALLOC_MAX_READS 16384
+int abea_align_batch_device_noalloc(abea_ctx *ctx, const abea_batch_t *batch, const abea_result_t *res,
+                                    void *stream);
+
+/*
  * Device time in milliseconds of each stage of the last direct call
  * (abea_align_batch or abea_align_batch_device), when the context was
  * created with ABEA_F_TIMING: out[0] k-mer parameter preparation, out[1] band

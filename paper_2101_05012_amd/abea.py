@@ -37,11 +37,14 @@ ABEA_CLEAR_EDGES = 2  # interior bands: only the two slots beside the band
 ABEA_ARENA_AUTO = 0  # arena_bytes: 0.9 of the device memory free at abea_create
 ABEA_ARENA_UNBOUNDED = (1 << 64) - 1  # arena_bytes: no trace budget
 ABEA_HOST_STAGING_CHUNK = 32 << 20
+ABEA_NOALLOC_SCRATCH_BYTES = 256 << 20  # the fixed device scratch of abea_align_batch_device_noalloc
+ABEA_NOALLOC_MAX_READS = 16384
 
 EXPORTED = (
     "abea_create",
     "abea_align_batch",
     "abea_align_batch_device",
+    "abea_align_batch_device_noalloc",
     "abea_get_timings",
     "abea_set_launch",
     "abea_cells_per_lane",
@@ -229,6 +232,9 @@ def lib() -> ctypes.CDLL:
         L.abea_align_batch.restype = ctypes.c_int
         L.abea_align_batch_device.argtypes = [P, ctypes.POINTER(abea_batch_t), ctypes.POINTER(abea_result_t), P]
         L.abea_align_batch_device.restype = ctypes.c_int
+        L.abea_align_batch_device_noalloc.argtypes = [P, ctypes.POINTER(abea_batch_t), ctypes.POINTER(abea_result_t),
+                                                      P]
+        L.abea_align_batch_device_noalloc.restype = ctypes.c_int
         L.abea_get_timings.argtypes = [P, P, ctypes.c_int]
         L.abea_get_timings.restype = ctypes.c_int
         L.abea_set_launch.argtypes = [P, ctypes.POINTER(abea_launch_t)]
@@ -391,6 +397,16 @@ class Aligner:
             lib().abea_align_batch_device(self.handle, ctypes.byref(b), ctypes.byref(r),
                                           ctypes.c_void_p(_stream_ptr(stream, self.device))),
             "abea_align_batch_device",
+        )
+
+    def align_device_noalloc(self, dbatch: "DeviceBatch", dres: "DeviceResult", stream=None) -> None:
+        """The same through abea_align_batch_device_noalloc: no allocation,
+        intermediate buffers in the library's fixed per-device scratch."""
+        b, r = _dev_structs(dbatch, dres)
+        self._check(
+            lib().abea_align_batch_device_noalloc(self.handle, ctypes.byref(b), ctypes.byref(r),
+                                                  ctypes.c_void_p(_stream_ptr(stream, self.device))),
+            "abea_align_batch_device_noalloc",
         )
 
     def timings(self) -> np.ndarray:

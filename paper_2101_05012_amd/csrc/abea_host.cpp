@@ -28,6 +28,8 @@
 
 using namespace abea;
 
+static_assert(NOALLOC_SCRATCH_BYTES == ABEA_NOALLOC_SCRATCH_BYTES, "one size of the fixed scratch");
+
 struct abea_graph {
   abea_ctx *ctx = nullptr;
   abea_rt::Work work;
@@ -97,6 +99,10 @@ int ensure(abea_ctx *ctx, Work *w, DevBuf &b, size_t bytes, hipStream_t st) {
 }
 
 void free_buf(DevBuf &b, hipStream_t st) {
+  if (b.borrowed) {
+    b = DevBuf();
+    return;
+  }
   if (b.p) {
     if (b.pooled)
       (void)hipFreeAsync(b.p, st);
@@ -202,12 +208,15 @@ bool edge_clearing(const abea_ctx *ctx, int waves) {
  *    part after the other.
  * Only a read whose own trace exceeds the budget is refused (ABEA_E_NOMEM). */
 int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t *ko,
-               uint64_t pair_capacity) {
+               uint64_t pair_capacity, bool fused_only, uint64_t budget_in) {
   Plan &P = w.plan;
   if (eo[0] != 0 || ko[0] != 0) return fail(ctx, ABEA_E_INVAL, "offsets must start at 0");
   P.n = n;
+  /* no allocation when the vectors already have the capacity (the
+   * no-allocation entry point reserves it at creation) */
   w.order.resize(n);
-  std::vector<uint64_t> comp(n);
+  w.comp.resize(n);
+  std::vector<uint64_t> &comp = w.comp;
   uint64_t need = 0;
   for (int r = 0; r < n; ++r) {
     if (eo[r + 1] < eo[r] || ko[r + 1] < ko[r])
@@ -222,14 +231,16 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
   if (pair_capacity < need)
     return fail(ctx, ABEA_E_CAPACITY, "pair_capacity %llu < %llu", (unsigned long long)pair_capacity,
                 (unsigned long long)need);
+  /* longest first, ties in read order (an in-place sort: no buffer) */
   std::iota(w.order.begin(), w.order.end(), 0);
-  std::stable_sort(w.order.begin(), w.order.end(), [&](int a, int b) { return comp[a] > comp[b]; });
+  std::sort(w.order.begin(), w.order.end(),
+            [&](int a, int b) { return comp[a] != comp[b] ? comp[a] > comp[b] : a < b; });
 
   /* trace words of planned read s, and the worker count */
   const int G = bands_per_group(ctx->cpl);
   auto words = [&](int s) -> uint64_t { return ((comp[w.order[s]] + G - 1) / G) * 64u; };
-  const uint64_t budget = ctx->trace_budget;
-  const bool split = split_kernels(ctx);
+  const uint64_t budget = budget_in == UINT64_MAX ? ctx->trace_budget : budget_in;
+  const bool split = split_kernels(ctx) && !fused_only;
   if (n > 0 && budget > 0 && words(0) * sizeof(uint2) > budget)
     return fail(ctx, ABEA_E_NOMEM, "the trace of the longest read (%llu bytes) exceeds the trace budget %llu",
                 (unsigned long long)(words(0) * sizeof(uint2)), (unsigned long long)budget);
@@ -593,6 +604,20 @@ int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **
     e = hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "stream: %s", hipGetErrorString(e)); break; }
     if ((rc = work_init(ctx, ctx->main))) break;
+    /* the no-allocation entry point: the device's fixed scratch (its
+     * address taken once per device, with the device current), and host
+     * buffers for a plan of up to ABEA_NOALLOC_MAX_READS reads */
+    e = noalloc_scratch(cfg->device, &ctx->noalloc_scratch);
+    if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "scratch address: %s", hipGetErrorString(e)); break; }
+    if ((rc = work_init(ctx, ctx->noalloc))) break;
+    ctx->noalloc.order.reserve(ABEA_NOALLOC_MAX_READS);
+    ctx->noalloc.comp.reserve(ABEA_NOALLOC_MAX_READS);
+    ctx->noalloc.plan.parts.reserve(ABEA_NOALLOC_MAX_READS + 2);
+    e = hipHostMalloc((void **)&ctx->noalloc.h_reads, sizeof(ReadDesc) * ABEA_NOALLOC_MAX_READS,
+                      hipHostMallocDefault);
+    if (e != hipSuccess) { rc = fail(ctx, ABEA_E_NOMEM, "pinned plan staging: %s", hipGetErrorString(e)); break; }
+    ctx->noalloc.h_cap = ABEA_NOALLOC_MAX_READS;
+    ctx->err.reserve(512); /* error messages never reallocate */
   } while (0);
   if (rc != ABEA_OK) {
     abea_destroy(ctx);
@@ -609,8 +634,10 @@ void abea_destroy(abea_ctx *ctx) {
    * API's copies on its stream), then release in order on its stream */
   (void)work_wait(ctx, ctx->main);
   hipStream_t st = ctx->own_stream;
+  (void)work_wait(ctx, ctx->noalloc);
   if (st) (void)hipStreamSynchronize(st);
   work_free(ctx->main, st);
+  work_free(ctx->noalloc, st);
   DevBuf *bufs[] = {&ctx->model, &ctx->events, &ctx->ranks, &ctx->scale, &ctx->shift,
                     &ctx->pairs, &ctx->pair_offset, &ctx->ll, &ctx->status, &ctx->cells};
   for (DevBuf *b : bufs) free_buf(*b, st);
@@ -693,6 +720,75 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   io.status = r->status;
   io.cells = r->cells;
   return run_planned(ctx, ctx->main, io, st);
+}
+
+int abea_align_batch_device_noalloc(abea_ctx *ctx, const abea_batch_t *b, const abea_result_t *r,
+                                    void *stream) {
+  int rc = check_batch(ctx, b, r);
+  if (rc) return rc;
+  if (b->n_reads > 0 && (!r->pairs && r->pair_capacity > 0)) return fail(ctx, ABEA_E_INVAL, "null pairs");
+  if (b->n_reads > ABEA_NOALLOC_MAX_READS)
+    return fail(ctx, ABEA_E_NOMEM, "%d reads: the no-allocation call takes at most %d", b->n_reads,
+                ABEA_NOALLOC_MAX_READS);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int n = b->n_reads;
+  const uint64_t *eo = b->event_offset, *ko = b->kmer_offset;
+  if (eo[0] != 0 || ko[0] != 0) return fail(ctx, ABEA_E_INVAL, "offsets must start at 0");
+  /* the buffers other than the trace, laid out in the scratch array */
+  uint64_t slots = 0;
+  for (int i = 0; i < n; ++i) {
+    if (eo[i + 1] < eo[i] || ko[i + 1] < ko[i]) return fail(ctx, ABEA_E_INVAL, "offsets decrease at read %d", i);
+    const uint64_t ne = eo[i + 1] - eo[i], nk = ko[i + 1] - ko[i];
+    if (ne > 0 && nk > 0) slots += ne + nk - 1;
+  }
+  const uint64_t nr = (uint64_t)std::max(n, 1);
+  auto up = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  Work &w = ctx->noalloc;
+  DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.path_len, &w.path_src, &w.xmean, &w.kparam, &w.scratch};
+  const uint64_t bytes[] = {sizeof(ReadDesc) * nr, sizeof(int32_t) * nr, sizeof(uint32_t), sizeof(uint64_t) * nr,
+                            sizeof(uint64_t) * nr, sizeof(float) * eo[n], sizeof(KParam) * ko[n],
+                            sizeof(int2) * slots};
+  uint64_t fixed = 0;
+  for (uint64_t x : bytes) fixed += up(x);
+  if (fixed >= ABEA_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, ABEA_E_NOMEM,
+                "the batch needs %llu bytes of scratch before its trace; the fixed array holds %llu",
+                (unsigned long long)fixed, (unsigned long long)ABEA_NOALLOC_SCRATCH_BYTES);
+  /* the rest holds the trace: the fused kernel admits as many reads at once
+   * as their traces fit in it */
+  const uint64_t budget = ABEA_NOALLOC_SCRATCH_BYTES - fixed;
+  if ((rc = plan_batch(ctx, w, n, eo, ko, r->pair_capacity, true, budget))) return rc;
+  if (n == 0) {
+    HIP_TRY(ctx, launch_scan(nullptr, 0, r->pair_offset, st));
+    return ABEA_OK;
+  }
+  unsigned char *base = (unsigned char *)ctx->noalloc_scratch;
+  uint64_t off = 0;
+  for (int i = 0; i < 8; ++i) {
+    bufs[i]->p = base + off;
+    bufs[i]->cap = bytes[i];
+    bufs[i]->borrowed = true;
+    off += up(bytes[i]);
+  }
+  w.trace.p = base + off;
+  w.trace.cap = budget;
+  w.trace.borrowed = true;
+  HIP_TRY(ctx, hipMemcpyAsync(w.reads.p, w.h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipEventRecord(w.staging_done, st));
+  w.staging_pending = true;
+  DevIO io;
+  io.events = (const float *)b->events;
+  io.ranks = b->kmer_rank;
+  io.scale = b->scale;
+  io.shift = b->shift;
+  io.pairs = (int2 *)r->pairs;
+  io.pair_offset = r->pair_offset;
+  io.ll = r->log_likelihood;
+  io.status = r->status;
+  io.cells = r->cells;
+  if ((rc = enqueue_kernels(ctx, w, io, st, false))) return rc;
+  return work_mark(ctx, w, st);
 }
 
 int abea_align_batch(abea_ctx *ctx, const abea_batch_t *b, abea_result_t *r) {

@@ -119,6 +119,13 @@ hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, bool edge
 /* resident workgroups of the fused kernel per CU (occupancy) */
 int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge);
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st);
+
+/* Fixed scratch of the no-allocation entry point (abea_kernels.hip). */
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+/* The device address of `device`'s scratch array (hipGetSymbolAddress on
+ * the first call for that device, which must be the current device). */
+hipError_t noalloc_scratch(int device, void **ptr);
 hipError_t launch_compact(const int2 *scratch, const uint64_t *path_src, const uint64_t *offset,
                           int n, int2 *pairs, hipStream_t st);
 

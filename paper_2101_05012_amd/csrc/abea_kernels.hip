@@ -46,6 +46,7 @@
 
 #include <hip/hip_ext.h>
 
+#include <mutex>
 #include <type_traits>
 
 #pragma clang fp contract(off)
@@ -1054,6 +1055,32 @@ hipError_t launch_compact(const int2 *scratch, const uint64_t *path_src, const u
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_compact, dim3(n), dim3(64), 0, st, scratch, path_src, offset, pairs);
   return hipGetLastError();
+}
+
+/* ------------------------------------------------ fixed device scratch */
+
+/* Scratch of the no-allocation entry point: one array per device, held from
+ * the library's load until the process ends.  Host code must not pass this
+ * name to a kernel or a copy (in host code it is a host-side stand-in, not a
+ * device address); it uses the address noalloc_scratch() returns. */
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+  /* hipGetSymbolAddress once per device, with that device current (the
+   * caller has made it current), kept for the life of the process */
+  static std::mutex mu;
+  static void *addr[NOALLOC_MAX_DEVICES] = {};
+  *ptr = nullptr;
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 }  // namespace abea

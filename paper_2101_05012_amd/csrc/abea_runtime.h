@@ -21,7 +21,8 @@ using namespace abea;
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
-  bool pooled = false; /* from the stream-ordered allocator (hipMallocAsync) */
+  bool pooled = false;   /* from the stream-ordered allocator (hipMallocAsync) */
+  bool borrowed = false; /* a range of memory the buffer does not own (never freed) */
 };
 
 struct Plan {
@@ -48,6 +49,7 @@ struct Plan {
 struct Work {
   Plan plan;
   std::vector<int> order;
+  std::vector<uint64_t> comp; /* per caller read: computed bands (n_e + n_k - 1, 0 if empty) */
   DevBuf reads, rstat, queue, xmean, kparam, trace, scratch, path_len, path_src;
   ReadDesc *h_reads = nullptr; /* pinned staging of the plan */
   size_t h_cap = 0;
@@ -99,6 +101,10 @@ struct abea_ctx {
   abea_rt::DevBuf model;
   hipStream_t own_stream = nullptr;
   abea_rt::Work main;
+  /* the no-allocation entry point: its own plan (host buffers sized at
+   * creation for ABEA_NOALLOC_MAX_READS) and the device's fixed scratch */
+  abea_rt::Work noalloc;
+  void *noalloc_scratch = nullptr;
   /* host-API copies of inputs (the event means only) and outputs */
   abea_rt::DevBuf events, ranks, scale, shift, pairs, pair_offset, ll, status, cells;
   /* host-API pinned staging ring: two chunks, each with the event of the
@@ -137,8 +143,11 @@ int work_wait(abea_ctx *ctx, Work &w);
 void work_free(Work &w, hipStream_t st = nullptr);
 /* Record w.done on `st` after a batch was enqueued there. */
 int work_mark(abea_ctx *ctx, Work &w, hipStream_t st);
-/* Plan a batch from host offsets into w (see the definition). */
-int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t *ko, uint64_t pair_capacity);
+/* Plan a batch from host offsets into w (see the definition).  fused_only:
+ * run the fused kernel even if the context's form is the split kernels;
+ * budget: the trace budget to plan with (UINT64_MAX: the context's). */
+int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t *ko, uint64_t pair_capacity,
+               bool fused_only = false, uint64_t budget = UINT64_MAX);
 /* Device buffers of a planned batch, grown in stream order on `st`. */
 int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st);
 /* Kernels of a planned batch whose plan is on the device. */
