@@ -60,9 +60,22 @@ struct Log2 {
   static constexpr int v = CPL == 1 ? 0 : CPL == 2 ? 1 : CPL == 4 ? 2 : CPL == 8 ? 3 : 4;
 };
 
-/* lane l receives v of lane l-1, lane 0 receives lane 63 (DPP wave_ror:1) */
+/* lane l receives v of lane l-1, lane 0 receives lane 63 (DPP wave_ror:1).
+ * Every lane has a source, so bound_ctrl changes nothing; it is set because
+ * it lets the compiler fold the rotation into the instruction that uses it. */
 __device__ __forceinline__ float rot_up(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x13C, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x13C, 0xF, 0xF, true));
+}
+/* rot_up(l) + a and rot_up(d) + b, the rotations folded into the adds (two
+ * v_add_f32_dpp, where a shared rotation would be a move and two adds).  The
+ * s_nop gives the two wait states a DPP read needs after a VALU write of
+ * its source, which the compiler does not track into inline assembly. */
+__device__ __forceinline__ void add_rot2(float l, float a, float d, float b, float &lo, float &dout) {
+  asm("s_nop 1\n\t"
+      "v_add_f32_dpp %0, %2, %3 wave_ror:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %1, %4, %5 wave_ror:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(lo), "=&v"(dout)
+      : "v"(l), "v"(a), "v"(d), "v"(b));
 }__device__ __forceinline__ float rlane(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -75,10 +88,16 @@ __device__ __forceinline__ float sel(float if_clear, float if_set, uint64_t mask
   asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(mask));
   return r;
 }
-/* per lane: the larger of a and b (one v_max_f32, no canonicalisation) */
-__device__ __forceinline__ float vmax(float a, float b) {
+/* a wave-uniform value held in a VGPR (one v_mov_b32) */
+__device__ __forceinline__ float to_vgpr(float s) {
   float r;
-  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(s));
+  return r;
+}
+/* per lane: the largest of a, b and c (one v_max3_f32, no canonicalisation) */
+__device__ __forceinline__ float vmax3(float a, float b, float c) {
+  float r;
+  asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
   return r;
 }
 /* per lane: acc*2 + (bit of `mask`), one v_addc */
@@ -365,6 +384,10 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   const int W = a.W;
 
   const float lp_skip = rd.lp_skip, lp_stay = rd.lp_stay, lp_step = rd.lp_step;
+  /* vector copies of the skip and step constants: the moves of a register's
+   * first slot add them to a rotated neighbour in one DPP add, whose second
+   * operand must be a vector register */
+  const float lp_skip_v = to_vgpr(lp_skip), lp_step_v = to_vgpr(lp_step);
   const float *__restrict__ xm = a.xmean + rd.ev_off;
   const float4 *__restrict__ kp = reinterpret_cast<const float4 *>(a.kparam + rd.km_off);
   const int H = W / 2;
@@ -469,7 +492,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   };
 
   const int last = n_e + n_k;
-  uint32_t TU = 0, TL = 0;
+  uint32_t TD = 0, TU = 0;
   uint64_t cells = 0;
 
   /* One band i = i0 + b: Spp = band i-2 (overwritten by band i), Sp = band
@@ -515,32 +538,37 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       wlo = klo;
       cells += (uint64_t)wlen;
     }
-    const float lf0 = rot_up(Sp[CPL - 1]);  /* left  (e, k-1): band i-1, slot s-1 */
-    const float dg0 = rot_up(Spp[CPL - 1]); /* diag (e-1, k-1): band i-2, slot s-1 */
+    /* slot s-1 of a register's first slot is the last register of lane l-1:
+     * left (e, k-1) in band i-1 and diag (e-1, k-1) in band i-2, each with
+     * its move's constant added */
+    float lf0, dg0;
+    add_rot2(Sp[CPL - 1], lp_skip_v, Spp[CPL - 1], lp_step_v, lf0, dg0);
     float nv[CPL]; /* band i; band i-2 is still read below */
     float sv[CPL]; /* band i before the window mask */
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
       const float x = X[c];
       const float up = Sp[c]; /* up (e-1, k): band i-1, slot s */
-      const float left = (c == 0) ? lf0 : Sp[c - 1];
-      const float diag = (c == 0) ? dg0 : Spp[c - 1];
+      /* left + lp_skip and diag + lp_step */
+      const float lsk = (c == 0) ? lf0 : Sp[c - 1] + lp_skip;
+      const float dst = (c == 0) ? dg0 : Spp[c - 1] + lp_step;
       /* Alg. 5.3 log-emission and Alg. 5.2 cell score */
       const float d = x - PM[c];
       const float t = d * d;
       const float u = t * PH[c];
       const float em = PC[c] - u;
-      const float sd = (diag + lp_step) + em;
+      const float sd = dst + em;
       const float su = (up + lp_stay) + em;
-      const float sl = left + lp_skip;
+      const float sl = lsk;
       /* first maximum in the order D, U, L.  The value is the plain maximum
-       * (scores are finite or -inf, never NaN or -0, so v_max gives the
-       * bits the selects would); the compares only set the trace bits and
-       * stay off the chain from one band to the next */
-      const uint64_t mu = ballot(su > sd);
-      const float s1 = vmax(sd, su);
-      const uint64_t ml = ballot(sl > s1);
-      sv[c] = vmax(s1, sl);
+       * (scores are finite or -inf, never NaN or -0, so v_max3 gives the
+       * bits of the first-maximum selects).  The trace bits say which
+       * candidates equal it: D won iff sd is the maximum; otherwise U won iff
+       * su is; otherwise L.  The compares stay off the chain from one band
+       * to the next */
+      sv[c] = vmax3(sd, su, sl);
+      const uint64_t md = ballot(sv[c] == sd);
+      const uint64_t mu = ballot(sv[c] == su);
       if constexpr (EDGE) {
         /* only the two slots beside the band are cleared: the next two bands
          * read no other slot outside this band (the others may hold any
@@ -550,10 +578,9 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
         const uint64_t valid = ballot((uint32_t)(kvs[c] - wlo) < (uint32_t)wlen);
         nv[c] = sel(NI, sv[c], valid);
       }
-      /* trace planes: up bit (U beats D), left bit (L beats both); a set
-       * left bit means L whatever the up bit */
+      /* trace planes: the D bit, and the U bit (read only when D is clear) */
+      TD = shift_in(TD, md);
       TU = shift_in(TU, mu);
-      TL = shift_in(TL, ml);
     }
     /* the end cells of this band for the next band's move.  Both lie in the
      * band; inside the table they are never masked, so they are read from
@@ -636,7 +663,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     } else {
       group(std::false_type(), i);
     }
-    trace[g * 64 + lane] = make_uint2(TU, TL);
+    trace[g * 64 + lane] = make_uint2(TD, TU);
     ++g;
     i += G;
   }
@@ -658,7 +685,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     }
     i = last + 1;
     const int sh = (G - gb) * CPL;
-    trace[g * 64 + lane] = make_uint2(TU << sh, TL << sh);
+    trace[g * 64 + lane] = make_uint2(TD << sh, TU << sh);
   }
 
   /* terminal cell (n_e-1, n_k-1) is in the last band if its k-mer is */
@@ -800,7 +827,7 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
     const int lower = gcur << LG;
     int t = e + k;
     int klo = 0x7fffffff; /* first k-mer of the loaded lane (none yet) */
-    uint64_t wxy = 0;     /* the lane's up-bit word (low half) and left-bit word (high half) */
+    uint64_t wxy = 0;     /* the lane's D-bit word (low half) and U-bit word (high half) */
     for (;;) {
       e = __builtin_amdgcn_readfirstlane(e);
       k = __builtin_amdgcn_readfirstlane(k);
@@ -813,12 +840,12 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
         klo = k & ~(CPL - 1);
       }
       const int bit = trace_bit<CPL>(t, k);
-      const uint64_t b2 = wxy >> bit; /* up bit at 0, left bit at 32 */
-      const uint32_t ub = (uint32_t)b2 & 1u;
-      const uint32_t lb = (uint32_t)(b2 >> 32) & 1u;
-      /* diagonal (0,0): e-1, k-1; up (1,0): e-1; left (x,1): k-1 */
-      e -= (int)(lb ^ 1u);
-      k -= (int)((~ub | lb) & 1u);
+      const uint64_t b2 = wxy >> bit; /* D bit at 0, U bit at 32 */
+      const uint32_t db = (uint32_t)b2 & 1u;
+      const uint32_t ub = (uint32_t)(b2 >> 32) & 1u;
+      /* diagonal (1,x): e-1, k-1; up (0,1): e-1; left (0,0): k-1 */
+      e -= (int)(db | ub);
+      k -= (int)((db | ~ub) & 1u);
       t = e + k;
       /* stop when the walk left the group (t falls by 1 or 2 per step, so
        * this also ends a walk that leaves the table; the caller checks that
