@@ -86,6 +86,18 @@ static float band_get(const float *S, int64_t band, int64_t jj, int32_t W) {
   return S[band * W + jj];
 }
 
+/* The trim cell of band i: (i-1, -1), the event i-1 left unaligned after
+ * the trim cell above it (band i-1; the origin for i = 1), if the band
+ * holds k-mer -1 and the event exists. */
+static void trim_cell(float *S, uint8_t *T, const int64_t *E, const int64_t *K, int64_t i, int64_t n_e,
+                      int32_t W, float lp_trim) {
+  const int64_t e = i - 1;
+  const int64_t j = -1 - K[i];
+  if (e < 0 || e > n_e - 1 || j < 0 || j >= W) return;
+  S[i * W + j] = band_get(S, i - 1, -1 - K[i - 1], W) + lp_trim;
+  T[i * W + j] = T_U;
+}
+
 int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
                  const uint32_t *rank, int64_t n_k,
                  const float *level_mean, const float *level_stdv,
@@ -112,6 +124,9 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
   float lp[3];
   oracle_transitions(n_e, n_k, lp);
   const float lp_skip = lp[0], lp_stay = lp[1], lp_step = lp[2];
+  /* trim: one event left unaligned, probability 1/100, in double then float */
+  const int trim = (flags & ORACLE_TRIM) != 0;
+  const float lp_trim = (float)log(1.0 / 100.0);
 
   /* Per-read scaling (paragraph after Alg. 5.3), sigma never scaled:
    * by default the model level of every k-mer of the read is scaled,
@@ -162,6 +177,8 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
   E[1] = E[0];
   K[1] = K[0] + 1;
   S[0 * W + half] = 0.0f;
+  /* with trim, band 1 holds the first trim cell (0, -1), up of the origin */
+  if (trim) trim_cell(S, T, E, K, 1, n_e, W, lp_trim);
 
   for (int64_t i = 2; i <= last; ++i) {
     /* Suzuki-Kasahara rule on the previous band: move towards the better of
@@ -197,9 +214,13 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
     for (int64_t j = min_j; j <= max_j; ++j) {
       const int64_t e = E[i] - j;
       const int64_t k = K[i] + j;
-      /* neighbours: up (e-1, k), left (e, k-1) in band i-1; diag (e-1, k-1) in band i-2 */
+      /* neighbours: up (e-1, k), left (e, k-1) in band i-1; diag (e-1, k-1)
+       * in band i-2.  The first k-mer has no left neighbour: (e, -1) is
+       * outside the table, or with trim a trim cell, which is entered from
+       * only by a diagonal step */
       const float up = band_get(S, i - 1, k - K[i - 1], W);
-      const float left = band_get(S, i - 1, k - 1 - K[i - 1], W);
+      const float left = (k == 0 && !(flags & ORACLE_PLANT_TRIM_SKIP_IN)) ? NEG_INF
+                                                                         : band_get(S, i - 1, k - 1 - K[i - 1], W);
       const float diag = band_get(S, i - 2, k - 1 - K[i - 2], W);
       const int64_t e_em = (flags & ORACLE_PLANT_EVENT_OFF_BY_ONE) ? (e > 0 ? e - 1 : 0) : e;
       const uint32_t r = rank[k];
@@ -216,16 +237,46 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
       S[i * W + j] = s;
       T[i * W + j] = d;
     }
+    if (trim) trim_cell(S, T, E, K, i, n_e, W, lp_trim);
   }
 
   int status = ORACLE_READ_OK;
-  const int64_t jt = E[last] - (n_e - 1);
-  if (jt < 0 || jt >= W || S[last * W + jt] == NEG_INF) {
+  /* the end of the path: (n_e-1, n_k-1), or with trim the last k-mer's cell
+   * that is best with the remaining events trimmed */
+  int64_t e_end = n_e - 1;
+  float end_score = NEG_INF;
+  {
+    const int64_t jt = E[last] - (n_e - 1);
+    if (jt >= 0 && jt < W) end_score = S[last * W + jt];
+  }
+  if (trim) {
+    float best = NEG_INF;
+    int64_t u = -1;
+    for (int64_t e = 0; e < n_e; ++e) {
+      const int64_t i = e + n_k + 1; /* the band of (e, n_k-1) */
+      const float s_end = band_get(S, i, E[i] - e, W);
+      const float t = (flags & ORACLE_PLANT_TRIM_NO_TAIL) ? NEG_INF : best + lp_trim;
+      if (t != NEG_INF && s_end != NEG_INF) {
+        const double mm = fabs((double)t - (double)s_end);
+        if (mm < st.min_margin) st.min_margin = mm;
+      }
+      if (t > s_end) {
+        best = t;
+      } else {
+        best = s_end;
+        u = e;
+      }
+    }
+    end_score = best;
+    e_end = u;
+  }
+  if (end_score == NEG_INF) {
     status = ORACLE_READ_BAND_LOST;
   } else {
-    *score = S[last * W + jt];
-    /* backtrack from (n_e-1, n_k-1) to the origin, emitting every cell */
-    int64_t e = n_e - 1, k = n_k - 1, n = 0;
+    *score = end_score;
+    /* backtrack from the end cell to the origin (with trim: to the trim
+     * column), emitting every cell */
+    int64_t e = e_end, k = n_k - 1, n = 0;
     while (e >= 0 && k >= 0) {
       pairs[2 * n + 0] = (int32_t)e;
       pairs[2 * n + 1] = (int32_t)k;
@@ -236,7 +287,8 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
       {
         /* decision margin of this path cell */
         const float up = band_get(S, i - 1, k - K[i - 1], W);
-        const float left = band_get(S, i - 1, k - 1 - K[i - 1], W);
+        const float left = (k == 0 && !(flags & ORACLE_PLANT_TRIM_SKIP_IN)) ? NEG_INF
+                                                                           : band_get(S, i - 1, k - 1 - K[i - 1], W);
         const float diag = band_get(S, i - 2, k - 1 - K[i - 2], W);
         const uint32_t r = rank[k];
         const float em = oracle_emission(xs[e], mu[k], level_stdv[r], c[r], h[r],
@@ -254,7 +306,10 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
       else if (d == T_L) { k--; }
       else { status = ORACLE_READ_BAND_LOST; n = 0; break; }
     }
-    if (status == ORACLE_READ_OK && !(e == -1 && k == -1)) {
+    /* the walk ends at the origin; with trim at the trim column, having
+     * left e+1 leading events unaligned */
+    const int ended = trim ? (k == -1 && e >= -1) : (e == -1 && k == -1);
+    if (status == ORACLE_READ_OK && !ended) {
       status = ORACLE_READ_BAND_LOST;
       n = 0;
     }

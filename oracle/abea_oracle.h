@@ -45,7 +45,21 @@ enum {
    * mean becomes x' = (x - shift) / scale (float32 subtract, then IEEE
    * float32 divide), and the model levels are used unscaled.  sigma is not
    * scaled in either mode. */
-  ORACLE_SCALE_EVENTS = 16u
+  ORACLE_SCALE_EVENTS = 16u,
+  /* Trim states (the trim paragraph after Alg. 5.3; the trim comments of the
+   * core-kernel, Alg. 5.6): open-pore or adaptor events at either end of a
+   * read may be left unaligned at ln(1/100) each.  A column at k-mer -1
+   * holds the leading trim, (e, -1) = (e-1, -1) + lp_trim from the origin;
+   * the first k-mer is entered from it by a diagonal step only; the path
+   * ends at the cell (u, n_k-1) that is best with the n_e-1-u trailing
+   * events trimmed, End(e) = max(S(e, n_k-1), End(e-1) + lp_trim) with ties
+   * to the smaller trim; the backtrack starts there and stops at k = -1. */
+  ORACLE_TRIM = 32u,
+  /* PLANTED MISTAKE for tests only (with ORACLE_TRIM): no trailing trim. */
+  ORACLE_PLANT_TRIM_NO_TAIL = 64u,
+  /* PLANTED MISTAKE for tests only (with ORACLE_TRIM): the first k-mer may
+   * also be entered from the trim column by a skip. */
+  ORACLE_PLANT_TRIM_SKIP_IN = 128u
 };
 
 typedef struct {

@@ -28,6 +28,9 @@ PLANT_SK_REVERSED = 2
 PLANT_DROP_UP_EMISSION = 4
 PLANT_EVENT_OFF_BY_ONE = 8
 SCALE_EVENTS = 16  # events scaled to the model: x' = (x - shift) / scale, model levels unscaled
+TRIM = 32  # trim states: leading and trailing events may be left unaligned at ln(1/100) each
+PLANT_TRIM_NO_TAIL = 64
+PLANT_TRIM_SKIP_IN = 128
 
 GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-pthread"]
 

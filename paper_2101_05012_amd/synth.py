@@ -40,6 +40,15 @@ WORKLOAD_SEED_BASE = 2026_0000
 SKIP_PROB = 0.05
 EVENTS_PER_KMER_MEAN = 1.8
 
+# Events outside the molecule (the trim paragraph after Alg. 5.3): open-pore
+# current before and after the read, and adaptor events between the leading
+# open pore and the read.  Open-pore current is far above every k-mer level
+# of the model (60..130 pA); adaptor events take arbitrary levels in the
+# model's range.
+OPEN_PORE_MEAN, OPEN_PORE_SD = 220.0, 4.0
+MAX_OPEN_PORE_EVENTS = 30
+MAX_ADAPTOR_EVENTS = 10
+
 # Workload shapes.  W is the band width, k the k-mer length.
 WORKLOADS = {
     "plain-64x1kb": dict(seed_index=0, n_reads=64, W=100, k=6, lengths="fixed1000"),
@@ -47,6 +56,9 @@ WORKLOADS = {
     "uneven-20000": dict(seed_index=2, n_reads=20000, W=100, k=6, lengths="mixed"),
     "serving-lognormal8kb": dict(seed_index=3, n_reads=None, W=100, k=6, lengths="lognormal8k"),
     "ultralong-200": dict(seed_index=4, n_reads=200, W=100, k=6, lengths="ultralong"),
+    # config-1 lengths with open-pore and adaptor events at the read ends
+    "plain-4000-lognormal5kb-ends": dict(seed_index=5, n_reads=4000, W=100, k=6, lengths="lognormal5k",
+                                         ends=True),
 }
 
 
@@ -138,11 +150,15 @@ def gen_read(
     L: int,
     model: PoreModel,
     noiseless: bool = False,
+    ends: bool = False,
 ) -> Read:
     """Draw one read of reference length L (see the module docstring).
 
     ``noiseless``: one event per k-mer, scale 1, shift 0 and every event mean
     equal to the model level of its k-mer, so the model levels need no scaling.
+    ``ends``: the read is preceded by U{0..30} open-pore events and U{0..10}
+    adaptor events and followed by U{0..30} open-pore events (drawn after
+    everything else, so the read's own events are those without ``ends``).
     """
     k = model.k
     bases = rng.integers(0, 4, L).astype(np.uint8)
@@ -166,7 +182,23 @@ def gen_read(
     ev[:, 0] = rng.normal(loc, model.level_stdv[r_ev].astype(np.float64))
     ev[:, 1] = rng.uniform(0.5, 3.0, n_e)
     ev[:, 2] = rng.exponential(0.0025, n_e)
+    if ends:
+        ev = np.concatenate([end_events(rng, True), ev, end_events(rng, False)])
     return Read(ev, ranks, scale, shift)
+
+
+def end_events(rng: np.random.Generator, leading: bool) -> np.ndarray:
+    """Events outside the molecule: open pore (and, before the read, adaptor
+    events after it), as [n, 3] float32 (mean, stdv, duration)."""
+    n_open = int(rng.integers(0, MAX_OPEN_PORE_EVENTS + 1))
+    n_adapt = int(rng.integers(0, MAX_ADAPTOR_EVENTS + 1)) if leading else 0
+    n = n_open + n_adapt
+    ev = np.empty((n, 3), np.float32)
+    ev[:n_open, 0] = rng.normal(OPEN_PORE_MEAN, OPEN_PORE_SD, n_open)
+    ev[n_open:, 0] = rng.uniform(60.0, 130.0, n_adapt)
+    ev[:, 1] = rng.uniform(0.5, 3.0, n)
+    ev[:, 2] = rng.exponential(0.0025, n)
+    return ev
 
 
 def make_batch(reads: Sequence[Read]) -> Batch:
@@ -201,7 +233,7 @@ def workload_read(workload: str, read_id: int, model: PoreModel) -> Read:
     """Read ``read_id`` of a workload; identical whatever batch it is in."""
     rng = read_rng(workload, read_id)
     L = draw_length(rng, WORKLOADS[workload]["lengths"])
-    return gen_read(rng, L, model)
+    return gen_read(rng, L, model, ends=WORKLOADS[workload].get("ends", False))
 
 
 def workload_batch(
