@@ -79,6 +79,9 @@ WORKLOADS = {
     "plain-64x1kb": dict(kind="plain", source="plain-64x1kb", W=100, k=6),
     # the same 4000 reads with the events scaled to the model instead
     "plain-4000-lognormal5kb-scale-events": dict(kind="plain", source="plain-4000-lognormal5kb", W=100, k=6, scale_events=True),
+    # reads with open-pore and adaptor events at both ends, aligned with trim states
+    "plain-4000-lognormal5kb-ends-trim": dict(kind="plain", source="plain-4000-lognormal5kb-ends", W=100, k=6,
+                                              trim=True),
     # launch: the autotuner's choice (cells per lane, reads per workgroup,
     # pool wavefronts per SIMD, batches per job)
     "uneven-20000-w100": dict(kind="persistent", source="uneven-20000", W=100, k=6, plain_batches=5,
@@ -109,15 +112,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(batch, model, W, idx, what, scale_events=False):
+def cpu_baseline(batch, model, W, idx, what, scale_events=False, trim=False):
     """The oracle on the host's cores (up to 16 threads) over reads idx."""
     from oracle import oracle as O
 
+    flags = (O.SCALE_EVENTS if scale_events else 0) | (O.TRIM if trim else 0)
     cores = min(16, os.cpu_count() or 1)
     sub = batch.subset(idx)
     om = O.Model(model.level_mean, model.level_stdv)
     t0 = time.perf_counter()
-    res = O.align_batch(sub, om, W, n_threads=cores, flags=O.SCALE_EVENTS if scale_events else 0)
+    res = O.align_batch(sub, om, W, n_threads=cores, flags=flags)
     dt = time.perf_counter() - t0
     cells = int(res.cells.sum())
     # one thread on the first reads of the same sample (about 0.25 G cells)
@@ -126,7 +130,7 @@ def cpu_baseline(batch, model, W, idx, what, scale_events=False):
     n1 = min(n1, len(idx))
     sub1 = batch.subset(list(idx)[:n1])
     t1 = time.perf_counter()
-    r1 = O.align_batch(sub1, om, W, n_threads=1, flags=O.SCALE_EVENTS if scale_events else 0)
+    r1 = O.align_batch(sub1, om, W, n_threads=1, flags=flags)
     dt1 = time.perf_counter() - t1
     c1 = int(r1.cells.sum())
     return {
@@ -285,7 +289,7 @@ def bench_plain(args, wl):
     for _ in range(P):
         al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True,
                           workers=args.workers, waves_per_group=args.wpg, band_clear=band_clear,
-                          scale_events=wl.get("scale_events", False))
+                          scale_events=wl.get("scale_events", False), trim=wl.get("trim", False))
         slots.append((al, abea.DeviceResult.empty(db, dev), torch.cuda.Stream(dev)))
     torch.cuda.synchronize()
 
@@ -348,6 +352,7 @@ def bench_plain(args, wl):
         "warmup_batches": warm,
         "band_clear": {1: "window", 2: "edges"}.get(plan.get("band_clear"), "?"),
         "per_read_scaling": "events to the model" if wl.get("scale_events") else "model to the events",
+        "trim_states": bool(wl.get("trim", False)),
     })
     out.update({
         "reads_per_s": round(n * args.steps / dt, 1),
@@ -368,7 +373,7 @@ def bench_plain(args, wl):
         log("bench: cpu baseline (oracle)")
         idx = list(range(min(args.cpu_sample_reads, n)))
         out["cpu_baseline"] = cpu_baseline(batch, model, W, idx, f"reads 0..{len(idx) - 1} of the same workload",
-                                           scale_events=wl.get("scale_events", False))
+                                           scale_events=wl.get("scale_events", False), trim=wl.get("trim", False))
     return out
 
 

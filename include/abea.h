@@ -60,7 +60,18 @@ extern "C" {
  * the model is scaled: mu' = fmaf(level_mean, scale[r], shift[r]).  sigma is
  * unscaled in both modes.  scale[r] must be finite and non-zero. */
 #define ABEA_F_SCALE_EVENTS 2u
-#define ABEA_F_ALL (ABEA_F_TIMING | ABEA_F_SCALE_EVENTS)
+/* Trim states (the trim paragraph after Alg. 5.3; the trim comments of the
+ * core-kernel, Alg. 5.6): events at either end of a read (open pore,
+ * adaptor) may stay unaligned at ln(1/100) each.  Leading trims form a column
+ * at k-mer -1 inside the bands, (e, -1) = (e-1, -1) + ln(1/100) from the
+ * origin, from which the first k-mer is entered by a diagonal step only; the
+ * path ends at the last k-mer's cell (u, n_k-1) that is best with the
+ * n_e-1-u trailing events trimmed (float32 sums in event order; ties to
+ * fewer trims).  The pairs then run from (t, 0) to (u, n_k-1), t and n_e-1-u
+ * the trimmed events; log_likelihood includes the trims.  Without the flag
+ * the alignment is global, from (0, 0) to (n_e-1, n_k-1). */
+#define ABEA_F_TRIM 4u
+#define ABEA_F_ALL (ABEA_F_TIMING | ABEA_F_SCALE_EVENTS | ABEA_F_TRIM)
 
 /* One event of the event table (Alg. 5.1 input "events[]": mean, stdv, n).
  * 12 bytes; only .mean is read (Alg. 5.3). */
@@ -124,7 +135,8 @@ typedef struct {
 
 /*
  * Results.  Read r's pairs are pairs[pair_offset[r] .. pair_offset[r+1]) in
- * path order, from (0, 0) to (n_e-1, n_k-1); every cell of the path is a pair
+ * path order, from (0, 0) to (n_e-1, n_k-1) (with ABEA_F_TRIM from the first
+ * untrimmed event to the last); every cell of the path is a pair
  * (a k-mer entered by a skip too).  pair_capacity must be at least
  * sum_r max(0, n_e_r + n_k_r - 1) (a path never has more cells).
  */
@@ -198,7 +210,7 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *batch,
  * many of the longest reads' traces fit in what the other buffers leave of
  * the array (admission by traceback bytes).
  * Limits: n_reads <= ABEA_NOALLOC_MAX_READS, and 4 B per event, 16 B per
- * k-mer, 8 B per path slot (sum of n_e + n_k - 1), 96 B per read and the
+ * k-mer, 8 B per path slot (sum of n_e + n_k - 1), 100 B per read and the
  * trace of at least the longest read (ceil((n_e + n_k - 1) / (32 /
  * cells_per_lane)) * 512 B) must fit in ABEA_NOALLOC_SCRATCH_BYTES; a batch
  * beyond them fails with ABEA_E_NOMEM and nothing is enqueued.

@@ -30,6 +30,7 @@ ABEA_MAX_BANDWIDTH = 512
 ABEA_MAX_K = 12
 ABEA_F_TIMING = 1
 ABEA_F_SCALE_EVENTS = 2  # events scaled to the model: (x - shift) / scale
+ABEA_F_TRIM = 4  # trim states: events at either end may stay unaligned at ln(1/100) each
 ABEA_WORKERS_SPLIT = -1
 ABEA_CLEAR_AUTO = 0  # band_clear: the library chooses
 ABEA_CLEAR_WINDOW = 1  # every slot outside the band's cells, every band
@@ -325,10 +326,12 @@ class Aligner:
         cells_per_lane: int = 0,
         scale_events: bool = False,
         band_clear: int = ABEA_CLEAR_AUTO,
+        trim: bool = False,
     ):
         self._lm = np.ascontiguousarray(level_mean, np.float32)
         self._ls = np.ascontiguousarray(level_stdv, np.float32)
-        flags = (ABEA_F_TIMING if timing else 0) | (ABEA_F_SCALE_EVENTS if scale_events else 0)
+        flags = ((ABEA_F_TIMING if timing else 0) | (ABEA_F_SCALE_EVENTS if scale_events else 0)
+                 | (ABEA_F_TRIM if trim else 0))
         cfg = abea_config_t(W, device, int(arena_bytes), flags)
         mdl = abea_model_t(k, self._lm.ctypes.data, self._ls.ctypes.data)
         h = ctypes.c_void_p()

@@ -138,7 +138,7 @@ void work_free(Work &w, hipStream_t st) {
   if (w.done_pending && w.done) (void)hipEventSynchronize(w.done);
   w.done_pending = false;
   DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.xmean, &w.kparam,
-                    &w.trace, &w.scratch, &w.path_len, &w.path_src};
+                    &w.trace, &w.scratch, &w.path_len, &w.path_src, &w.tend};
   for (DevBuf *b : bufs) free_buf(*b, st);
   if (w.staging_pending && w.staging_done) (void)hipEventSynchronize(w.staging_done);
   w.staging_pending = false;
@@ -173,8 +173,8 @@ bool split_kernels(const abea_ctx *ctx) { return ctx->launch.workers == ABEA_WOR
 
 /* Wavefronts of the fused kernel that are resident at once on the device. */
 int resident_workers(abea_ctx *ctx, bool edge) {
-  const int gpc =
-      align_groups_per_cu(ctx->cpl, refills_per_group(ctx->W, ctx->cpl), ctx->launch.waves_per_group, edge);
+  const int gpc = align_groups_per_cu(ctx->cpl, refills_per_group(ctx->W, ctx->cpl), ctx->launch.waves_per_group,
+                                      edge, (ctx->flags & ABEA_F_TRIM) != 0);
   return std::max(1, gpc * ctx->num_cus * ctx->launch.waves_per_group);
 }
 
@@ -325,6 +325,7 @@ int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st) {
   if ((rc = ensure(ctx, &w, w.scratch, sizeof(int2) * (size_t)P.n_scratch, st))) return rc;
   if ((rc = ensure(ctx, &w, w.path_len, sizeof(uint64_t) * n, st))) return rc;
   if ((rc = ensure(ctx, &w, w.path_src, sizeof(uint64_t) * n, st))) return rc;
+  if ((rc = ensure(ctx, &w, w.tend, sizeof(int32_t) * n, st))) return rc;
   return ABEA_OK;
 }
 
@@ -358,6 +359,10 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   a.n_workers = P.workers;
   a.W = ctx->W;
   a.urgent_len = P.urgent_len;
+  a.tend = (int32_t *)w.tend.p;
+  a.trim = (ctx->flags & ABEA_F_TRIM) != 0;
+  /* one trimmed event, probability 1/100: in double, rounded once */
+  a.lp_trim = (float)std::log(1.0 / 100.0);
   /* the band or fused kernel's own start and end: with other batches in
    * flight its dispatch may wait for free CUs, which these do not count */
   hipEvent_t k0 = timed ? w.tev[2] : nullptr, k1 = timed ? w.tev[3] : nullptr;
@@ -745,10 +750,11 @@ int abea_align_batch_device_noalloc(abea_ctx *ctx, const abea_batch_t *b, const 
   const uint64_t nr = (uint64_t)std::max(n, 1);
   auto up = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
   Work &w = ctx->noalloc;
-  DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.path_len, &w.path_src, &w.xmean, &w.kparam, &w.scratch};
+  DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.path_len, &w.path_src, &w.tend,
+                    &w.xmean, &w.kparam, &w.scratch};
   const uint64_t bytes[] = {sizeof(ReadDesc) * nr, sizeof(int32_t) * nr, sizeof(uint32_t), sizeof(uint64_t) * nr,
-                            sizeof(uint64_t) * nr, sizeof(float) * eo[n], sizeof(KParam) * ko[n],
-                            sizeof(int2) * slots};
+                            sizeof(uint64_t) * nr, sizeof(int32_t) * nr, sizeof(float) * eo[n],
+                            sizeof(KParam) * ko[n], sizeof(int2) * slots};
   uint64_t fixed = 0;
   for (uint64_t x : bytes) fixed += up(x);
   if (fixed >= ABEA_NOALLOC_SCRATCH_BYTES)
@@ -765,7 +771,7 @@ int abea_align_batch_device_noalloc(abea_ctx *ctx, const abea_batch_t *b, const 
   }
   unsigned char *base = (unsigned char *)ctx->noalloc_scratch;
   uint64_t off = 0;
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < 9; ++i) {
     bufs[i]->p = base + off;
     bufs[i]->cap = bytes[i];
     bufs[i]->borrowed = true;

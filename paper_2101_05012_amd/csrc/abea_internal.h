@@ -92,6 +92,9 @@ struct AlignArgs {
   int32_t n_workers;     /* fused kernel: wavefronts; worker w starts with read w */
   int32_t W;
   int32_t urgent_len;    /* reads with n_e + n_k >= this run at raised wave priority */
+  int32_t *tend;         /* [n_reads] split kernels: the event of each read's end cell (trim) */
+  float lp_trim;         /* trim states: ln(1/100) per trimmed event */
+  int32_t trim;          /* trim states on (leading and trailing events may stay unaligned) */
 };
 
 /* Kernel launchers (abea_kernels.hip). */
@@ -117,7 +120,7 @@ hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st);
 hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, bool edge, hipStream_t st,
                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 /* resident workgroups of the fused kernel per CU (occupancy) */
-int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge);
+int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge, bool trim);
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st);
 
 /* Fixed scratch of the no-allocation entry point (abea_kernels.hip). */

@@ -368,9 +368,9 @@ struct WaveLds {
  * and what those slots hold (scores of k-mers outside the band, or NaN from
  * stale ring entries) never reaches the band, its end cells or the trace bits
  * of its cells. */
-template <int CPL, int RPG, bool CLEAR_EDGES>
+template <int CPL, int RPG, bool CLEAR_EDGES, bool TRIM>
 __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd, uint2 *trace,
-                                         float *__restrict__ lx, float4 *__restrict__ lk) {
+                                         float *__restrict__ lx, float4 *__restrict__ lk, int &e_end) {
   constexpr int N = Geom<CPL>::N;
   constexpr int LC = Geom<CPL>::LC;
   constexpr int G = Geom<CPL>::G;
@@ -411,15 +411,29 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   };
   auto put_k = [&](int q, float4 v) { lk[(q * 64 + lane) & (RK - 1)] = v; };
 
+  /* Trim states (the trim paragraph after Alg. 5.3): a column at k-mer -1
+   * whose cell (e, -1) is (e-1, -1) + lp_trim, every event before the read
+   * left unaligned; it lies in a band only while the band's first k-mer is
+   * -1 or less, i.e. in bands with cells outside the table.  The first
+   * k-mer is entered from it diagonally only (its left neighbour is -inf).
+   * The end: end_best over the bands of the last k-mer's cells, the best of
+   * (e, n_k-1) and the previous best with event e trimmed (ties to fewer
+   * trims); end_u the end cell's event. */
+  constexpr bool trim = TRIM;
+  const float lp_trim = a.lp_trim;
+  float end_best = ABEA_NINF;
+  int end_u = -1;
+
   /* Band 1 (initialise_first_two_bands): band 0 has lower-left (W/2-1,
    * -1-W/2) and holds only the virtual origin (-1,-1) with score 0; band 1 is
-   * band 0 moved one k-mer and is all -inf.  K is the first k-mer of the
-   * latest band, E the event of its first cell. */
+   * band 0 moved one k-mer and is all -inf (with trim: but for the trim cell
+   * (0, -1) at offset W/2-1).  K is the first k-mer of the latest band, E the
+   * event of its first cell. */
   int K = -H;
   int E = H - 1;
   /* bits of the end cells of the latest band, for the next band's move:
-   * band 1 is all -inf */
-  int lo_c = ABEA_NINF_BITS, hi_c = ABEA_NINF_BITS;
+   * band 1's are -inf, unless the trim cell is its first (W = 2, 3) */
+  int lo_c = (trim && H == 1) ? __float_as_int(lp_trim) : ABEA_NINF_BITS, hi_c = ABEA_NINF_BITS;
   /* edge kernels at two slots per lane keep the last end cell in its
    * register (hv, lane hl) and decide the move by one compare against every
    * lane; at four slots per lane (three or fewer wavefronts per SIMD) the
@@ -443,8 +457,8 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
     const int kv = K + ((lane * CPL + c - K) & (N - 1));
-    Spp[c] = (kv == -1) ? 0.0f : NI; /* band 0: the origin, k-mer -1 */
-    Sp[c] = NI;
+    Spp[c] = (kv == -1) ? 0.0f : NI;                   /* band 0: the origin, k-mer -1 */
+    Sp[c] = (trim && kv == -1) ? 0.0f + lp_trim : NI; /* band 1: the trim cell (0, -1) */
     PM[c] = PC[c] = PH[c] = 0.0f;
     kvs[c] = kv;
     xb[c] = 0;
@@ -545,6 +559,14 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     add_rot2(Sp[CPL - 1], lp_skip_v, Spp[CPL - 1], lp_step_v, lf0, dg0);
     float nv[CPL]; /* band i; band i-2 is still read below */
     float sv[CPL]; /* band i before the window mask */
+    /* trim, in bands with cells outside the table: the first k-mer takes no
+     * skip from the trim column (while the previous band may hold it), and
+     * the trim cell (i-1, -1) of this band (while the band holds k-mer -1) */
+    bool no_skip_in = false, trim_cell = false;
+    if constexpr (!INTERIOR && TRIM) {
+      no_skip_in = K <= 0;
+      trim_cell = K <= -1 && i - 1 <= n_e - 1;
+    }
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
       const float x = X[c];
@@ -559,7 +581,10 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       const float em = PC[c] - u;
       const float sd = dst + em;
       const float su = (up + lp_stay) + em;
-      const float sl = lsk;
+      float sl = lsk;
+      if constexpr (!INTERIOR && TRIM) {
+        if (no_skip_in) sl = sel(sl, NI, ballot(kvs[c] == 0));
+      }
       /* first maximum in the order D, U, L.  The value is the plain maximum
        * (scores are finite or -inf, never NaN or -0, so v_max3 gives the
        * bits of the first-maximum selects).  The trace bits say which
@@ -577,6 +602,9 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       } else {
         const uint64_t valid = ballot((uint32_t)(kvs[c] - wlo) < (uint32_t)wlen);
         nv[c] = sel(NI, sv[c], valid);
+        if constexpr (!INTERIOR && TRIM) {
+          if (trim_cell) nv[c] = sel(nv[c], up + lp_trim, ballot(kvs[c] == -1));
+        }
       }
       /* trace planes: the D bit, and the U bit (read only when D is clear) */
       TD = shift_in(TD, md);
@@ -606,6 +634,20 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       } else {
         lo_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sf & (CPL - 1))), sf >> LC);
         hi_c = __builtin_amdgcn_readlane(__float_as_int(pick<CPL>(src, sh & (CPL - 1))), sh >> LC);
+      }
+    }
+    if constexpr (!INTERIOR && TRIM) {
+      /* trim: band i holds (i-1-n_k, n_k-1) if it holds the last k-mer */
+      if (i >= n_k + 1) {
+        const float s_end =
+            (n_k - 1 >= K && n_k - 1 <= K + W - 1) ? read_slot<CPL>(nv, (n_k - 1) & (N - 1)) : ABEA_NINF;
+        const float t = end_best + lp_trim;
+        if (t > s_end) {
+          end_best = t;
+        } else {
+          end_best = s_end;
+          end_u = i - 1 - n_k;
+        }
       }
     }
 #pragma unroll
@@ -655,8 +697,10 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     K = __builtin_amdgcn_readfirstlane(K);
     E = i - 3 - K; /* band i - 1 is the latest */
     advance_rings();
+    /* with trim the last k-mer stays out of interior bands, whose cells the
+     * end recurrence does not read */
     const bool interior = gap_ok & (K >= 0) & (E >= W - 1) & (E + G <= n_e - 1) &
-                          (K + G + W - 1 <= n_k - 1);
+                          (K + G + W - 1 <= n_k - 1 - (int)trim);
     if (interior) {
       group(std::true_type(), i);
       cells += (uint64_t)W * G;
@@ -688,12 +732,19 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     trace[g * 64 + lane] = make_uint2(TD << sh, TU << sh);
   }
 
-  /* terminal cell (n_e-1, n_k-1) is in the last band if its k-mer is */
-  float F[CPL];
-#pragma unroll
-  for (int c = 0; c < CPL; ++c) F[c] = (last & 1) ? Sp[c] : Spp[c];
+  /* terminal cell (n_e-1, n_k-1) is in the last band if its k-mer is; with
+   * trim the end cell the end recurrence chose */
   float sc = ABEA_NINF;
-  if (n_k - 1 >= K && n_k - 1 <= K + W - 1) sc = read_slot<CPL>(F, (n_k - 1) & (N - 1));
+  e_end = n_e - 1;
+  if constexpr (TRIM) {
+    sc = end_best;
+    e_end = end_u;
+  } else {
+    float F[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) F[c] = (last & 1) ? Sp[c] : Spp[c];
+    if (n_k - 1 >= K && n_k - 1 <= K + W - 1) sc = read_slot<CPL>(F, (n_k - 1) & (N - 1));
+  }
   if (lane == 0) {
     a.out_ll[rd.orig] = sc;
     if (a.out_cells) a.out_cells[rd.orig] = cells;
@@ -710,7 +761,7 @@ __device__ __forceinline__ void band_skipped(const AlignArgs &a, const ReadDesc 
 }
 
 /* Band fill alone, one wavefront per planned read. */
-template <int CPL, int RPG, bool EDGE>
+template <int CPL, int RPG, bool EDGE, bool TRIM>
 __global__ __launch_bounds__(64) void k_band(const AlignArgs a) {
   __shared__ WaveLds<CPL> lds;
   const int s = blockIdx.x;
@@ -722,9 +773,13 @@ __global__ __launch_bounds__(64) void k_band(const AlignArgs a) {
   /* the longest reads set the kernel's duration: let them issue first */
   const bool urgent = rd.n_e + rd.n_k >= a.urgent_len;
   if (urgent) __builtin_amdgcn_s_setprio(2);
-  const int st = band_read<CPL, RPG, EDGE>(a, rd, a.trace + rd.tr_off, lds.band.lx, lds.band.lk);
+  int e_end;
+  const int st = band_read<CPL, RPG, EDGE, TRIM>(a, rd, a.trace + rd.tr_off, lds.band.lx, lds.band.lk, e_end);
   if (urgent) __builtin_amdgcn_s_setprio(0);
-  if (threadIdx.x == 0) a.rstat[s] = st;
+  if (threadIdx.x == 0) {
+    a.rstat[s] = st;
+    a.tend[s] = e_end;
+  }
 }
 
 /* ------------------------------------------------------------- backtrack */
@@ -758,9 +813,12 @@ __device__ __forceinline__ int trace_bit(int t, int k) {
 /* Backtrack of one read (Alg. 5.1, after the band loop) by the calling
  * wavefront, from its trace tiles: writes the path's pairs backwards into
  * the read's scratch slots, its length and first slot, and its final status
- * (and -inf as log-likelihood if the walk fails). */
-template <int CPL>
-__device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDesc &rd, int status,
+ * (and -inf as log-likelihood if the walk fails).  The walk starts at
+ * (e_start, n_k-1): (n_e-1, n_k-1), or with TRIM the end cell the band fill
+ * chose; it ends at the origin, or with TRIM on reaching the trim column
+ * k = -1 (whose cells are not pairs). */
+template <int CPL, bool TRIM>
+__device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDesc &rd, int status, int e_start,
                                                const uint2 *__restrict__ tr,
                                                uint2 *__restrict__ ring) {
   constexpr int N = 64 * CPL;
@@ -788,7 +846,7 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
     return v;
   };
 
-  int e = n_e - 1, k = n_k - 1;
+  int e = __builtin_amdgcn_readfirstlane(e_start), k = n_k - 1;
   int gcur = (e + k) >> LG;
   /* quarters of QG groups, walked downwards: quarters qa, qa-1, qa-2 are in
    * the ring, qa-3 waits in registers */
@@ -849,8 +907,11 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
       t = e + k;
       /* stop when the walk left the group (t falls by 1 or 2 per step, so
        * this also ends a walk that leaves the table; the caller checks that
-       * it ended at the origin) */
+       * it ended at the origin), or with TRIM entered the trim column */
       if (t < lower) break;
+      if constexpr (TRIM) {
+        if (k < 0) break;
+      }
     }
     if ((e | k) < 0) break;
     const int gi = t >> LG;
@@ -868,7 +929,7 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
     }
   }
   flush();
-  if (ok && !(e == -1 && k == -1)) ok = false;
+  if (ok && !(TRIM ? (k == -1 && e >= -1) : (e == -1 && k == -1))) ok = false;
   if (lane == 0) {
     a.path_len[orig] = ok ? q : 0;
     a.path_src[orig] = res_end - q;
@@ -878,12 +939,12 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
 }
 
 /* Backtrack alone, one wavefront per planned read. */
-template <int CPL>
+template <int CPL, bool TRIM>
 __global__ __launch_bounds__(64) void k_backtrack(const AlignArgs a) {
   __shared__ WaveLds<CPL> lds;
   const int s = blockIdx.x;
   const ReadDesc rd = a.reads[s];
-  backtrack_read<CPL>(a, rd, a.rstat[s], a.trace + rd.tr_off, lds.ring);
+  backtrack_read<CPL, TRIM>(a, rd, a.rstat[s], TRIM ? a.tend[s] : rd.n_e - 1, a.trace + rd.tr_off, lds.ring);
 }
 
 /* ----------------------------------------------------------------- fused */
@@ -896,7 +957,7 @@ __global__ __launch_bounds__(64) void k_backtrack(const AlignArgs a) {
  * keeps read w's trace region for all its reads.  n_workers = n_reads is the
  * plain one-launch form; fewer workers bound the trace memory (admission by
  * traceback bytes) and let the longest reads of the batch overlap the rest. */
-template <int CPL, int RPG, int WPG, bool EDGE>
+template <int CPL, int RPG, int WPG, bool EDGE, bool TRIM>
 __global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
   __shared__ WaveLds<CPL> lds[WPG];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -910,15 +971,16 @@ __global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
     /* the longest reads set the kernel's duration: let them issue first */
     const bool urgent = rd.n_e + rd.n_k >= a.urgent_len;
     if (urgent) __builtin_amdgcn_s_setprio(2);
+    int e_end = rd.n_e - 1;
     if (st == READ_OK)
-      st = band_read<CPL, RPG, EDGE>(a, rd, slab, lds[wv].band.lx, lds[wv].band.lk);
+      st = band_read<CPL, RPG, EDGE, TRIM>(a, rd, slab, lds[wv].band.lx, lds[wv].band.lk, e_end);
     else
       band_skipped(a, rd);
     /* the walk reads back what this wavefront's lanes just stored (each lane
      * its own words); keep the compiler from moving loads above the stores */
     __builtin_amdgcn_s_waitcnt(0);
     asm volatile("" ::: "memory");
-    backtrack_read<CPL>(a, rd, st, slab, lds[wv].ring);
+    backtrack_read<CPL, TRIM>(a, rd, st, e_end, slab, lds[wv].ring);
     if (urgent) __builtin_amdgcn_s_setprio(0);
     asm volatile("" ::: "memory");
     uint32_t q = 0;
@@ -1007,37 +1069,45 @@ hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events
 hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, bool edge, hipStream_t st, hipEvent_t t0,
                        hipEvent_t t1) {
   if (a.n_reads <= 0) return hipSuccess;
-#define ABEA_L(C, R, E)                                                                       \
-  {                                                                                           \
-    hipExtLaunchKernelGGL((k_band<C, R, E>), dim3(a.n_reads), dim3(64), 0, st, t0, t1, 0, a); \
-    return hipGetLastError();                                                                 \
+#define ABEA_L(C, R, E)                                                                                 \
+  {                                                                                                     \
+    if (a.trim)                                                                                         \
+      hipExtLaunchKernelGGL((k_band<C, R, E, true>), dim3(a.n_reads), dim3(64), 0, st, t0, t1, 0, a);  \
+    else                                                                                                \
+      hipExtLaunchKernelGGL((k_band<C, R, E, false>), dim3(a.n_reads), dim3(64), 0, st, t0, t1, 0, a); \
+    return hipGetLastError();                                                                           \
   }
   ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st) {
-  if (a.n_reads <= 0) return hipSuccess;
+template <bool TRIM>
+static hipError_t launch_backtrack_t(const AlignArgs &a, int cpl, hipStream_t st) {
   switch (cpl) {
-    case 1: hipLaunchKernelGGL(k_backtrack<1>, dim3(a.n_reads), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_backtrack<2>, dim3(a.n_reads), dim3(64), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_backtrack<4>, dim3(a.n_reads), dim3(64), 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_backtrack<8>, dim3(a.n_reads), dim3(64), 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_backtrack<16>, dim3(a.n_reads), dim3(64), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_backtrack<1, TRIM>), dim3(a.n_reads), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_backtrack<2, TRIM>), dim3(a.n_reads), dim3(64), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_backtrack<4, TRIM>), dim3(a.n_reads), dim3(64), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_backtrack<8, TRIM>), dim3(a.n_reads), dim3(64), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_backtrack<16, TRIM>), dim3(a.n_reads), dim3(64), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <int CPL, int RPG, bool EDGE>
+hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st) {
+  if (a.n_reads <= 0) return hipSuccess;
+  return a.trim ? launch_backtrack_t<true>(a, cpl, st) : launch_backtrack_t<false>(a, cpl, st);
+}
+
+template <int CPL, int RPG, bool EDGE, bool TRIM>
 static hipError_t launch_align_c(const AlignArgs &a, int wpg, hipStream_t st, hipEvent_t t0,
                                  hipEvent_t t1) {
   const dim3 grid((a.n_workers + wpg - 1) / wpg);
   switch (wpg) {
-    case 1: hipExtLaunchKernelGGL((k_align<CPL, RPG, 1, EDGE>), grid, dim3(64), 0, st, t0, t1, 0, a); break;
-    case 2: hipExtLaunchKernelGGL((k_align<CPL, RPG, 2, EDGE>), grid, dim3(128), 0, st, t0, t1, 0, a); break;
-    case 4: hipExtLaunchKernelGGL((k_align<CPL, RPG, 4, EDGE>), grid, dim3(256), 0, st, t0, t1, 0, a); break;
+    case 1: hipExtLaunchKernelGGL((k_align<CPL, RPG, 1, EDGE, TRIM>), grid, dim3(64), 0, st, t0, t1, 0, a); break;
+    case 2: hipExtLaunchKernelGGL((k_align<CPL, RPG, 2, EDGE, TRIM>), grid, dim3(128), 0, st, t0, t1, 0, a); break;
+    case 4: hipExtLaunchKernelGGL((k_align<CPL, RPG, 4, EDGE, TRIM>), grid, dim3(256), 0, st, t0, t1, 0, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1047,26 +1117,27 @@ hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, bool edge
                         hipEvent_t t0, hipEvent_t t1) {
   if (a.n_reads <= 0 || a.n_workers <= 0) return hipSuccess;
   if (a.n_workers > a.n_reads) return hipErrorInvalidValue;
-#define ABEA_L(C, R, E) return launch_align_c<C, R, E>(a, wpg, st, t0, t1)
+#define ABEA_L(C, R, E)                                                                                       \
+  return a.trim ? launch_align_c<C, R, E, true>(a, wpg, st, t0, t1) : launch_align_c<C, R, E, false>(a, wpg, st, t0, t1)
   ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
   return hipErrorInvalidValue;
 }
 
-template <int CPL, int RPG, bool EDGE>
+template <int CPL, int RPG, bool EDGE, bool TRIM>
 static int groups_per_cu_c(int wpg) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (wpg) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 1, EDGE>, 64, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 2, EDGE>, 128, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 4, EDGE>, 256, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 1, EDGE, TRIM>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 2, EDGE, TRIM>, 128, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_align<CPL, RPG, 4, EDGE, TRIM>, 256, 0); break;
   }
   return e == hipSuccess ? n : 0;
 }
 
-int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge) {
-#define ABEA_L(C, R, E) return groups_per_cu_c<C, R, E>(wpg)
+int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge, bool trim) {
+#define ABEA_L(C, R, E) return trim ? groups_per_cu_c<C, R, E, true>(wpg) : groups_per_cu_c<C, R, E, false>(wpg)
   ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
   return 0;

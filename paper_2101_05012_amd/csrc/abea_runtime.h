@@ -50,7 +50,7 @@ struct Work {
   Plan plan;
   std::vector<int> order;
   std::vector<uint64_t> comp; /* per caller read: computed bands (n_e + n_k - 1, 0 if empty) */
-  DevBuf reads, rstat, queue, xmean, kparam, trace, scratch, path_len, path_src;
+  DevBuf reads, rstat, queue, xmean, kparam, trace, scratch, path_len, path_src, tend;
   ReadDesc *h_reads = nullptr; /* pinned staging of the plan */
   size_t h_cap = 0;
   hipEvent_t staging_done = nullptr;

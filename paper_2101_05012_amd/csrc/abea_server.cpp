@@ -323,6 +323,7 @@ int slot_init(abea_server *S, Slot &s) {
   if ((rc = ensure(ctx, nullptr, w.scratch, sizeof(int2) * np))) return rc;
   if ((rc = ensure(ctx, nullptr, w.path_len, sizeof(uint64_t) * nr))) return rc;
   if ((rc = ensure(ctx, nullptr, w.path_src, sizeof(uint64_t) * nr))) return rc;
+  if ((rc = ensure(ctx, nullptr, w.tend, sizeof(int32_t) * nr))) return rc;
   if ((rc = host_alloc(ctx, &w.h_reads, nr))) return rc;
   w.h_cap = nr;
   return ABEA_OK;
