@@ -58,7 +58,7 @@ def test_create_rejects_bad_config_without_touching_the_gpu():
     ls0[3] = 0
     bad2 = abea.abea_model_t(2, lm.ctypes.data, ls0.ctypes.data)
     assert lib.abea_create(ctypes.byref(cfg), ctypes.byref(bad2), ctypes.byref(h)) == abea.ABEA_E_INVAL
-    for flags in (4, 8, 1 << 31):  # bits no ABEA_F_* defines
+    for flags in (8, 16, 1 << 31):  # bits no ABEA_F_* defines
         cfg_f = abea.abea_config_t(100, 0, 0, flags)
         assert lib.abea_create(ctypes.byref(cfg_f), ctypes.byref(mdl), ctypes.byref(h)) == abea.ABEA_E_INVAL
 
