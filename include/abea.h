@@ -43,6 +43,8 @@ extern "C" {
 #define ABEA_READ_EMPTY 1     /* the read has no events or no k-mers */
 #define ABEA_READ_BAND_LOST 2 /* terminal cell (n_e-1, n_k-1) outside the last band, or -inf */
 #define ABEA_READ_BAD_RANK 3  /* a k-mer rank >= 4^k */
+#define ABEA_READ_CANCELLED 4 /* serving: cancelled while queued (abea_server_cancel) */
+#define ABEA_READ_TIMED_OUT 5 /* serving: queued longer than max_queue_wait_ns */
 
 /* Failed reads (status != ABEA_READ_OK) get zero pairs and log_likelihood = -INFINITY. */
 
@@ -354,11 +356,15 @@ typedef struct {
   uint64_t trace_budget_bytes;/* traceback bytes of all reads on the device (0 = none) */
   uint64_t host_staging_bytes;/* pinned host arena for queued reads (0 = 1 GiB); reads beyond
                                  it are queued in pageable memory and staged at launch */
+  int64_t max_queue_wait_ns;  /* a read still queued this long after its arrival completes as
+                                 ABEA_READ_TIMED_OUT without running (0 = no limit); checked
+                                 by the background thread in queue order */
 } abea_server_config_t;
 
 /* One finished read.  Times are abea_server_now_ns() values: arrival (given
- * at submission), admission into a micro-batch, and the moment its results
- * were in host memory. */
+ * at submission), admission into a micro-batch (for a cancelled or timed-out
+ * read: when it left the queue), and the moment its results were in host
+ * memory. */
 typedef struct {
   uint64_t tag;
   int32_t status;         /* ABEA_READ_* */
@@ -387,6 +393,8 @@ typedef struct {
   uint64_t submit_ns, submit_copy_ns;
   /* reads that found the pinned arena full and took a pageable buffer */
   uint64_t pageable_reads;
+  /* reads that completed without running: cancelled, timed out in the queue */
+  uint64_t cancelled, timed_out;
 } abea_server_stats_t;
 
 typedef struct abea_server abea_server;
@@ -405,6 +413,14 @@ int abea_server_create(abea_ctx *ctx, const abea_server_config_t *cfg, abea_serv
  * or the background thread's sticky error. */
 int abea_server_submit(abea_server *server, const abea_batch_t *reads, const uint64_t *tags,
                        const int64_t *arrival_ns);
+
+/* Cancel queued reads: every read with one of the n tags that has not been
+ * admitted into a micro-batch yet leaves the queue and completes, through
+ * abea_server_poll, with status ABEA_READ_CANCELLED, no pairs and
+ * log_likelihood -INFINITY.  Reads already admitted run to the end.
+ * *n_cancelled (may be NULL) receives how many reads were cancelled.  Every
+ * submitted read still completes exactly once.  Errors: ABEA_E_INVAL. */
+int abea_server_cancel(abea_server *server, const uint64_t *tags, int n, int *n_cancelled);
 
 /* Collect up to max_out finished reads, waiting up to timeout_us for the
  * first; their pairs are copied into pairs[] (capacity pair_capacity), read

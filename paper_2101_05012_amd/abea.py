@@ -26,6 +26,7 @@ ABEA_E_CAPACITY = -4
 ABEA_E_UNSUPPORTED = -5
 
 READ_OK, READ_EMPTY, READ_BAND_LOST, READ_BAD_RANK = 0, 1, 2, 3
+READ_CANCELLED, READ_TIMED_OUT = 4, 5  # serving: completed without running
 ABEA_MAX_BANDWIDTH = 512
 ABEA_MAX_K = 12
 ABEA_F_TIMING = 1
@@ -57,6 +58,7 @@ EXPORTED = (
     "abea_server_now_ns",
     "abea_server_create",
     "abea_server_submit",
+    "abea_server_cancel",
     "abea_server_poll",
     "abea_server_stats",
     "abea_server_destroy",
@@ -150,6 +152,7 @@ class abea_server_config_t(ctypes.Structure):
         ("max_batch_kmers", ctypes.c_uint64),
         ("trace_budget_bytes", ctypes.c_uint64),
         ("host_staging_bytes", ctypes.c_uint64),
+        ("max_queue_wait_ns", ctypes.c_int64),
     ]
 
 
@@ -201,6 +204,8 @@ class abea_server_stats_t(ctypes.Structure):
         ("submit_ns", ctypes.c_uint64),
         ("submit_copy_ns", ctypes.c_uint64),
         ("pageable_reads", ctypes.c_uint64),
+        ("cancelled", ctypes.c_uint64),
+        ("timed_out", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -258,6 +263,8 @@ def lib() -> ctypes.CDLL:
         L.abea_server_create.restype = ctypes.c_int
         L.abea_server_submit.argtypes = [P, ctypes.POINTER(abea_batch_t), P, P]
         L.abea_server_submit.restype = ctypes.c_int
+        L.abea_server_cancel.argtypes = [P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.abea_server_cancel.restype = ctypes.c_int
         L.abea_server_poll.argtypes = [P, P, ctypes.c_int, P, ctypes.c_uint64, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int)]
         L.abea_server_poll.restype = ctypes.c_int
@@ -557,10 +564,10 @@ class Server:
 
     def __init__(self, aligner: Aligner, slots: int = 4, max_batch_reads: int = 1024,
                  max_batch_events: int = 1 << 24, max_batch_kmers: int = 1 << 23, trace_budget_bytes: int = 0,
-                 host_staging_bytes: int = 0):
+                 host_staging_bytes: int = 0, max_queue_wait_ns: int = 0):
         self.aligner = aligner
         cfg = abea_server_config_t(int(slots), int(max_batch_reads), int(max_batch_events), int(max_batch_kmers),
-                                   int(trace_budget_bytes), int(host_staging_bytes))
+                                   int(trace_budget_bytes), int(host_staging_bytes), int(max_queue_wait_ns))
         h = ctypes.c_void_p()
         aligner._check(lib().abea_server_create(aligner.handle, ctypes.byref(cfg), ctypes.byref(h)),
                        "abea_server_create")
@@ -585,6 +592,15 @@ class Server:
         b = abea_batch_t(hi - lo, _ptr(ev), _ptr(eor), _ptr(rk), _ptr(kor), _ptr(sc), _ptr(sh))
         self.aligner._check(lib().abea_server_submit(self.handle, ctypes.byref(b), _ptr(tg), _ptr(at)),
                             "abea_server_submit")
+
+    def cancel(self, tags) -> int:
+        """Cancel the queued reads with these tags (abea_server_cancel); returns
+        how many were still queued and are now cancelled."""
+        tg = np.ascontiguousarray(tags, np.uint64)
+        k = ctypes.c_int(0)
+        self.aligner._check(lib().abea_server_cancel(self.handle, _ptr(tg), int(tg.shape[0]), ctypes.byref(k)),
+                            "abea_server_cancel")
+        return k.value
 
     def poll(self, max_out: int = 4096, timeout_us: int = 1000, pair_capacity: int = 1 << 22, want_pairs: bool = True):
         """Finished reads: (completions structured array, pairs int32 [total, 2]

@@ -33,6 +33,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/abea.h"
@@ -168,7 +169,8 @@ struct SrvRead {
 };
 
 /* A finished read; its pairs wait in its slot's pinned result buffer, which
- * the slot keeps until every result of its micro-batch has been polled. */
+ * the slot keeps until every result of its micro-batch has been polled
+ * (slot -1: a read that completed without running, with no pairs). */
 struct Done {
   abea_completion_t c;
   int slot;
@@ -242,6 +244,50 @@ void release_read(abea_server *S, SrvRead &R) {
 
 void release_reads(abea_server *S, std::vector<SrvRead> &reads) {
   for (SrvRead &R : reads) release_read(S, R);
+}
+
+/* Complete a queued read without running it (cancelled, timed out), under
+ * the server lock: its buffer goes back to the pool, its completion has no
+ * pairs. */
+void complete_unrun(abea_server *S, SrvRead &R, int status, int64_t t) {
+  Done d;
+  d.c.tag = R.tag;
+  d.c.status = status;
+  d.c.log_likelihood = -__builtin_inff();
+  d.c.cells = 0;
+  d.c.n_pairs = 0;
+  d.c.pair_offset = 0;
+  d.c.t_arrival_ns = R.t_arrival;
+  d.c.t_admit_ns = t;
+  d.c.t_done_ns = t;
+  d.slot = -1;
+  d.off = 0;
+  release_read(S, R);
+  S->done.push_back(d);
+  S->n_pending -= 1;
+  S->stats.completed += 1;
+  if (status == ABEA_READ_CANCELLED) S->stats.cancelled += 1;
+  if (status == ABEA_READ_TIMED_OUT) S->stats.timed_out += 1;
+}
+
+/* Reads queued longer than max_queue_wait_ns complete as timed out; each
+ * class's queue is checked from its front (its oldest reads). */
+bool expire(abea_server *S) {
+  const int64_t limit = S->cfg.max_queue_wait_ns;
+  if (limit <= 0) return false;
+  bool any = false;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    const int64_t t = now_ns();
+    for (auto &P : S->pending)
+      while (!P.empty() && t - P.front().t_arrival > limit) {
+        complete_unrun(S, P.front(), ABEA_READ_TIMED_OUT, t);
+        P.pop_front();
+        any = true;
+      }
+  }
+  if (any) S->cv_done.notify_all();
+  return any;
 }
 
 void slot_free(abea_server *S, Slot &s) {
@@ -529,6 +575,7 @@ void worker_main(abea_server *S) {
     int rc = ABEA_OK;
     for (int si = 0; si < ns && !rc; ++si)
       if (slot_poll(S, si, &rc)) progress = true;
+    if (!rc && expire(S)) progress = true;
     if (!rc) {
       bool stopping;
       {
@@ -673,6 +720,40 @@ int abea_server_submit(abea_server *S, const abea_batch_t *b, const uint64_t *ta
   return ABEA_OK;
 }
 
+int abea_server_cancel(abea_server *S, const uint64_t *tags, int n, int *n_cancelled) {
+  if (!S) return ABEA_E_INVAL;
+  if (n_cancelled) *n_cancelled = 0;
+  if (n < 0 || (n > 0 && !tags)) return fail(S->ctx, ABEA_E_INVAL, "bad tags");
+  if (n == 0) return ABEA_OK;
+  int k = 0;
+  {
+    std::unordered_set<uint64_t> want;
+    try {
+      want.insert(tags, tags + n);
+    } catch (...) {
+      return fail(S->ctx, ABEA_E_NOMEM, "tag set");
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    const int64_t t = now_ns();
+    for (auto &P : S->pending) {
+      if (P.empty()) continue;
+      std::deque<SrvRead> keep;
+      for (SrvRead &R : P) {
+        if (want.count(R.tag)) {
+          complete_unrun(S, R, ABEA_READ_CANCELLED, t);
+          ++k;
+        } else {
+          keep.push_back(std::move(R));
+        }
+      }
+      P.swap(keep);
+    }
+  }
+  if (n_cancelled) *n_cancelled = k;
+  if (k) S->cv_done.notify_all();
+  return ABEA_OK;
+}
+
 int abea_server_poll(abea_server *S, abea_completion_t *out, int max_out, abea_pair_t *pairs, uint64_t pair_capacity,
                      int32_t timeout_us, int *n_out) {
   if (!S) return ABEA_E_INVAL;
@@ -708,7 +789,7 @@ int abea_server_poll(abea_server *S, abea_completion_t *out, int max_out, abea_p
   const int k = (int)taken.size();
   for (int i = 0; i < k; ++i) {
     const Done &d = taken[i];
-    if (pairs && d.c.n_pairs)
+    if (pairs && d.c.n_pairs && d.slot >= 0)
       std::memcpy(pairs + d.c.pair_offset, S->slots[d.slot].h_pairs + d.off, sizeof(abea_pair_t) * d.c.n_pairs);
     out[i] = d.c;
   }
@@ -716,7 +797,7 @@ int abea_server_poll(abea_server *S, abea_completion_t *out, int max_out, abea_p
   if (k) {
     std::lock_guard<std::mutex> lk(S->mu);
     for (const Done &d : taken)
-      if (--S->slots[d.slot].outstanding == 0) freed = true;
+      if (d.slot >= 0 && --S->slots[d.slot].outstanding == 0) freed = true;
   }
   *n_out = k;
   if (freed) S->cv_work.notify_one();

@@ -124,3 +124,84 @@ def test_oversize_read_is_refused(m6, reads):
     assert got == 1
     srv.close()
     al.close()
+
+
+def _collect(srv, n, timeout_s=60.0):
+    import time
+
+    got, pairs = [], {}
+    deadline = time.monotonic() + timeout_s
+    while sum(c.shape[0] for c in got) < n:
+        assert time.monotonic() < deadline, "serving: results missing"
+        c, p = srv.poll(timeout_us=5000)
+        if c.shape[0]:
+            got.append(c)
+            for rec in c:
+                pairs[int(rec["tag"])] = p[int(rec["pair_offset"]): int(rec["pair_offset"]) + int(rec["n_pairs"])]
+    c = np.concatenate(got)
+    return c[np.argsort(c["tag"])], pairs
+
+
+def _check_unrun(rec):
+    assert rec["n_pairs"] == 0 and rec["cells"] == 0
+    assert np.isneginf(rec["log_likelihood"])
+    assert rec["t_done_ns"] >= rec["t_admit_ns"] >= rec["t_arrival_ns"]
+
+
+def test_cancel_queued_reads(m6, reads, alone):
+    """120 reads submitted at once to one slot of four reads: cancelling the
+    odd tags right away cancels those still queued; they come back as
+    cancelled with no pairs, every other read as if aligned alone, each read
+    exactly once."""
+    al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100)
+    srv = abea.Server(al, slots=1, max_batch_reads=4)
+    n = 120
+    say("gpu: serving cancel")
+    srv.submit(reads, 0, n, np.arange(n, dtype=np.uint64))
+    k = srv.cancel(np.arange(1, n, 2, dtype=np.uint64))
+    c, pairs = _collect(srv, n)
+    assert np.array_equal(c["tag"], np.arange(n, dtype=np.uint64))
+    cancelled = c["status"] == abea.READ_CANCELLED
+    assert 0 < k == int(cancelled.sum())
+    assert np.all(c["tag"][cancelled] % 2 == 1)
+    for r in range(n):
+        if cancelled[r]:
+            _check_unrun(c[r])
+        else:
+            assert c[r]["status"] == alone[r].status[0]
+            assert np.float32(c[r]["log_likelihood"]).view(np.uint32) == alone[r].log_likelihood[0:1].view(np.uint32)[0]
+            assert np.array_equal(pairs[r], alone[r].read_pairs(0))
+    st = srv.stats()
+    assert st["cancelled"] == k and st["completed"] == n and st["pending"] == 0
+    # cancelling what is no longer queued cancels nothing
+    assert srv.cancel(np.arange(n, dtype=np.uint64)) == 0
+    srv.close()
+    al.close()
+
+
+def test_queue_timeout(m6, reads, alone):
+    """100 reads submitted at once to one slot of two reads with a 50 ms
+    queue limit (counted from the arrival stamp, which precedes the submit
+    call's own copying): the reads the slot cannot reach in time complete as
+    timed out, the others as if aligned alone, each read exactly once."""
+    limit = 50_000_000
+    al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100)
+    srv = abea.Server(al, slots=1, max_batch_reads=2, max_queue_wait_ns=limit)
+    n = 100
+    say("gpu: serving queue timeout")
+    srv.submit(reads, 0, n, np.arange(n, dtype=np.uint64))
+    c, pairs = _collect(srv, n)
+    assert np.array_equal(c["tag"], np.arange(n, dtype=np.uint64))
+    out = c["status"] == abea.READ_TIMED_OUT
+    assert out.sum() > 0 and (~out).sum() > 0
+    for r in range(n):
+        if out[r]:
+            _check_unrun(c[r])
+            assert c[r]["t_admit_ns"] - c[r]["t_arrival_ns"] >= limit
+        else:
+            assert np.float32(c[r]["log_likelihood"]).view(np.uint32) == alone[r].log_likelihood[0:1].view(np.uint32)[0]
+            assert np.array_equal(pairs[r], alone[r].read_pairs(0))
+    st = srv.stats()
+    assert st["timed_out"] == int(out.sum()) and st["completed"] == n and st["pending"] == 0
+    srv.close()
+    al.close()
