@@ -76,7 +76,8 @@ __device__ __forceinline__ void add_rot2(float l, float a, float d, float b, flo
       "v_add_f32_dpp %1, %4, %5 wave_ror:1 row_mask:0xf bank_mask:0xf"
       : "=&v"(lo), "=&v"(dout)
       : "v"(l), "v"(a), "v"(d), "v"(b));
-}__device__ __forceinline__ float rlane(float v, int lane) {
+}
+__device__ __forceinline__ float rlane(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 __device__ __forceinline__ uint32_t rlane_u(uint32_t v, int lane) {
@@ -319,7 +320,16 @@ __device__ __forceinline__ void edge_move(uint64_t (&m)[CPL], int mneg) {
  *   G   bands per trace word (32/CPL, even)
  *   RX  entries of the event ring: holds every event of the band window
  *       plus the next G, in quarters of 64, one quarter spare (W + G <= RX - 128)
- *   RK  entries of the k-mer ring: holds k-mers K .. K+N+G, same rule */
+ *   RK  entries of the k-mer ring: holds k-mers K .. K+N+G, same rule
+ *   S   sub-rings of the event ring: event e is in sub-ring e mod S.  At four
+ *       slots per lane a register's slots hold k-mers of one residue mod 4,
+ *       consecutive lanes k-mers 4 apart, so in a band the lanes of a
+ *       register read events 4 apart: from one sub-ring, consecutive words
+ *       (no LDS bank conflict), where a single ring would put them 4 words
+ *       apart.  At two slots per lane the 2-way conflict of a single ring
+ *       costs less than the sub-ring index arithmetic (measured on the
+ *       W = 100 workloads); at one, lanes already read consecutive events.
+ *   XS  floats of a sub-ring: RX/S entries and a mirror of its first G/S */
 template <int CPL>
 struct Geom {
   static constexpr int N = 64 * CPL;
@@ -327,17 +337,20 @@ struct Geom {
   static constexpr int G = 32 / CPL;
   static constexpr int RX = CPL == 1 ? 256 : (128 * CPL > 1024 ? 1024 : 128 * CPL);
   static constexpr int RK = CPL == 1 ? 256 : 128 * CPL;
+  static constexpr int S = CPL == 4 ? 4 : 1;
+  static constexpr int LS = Log2<S>::v;
+  static constexpr int XS = RX / S + G / S;
 };
 
-/* LDS of one wavefront: the band fill's event ring (with a mirror of its
- * first G entries behind the end, so that a run of G reads never wraps) and
- * k-mer ring, or the backtrack's trace-tile ring; the two phases of a read
- * never overlap. */
+/* LDS of one wavefront: the band fill's event ring (S sub-rings, each with a
+ * mirror of its first G/S entries behind its end, so that a run of G reads
+ * never wraps) and k-mer ring, or the backtrack's trace-tile ring; the two
+ * phases of a read never overlap. */
 template <int CPL>
 struct WaveLds {
   union {
     struct {
-      float lx[Geom<CPL>::RX + Geom<CPL>::G];
+      float lx[Geom<CPL>::S * Geom<CPL>::XS];
       float4 lk[Geom<CPL>::RK];
     } band;
     uint2 ring[BT_RING_GROUPS * 64];
@@ -376,6 +389,12 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   constexpr int G = Geom<CPL>::G;
   constexpr int RX = Geom<CPL>::RX;
   constexpr int RK = Geom<CPL>::RK;
+  constexpr int S = Geom<CPL>::S;
+  constexpr int LS = Geom<CPL>::LS;
+  constexpr int XS = Geom<CPL>::XS;
+  constexpr int RXS = RX / S;
+  static_assert(S == 1 || (G % S == 0 && (G / RPG) % S == 0),
+                "refills at band offsets that are multiples of S keep each register's sub-ring fixed");
   constexpr int RF = G / RPG; /* bands between slot refills (RPG refills per group) */
   static_assert(RF >= 2 && RF % 2 == 0, "refill interval must be an even band count");
 
@@ -385,8 +404,8 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
 
   const float lp_skip = rd.lp_skip, lp_stay = rd.lp_stay, lp_step = rd.lp_step;
   /* vector copies of the skip and step constants: the moves of a register's
-   * first slot add them to a rotated neighbour in one DPP add, whose second
-   * operand must be a vector register */
+   * first slot add them to a rotated neighbour, and only with a vector second
+   * operand can the rotation fold into the add (v_add_f32_dpp) */
   const float lp_skip_v = to_vgpr(lp_skip), lp_step_v = to_vgpr(lp_step);
   const float *__restrict__ xm = a.xmean + rd.ev_off;
   const float4 *__restrict__ kp = reinterpret_cast<const float4 *>(a.kparam + rd.km_off);
@@ -404,10 +423,13 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     if (k >= 0 && k < n_k) v = kp[k];
     return v;
   };
+  /* event e = 64q + lane: sub-ring e mod S (the lane's low bits), entry
+   * floor(e / S) mod RX/S */
   auto put_x = [&](int q, float v) {
-    const int idx = (q * 64 + lane) & (RX - 1);
-    lx[idx] = v;
-    if (idx < G) lx[RX + idx] = v;
+    float *sub = lx + (lane & (S - 1)) * XS;
+    const int idx = ((q * 64 + lane) >> LS) & (RXS - 1);
+    sub[idx] = v;
+    if (idx < G / S) sub[RXS + idx] = v;
   };
   auto put_k = [&](int q, float4 v) { lk[(q * 64 + lane) & (RK - 1)] = v; };
 
@@ -464,9 +486,9 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     xb[c] = 0;
   }
 
-  /* Rings: event e at lx[e mod RX], k-mer k at lk[k mod RK], written a
-   * quarter (64 entries) at a time; the quarter after the top one waits in
-   * registers. */
+  /* Rings: event e in sub-ring e mod S at entry (e / S) mod (RX / S), k-mer
+   * k at lk[k mod RK], written a quarter (64 entries) at a time; the quarter
+   * after the top one waits in registers. */
   int xtop = (E + G) >> 6;
   int ktop = (K + N + G - 1) >> 6;
   for (int q = (E - W + 1) >> 6; q <= xtop; ++q) put_x(q, ldx(q * 64 + lane));
@@ -501,7 +523,10 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
       PM[c] = p.x;
       PC[c] = p.y;
       PH[c] = p.z;
-      xb[c] = ((i - 2 - kv) & (RX - 1)) - b;
+      /* the slot's event at this refill band i: e = i - 2 - kv, with e
+       * mod S = (S - c) mod S for every lane (kv = c mod S, i = 2 mod S);
+       * its sub-ring entry less the band offset (b is a multiple of S) */
+      xb[c] = (((i - 2 - kv) >> LS) & (RXS - 1)) - (b >> LS);
     }
   };
 
@@ -513,8 +538,13 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
    * i-1.  INTERIOR: all W cells of band i are inside the DP table. */
   /* the events of the slots for band b (of the current refill interval) */
   auto load_x = [&](float(&x)[CPL], int b) {
+    /* event e_ref + (b - b_ref) of slot register c: sub-ring (r0 + b) mod S,
+     * entry xb[c] + (r0 + b) / S, with r0 = e_ref mod S = (S - c) mod S */
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) x[c] = lx[xb[c] + b];
+    for (int c = 0; c < CPL; ++c) {
+      const int r0 = (S - (c & (S - 1))) & (S - 1);
+      x[c] = lx[((r0 + b) & (S - 1)) * XS + xb[c] + ((r0 + b) >> LS)];
+    }
   };
 
   auto band = [&](auto interior_tag, float(&Spp)[CPL], const float(&Sp)[CPL], int i, int b,
