@@ -840,6 +840,21 @@ __device__ __forceinline__ int trace_bit(int t, int k) {
   return b;
 }
 
+/* The walk's move from its cell (t = e + k, k), whose trace bits sit at bit
+ * `bit` of the lane's words: t falls by 1, and by 2 on a diagonal (D bit);
+ * k falls unless the move is up (D bit, or no U bit: the word wk = D | ~U).
+ * Each bit goes straight into SCC (s_bitcmp1) and one subtract with borrow
+ * applies it: four SALU instructions. */
+__device__ __forceinline__ void walk_move(int &t, int &k, uint32_t wd, uint32_t wk, int bit) {
+  asm("s_bitcmp1_b32 %2, %4\n\t"
+      "s_subb_u32 %0, %0, 1\n\t"
+      "s_bitcmp1_b32 %3, %4\n\t"
+      "s_subb_u32 %1, %1, 0"
+      : "+s"(t), "+s"(k)
+      : "s"(wd), "s"(wk), "s"(bit)
+      : "scc");
+}
+
 /* Backtrack of one read (Alg. 5.1, after the band loop) by the calling
  * wavefront, from its trace tiles: writes the path's pairs backwards into
  * the read's scratch slots, its length and first slot, and its final status
@@ -892,16 +907,16 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
   uint2 T = ring[(gcur & (RG - 1)) * 64 + lane];
   uint2 Tn = ring[((gcur - 1) & (RG - 1)) * 64 + lane];
 
-  int PE = 0, PK = 0;
-  uint64_t q = 0;  /* cells stored */
-  uint32_t qn = 0; /* cells gathered in lanes 0 .. qn-1, not stored yet */
+  int PT = 0, PK = 0; /* gathered cells as t = e + k and k */
+  uint64_t q = 0;      /* cells stored */
+  uint32_t qn = 0;     /* cells gathered in lanes 0 .. qn-1, not stored yet */
   const uint64_t res_end = rd.pr_off + (uint64_t)(n_e + n_k - 1);
   int2 *__restrict__ out = a.scratch;
   bool ok = true;
   /* store the gathered cells in one coalesced store: lane l holds cell q + l
    * counted from the end of the read's slots */
   auto flush = [&]() {
-    if (lane < (int)qn) out[res_end - 1 - (q + lane)] = make_int2(PE, PK);
+    if (lane < (int)qn) out[res_end - 1 - (q + lane)] = make_int2(PT - PK, PK);
     q += qn;
     qn = 0;
   };
@@ -915,26 +930,21 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
     const int lower = gcur << LG;
     int t = e + k;
     int klo = 0x7fffffff; /* first k-mer of the loaded lane (none yet) */
-    uint64_t wxy = 0;     /* the lane's D-bit word (low half) and U-bit word (high half) */
+    uint32_t wd = 0, wk = 0; /* the lane's D-bit word, and its D | ~U word */
     for (;;) {
-      e = __builtin_amdgcn_readfirstlane(e);
+      t = __builtin_amdgcn_readfirstlane(t);
       k = __builtin_amdgcn_readfirstlane(k);
-      PE = writelane(e, (int)qn, PE);
+      PT = writelane(t, (int)qn, PT);
       PK = writelane(k, (int)qn, PK);
       ++qn;
       if (k < klo) {
         const int ln = (k & (N - 1)) >> LC;
-        wxy = (uint64_t)rlane_u(T.x, ln) | ((uint64_t)rlane_u(T.y, ln) << 32);
+        wd = rlane_u(T.x, ln);
+        wk = wd | ~rlane_u(T.y, ln);
         klo = k & ~(CPL - 1);
       }
-      const int bit = trace_bit<CPL>(t, k);
-      const uint64_t b2 = wxy >> bit; /* D bit at 0, U bit at 32 */
-      const uint32_t db = (uint32_t)b2 & 1u;
-      const uint32_t ub = (uint32_t)(b2 >> 32) & 1u;
       /* diagonal (1,x): e-1, k-1; up (0,1): e-1; left (0,0): k-1 */
-      e -= (int)(db | ub);
-      k -= (int)((db | ~ub) & 1u);
-      t = e + k;
+      walk_move(t, k, wd, wk, trace_bit<CPL>(t, k));
       /* stop when the walk left the group (t falls by 1 or 2 per step, so
        * this also ends a walk that leaves the table; the caller checks that
        * it ended at the origin), or with TRIM entered the trim column */
@@ -943,6 +953,7 @@ __device__ __forceinline__ void backtrack_read(const AlignArgs &a, const ReadDes
         if (k < 0) break;
       }
     }
+    e = t - k;
     if ((e | k) < 0) break;
     const int gi = t >> LG;
     if (gi != gcur) { /* the walk moved down by one group */

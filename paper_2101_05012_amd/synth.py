@@ -56,7 +56,8 @@ WORKLOADS = {
     "uneven-20000": dict(seed_index=2, n_reads=20000, W=100, k=6, lengths="mixed"),
     "serving-lognormal8kb": dict(seed_index=3, n_reads=None, W=100, k=6, lengths="lognormal8k"),
     "ultralong-200": dict(seed_index=4, n_reads=200, W=100, k=6, lengths="ultralong"),
-    # config-1 lengths with open-pore and adaptor events at the read ends
+    # the 4000-read log-normal lengths with open-pore and adaptor events at
+    # the read ends
     "plain-4000-lognormal5kb-ends": dict(seed_index=5, n_reads=4000, W=100, k=6, lengths="lognormal5k",
                                          ends=True),
 }
