@@ -102,10 +102,10 @@ WORKLOADS = {
 SERVING_LEVELS = [(1, 300), (10, 1000), (100, 4000), (1000, 20000), (3000, 30000), (10000, 30000)]
 
 # HBM bytes of one fused-kernel launch (k_align), from two rocprofv3 --pmc
-# runs (FETCH_SIZE x 1.99990, WRITE_SIZE x 1.0: the factors a 1 GiB device
+# runs (FETCH_SIZE x 1.99989, WRITE_SIZE x 1.0: the factors a 1 GiB device
 # copy needs to read its known size), by workload; a workload without a
 # measurement of the current kernel reports null.
-ALIGN_TRAFFIC_BYTES = {"uneven-20000-w100": 148.91e9}
+ALIGN_TRAFFIC_BYTES = {"uneven-20000-w100": 148.94e9}
 
 
 def log(*a):

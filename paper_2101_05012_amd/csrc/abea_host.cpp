@@ -174,7 +174,7 @@ bool split_kernels(const abea_ctx *ctx) { return ctx->launch.workers == ABEA_WOR
 /* Wavefronts of the fused kernel that are resident at once on the device. */
 int resident_workers(abea_ctx *ctx, bool edge) {
   const int gpc = align_groups_per_cu(ctx->cpl, refills_per_group(ctx->W, ctx->cpl), ctx->launch.waves_per_group,
-                                      edge, (ctx->flags & ABEA_F_TRIM) != 0);
+                                      edge, (ctx->flags & ABEA_F_TRIM) != 0, ctx->W);
   return std::max(1, gpc * ctx->num_cus * ctx->launch.waves_per_group);
 }
 

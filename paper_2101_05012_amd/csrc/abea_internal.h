@@ -119,8 +119,8 @@ hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st);
 /* fused band + backtrack with a.n_workers wavefronts, wpg per workgroup */
 hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, bool edge, hipStream_t st,
                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-/* resident workgroups of the fused kernel per CU (occupancy) */
-int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge, bool trim);
+/* resident workgroups of the fused kernel per CU (occupancy) for band width W */
+int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge, bool trim, int W);
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st);
 
 /* Fixed scratch of the no-allocation entry point (abea_kernels.hip). */

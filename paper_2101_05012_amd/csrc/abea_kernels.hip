@@ -225,10 +225,9 @@ __device__ __forceinline__ uint64_t sk_move_mask(int lo, int hi, float nfm) {
 /* The same decision with the last end cell left in its register: one compare
  * of lo against every lane's value of that register (raised to -FLT_MAX for
  * odd bands), whose bit for the end cell's lane is the answer.  No readlane
- * and no move of the last end cell into a VGPR; two scalar instructions read
- * the bit. */
+ * and no move of the last end cell into a VGPR. */
 template <bool ODD>
-__device__ __forceinline__ uint64_t sk_move_mask_lane(int lo, float hv, int hl, float nfm) {
+__device__ __forceinline__ uint64_t sk_cmp_lane(int lo, float hv, float nfm) {
   float tv;
   uint64_t cm;
   if (ODD)
@@ -239,7 +238,27 @@ __device__ __forceinline__ uint64_t sk_move_mask_lane(int lo, float hv, int hl, 
         : [lo] "s"(lo), [h] "v"(hv), [nfm] "v"(nfm));
   else
     asm volatile("v_cmp_lt_f32_e64 %[cm], %[lo], %[h]" : [cm] "=s"(cm) : [lo] "s"(lo), [h] "v"(hv));
-  return ((cm >> (hl & 63)) & 1ull) ? ~0ull : 0ull;
+  return cm;
+}
+
+/* The band move at two slots per lane with edge masks, from the lane
+ * compare's mask cm: its bit hl (the last end cell's lane) goes straight into
+ * SCC, and SCC moves the two edge masks one slot up, makes the move's wave
+ * mask and adds the move to K (the shifted copy n0 of the top mask does not
+ * depend on the move).  Returns the wave mask: all ones on a k-mer move. */
+__device__ __forceinline__ uint64_t sk_move_edges2(uint64_t cm, int hl, uint64_t (&m)[2], int &K) {
+  const uint64_t top = m[1];
+  const uint64_t n0 = (top << 1) | (top >> 63); /* the top register, one slot higher */
+  uint64_t mv;
+  asm("s_bitcmp1_b64 %[cm], %[hl]\n\t"
+      "s_cselect_b64 %[m1], %[m0], %[m1]\n\t"
+      "s_cselect_b64 %[m0], %[n0], %[m0]\n\t"
+      "s_cselect_b64 %[mv], -1, 0\n\t"
+      "s_addc_u32 %[K], %[K], 0"
+      : [m0] "+&s"(m[0]), [m1] "+&s"(m[1]), [mv] "=&s"(mv), [K] "+&s"(K)
+      : [cm] "s"(cm), [hl] "s"(hl), [n0] "s"(n0)
+      : "scc");
+  return mv;
 }
 
 /* The register of slot (.. % CPL == r) of every lane, as one VGPR. */
@@ -381,9 +400,15 @@ struct WaveLds {
  * and what those slots hold (scores of k-mers outside the band, or NaN from
  * stale ring entries) never reaches the band, its end cells or the trace bits
  * of its cells. */
-template <int CPL, int RPG, bool CLEAR_EDGES, bool TRIM>
+template <int CPL, int RPG, int CLEAR, bool TRIM>
 __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd, uint2 *trace,
                                          float *__restrict__ lx, float4 *__restrict__ lk, int &e_end) {
+  /* CLEAR: slot clearing of interior bands, 0 the window, 1 the two edge
+   * slots, 2 the two edge slots with W even at two slots per lane (then the
+   * band's first and last slots always lie in different registers) */
+  constexpr bool CLEAR_EDGES = CLEAR != 0;
+  constexpr bool W_EVEN = CLEAR == 2;
+  static_assert(!W_EVEN || CPL == 2, "the even-W form is for two slots per lane");
   constexpr int N = Geom<CPL>::N;
   constexpr int LC = Geom<CPL>::LC;
   constexpr int G = Geom<CPL>::G;
@@ -472,7 +497,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   /* at two slots per lane: all ones when the first (last) slot of the latest
    * band is odd, i.e. in register 1 */
   uint64_t plo = (K & 1) ? ~0ull : 0ull;
-  uint64_t phi = ((K + W - 1) & 1) ? ~0ull : 0ull;
+  uint64_t phi = ((K + W - 1) & 1) ? ~0ull : 0ull; /* ~plo when W is even */
   float Spp[CPL], Sp[CPL], PM[CPL], PC[CPL], PH[CPL];
   int kvs[CPL]; /* kv(slot), the k-mer the slot holds */
   int xb[CPL]; /* ring index of the slot's event at band b = 0 of the group */
@@ -559,17 +584,20 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
      * in band i. */
     const int lo = lo_c, hi = hi_c;
     uint64_t mv;
-    if constexpr (LANE_MOVE)
-      mv = (b & 1) ? sk_move_mask_lane<true>(lo, hv, hl, NFM) : sk_move_mask_lane<false>(lo, hv, hl, NFM);
-    else
+    if constexpr (LANE_MOVE) {
+      static_assert(EDGE_MASKS && CPL == 2, "the lane-compare move keeps two-slot edge masks");
+      const uint64_t cm = (b & 1) ? sk_cmp_lane<true>(lo, hv, NFM) : sk_cmp_lane<false>(lo, hv, NFM);
+      mv = sk_move_edges2(cm, __builtin_amdgcn_readfirstlane(hl), edge, K);
+    } else {
       mv = (b & 1) ? sk_move_mask<true>(lo, hi, NFM) : sk_move_mask<false>(lo, hi, NFM);
-    const int mneg = __builtin_amdgcn_readfirstlane((int)(uint32_t)mv);
-    K -= mneg;
-    if constexpr (EDGE_MASKS) edge_move<CPL>(edge, mneg);
+      const int mneg = __builtin_amdgcn_readfirstlane((int)(uint32_t)mv);
+      K -= mneg;
+      if constexpr (EDGE_MASKS) edge_move<CPL>(edge, mneg);
+    }
     if constexpr (CPL == 2) {
       /* a k-mer move changes the parity of both end slots */
       plo ^= mv;
-      phi ^= mv;
+      if constexpr (!W_EVEN) phi ^= mv;
     }
 
     /* cells of band i inside the band and the table: k-mers kv with
@@ -653,7 +681,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
          * the SALU */
         lo_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], plo)), sf >> LC);
         if constexpr (LANE_MOVE) {
-          hv = sel(src[0], src[1], phi);
+          hv = W_EVEN ? sel(src[1], src[0], plo) : sel(src[0], src[1], phi);
           hl = sh >> LC;
         } else {
           hi_c = __builtin_amdgcn_readlane(__float_as_int(sel(src[0], src[1], phi)), sh >> LC);
@@ -791,7 +819,7 @@ __device__ __forceinline__ void band_skipped(const AlignArgs &a, const ReadDesc 
 }
 
 /* Band fill alone, one wavefront per planned read. */
-template <int CPL, int RPG, bool EDGE, bool TRIM>
+template <int CPL, int RPG, int EDGE, bool TRIM>
 __global__ __launch_bounds__(64) void k_band(const AlignArgs a) {
   __shared__ WaveLds<CPL> lds;
   const int s = blockIdx.x;
@@ -998,7 +1026,7 @@ __global__ __launch_bounds__(64) void k_backtrack(const AlignArgs a) {
  * keeps read w's trace region for all its reads.  n_workers = n_reads is the
  * plain one-launch form; fewer workers bound the trace memory (admission by
  * traceback bytes) and let the longest reads of the batch overlap the rest. */
-template <int CPL, int RPG, int WPG, bool EDGE, bool TRIM>
+template <int CPL, int RPG, int WPG, int EDGE, bool TRIM>
 __global__ __launch_bounds__(64 * WPG) void k_align(const AlignArgs a) {
   __shared__ WaveLds<CPL> lds[WPG];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1092,24 +1120,29 @@ hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events
 }
 
 /* Kernel variant for (cells per lane, refills per group, edge clearing). */
-#define ABEA_VARIANTS(CALL)                                  \
-  if (cpl == 1 && rpg == 1 && !edge) CALL(1, 1, false);      \
-  if (cpl == 1 && rpg == 2 && !edge) CALL(1, 2, false);      \
-  if (cpl == 2 && rpg == 1 && !edge) CALL(2, 1, false);      \
-  if (cpl == 2 && rpg == 2 && !edge) CALL(2, 2, false);      \
-  if (cpl == 2 && rpg == 1 && edge) CALL(2, 1, true);        \
-  if (cpl == 2 && rpg == 2 && edge) CALL(2, 2, true);        \
-  if (cpl == 4 && rpg == 1 && !edge) CALL(4, 1, false);      \
-  if (cpl == 4 && rpg == 2 && !edge) CALL(4, 2, false);      \
-  if (cpl == 4 && rpg == 1 && edge) CALL(4, 1, true);        \
-  if (cpl == 4 && rpg == 2 && edge) CALL(4, 2, true);        \
-  if (cpl == 8 && rpg == 1 && !edge) CALL(8, 1, false);      \
-  if (cpl == 8 && rpg == 2 && !edge) CALL(8, 2, false);      \
-  if (cpl == 16 && rpg == 1 && !edge) CALL(16, 1, false);
+/* the third argument is the clearing form (band_read's CLEAR); w_odd is the
+ * parity of W */
+#define ABEA_VARIANTS(CALL)                                          \
+  if (cpl == 1 && rpg == 1 && !edge) CALL(1, 1, 0);                  \
+  if (cpl == 1 && rpg == 2 && !edge) CALL(1, 2, 0);                  \
+  if (cpl == 2 && rpg == 1 && !edge) CALL(2, 1, 0);                  \
+  if (cpl == 2 && rpg == 2 && !edge) CALL(2, 2, 0);                  \
+  if (cpl == 2 && rpg == 1 && edge && w_odd) CALL(2, 1, 1);          \
+  if (cpl == 2 && rpg == 2 && edge && w_odd) CALL(2, 2, 1);          \
+  if (cpl == 2 && rpg == 1 && edge && !w_odd) CALL(2, 1, 2);         \
+  if (cpl == 2 && rpg == 2 && edge && !w_odd) CALL(2, 2, 2);         \
+  if (cpl == 4 && rpg == 1 && !edge) CALL(4, 1, 0);                  \
+  if (cpl == 4 && rpg == 2 && !edge) CALL(4, 2, 0);                  \
+  if (cpl == 4 && rpg == 1 && edge) CALL(4, 1, 1);                   \
+  if (cpl == 4 && rpg == 2 && edge) CALL(4, 2, 1);                   \
+  if (cpl == 8 && rpg == 1 && !edge) CALL(8, 1, 0);                  \
+  if (cpl == 8 && rpg == 2 && !edge) CALL(8, 2, 0);                  \
+  if (cpl == 16 && rpg == 1 && !edge) CALL(16, 1, 0);
 
 hipError_t launch_band(const AlignArgs &a, int cpl, int rpg, bool edge, hipStream_t st, hipEvent_t t0,
                        hipEvent_t t1) {
   if (a.n_reads <= 0) return hipSuccess;
+  const bool w_odd = (a.W & 1) != 0;
 #define ABEA_L(C, R, E)                                                                                 \
   {                                                                                                     \
     if (a.trim)                                                                                         \
@@ -1141,7 +1174,7 @@ hipError_t launch_backtrack(const AlignArgs &a, int cpl, hipStream_t st) {
   return a.trim ? launch_backtrack_t<true>(a, cpl, st) : launch_backtrack_t<false>(a, cpl, st);
 }
 
-template <int CPL, int RPG, bool EDGE, bool TRIM>
+template <int CPL, int RPG, int EDGE, bool TRIM>
 static hipError_t launch_align_c(const AlignArgs &a, int wpg, hipStream_t st, hipEvent_t t0,
                                  hipEvent_t t1) {
   const dim3 grid((a.n_workers + wpg - 1) / wpg);
@@ -1158,6 +1191,7 @@ hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, bool edge
                         hipEvent_t t0, hipEvent_t t1) {
   if (a.n_reads <= 0 || a.n_workers <= 0) return hipSuccess;
   if (a.n_workers > a.n_reads) return hipErrorInvalidValue;
+  const bool w_odd = (a.W & 1) != 0;
 #define ABEA_L(C, R, E)                                                                                       \
   return a.trim ? launch_align_c<C, R, E, true>(a, wpg, st, t0, t1) : launch_align_c<C, R, E, false>(a, wpg, st, t0, t1)
   ABEA_VARIANTS(ABEA_L)
@@ -1165,7 +1199,7 @@ hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, bool edge
   return hipErrorInvalidValue;
 }
 
-template <int CPL, int RPG, bool EDGE, bool TRIM>
+template <int CPL, int RPG, int EDGE, bool TRIM>
 static int groups_per_cu_c(int wpg) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
@@ -1177,7 +1211,8 @@ static int groups_per_cu_c(int wpg) {
   return e == hipSuccess ? n : 0;
 }
 
-int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge, bool trim) {
+int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge, bool trim, int W) {
+  const bool w_odd = (W & 1) != 0;
 #define ABEA_L(C, R, E) return trim ? groups_per_cu_c<C, R, E, true>(wpg) : groups_per_cu_c<C, R, E, false>(wpg)
   ABEA_VARIANTS(ABEA_L)
 #undef ABEA_L
