@@ -238,6 +238,12 @@ int oracle_align(const float *event_mean, int64_t event_stride, int64_t n_e,
       T[i * W + j] = d;
     }
     if (trim) trim_cell(S, T, E, K, i, n_e, W, lp_trim);
+    /* a band wholly inside the table: are its end cells, which place the
+     * next band, finite? (both -inf is the case the move rule alternates) */
+    if (K[i] >= 0 && K[i] + W - 1 <= n_k - 1 && E[i] <= n_e - 1 && E[i] - (W - 1) >= 0) {
+      st.in_table_bands++;
+      if (S[i * W] == NEG_INF || S[i * W + W - 1] == NEG_INF) st.in_table_inf_ends++;
+    }
   }
 
   int status = ORACLE_READ_OK;

@@ -69,6 +69,8 @@ typedef struct {
   int64_t path_len;    /* number of (event, k-mer) pairs */
   double min_margin;   /* smallest decision margin (band moves and path cells) */
   double min_move_margin; /* smallest band-move margin alone */
+  int64_t in_table_bands;    /* bands (2..n_e+n_k) whose W cells all lie in the table */
+  int64_t in_table_inf_ends; /* of those, bands with an end cell (offset 0 or W-1) at -inf */
 } oracle_stats_t;
 
 /* Transition log-probabilities of Alg. 5.2: out = {lp_skip, lp_stay, lp_step},

@@ -53,6 +53,8 @@ class _Stats(ctypes.Structure):
         ("path_len", ctypes.c_int64),
         ("min_margin", ctypes.c_double),
         ("min_move_margin", ctypes.c_double),
+        ("in_table_bands", ctypes.c_int64),
+        ("in_table_inf_ends", ctypes.c_int64),
     ]
 
 
@@ -125,6 +127,8 @@ class Result:
     min_move_margin: float
     trace: Optional[np.ndarray] = None  # uint8 [n_bands, W]
     ll: Optional[np.ndarray] = None  # int64 [n_bands, 2]
+    in_table_bands: int = 0  # bands whose W cells all lie in the table
+    in_table_inf_ends: int = 0  # of those, bands with an end cell at -inf
 
 
 class Model:
@@ -173,7 +177,7 @@ def align(
         raise RuntimeError(f"oracle_align error {s}")
     return Result(
         s, score[0], pairs[: st.path_len].copy(), st.cells, st.n_bands, st.kmer_moves,
-        st.min_margin, st.min_move_margin, trace, ll,
+        st.min_margin, st.min_move_margin, trace, ll, st.in_table_bands, st.in_table_inf_ends,
     )
 
 
