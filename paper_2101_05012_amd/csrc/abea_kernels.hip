@@ -108,6 +108,13 @@ __device__ __forceinline__ uint32_t shift_in(uint32_t acc, uint64_t mask) {
   asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=s"(co) : "v"(acc), "s"(mask));
   return r;
 }
+/* per lane: the bit of `mask`, the first bit of a new accumulator (one
+ * v_cndmask, where a shift-in would need a zeroed register) */
+__device__ __forceinline__ uint32_t first_bit(uint64_t mask) {
+  uint32_t r;
+  asm("v_cndmask_b32_e64 %0, 0, 1, %1" : "=v"(r) : "s"(mask));
+  return r;
+}
 __device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 /* lane `lane` of the result is `val` (uniform), the others keep `old`
  * (v_writelane; the compiler places the lane index in M0) */
@@ -572,8 +579,11 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     }
   };
 
+  /* fresh: the band opens a trace word (its first register's bits start the
+   * words TD and TU; a full group's G*CPL bits fill them, so nothing carries
+   * from one group to the next) */
   auto band = [&](auto interior_tag, float(&Spp)[CPL], const float(&Sp)[CPL], int i, int b,
-                  const float(&X)[CPL]) {
+                  const float(&X)[CPL], bool fresh) {
     constexpr bool INTERIOR = decltype(interior_tag)::value;
     constexpr bool EDGE = INTERIOR && EDGE_MASKS;
     /* the band position is wave-uniform: keep it in SGPRs */
@@ -586,7 +596,11 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     uint64_t mv;
     if constexpr (LANE_MOVE) {
       static_assert(EDGE_MASKS && CPL == 2, "the lane-compare move keeps two-slot edge masks");
-      const uint64_t cm = (b & 1) ? sk_cmp_lane<true>(lo, hv, NFM) : sk_cmp_lane<false>(lo, hv, NFM);
+      /* the previous band of an interior band lies wholly inside the table,
+       * so both its end cells are finite (each of its cells has its up or
+       * left neighbour in the band before): the alternation for two -inf
+       * end cells never applies, and odd bands compare as even ones */
+      const uint64_t cm = ((b & 1) && !INTERIOR) ? sk_cmp_lane<true>(lo, hv, NFM) : sk_cmp_lane<false>(lo, hv, NFM);
       mv = sk_move_edges2(cm, __builtin_amdgcn_readfirstlane(hl), edge, K);
     } else {
       mv = (b & 1) ? sk_move_mask<true>(lo, hi, NFM) : sk_move_mask<false>(lo, hi, NFM);
@@ -665,8 +679,13 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
         }
       }
       /* trace planes: the D bit, and the U bit (read only when D is clear) */
-      TD = shift_in(TD, md);
-      TU = shift_in(TU, mu);
+      if (fresh && c == 0) {
+        TD = first_bit(md);
+        TU = first_bit(mu);
+      } else {
+        TD = shift_in(TD, md);
+        TU = shift_in(TU, mu);
+      }
     }
     /* the end cells of this band for the next band's move.  Both lie in the
      * band; inside the table they are never masked, so they are read from
@@ -728,8 +747,8 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
         load_x(xn[1], b + 3);
       }
       __builtin_amdgcn_sched_barrier(0);
-      band(interior_tag, Spp, Sp, i + b, b, xa[0]);
-      band(interior_tag, Sp, Spp, i + b + 1, b + 1, xa[1]);
+      band(interior_tag, Spp, Sp, i + b, b, xa[0], b == 0);
+      band(interior_tag, Sp, Spp, i + b + 1, b + 1, xa[1], false);
       if (b + 2 < G) {
         if ((b + 2) % RF == 0) {
           refill(i + b + 2, b + 2);
@@ -775,14 +794,16 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     E = i - 3 - K;
     advance_rings();
     const int gb = last - i + 1;
+    TD = 0;
+    TU = 0;
     for (int b = 0;; b += 2) {
       if (b % RF == 0) refill(i + b, b);
       float x0[CPL], x1[CPL];
       load_x(x0, b);
       load_x(x1, b + 1);
-      band(std::false_type(), Spp, Sp, i + b, b, x0);
+      band(std::false_type(), Spp, Sp, i + b, b, x0, false);
       if (i + b + 1 > last) break;
-      band(std::false_type(), Sp, Spp, i + b + 1, b + 1, x1);
+      band(std::false_type(), Sp, Spp, i + b + 1, b + 1, x1, false);
       if (i + b + 2 > last) break;
     }
     i = last + 1;
