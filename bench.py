@@ -105,7 +105,7 @@ SERVING_LEVELS = [(1, 300), (10, 1000), (100, 4000), (1000, 20000), (3000, 30000
 # runs (FETCH_SIZE x 1.99989, WRITE_SIZE x 1.0: the factors a 1 GiB device
 # copy needs to read its known size), by workload; a workload without a
 # measurement of the current kernel reports null.
-ALIGN_TRAFFIC_BYTES = {"uneven-20000-w100": 148.94e9, "plain-4000-lognormal5kb": 6.735e9}
+ALIGN_TRAFFIC_BYTES = {}
 
 
 def log(*a):

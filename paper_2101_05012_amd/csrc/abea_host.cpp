@@ -312,14 +312,16 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
   return ABEA_OK;
 }
 
-int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st) {
+int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st, bool staged_events) {
   const Plan &P = w.plan;
   const size_t n = (size_t)std::max(P.n, 1);
   int rc;
   if ((rc = ensure(ctx, &w, w.reads, sizeof(ReadDesc) * n, st))) return rc;
   if ((rc = ensure(ctx, &w, w.rstat, sizeof(int32_t) * n, st))) return rc;
   if ((rc = ensure(ctx, &w, w.queue, sizeof(uint32_t), st))) return rc;
-  if ((rc = ensure(ctx, &w, w.xmean, sizeof(float) * (size_t)P.n_events, st))) return rc;
+  if ((staged_events || (ctx->flags & ABEA_F_SCALE_EVENTS)) &&
+      (rc = ensure(ctx, &w, w.xmean, sizeof(float) * (size_t)P.n_events, st)))
+    return rc;
   if ((rc = ensure(ctx, &w, w.kparam, sizeof(KParam) * (size_t)P.n_kmers, st))) return rc;
   if ((rc = ensure(ctx, &w, w.trace, sizeof(uint2) * (size_t)P.n_trace, st))) return rc;
   if ((rc = ensure(ctx, &w, w.scratch, sizeof(int2) * (size_t)P.n_scratch, st))) return rc;
@@ -336,15 +338,21 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   const ReadDesc *reads = (const ReadDesc *)w.reads.p;
   int32_t *rstat = (int32_t *)w.rstat.p;
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[0], st));
+  /* inputs at per-read addresses (serving: mapped host memory), and events
+   * scaled to the model, are staged by k_prep; otherwise the band fill reads
+   * the means in place from the device batch's event records */
+  const bool scale_events = (ctx->flags & ABEA_F_SCALE_EVENTS) != 0;
+  const bool staged = io.in_addr != nullptr || scale_events;
   HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ev_stride, io.ranks, io.in_addr, io.scale, io.shift,
-                           (const ModelEntry *)ctx->model.p, ctx->n_model,
-                           (ctx->flags & ABEA_F_SCALE_EVENTS) != 0, (float *)w.xmean.p,
-                           (KParam *)w.kparam.p, rstat, (uint32_t *)w.queue.p, st));
+                           (const ModelEntry *)ctx->model.p, ctx->n_model, scale_events,
+                           staged ? (float *)w.xmean.p : nullptr, (KParam *)w.kparam.p, rstat,
+                           (uint32_t *)w.queue.p, st));
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[1], st));
 
   AlignArgs a;
   a.reads = reads;
-  a.xmean = (const float *)w.xmean.p;
+  a.xsrc = staged ? (const float *)w.xmean.p : io.events;
+  a.xstride = staged ? 1 : io.ev_stride;
   a.kparam = (const KParam *)w.kparam.p;
   a.rstat = rstat;
   a.trace = (uint2 *)w.trace.p;
@@ -750,11 +758,15 @@ int abea_align_batch_device_noalloc(abea_ctx *ctx, const abea_batch_t *b, const 
   const uint64_t nr = (uint64_t)std::max(n, 1);
   auto up = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
   Work &w = ctx->noalloc;
+  /* the event means are staged only for events scaled to the model (the
+   * band fill reads them in place otherwise) */
+  const uint64_t xbytes = (ctx->flags & ABEA_F_SCALE_EVENTS) ? sizeof(float) * eo[n] : 0;
   DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.path_len, &w.path_src, &w.tend,
                     &w.xmean, &w.kparam, &w.scratch};
   const uint64_t bytes[] = {sizeof(ReadDesc) * nr, sizeof(int32_t) * nr, sizeof(uint32_t), sizeof(uint64_t) * nr,
-                            sizeof(uint64_t) * nr, sizeof(int32_t) * nr, sizeof(float) * eo[n],
+                            sizeof(uint64_t) * nr, sizeof(int32_t) * nr, xbytes,
                             sizeof(KParam) * ko[n], sizeof(int2) * slots};
+  static_assert(sizeof(bufs) / sizeof(bufs[0]) == sizeof(bytes) / sizeof(bytes[0]), "one size per buffer");
   uint64_t fixed = 0;
   for (uint64_t x : bytes) fixed += up(x);
   if (fixed >= ABEA_NOALLOC_SCRATCH_BYTES)
@@ -771,7 +783,7 @@ int abea_align_batch_device_noalloc(abea_ctx *ctx, const abea_batch_t *b, const 
   }
   unsigned char *base = (unsigned char *)ctx->noalloc_scratch;
   uint64_t off = 0;
-  for (int i = 0; i < 9; ++i) {
+  for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i) {
     bufs[i]->p = base + off;
     bufs[i]->cap = bytes[i];
     bufs[i]->borrowed = true;

@@ -77,7 +77,12 @@ constexpr int BT_RING_GROUPS = 16;
 /* Arguments of the band, backtrack and fused alignment kernels. */
 struct AlignArgs {
   const ReadDesc *reads; /* [n_reads] planned reads, longest first */
-  const float *xmean;    /* event means, compacted by k_prep (batch event order) */
+  /* event means: read in place from the batch's event records (xstride
+   * floats apart, the caller's device array), or the means k_prep staged
+   * (xstride 1) when the reads' inputs sit at addresses of their own or the
+   * events are scaled to the model */
+  const float *xsrc;
+  int32_t xstride;
   const KParam *kparam;
   int32_t *rstat;        /* [n_reads] status from k_prep; k_band writes the band outcome */
   uint2 *trace;          /* bit-plane trace tiles: 64 lanes x uint2 per group of bands */
@@ -102,7 +107,9 @@ struct AlignArgs {
  * event means (in_addr[2r], one float per event) and ranks (in_addr[2r+1]),
  * used instead of the batch arrays. */
 /* scale_events: event means become (x - shift)/scale and the model levels
- * stay unscaled, instead of mu' = fmaf(level, scale, shift) */
+ * stay unscaled, instead of mu' = fmaf(level, scale, shift)
+ * xmean: null (the band fill reads the events in place), or where to stage
+ * the event means (scaled when scale_events) */
 /* ev_stride: floats from one event mean to the next in `events` (3 for the
  * 12-byte event records, 1 for a compact array of means) */
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events, int ev_stride,

@@ -187,7 +187,9 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
     }
     kparam[rd.km_off + k] = p;
   }
-  if (scale_events) {
+  if (!xmean) {
+    /* the band fill reads the events in place */
+  } else if (scale_events) {
     /* x' = (x - shift) / scale: float32 subtract, correctly rounded divide */
     for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) {
       const float d = ev[(int64_t)ev_stride * e] - sh;
@@ -439,7 +441,9 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
    * first slot add them to a rotated neighbour, and only with a vector second
    * operand can the rotation fold into the add (v_add_f32_dpp) */
   const float lp_skip_v = to_vgpr(lp_skip), lp_step_v = to_vgpr(lp_step);
-  const float *__restrict__ xm = a.xmean + rd.ev_off;
+  /* the read's event means, in place (every xstride-th float) or staged */
+  const int xs = a.xstride;
+  const float *__restrict__ xm = a.xsrc + (uint64_t)xs * rd.ev_off;
   const float4 *__restrict__ kp = reinterpret_cast<const float4 *>(a.kparam + rd.km_off);
   const int H = W / 2;
   const float NI = ABEA_NINF;
@@ -447,7 +451,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
 
   auto ldx = [&](int e) -> float {
     float v = 0.0f;
-    if (e >= 0 && e < n_e) v = xm[e];
+    if (e >= 0 && e < n_e) v = xm[(int64_t)xs * e];
     return v;
   };
   auto ldk = [&](int k) -> float4 {

@@ -148,8 +148,12 @@ int work_mark(abea_ctx *ctx, Work &w, hipStream_t st);
  * budget: the trace budget to plan with (UINT64_MAX: the context's). */
 int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t *ko, uint64_t pair_capacity,
                bool fused_only = false, uint64_t budget = UINT64_MAX);
-/* Device buffers of a planned batch, grown in stream order on `st`. */
-int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st);
+/* Device buffers of a planned batch, grown in stream order on `st`.
+ * staged_events: the batch's inputs sit at per-read addresses and k_prep
+ * stages the event means, as it does for events scaled to the model
+ * (otherwise the band fill reads the device batch's event records in place
+ * and no staging buffer is needed). */
+int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st, bool staged_events = false);
 /* Kernels of a planned batch whose plan is on the device. */
 int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, bool timed);
 

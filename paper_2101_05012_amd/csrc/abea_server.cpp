@@ -396,7 +396,7 @@ int slot_launch(abea_server *S, Slot &s) {
   }
   int rc;
   if ((rc = plan_batch(ctx, s.work, n, s.h_eo, s.h_ko, eo + ko))) return rc;
-  if ((rc = ensure_work(ctx, s.work, st))) return rc;
+  if ((rc = ensure_work(ctx, s.work, st, true))) return rc;
   /* the prep kernel reads every read's events and ranks in place from
    * mapped pinned host memory: from the read's own buffer, or for a read
    * queued in pageable memory from the slot's mapped staging */
