@@ -202,9 +202,9 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *batch,
  * inputs and outputs, host offsets, asynchronous on `stream`) and results,
  * bit for bit, but the call allocates nothing:
  *   - every device buffer beyond the caller's inputs and outputs (plan,
- *     k-mer parameters, trace tiles, pair scratch, per-read lengths, and
- *     with ABEA_F_SCALE_EVENTS the scaled event means) lies in one fixed
- *     array of ABEA_NOALLOC_SCRATCH_BYTES that the
+ *     trace tiles, pair scratch, per-read lengths, and with
+ *     ABEA_F_SCALE_EVENTS the scaled event means; ranks and events are read
+ *     in place) lies in one fixed array of ABEA_NOALLOC_SCRATCH_BYTES that the
  *     library holds on each device it runs on until the process ends;
  *   - the plan is staged through pinned host memory that abea_create set
  *     aside for ABEA_NOALLOC_MAX_READS reads.
@@ -212,8 +212,8 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *batch,
  * per read) with the context's worker count (0: one per read), capped by how
  * many of the longest reads' traces fit in what the other buffers leave of
  * the array (admission by traceback bytes).
- * Limits: n_reads <= ABEA_NOALLOC_MAX_READS, and 16 B per k-mer, 8 B per
- * path slot (sum of n_e + n_k - 1), 100 B per read (and 4 B per event with
+ * Limits: n_reads <= ABEA_NOALLOC_MAX_READS, and 8 B per path slot (sum
+ * of n_e + n_k - 1), 100 B per read (and 4 B per event with
  * ABEA_F_SCALE_EVENTS) and the
  * trace of at least the longest read (ceil((n_e + n_k - 1) / (32 /
  * cells_per_lane)) * 512 B) must fit in ABEA_NOALLOC_SCRATCH_BYTES; a batch

@@ -137,7 +137,7 @@ int work_mark(abea_ctx *ctx, Work &w, hipStream_t st) {
 void work_free(Work &w, hipStream_t st) {
   if (w.done_pending && w.done) (void)hipEventSynchronize(w.done);
   w.done_pending = false;
-  DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.xmean, &w.kparam,
+  DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.xmean, &w.krank,
                     &w.trace, &w.scratch, &w.path_len, &w.path_src, &w.tend};
   for (DevBuf *b : bufs) free_buf(*b, st);
   if (w.staging_pending && w.staging_done) (void)hipEventSynchronize(w.staging_done);
@@ -322,7 +322,7 @@ int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st, bool staged_events) {
   if ((staged_events || (ctx->flags & ABEA_F_SCALE_EVENTS)) &&
       (rc = ensure(ctx, &w, w.xmean, sizeof(float) * (size_t)P.n_events, st)))
     return rc;
-  if ((rc = ensure(ctx, &w, w.kparam, sizeof(KParam) * (size_t)P.n_kmers, st))) return rc;
+  if (staged_events && (rc = ensure(ctx, &w, w.krank, sizeof(uint32_t) * (size_t)P.n_kmers, st))) return rc;
   if ((rc = ensure(ctx, &w, w.trace, sizeof(uint2) * (size_t)P.n_trace, st))) return rc;
   if ((rc = ensure(ctx, &w, w.scratch, sizeof(int2) * (size_t)P.n_scratch, st))) return rc;
   if ((rc = ensure(ctx, &w, w.path_len, sizeof(uint64_t) * n, st))) return rc;
@@ -338,22 +338,28 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   const ReadDesc *reads = (const ReadDesc *)w.reads.p;
   int32_t *rstat = (int32_t *)w.rstat.p;
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[0], st));
-  /* inputs at per-read addresses (serving: mapped host memory), and events
-   * scaled to the model, are staged by k_prep; otherwise the band fill reads
-   * the means in place from the device batch's event records */
+  /* inputs at per-read addresses (serving: mapped host memory) are staged
+   * by k_prep, ranks and event means, and so are the means of events scaled
+   * to the model; otherwise the band fill reads both in place from the
+   * device batch */
   const bool scale_events = (ctx->flags & ABEA_F_SCALE_EVENTS) != 0;
-  const bool staged = io.in_addr != nullptr || scale_events;
+  const bool staged_in = io.in_addr != nullptr;
+  const bool staged = staged_in || scale_events;
   HIP_TRY(ctx, launch_prep(reads, n, io.events, io.ev_stride, io.ranks, io.in_addr, io.scale, io.shift,
-                           (const ModelEntry *)ctx->model.p, ctx->n_model, scale_events,
-                           staged ? (float *)w.xmean.p : nullptr, (KParam *)w.kparam.p, rstat,
-                           (uint32_t *)w.queue.p, st));
+                           scale_events, staged ? (float *)w.xmean.p : nullptr,
+                           staged_in ? (uint32_t *)w.krank.p : nullptr, rstat, (uint32_t *)w.queue.p, st));
   if (timed) HIP_TRY(ctx, hipEventRecord(w.tev[1], st));
 
   AlignArgs a;
   a.reads = reads;
   a.xsrc = staged ? (const float *)w.xmean.p : io.events;
   a.xstride = staged ? 1 : io.ev_stride;
-  a.kparam = (const KParam *)w.kparam.p;
+  a.ranks = staged_in ? (const uint32_t *)w.krank.p : io.ranks;
+  a.model = (const ModelEntry *)ctx->model.p;
+  a.n_model = ctx->n_model;
+  a.scale_events = scale_events ? 1 : 0;
+  a.scale = io.scale;
+  a.shift = io.shift;
   a.rstat = rstat;
   a.trace = (uint2 *)w.trace.p;
   a.scratch = (int2 *)w.scratch.p;
@@ -761,11 +767,9 @@ int abea_align_batch_device_noalloc(abea_ctx *ctx, const abea_batch_t *b, const 
   /* the event means are staged only for events scaled to the model (the
    * band fill reads them in place otherwise) */
   const uint64_t xbytes = (ctx->flags & ABEA_F_SCALE_EVENTS) ? sizeof(float) * eo[n] : 0;
-  DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.path_len, &w.path_src, &w.tend,
-                    &w.xmean, &w.kparam, &w.scratch};
+  DevBuf *bufs[] = {&w.reads, &w.rstat, &w.queue, &w.path_len, &w.path_src, &w.tend, &w.xmean, &w.scratch};
   const uint64_t bytes[] = {sizeof(ReadDesc) * nr, sizeof(int32_t) * nr, sizeof(uint32_t), sizeof(uint64_t) * nr,
-                            sizeof(uint64_t) * nr, sizeof(int32_t) * nr, xbytes,
-                            sizeof(KParam) * ko[n], sizeof(int2) * slots};
+                            sizeof(uint64_t) * nr, sizeof(int32_t) * nr, xbytes, sizeof(int2) * slots};
   static_assert(sizeof(bufs) / sizeof(bufs[0]) == sizeof(bytes) / sizeof(bytes[0]), "one size per buffer");
   uint64_t fixed = 0;
   for (uint64_t x : bytes) fixed += up(x);

@@ -36,14 +36,6 @@ struct ModelEntry {
   float pad;
 };
 
-/* Per-read k-parameters prepared for the band kernel: mu' = fma(mean, scale,
- * shift), c and h of the read's k-mer at that position. */
-struct KParam {
-  float mu;
-  float c;
-  float h;
-  float pad;
-};
 
 enum : int32_t { READ_OK = 0, READ_EMPTY = 1, READ_BAND_LOST = 2, READ_BAD_RANK = 3 };
 
@@ -83,7 +75,14 @@ struct AlignArgs {
    * events are scaled to the model */
   const float *xsrc;
   int32_t xstride;
-  const KParam *kparam;
+  /* k-mer ranks: the batch's, read in place, or the copy k_prep staged; the
+   * band fill gathers each one's model entry and scales it per read */
+  const uint32_t *ranks;
+  const ModelEntry *model;
+  uint32_t n_model;
+  int32_t scale_events;  /* events scaled to the model: the model levels stay unscaled */
+  const float *scale;    /* [caller reads] */
+  const float *shift;    /* [caller reads] */
   int32_t *rstat;        /* [n_reads] status from k_prep; k_band writes the band outcome */
   uint2 *trace;          /* bit-plane trace tiles: 64 lanes x uint2 per group of bands */
   int2 *scratch;         /* reversed-path pair scratch */
@@ -106,17 +105,18 @@ struct AlignArgs {
 /* in_addr: null, or per original read index r the device addresses of its
  * event means (in_addr[2r], one float per event) and ranks (in_addr[2r+1]),
  * used instead of the batch arrays. */
-/* scale_events: event means become (x - shift)/scale and the model levels
- * stay unscaled, instead of mu' = fmaf(level, scale, shift)
- * xmean: null (the band fill reads the events in place), or where to stage
- * the event means (scaled when scale_events) */
+/* k_prep sets each planned read's status (empty or not; the band fill finds
+ * bad ranks), zeroes the work-queue counter and stages what the band fill
+ * cannot read in place:
+ * xmean: null, or where to stage the event means (scaled to the model as
+ *   (x - shift)/scale when scale_events);
+ * krank: null, or where to copy the ranks (for inputs at per-read addresses). */
 /* ev_stride: floats from one event mean to the next in `events` (3 for the
  * 12-byte event records, 1 for a compact array of means) */
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events, int ev_stride,
                        const uint32_t *ranks, const uint64_t *in_addr, const float *scale,
-                       const float *shift, const ModelEntry *model, uint32_t n_model,
-                       bool scale_events, float *xmean, KParam *kparam, int32_t *rstat,
-                       uint32_t *queue, hipStream_t st);
+                       const float *shift, bool scale_events, float *xmean, uint32_t *krank,
+                       int32_t *rstat, uint32_t *queue, hipStream_t st);
 /* t0, t1: null, or events that take the start and end time of the kernel's
  * own dispatch.  edge: interior bands clear only the two slots beside the
  * band (cpl 2 or 4), else every slot outside the band's cells */

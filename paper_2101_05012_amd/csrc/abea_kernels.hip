@@ -8,10 +8,14 @@
  * a post-kernel (§5.4.1.3: one thread per read backtracks).  The same three
  * stages are here, re-designed for CDNA4:
  *
- *  k_prep      one workgroup per read: the scaled model level of every k-mer
- *              position, mu' = fma(mean, scale, shift) (paragraph after
- *              Alg. 5.3), with its emission terms (the kcache), and a compact
- *              copy of the event means.
+ *  k_prep      one workgroup per read: the read's status and, only where the
+ *              band fill cannot read them in place (inputs at addresses of
+ *              their own, e.g. mapped host memory, or events scaled to the
+ *              model), a copy of the ranks and the event means.  The
+ *              scaled model level of every k-mer position, mu' = fma(mean,
+ *              scale, shift) (paragraph after Alg. 5.3), and its emission
+ *              terms (the kcache) are made by the band fill itself, from
+ *              the rank and the model entry it gathers.
  *  k_band      one 64-lane wavefront per read, no barrier and no score in
  *              memory.  K-mer k of a band lives in slot k mod N (N = 64*CPL >
  *              W; slot s is lane s / CPL, register s % CPL), so a cell's up
@@ -146,10 +150,9 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
                                               const uint64_t *__restrict__ in_addr,
                                               const float *__restrict__ scale,
                                               const float *__restrict__ shift,
-                                              const ModelEntry *__restrict__ model, uint32_t n_model,
                                               int scale_events,
                                               float *__restrict__ xmean,
-                                              KParam *__restrict__ kparam,
+                                              uint32_t *__restrict__ krank,
                                               int32_t *__restrict__ rstat,
                                               uint32_t *__restrict__ queue) {
   /* the work-queue counter of the alignment kernel that follows */
@@ -159,38 +162,25 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
     if (threadIdx.x == 0) rstat[blockIdx.x] = READ_EMPTY;
     return;
   }
+  /* a rank outside the model is found by the band fill, which reads every
+   * rank of the read */
+  if (threadIdx.x == 0) rstat[blockIdx.x] = READ_OK;
   /* the read's events and ranks: in the batch arrays at its offsets (12-byte
    * events with the mean first, or the means alone), or (in_addr) at
-   * addresses of its own, e.g. in mapped host memory, where only the event
-   * means are stored */
+   * addresses of its own, where only the event means are stored */
   const int ev_stride = in_addr ? 1 : events_stride;
   const float *ev =
       in_addr ? reinterpret_cast<const float *>(in_addr[2 * rd.orig]) : events + (uint64_t)ev_stride * rd.ev_off;
   const uint32_t *rk =
       in_addr ? reinterpret_cast<const uint32_t *>(in_addr[2 * rd.orig + 1]) : ranks + rd.km_off;
-  const float sc = scale[rd.orig];
-  const float sh = shift[rd.orig];
-  int bad = 0;
-  for (int k = threadIdx.x; k < rd.n_k; k += blockDim.x) {
-    const uint32_t r = rk[k];
-    KParam p;
-    p.mu = p.c = p.h = p.pad = 0.0f;
-    if (r < n_model) {
-      const ModelEntry me = model[r];
-      /* per-read scaling (paragraph after Alg. 5.3): the model to the
-       * events with one rounding, or, scaling the events instead, unscaled */
-      p.mu = scale_events ? me.mean : __builtin_fmaf(me.mean, sc, sh);
-      p.c = me.c;
-      p.h = me.h;
-    } else {
-      bad = 1;
-    }
-    kparam[rd.km_off + k] = p;
-  }
-  if (!xmean) {
-    /* the band fill reads the events in place */
-  } else if (scale_events) {
-    /* x' = (x - shift) / scale: float32 subtract, correctly rounded divide */
+  if (krank)
+    for (int k = threadIdx.x; k < rd.n_k; k += blockDim.x) krank[rd.km_off + k] = rk[k];
+  if (!xmean) return;
+  if (scale_events) {
+    /* per-read scaling (paragraph after Alg. 5.3), the events to the model:
+     * x' = (x - shift) / scale, float32 subtract, correctly rounded divide */
+    const float sc = scale[rd.orig];
+    const float sh = shift[rd.orig];
     for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) {
       const float d = ev[(int64_t)ev_stride * e] - sh;
       xmean[rd.ev_off + e] = d / sc;
@@ -198,8 +188,6 @@ __global__ __launch_bounds__(256) void k_prep(const ReadDesc *__restrict__ reads
   } else {
     for (int e = threadIdx.x; e < rd.n_e; e += blockDim.x) xmean[rd.ev_off + e] = ev[(int64_t)ev_stride * e];
   }
-  bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) rstat[blockIdx.x] = bad ? READ_BAD_RANK : READ_OK;
 }
 
 /* ------------------------------------------------------------------ band */
@@ -444,7 +432,17 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   /* the read's event means, in place (every xstride-th float) or staged */
   const int xs = a.xstride;
   const float *__restrict__ xm = a.xsrc + (uint64_t)xs * rd.ev_off;
-  const float4 *__restrict__ kp = reinterpret_cast<const float4 *>(a.kparam + rd.km_off);
+  /* the read's ranks and the model they index; each k-mer's parameters are
+   * made here (the kcache of the paragraph after Alg. 5.3): mu' =
+   * fma(mean, scale, shift) with one rounding, or the unscaled mean when the
+   * events are scaled to the model, and the entry's emission terms c, h */
+  const uint32_t *__restrict__ rk = a.ranks + rd.km_off;
+  const float4 *__restrict__ mdl = reinterpret_cast<const float4 *>(a.model);
+  const uint32_t n_model = a.n_model;
+  const bool scale_ev = a.scale_events != 0;
+  const float ksc = a.scale[rd.orig];
+  const float ksh = a.shift[rd.orig];
+  uint32_t bad_rank = 0; /* this lane met a rank outside the model */
   const int H = W / 2;
   const float NI = ABEA_NINF;
   const float NFM = __int_as_float((int)0xff7fffff); /* -FLT_MAX */
@@ -454,10 +452,23 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     if (e >= 0 && e < n_e) v = xm[(int64_t)xs * e];
     return v;
   };
-  auto ldk = [&](int k) -> float4 {
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (k >= 0 && k < n_k) v = kp[k];
-    return v;
+  /* a k-mer's rank (positions outside the read take rank 0: their slots are
+   * outside the table, whatever they hold never reaches a cell of it) */
+  auto ldr = [&](int k) -> uint32_t {
+    uint32_t r = 0;
+    if (k >= 0 && k < n_k) r = rk[k];
+    return r;
+  };
+  /* its model entry, gathered (a rank outside the model is noted, and
+   * entry 0 read in its place) */
+  auto gather = [&](uint32_t r) -> float4 {
+    const bool ok = r < n_model;
+    bad_rank |= ok ? 0u : 1u;
+    return mdl[ok ? r : 0u];
+  };
+  /* the slot parameters (mu', c, h) of a gathered entry */
+  auto kparam = [&](float4 m) -> float4 {
+    return make_float4(scale_ev ? m.x : __builtin_fmaf(m.x, ksc, ksh), m.y, m.z, 0.0f);
   };
   /* event e = 64q + lane: sub-ring e mod S (the lane's low bits), entry
    * floor(e / S) mod RX/S */
@@ -528,9 +539,12 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   int xtop = (E + G) >> 6;
   int ktop = (K + N + G - 1) >> 6;
   for (int q = (E - W + 1) >> 6; q <= xtop; ++q) put_x(q, ldx(q * 64 + lane));
-  for (int q = K >> 6; q <= ktop; ++q) put_k(q, ldk(q * 64 + lane));
+  for (int q = K >> 6; q <= ktop; ++q) put_k(q, kparam(gather(ldr(q * 64 + lane))));
   float xpend = ldx((xtop + 1) * 64 + lane);
-  float4 kpend = ldk((ktop + 1) * 64 + lane);
+  /* the k-mer quarter after the top one: its model entries, gathered; the
+   * one after that: its ranks (two loads in a chain, each a refill ahead) */
+  float4 kpend = gather(ldr((ktop + 1) * 64 + lane));
+  uint32_t rpend = ldr((ktop + 2) * 64 + lane);
 
   auto advance_rings = [&]() {
     if (((E + G) >> 6) > xtop) {
@@ -540,8 +554,9 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     }
     if (((K + N + G - 1) >> 6) > ktop) {
       ++ktop;
-      put_k(ktop, kpend);
-      kpend = ldk((ktop + 1) * 64 + lane);
+      put_k(ktop, kparam(kpend));
+      kpend = gather(rpend);
+      rpend = ldr((ktop + 2) * 64 + lane);
     }
   };
 
@@ -828,6 +843,15 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
     for (int c = 0; c < CPL; ++c) F[c] = (last & 1) ? Sp[c] : Spp[c];
     if (n_k - 1 >= K && n_k - 1 <= K + W - 1) sc = read_slot<CPL>(F, (n_k - 1) & (N - 1));
   }
+  /* every rank of the read has passed through the k-mer ring: one outside
+   * the model makes the read's outcome a bad rank, with no alignment */
+  if (ballot(bad_rank != 0u)) {
+    if (lane == 0) {
+      a.out_ll[rd.orig] = ABEA_NINF;
+      if (a.out_cells) a.out_cells[rd.orig] = 0;
+    }
+    return READ_BAD_RANK;
+  }
   if (lane == 0) {
     a.out_ll[rd.orig] = sc;
     if (a.out_cells) a.out_cells[rd.orig] = cells;
@@ -835,7 +859,7 @@ __device__ __forceinline__ int band_read(const AlignArgs &a, const ReadDesc &rd,
   return (__float_as_int(sc) == ABEA_NINF_BITS) ? READ_BAND_LOST : READ_OK;
 }
 
-/* Outputs of a read whose band fill did not run (empty read, bad rank). */
+/* Outputs of a read whose band fill did not run (an empty read). */
 __device__ __forceinline__ void band_skipped(const AlignArgs &a, const ReadDesc &rd) {
   if ((threadIdx.x & 63) == 0) {
     a.out_ll[rd.orig] = ABEA_NINF;
@@ -1135,12 +1159,13 @@ __global__ __launch_bounds__(64) void k_compact(const int2 *__restrict__ scratch
 
 hipError_t launch_prep(const ReadDesc *reads, int n_planned, const float *events, int ev_stride,
                        const uint32_t *ranks, const uint64_t *in_addr, const float *scale,
-                       const float *shift, const ModelEntry *model, uint32_t n_model,
-                       bool scale_events, float *xmean, KParam *kparam, int32_t *rstat,
-                       uint32_t *queue, hipStream_t st) {
+                       const float *shift, bool scale_events, float *xmean, uint32_t *krank,
+                       int32_t *rstat, uint32_t *queue, hipStream_t st) {
   if (n_planned <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(256), 0, st, reads, events, ev_stride, ranks, in_addr,
-                     scale, shift, model, n_model, (int)scale_events, xmean, kparam, rstat, queue);
+  /* one wavefront per read when there is nothing to stage */
+  const int threads = (xmean || krank) ? 256 : 64;
+  hipLaunchKernelGGL(k_prep, dim3(n_planned), dim3(threads), 0, st, reads, events, ev_stride, ranks, in_addr,
+                     scale, shift, (int)scale_events, xmean, krank, rstat, queue);
   return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ struct Work {
   Plan plan;
   std::vector<int> order;
   std::vector<uint64_t> comp; /* per caller read: computed bands (n_e + n_k - 1, 0 if empty) */
-  DevBuf reads, rstat, queue, xmean, kparam, trace, scratch, path_len, path_src, tend;
+  DevBuf reads, rstat, queue, xmean, krank, trace, scratch, path_len, path_src, tend;
   ReadDesc *h_reads = nullptr; /* pinned staging of the plan */
   size_t h_cap = 0;
   hipEvent_t staging_done = nullptr;
@@ -150,9 +150,9 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
                bool fused_only = false, uint64_t budget = UINT64_MAX);
 /* Device buffers of a planned batch, grown in stream order on `st`.
  * staged_events: the batch's inputs sit at per-read addresses and k_prep
- * stages the event means, as it does for events scaled to the model
- * (otherwise the band fill reads the device batch's event records in place
- * and no staging buffer is needed). */
+ * stages the ranks and the event means (the means also for events scaled to
+ * the model); otherwise the band fill reads the device batch in place and no
+ * staging buffer is needed. */
 int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st, bool staged_events = false);
 /* Kernels of a planned batch whose plan is on the device. */
 int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, bool timed);

@@ -362,7 +362,7 @@ int slot_init(abea_server *S, Slot &s) {
   if ((rc = ensure(ctx, nullptr, w.rstat, sizeof(int32_t) * nr))) return rc;
   if ((rc = ensure(ctx, nullptr, w.queue, sizeof(uint32_t)))) return rc;
   if ((rc = ensure(ctx, nullptr, w.xmean, sizeof(float) * ne))) return rc;
-  if ((rc = ensure(ctx, nullptr, w.kparam, sizeof(KParam) * nk))) return rc;
+  if ((rc = ensure(ctx, nullptr, w.krank, sizeof(uint32_t) * nk))) return rc;
   if ((rc = ensure(ctx, nullptr, w.trace,
                    c.trace_budget_bytes ? std::min<uint64_t>(c.trace_budget_bytes, trace_max) : trace_max)))
     return rc;
