@@ -105,7 +105,7 @@ SERVING_LEVELS = [(1, 300), (10, 1000), (100, 4000), (1000, 20000), (3000, 30000
 # runs (FETCH_SIZE x 1.99989, WRITE_SIZE x 1.0: the factors a 1 GiB device
 # copy needs to read its known size), by workload; a workload without a
 # measurement of the current kernel reports null.
-ALIGN_TRAFFIC_BYTES = {}
+ALIGN_TRAFFIC_BYTES = {"uneven-20000-w100": 150.22e9, "plain-4000-lognormal5kb": 6.806e9}
 
 
 def log(*a):

@@ -1134,6 +1134,11 @@ __global__ __launch_bounds__(64) void k_scan(const uint64_t *__restrict__ len, i
   if (lane == 63) off[n] = inc;
 }
 
+/* Read r's pairs (a contiguous run in the scratch, in path order) to its
+ * place in the caller's array: COMPACT_SPLIT wavefronts per read, wavefront
+ * y copying the y-th slice, so that the longest reads do not leave one
+ * wavefront copying megabytes at the end of the kernel. */
+constexpr int COMPACT_SPLIT = 8;
 __global__ __launch_bounds__(64) void k_compact(const int2 *__restrict__ scratch,
                                                 const uint64_t *__restrict__ src,
                                                 const uint64_t *__restrict__ off,
@@ -1141,18 +1146,22 @@ __global__ __launch_bounds__(64) void k_compact(const int2 *__restrict__ scratch
   const int r = blockIdx.x;
   const uint64_t o = off[r];
   const uint64_t n = off[r + 1] - o;
+  /* slices in whole 64-pair steps */
+  const uint64_t steps = (n + 63) >> 6;
+  const uint64_t s0 = steps * blockIdx.y / COMPACT_SPLIT, s1 = steps * (blockIdx.y + 1) / COMPACT_SPLIT;
+  const uint64_t end = min(n, s1 << 6);
   const int2 *__restrict__ in = scratch + src[r];
   int2 *__restrict__ out = pairs + o;
-  uint64_t t = threadIdx.x;
-  /* four loads in flight per lane */
-  for (; t + 192 < n; t += 256) {
-    const int2 a = in[t], b = in[t + 64], c = in[t + 128], d = in[t + 192];
-    out[t] = a;
-    out[t + 64] = b;
-    out[t + 128] = c;
-    out[t + 192] = d;
+  uint64_t t = (s0 << 6) + threadIdx.x;
+  /* eight loads in flight per lane */
+  for (; t + 448 < end; t += 512) {
+    int2 v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = in[t + 64 * j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) out[t + 64 * j] = v[j];
   }
-  for (; t < n; t += 64) out[t] = in[t];
+  for (; t < end; t += 64) out[t] = in[t];
 }
 
 /* ------------------------------------------------------------- launchers */
@@ -1277,7 +1286,7 @@ hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t
 hipError_t launch_compact(const int2 *scratch, const uint64_t *path_src, const uint64_t *offset,
                           int n, int2 *pairs, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact, dim3(n), dim3(64), 0, st, scratch, path_src, offset, pairs);
+  hipLaunchKernelGGL(k_compact, dim3(n, COMPACT_SPLIT), dim3(64), 0, st, scratch, path_src, offset, pairs);
   return hipGetLastError();
 }
 
