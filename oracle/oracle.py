@@ -18,6 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "abea_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "event_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 READ_OK, READ_EMPTY, READ_BAND_LOST, READ_BAD_RANK = 0, 1, 2, 3
@@ -38,9 +39,9 @@ GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-f
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, no fused multiply-add except the
     explicit fmaf of the model scaling)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(f) for f in SRCS):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", *GCC_FLAGS, SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *GCC_FLAGS, *SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -82,6 +83,16 @@ def lib():
         L.oracle_align_batch.argtypes = [i32, P, i64, P, P, P, P, P, P, P, P, P, i64, i32, u32, i32,
                                          P, P, P, P, P, P, P]
         L.oracle_align_batch.restype = ctypes.c_int
+        L.oracle_ed_stat.argtypes = [P, i64, i32, i64]
+        L.oracle_ed_stat.restype = f32
+        L.oracle_ed_stats.argtypes = [P, i64, f32, f32, P]
+        L.oracle_ed_stats.restype = None
+        L.oracle_ed_change_points.argtypes = [P, i64, P, P]
+        L.oracle_ed_change_points.restype = i64
+        L.oracle_ed_read.argtypes = [P, i64, f32, f32, P, P]
+        L.oracle_ed_read.restype = i64
+        L.oracle_ed_batch.argtypes = [i32, P, P, P, P, P, i32, P, P]
+        L.oracle_ed_batch.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -224,3 +235,80 @@ def align_batch(batch, model: Model, W: int, n_threads: int = 1, flags: int = 0)
     if err < 0:
         raise RuntimeError(f"oracle_align_batch error {err}")
     return BatchResult(status, score, path_len, cells, slot[:-1], pairs, margin)
+
+
+# ---- event detection (event_oracle.c) ----------------------------------------
+
+
+class EdParams(ctypes.Structure):
+    """Detector parameters: a short and a long window (samples) with their t
+    thresholds."""
+
+    _fields_ = [("w_short", ctypes.c_int32), ("w_long", ctypes.c_int32),
+                ("t_short", ctypes.c_float), ("t_long", ctypes.c_float)]
+
+
+def ed_params(w_short: int = 3, t_short: float = 1.5, w_long: int = 8, t_long: float = 5.0) -> EdParams:
+    return EdParams(w_short, w_long, t_short, t_long)
+
+
+def _raw(x) -> np.ndarray:
+    return np.ascontiguousarray(x, np.int16)
+
+
+def ed_stat(x, w: int, i: int) -> np.float32:
+    """T(i) of the detector with window w (-1 where undefined)."""
+    x = _raw(x)
+    return np.float32(lib().oracle_ed_stat(_p(x), x.shape[0], w, i))
+
+
+def ed_stats(x, offset: float, pa_scale: float) -> np.ndarray:
+    """{mean, stdv, duration} of one event's samples."""
+    x = _raw(x)
+    out = np.zeros(3, np.float32)
+    lib().oracle_ed_stats(_p(x), x.shape[0], float(np.float32(offset)), float(np.float32(pa_scale)), _p(out))
+    return out
+
+
+def ed_change_points(x, params: Optional[EdParams] = None) -> np.ndarray:
+    """Sample indices where events start (besides sample 0)."""
+    x = _raw(x)
+    cp = np.zeros(x.shape[0] + 1, np.uint8)
+    m = lib().oracle_ed_change_points(_p(x), x.shape[0], ctypes.byref(params or ed_params()), _p(cp))
+    if m < 0:
+        raise RuntimeError("oracle_ed_change_points failed")
+    return np.nonzero(cp)[0].astype(np.int64)
+
+
+def ed_read(x, offset: float, pa_scale: float, params: Optional[EdParams] = None) -> np.ndarray:
+    """Events of one read as float32 [m, 3] (mean, stdv, duration)."""
+    x = _raw(x)
+    ev = np.zeros((max(x.shape[0], 1), 3), np.float32)
+    m = lib().oracle_ed_read(_p(x), x.shape[0], float(np.float32(offset)), float(np.float32(pa_scale)),
+                             ctypes.byref(params or ed_params()), _p(ev))
+    if m < 0:
+        raise RuntimeError("oracle_ed_read failed")
+    return ev[:m].copy()
+
+
+def ed_batch(raw_batch, params: Optional[EdParams] = None, n_threads: int = 1):
+    """Events of a raw batch (``paper_2101_05012_amd.synth.RawBatch``):
+    (events float32 [m, 3], event_offset uint64 [n+1])."""
+    n = raw_batch.n_reads
+    raw = _raw(raw_batch.raw)
+    so = np.ascontiguousarray(raw_batch.sample_offset, np.uint64)
+    off = np.ascontiguousarray(raw_batch.offset, np.float32)
+    sc = np.ascontiguousarray(raw_batch.pa_scale, np.float32)
+    ev = np.zeros((max(int(so[-1]) if n else 0, 1), 3), np.float32)
+    cnt = np.zeros(max(n, 1), np.int64)
+    err = lib().oracle_ed_batch(n, _p(raw), _p(so), _p(off), _p(sc), ctypes.byref(params or ed_params()),
+                                n_threads, _p(ev), _p(cnt))
+    if err < 0:
+        raise RuntimeError("oracle_ed_batch failed")
+    eo = np.zeros(n + 1, np.uint64)
+    np.cumsum(cnt[:n], out=eo[1:])
+    out = np.zeros((int(eo[-1]), 3), np.float32)
+    for r in range(n):
+        a = int(so[r])
+        out[int(eo[r]):int(eo[r + 1])] = ev[a:a + int(cnt[r])]
+    return out, eo

@@ -22,6 +22,17 @@ D_rapid), which are not available here.  What is drawn, and why:
   level_stdv), stdv ~ U(0.5, 3), duration ~ Exp(mean 2.5 ms), all float32.
   Only the mean is read by the alignment (Alg. 5.3).
 
+Raw signal (the input of event detection, Ch. 5 §5.2.2 "Methylation
+calling"; sampling figures of the "Nanopore sequencing and the raw signal"
+paragraph): the current is sampled at 4000 Hz while the strand moves at about
+450 bases/s, so a k-mer dwells about 8.9 samples on average.  Each k-mer's
+dwell is round(Gamma(shape 2, mean 8.89)), at least 1 sample (the speed
+varies: the signal warps in time).  Each sample is
+level_mean*scale + shift + N(0, level_stdv) pA, digitised as
+round(pA / pa_scale - offset) into int16 with, per read,
+pa_scale = U(1380, 1420) pA / 8192 levels and offset ~ U(-20, 20): the
+reading back to pA is (raw + offset) * pa_scale.
+
 Every read draws from its own stream ``default_rng([workload_seed, read_id])``,
 so a read's bytes do not depend on which batch it is in or where.
 """
@@ -60,7 +71,16 @@ WORKLOADS = {
     # the read ends
     "plain-4000-lognormal5kb-ends": dict(seed_index=5, n_reads=4000, W=100, k=6, lengths="lognormal5k",
                                          ends=True),
+    # raw signal of reads of the same length mix (event detection's input)
+    "raw-4000-lognormal5kb": dict(seed_index=6, n_reads=4000, W=100, k=6, lengths="lognormal5k", raw=True),
 }
+
+SAMPLE_RATE_HZ = 4000.0
+BASES_PER_S = 450.0
+DWELL_GAMMA_SHAPE = 2.0
+RAW_DIGITISATION = 8192.0
+RAW_RANGE_PA = (1380.0, 1420.0)
+RAW_OFFSET = (-20.0, 20.0)
 
 
 @dataclasses.dataclass
@@ -200,6 +220,101 @@ def end_events(rng: np.random.Generator, leading: bool) -> np.ndarray:
     ev[:, 1] = rng.uniform(0.5, 3.0, n)
     ev[:, 2] = rng.exponential(0.0025, n)
     return ev
+
+
+@dataclasses.dataclass
+class RawRead:
+    raw: np.ndarray  # int16 [n_samples]
+    ranks: np.ndarray  # uint32 [n_k]
+    offset: np.float32  # pA = (raw + offset) * pa_scale
+    pa_scale: np.float32
+    scale: np.float32  # model scaling of the alignment (mu' = level_mean * scale + shift)
+    shift: np.float32
+    dwell: np.ndarray  # int64 [n_k]: samples of each k-mer (ground truth)
+
+
+@dataclasses.dataclass
+class RawBatch:
+    """Concatenated raw reads with exclusive prefix-sum offsets."""
+
+    raw: np.ndarray  # int16 [sum n]
+    sample_offset: np.ndarray  # uint64 [n+1]
+    ranks: np.ndarray  # uint32 [sum n_k]
+    kmer_offset: np.ndarray  # uint64 [n+1]
+    offset: np.ndarray  # float32 [n]
+    pa_scale: np.ndarray  # float32 [n]
+    scale: np.ndarray  # float32 [n]
+    shift: np.ndarray  # float32 [n]
+    dwell: np.ndarray  # int64 [sum n_k]
+
+    @property
+    def n_reads(self) -> int:
+        return int(self.offset.shape[0])
+
+    def read_raw(self, i: int) -> np.ndarray:
+        return self.raw[int(self.sample_offset[i]) : int(self.sample_offset[i + 1])]
+
+    def read_ranks(self, i: int) -> np.ndarray:
+        return self.ranks[int(self.kmer_offset[i]) : int(self.kmer_offset[i + 1])]
+
+
+def gen_raw_read(rng: np.random.Generator, L: int, model: PoreModel, noiseless: bool = False) -> RawRead:
+    """Raw signal of one read of reference length L (see the module
+    docstring).  ``noiseless``: every sample is exactly its k-mer's level."""
+    k = model.k
+    bases = rng.integers(0, 4, L).astype(np.uint8)
+    ranks = kmer_ranks(bases, k)
+    n_k = ranks.shape[0]
+    scale = np.float32(rng.uniform(0.9, 1.1))
+    shift = np.float32(rng.uniform(-5.0, 5.0))
+    mean_dwell = SAMPLE_RATE_HZ / BASES_PER_S
+    dwell = np.maximum(1, np.round(rng.gamma(DWELL_GAMMA_SHAPE, mean_dwell / DWELL_GAMMA_SHAPE, n_k))).astype(
+        np.int64)
+    r = np.repeat(ranks, dwell)
+    pa = model.level_mean[r].astype(np.float64) * float(scale) + float(shift)
+    if not noiseless:
+        pa = pa + rng.normal(0.0, 1.0, r.shape[0]) * model.level_stdv[r].astype(np.float64)
+    pa_scale = np.float32(rng.uniform(*RAW_RANGE_PA) / RAW_DIGITISATION)
+    offset = np.float32(rng.uniform(*RAW_OFFSET))
+    raw = np.clip(np.round(pa / float(pa_scale) - float(offset)), -32768, 32767).astype(np.int16)
+    return RawRead(raw, ranks, offset, pa_scale, scale, shift, dwell)
+
+
+def make_raw_batch(reads: Sequence[RawRead]) -> RawBatch:
+    n = len(reads)
+    ns = np.array([r.raw.shape[0] for r in reads], np.uint64)
+    nk = np.array([r.ranks.shape[0] for r in reads], np.uint64)
+    so = np.zeros(n + 1, np.uint64)
+    ko = np.zeros(n + 1, np.uint64)
+    np.cumsum(ns, out=so[1:])
+    np.cumsum(nk, out=ko[1:])
+
+    def cat(xs, dt):
+        return np.ascontiguousarray(np.concatenate(xs) if n else np.zeros(0, dt), dt)
+
+    return RawBatch(
+        cat([r.raw for r in reads], np.int16), so, cat([r.ranks for r in reads], np.uint32), ko,
+        np.array([r.offset for r in reads], np.float32), np.array([r.pa_scale for r in reads], np.float32),
+        np.array([r.scale for r in reads], np.float32), np.array([r.shift for r in reads], np.float32),
+        cat([r.dwell for r in reads], np.int64),
+    )
+
+
+def workload_raw_batch(workload: str, model: Optional[PoreModel] = None,
+                       read_ids: Optional[Sequence[int]] = None) -> RawBatch:
+    """Raw reads of a raw-signal workload; read ``i`` is identical whatever
+    batch it is in."""
+    cfg = WORKLOADS[workload]
+    assert cfg.get("raw"), workload
+    if model is None:
+        model = pore_model(cfg["k"])
+    if read_ids is None:
+        read_ids = range(cfg["n_reads"])
+    out = []
+    for i in read_ids:
+        rng = read_rng(workload, int(i))
+        out.append(gen_raw_read(rng, draw_length(rng, cfg["lengths"]), model))
+    return make_raw_batch(out)
 
 
 def make_batch(reads: Sequence[Read]) -> Batch:

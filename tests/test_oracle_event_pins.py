@@ -1,0 +1,222 @@
+"""Pins of the event-detection oracle (oracle/event_oracle.c) against what
+the mathematics fixes, independent of the oracle's own formulas.
+
+The detector is a reading (the thesis names event detection, Ch. 5 §5.2.2,
+but gives no algorithm): the squared two-sample t statistic of the windows
+before and after a boundary, local maxima above a threshold, two detectors.
+Each pin below is chosen so that a plausible mistake fails it:
+
+* E1 the statistic equals the textbook t^2 (means and population variances,
+  exact rationals) within its float32 rounding bound: a sample instead of a
+  population variance, a window off by one sample, a missing factor w fail;
+* E2 noiseless steps: change points exactly at the steps, means and lengths in
+  closed form, stdv 0: a peak one boundary off, a wrong event split fail;
+* E3 event statistics against numpy's mean and std;
+* E4 invariances: a constant added to the raw values changes nothing; the
+  time-reversed signal has the mirrored change points (no ties); a higher
+  threshold never adds a change point;
+* E5 the synthetic raw workload is over-segmented by the thesis's factor
+  (events exceed k-mers by 1.5-2, the ABEA subsection of Ch. 5 §5.2);
+* E6 the degenerate reads: empty, shorter than any window, constant.
+"""
+
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2101_05012_amd import synth
+
+F32_EPS = 2.0**-24
+
+
+def textbook_t2(x, w, i):
+    left = [Fraction(int(v)) for v in x[i - w:i]]
+    right = [Fraction(int(v)) for v in x[i:i + w]]
+    ml = sum(left) / w
+    mr = sum(right) / w
+    vl = sum((v - ml) ** 2 for v in left) / w
+    vr = sum((v - mr) ** 2 for v in right) / w
+    den = (vl + vr) / w
+    if den == 0:
+        return None if mr != ml else Fraction(0)
+    return (mr - ml) ** 2 / den
+
+
+@pytest.mark.parametrize("w", [2, 3, 5, 8, 16])
+def test_e1_statistic_is_the_textbook_t2(w):
+    rng = np.random.default_rng(100 + w)
+    for trial in range(60):
+        n = 2 * w + int(rng.integers(0, 8))
+        if trial % 3 == 0:
+            x = rng.integers(-32768, 32768, n)  # full int16 range: the integer sums' extremes
+        elif trial % 3 == 1:
+            x = np.round(rng.normal(600, 12, n))
+        else:
+            x = np.concatenate([np.full(n // 2, 500), np.full(n - n // 2, 530)]) + rng.integers(-2, 3, n)
+        x = x.astype(np.int16)
+        for i in range(w, n - w + 1):
+            want = textbook_t2(x, w, i)
+            got = orc.ed_stat(x, w, i)
+            if want is None:
+                assert np.isposinf(got)
+            elif want == 0:
+                assert got == 0.0
+            else:
+                # D exact; (float)D^2, *w, (float)V and the quotient: four roundings
+                assert abs(Fraction(float(got)) - want) <= want * Fraction(5 * F32_EPS), (w, i, got, float(want))
+    # undefined boundaries
+    x = np.arange(10, dtype=np.int16)
+    assert orc.ed_stat(x, 3, 2) == -1.0 and orc.ed_stat(x, 3, 8) == -1.0 and orc.ed_stat(x, 3, 7) >= 0.0
+
+
+def test_e1_catches_a_sample_variance():
+    """The textbook value with sample variances differs by far more than the
+    bound above, so E1 separates the two readings."""
+    x = np.array([10, 13, 11, 30, 28, 33], np.int16)
+    pop = textbook_t2(x, 3, 3)
+    samp = pop * Fraction(2, 3)  # (n-1)/n per variance: t^2 scales by (w-1)/w
+    assert abs(Fraction(float(orc.ed_stat(x, 3, 3))) - samp) > samp * Fraction(1, 10)
+
+
+def noiseless_steps(rng, n_seg, min_len, max_len):
+    lens = rng.integers(min_len, max_len + 1, n_seg)
+    levels = rng.choice(np.arange(200, 900), n_seg, replace=False)
+    x = np.repeat(levels, lens).astype(np.int16)
+    starts = np.cumsum(lens)[:-1]
+    return x, lens, levels, starts
+
+
+def test_e2_noiseless_steps_closed_form():
+    p = orc.ed_params()
+    rng = np.random.default_rng(7)
+    for trial in range(40):
+        x, lens, levels, starts = noiseless_steps(rng, int(rng.integers(1, 30)), 2 * p.w_long, 60)
+        offset = np.float32(rng.uniform(-20, 20))
+        pa = np.float32(rng.uniform(1380, 1420) / 8192)
+        assert np.array_equal(orc.ed_change_points(x, p), starts)
+        ev = orc.ed_read(x, offset, pa, p)
+        assert ev.shape[0] == lens.shape[0]
+        want_mean = ((levels.astype(np.float64) + np.float64(offset)) * np.float64(pa)).astype(np.float32)
+        assert np.array_equal(ev[:, 0], want_mean)
+        assert np.all(ev[:, 1] == 0.0)
+        assert np.array_equal(ev[:, 2], lens.astype(np.float32))
+
+
+def test_e2_short_steps_found_by_the_short_window():
+    """Steps 2*w_short apart but closer than the long window: the short
+    detector still places every change point exactly."""
+    p = orc.ed_params()
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        x, lens, levels, starts = noiseless_steps(rng, 12, 2 * p.w_short, 2 * p.w_short + 2)
+        got = orc.ed_change_points(x, p)
+        assert set(starts.tolist()) <= set(got.tolist())
+
+
+def test_e3_stats_against_numpy():
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        n = int(rng.integers(1, 200))
+        x = np.round(rng.normal(rng.uniform(-5000, 5000), rng.uniform(0, 50), n)).astype(np.int16)
+        off = np.float32(rng.uniform(-20, 20))
+        pa = np.float32(rng.uniform(0.1, 0.2))
+        m, s, d = orc.ed_stats(x, off, pa)
+        xm = x.astype(np.float64).mean()  # sum of int16 in float64 is exact
+        assert m == np.float32((xm + np.float64(off)) * np.float64(pa))
+        want_s = np.float32(x.astype(np.float64).std() * np.float64(pa))
+        assert abs(float(s) - float(want_s)) <= 2e-6 * max(float(want_s), 1e-30) + 1e-12
+        assert d == n
+
+
+def test_e4_invariances():
+    p = orc.ed_params()
+    rng = np.random.default_rng(10)
+    m = synth.pore_model(6)
+    for r in range(10):
+        rd = synth.gen_raw_read(np.random.default_rng([11, r]), 400, m)
+        x = rd.raw
+        cp = orc.ed_change_points(x, p)
+        # a constant added to every raw value
+        c = int(rng.integers(-200, 200))
+        assert np.array_equal(orc.ed_change_points((x.astype(np.int32) + c).astype(np.int16), p), cp)
+        # a higher threshold only removes change points
+        hi = orc.ed_params(p.w_short, p.t_short * 1.5, p.w_long, p.t_long * 1.5)
+        assert set(orc.ed_change_points(x, hi).tolist()) <= set(cp.tolist())
+    # time reversal: boundaries i and n - i swap sides (wide noise: no ties)
+    for r in range(10):
+        x = np.round(rng.normal(0, 1500, 500) + np.repeat(rng.normal(0, 6000, 25), 20)).clip(-32768, 32767)
+        x = x.astype(np.int16)
+        n = x.shape[0]
+        for w in (3, 8):
+            T = np.array([orc.ed_stat(x, w, i) for i in range(w, n - w + 1)])
+            for d in range(1, w):
+                assert not np.any(T[d:] == T[:-d]), "a tie inside a neighbourhood: pick another seed"
+        cp = orc.ed_change_points(x, p)
+        cr = orc.ed_change_points(x[::-1].copy(), p)
+        assert np.array_equal(np.sort(n - cr), cp)
+
+
+def test_e5_workload_over_segmentation():
+    """Events per k-mer of the raw workload in the thesis's range, and the
+    true k-mer boundaries found (within one sample) for at least 90%."""
+    b = synth.workload_raw_batch("raw-4000-lognormal5kb", read_ids=range(60))
+    ev, eo = orc.ed_batch(b, n_threads=8)
+    ratio = float(eo[-1]) / float(b.kmer_offset[-1])
+    assert 1.5 <= ratio <= 2.0, ratio
+    found = total = 0
+    d0 = 0
+    for r in range(b.n_reads):
+        x = b.read_raw(r)
+        cp = orc.ed_change_points(x)
+        nk = int(b.kmer_offset[r + 1] - b.kmer_offset[r])
+        true = np.cumsum(b.dwell[d0:d0 + nk])[:-1]
+        d0 += nk
+        near = np.zeros(x.shape[0] + 2, bool)
+        for s in (-1, 0, 1):
+            near[np.clip(cp + s, 0, x.shape[0])] = True
+        found += int(near[true].sum())
+        total += true.shape[0]
+        # the events tile the read
+        assert float(ev[int(eo[r]):int(eo[r + 1]), 2].sum()) == x.shape[0]
+    assert found / total >= 0.9
+
+
+def test_e6_degenerate_reads():
+    p = orc.ed_params()
+    assert orc.ed_read(np.zeros(0, np.int16), 0.0, 0.17, p).shape == (0, 3)
+    one = orc.ed_read(np.array([700], np.int16), 1.0, 0.5, p)
+    assert one.shape == (1, 3) and one[0, 0] == np.float32(350.5) and one[0, 1] == 0 and one[0, 2] == 1
+    short = np.array([100, 900, 100, 900, 100], np.int16)  # shorter than 2 * w_short + 1 boundaries
+    assert orc.ed_change_points(short, p).shape == (0,)
+    assert orc.ed_read(short, 0.0, 1.0, p).shape == (1, 3)
+    const = np.full(1000, 555, np.int16)
+    ev = orc.ed_read(const, 0.0, 1.0, p)
+    assert ev.shape == (1, 3) and ev[0, 0] == 555 and ev[0, 1] == 0 and ev[0, 2] == 1000
+
+
+@pytest.mark.parametrize("b", [900, 100, 32767, -32768])
+def test_e7_spike_plateau_and_threshold(b):
+    """One sample b on a constant level a: every boundary with the spike in
+    one window has t^2 = w/(w-1) exactly (the spike window's population
+    variance is (w-1)(b-a)^2/w^2), 2w equal values in a row.  The plateau keeps
+    its first boundary, i = p-w+1, for each detector; and the threshold
+    compares t^2: for w = 3 the plateau (1.5) lies between 1.2^2 and 1.3^2."""
+    a, p, n = 500, 60, 140
+    x = np.full(n, a, np.int16)
+    x[p] = b
+    for w in (2, 3, 5, 8, 16):
+        want = Fraction(w, w - 1)
+        for i in range(w, n - w + 1):
+            t = orc.ed_stat(x, w, i)
+            if p - w + 1 <= i <= p + w:
+                assert abs(Fraction(float(t)) - want) <= want * Fraction(5 * F32_EPS)
+            else:
+                assert t == 0.0
+    low = orc.ed_params(3, 1.2, 8, 1.0)
+    assert orc.ed_change_points(x, low).tolist() == [p - 8 + 1, p - 3 + 1]
+    high = orc.ed_params(3, 1.3, 8, 1.0)  # 8/7 > 1.0^2 still: only the long detector's boundary
+    assert orc.ed_change_points(x, high).tolist() == [p - 8 + 1]
+    none = orc.ed_params(3, 1.3, 8, 1.07)  # 1.07^2 = 1.1449 > 8/7
+    assert orc.ed_change_points(x, none).tolist() == []
