@@ -26,11 +26,13 @@
  *              either starts an event.  The events are the runs of samples
  *              between consecutive change points, from sample 0 to sample n
  *              (none if n = 0).
- *   stats      For an event of samples a..b-1 (len = b-a):
- *              m = (double)sum / len; M2 = sum over the samples, in order, of
- *              ((double)x - m)^2 in double; then, in pA,
+ *   stats      For an event of samples a..b-1 (len = b-a) with the exact
+ *              integer sum S and sum of squares Q: m = (double)S / len and
+ *              V = len*Q - S^2 (len^2 times the population variance, an exact
+ *              integer, rounded once to double); then, in pA,
  *              mean = (float)((m + offset) * pa_scale),
- *              stdv = (float)(sqrt(M2 / len) * pa_scale), duration = (float)len.
+ *              stdv = (float)(sqrt((double)V) / len * pa_scale),
+ *              duration = (float)len.
  *
  * Build with -ffp-contract=off: no operation is fused.
  */
@@ -61,16 +63,15 @@ float oracle_ed_stat(const int16_t *x, int64_t n, int32_t w, int64_t i) {
 }
 
 void oracle_ed_stats(const int16_t *x, int64_t len, float offset, float pa_scale, float out[3]) {
-  int64_t s = 0;
-  for (int64_t j = 0; j < len; ++j) s += x[j];
-  const double m = (double)s / (double)len;
-  double m2 = 0.0;
+  int64_t s = 0, q = 0;
   for (int64_t j = 0; j < len; ++j) {
-    const double d = (double)x[j] - m;
-    m2 += d * d;
+    s += x[j];
+    q += (int64_t)x[j] * x[j];
   }
+  const double m = (double)s / (double)len;
+  const __int128 v = (__int128)len * q - (__int128)s * s;
   out[0] = (float)((m + (double)offset) * (double)pa_scale);
-  out[1] = (float)(sqrt(m2 / (double)len) * (double)pa_scale);
+  out[1] = (float)(sqrt((double)v) / (double)len * (double)pa_scale);
   out[2] = (float)len;
 }
 

@@ -11,7 +11,8 @@ Each pin below is chosen so that a plausible mistake fails it:
   population variance, a window off by one sample, a missing factor w fail;
 * E2 noiseless steps: change points exactly at the steps, means and lengths in
   closed form, stdv 0: a peak one boundary off, a wrong event split fail;
-* E3 event statistics against numpy's mean and std;
+* E3 event statistics against numpy's mean and std, and the stdv against the
+  exact population standard deviation (integer arithmetic) within one ulp;
 * E4 invariances: a constant added to the raw values changes nothing; the
   time-reversed signal has the mirrored change points (no ties); a higher
   threshold never adds a change point;
@@ -20,6 +21,7 @@ Each pin below is chosen so that a plausible mistake fails it:
 * E6 the degenerate reads: empty, shorter than any window, constant.
 """
 
+import math
 from fractions import Fraction
 
 import numpy as np
@@ -128,6 +130,36 @@ def test_e3_stats_against_numpy():
         want_s = np.float32(x.astype(np.float64).std() * np.float64(pa))
         assert abs(float(s) - float(want_s)) <= 2e-6 * max(float(want_s), 1e-30) + 1e-12
         assert d == n
+
+
+def exact_stdv_float(x, pa):
+    """The population standard deviation of integer samples times pa, to
+    about 60 significant bits (integer square root of the scaled variance)."""
+    n = len(x)
+    S = int(sum(int(v) for v in x))
+    Q = int(sum(int(v) * int(v) for v in x))
+    V = n * Q - S * S  # n^2 * variance, exact
+    scale = 1 << 120
+    r = math.isqrt(V * scale * scale)  # sqrt(V) * 2^120, floored
+    return Fraction(r, scale) / n * Fraction(float(pa))
+
+
+def test_e3_stdv_is_the_exact_population_stdv():
+    """The event stdv is the exact population standard deviation (times the
+    pA scale) up to its float rounding: within one float32 ulp."""
+    rng = np.random.default_rng(12)
+    for trial in range(400):
+        n = int(rng.integers(1, 3000 if trial % 10 == 0 else 40))
+        if trial % 4 == 0:
+            x = rng.integers(-32768, 32768, n)
+        else:
+            x = np.round(rng.normal(rng.uniform(-3000, 3000), rng.uniform(0, 400), n))
+        x = x.astype(np.int16)
+        pa = np.float32(rng.uniform(0.1, 0.2))
+        got = orc.ed_stats(x, 0.0, pa)[1]
+        want = exact_stdv_float(x, pa)
+        ulp = np.spacing(np.float32(float(want))) if want > 0 else np.float32(0)
+        assert abs(Fraction(float(got)) - want) <= Fraction(float(ulp)), (trial, n, got, float(want))
 
 
 def test_e4_invariances():
