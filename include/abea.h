@@ -230,6 +230,90 @@ int abea_align_batch_device(abea_ctx *ctx, const abea_batch_t *batch,
 int abea_align_batch_device_noalloc(abea_ctx *ctx, const abea_batch_t *batch, const abea_result_t *res,
                                     void *stream);
 
+/* ---- event detection ------------------------------------------------------
+ * The step before the alignment: each read's raw signal (digitised current
+ * samples) is cut into events {mean, stdv, n} where the signal level changes
+ * suddenly (the thesis, Ch. 5 §5.2.2 "Methylation calling", its
+ * event-detection paragraph; the events are the event table of Alg. 5.1).
+ * The thesis gives no algorithm for the step; the detector is a two-window
+ * change-point test:
+ *   - statistic: at a boundary i of a read of n samples (between samples i-1
+ *     and i, w <= i <= n-w) the squared two-sample t statistic of the w
+ *     samples before and the w after with population variances,
+ *     w D^2 / V, D = S_r - S_l, V = w (Q_l + Q_r) - S_l^2 - S_r^2 over the
+ *     integer sums S and sums of squares Q, evaluated in float32 as
+ *     ((float)D * (float)D) * (float)w / (float)(double)V (+inf when V = 0
+ *     and D != 0, 0 when both are 0);
+ *   - peaks: boundary i is a change point of a detector (w, t) if its
+ *     statistic exceeds (float)(t*t), is greater than at every defined
+ *     boundary up to w-1 before it and not less than at every one up to w-1
+ *     after it; a short and a long detector, every peak of either starts an
+ *     event;
+ *   - events: the runs of samples between consecutive change points (sample
+ *     0 to the first, ..., the last to n), none for a read without samples;
+ *     for an event of len samples with integer sum s,
+ *     m = (double)s / len, M2 = the sum in sample order of ((double)x - m)^2,
+ *     mean = (float)((m + offset) * pa_scale),
+ *     stdv = (float)(sqrt(M2 / len) * pa_scale), duration = (float)len (samples).
+ * Results are bit-identical to the CPU reference of the same definition. */
+#define ABEA_DETECT_MAX_WINDOW 16
+
+typedef struct {
+  int32_t window_short;    /* 2 <= window_short <= window_long <= ABEA_DETECT_MAX_WINDOW */
+  int32_t window_long;
+  float threshold_short;   /* t thresholds (finite, >= 0) */
+  float threshold_long;
+} abea_detect_params_t;
+
+/* Defaults, fitted to 4 kHz sampling at 450 bases/s: about 1.7 events per
+ * k-mer, the over-segmentation the thesis reports (1.5-2 events per k-mer). */
+#define ABEA_DETECT_DEFAULT_PARAMS {3, 8, 1.5f, 5.0f}
+
+/*
+ * A batch of raw reads, serialised as the alignment batches (Alg. 5.9):
+ * read r owns samples[sample_offset[r] .. sample_offset[r+1]) (int16 digitiser
+ * levels; at most 2^31 - 1 samples per read); its current in pA is
+ * (sample + offset[r]) * pa_scale[r], pa_scale[r] > 0.
+ */
+typedef struct {
+  int32_t n_reads;
+  const int16_t *samples;
+  const uint64_t *sample_offset; /* HOST array [n_reads+1], exclusive prefix sums from 0 */
+  const float *offset;           /* [n_reads] */
+  const float *pa_scale;         /* [n_reads] */
+} abea_raw_batch_t;
+
+/*
+ * Detect the events of a raw batch held in device memory; asynchronous on
+ * `stream` (a hipStream_t, NULL = the default stream).
+ *   raw->samples, ->offset, ->pa_scale : DEVICE pointers; raw->sample_offset
+ *       a HOST array the library plans from (and uploads);
+ *   events : DEVICE array of event_capacity records: the batch's events, read
+ *       by read; event_offset : DEVICE array [n_reads+1] receiving each read's
+ *       first event and, in event_offset[n_reads], the batch's event count.
+ * A read has at most as many events as samples, so event_capacity >= the
+ * batch's sample count always suffices.  With less, the events at index
+ * event_capacity and beyond are not written: once the stream is
+ * synchronised, event_offset[n_reads] > event_capacity tells the caller.
+ * Device buffers of the context are reused by the next call, so detection
+ * calls on one context must be ordered on one stream.
+ * Errors: ABEA_E_INVAL (null pointer, n_reads < 0, offsets not starting at 0
+ * or decreasing, a read of 2^31 samples or more, windows or thresholds out of
+ * range), ABEA_E_NOMEM, ABEA_E_HIP.
+ */
+int abea_detect_events_device(abea_ctx *ctx, const abea_raw_batch_t *raw, const abea_detect_params_t *params,
+                              abea_event_t *events, uint64_t event_capacity, uint64_t *event_offset,
+                              void *stream);
+
+/*
+ * The same for a raw batch in host memory; synchronous.  Every pointer is a
+ * host pointer (events: event_capacity records; event_offset: n_reads+1).
+ * Errors: as abea_detect_events_device, and ABEA_E_CAPACITY (nothing written
+ * to events; event_offset holds the offsets that were needed).
+ */
+int abea_detect_events(abea_ctx *ctx, const abea_raw_batch_t *raw, const abea_detect_params_t *params,
+                       abea_event_t *events, uint64_t event_capacity, uint64_t *event_offset);
+
 /*
  * Device time in milliseconds of each stage of the last direct call
  * (abea_align_batch or abea_align_batch_device), when the context was

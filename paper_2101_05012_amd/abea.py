@@ -41,12 +41,16 @@ ABEA_ARENA_UNBOUNDED = (1 << 64) - 1  # arena_bytes: no trace budget
 ABEA_HOST_STAGING_CHUNK = 32 << 20
 ABEA_NOALLOC_SCRATCH_BYTES = 256 << 20  # the fixed device scratch of abea_align_batch_device_noalloc
 ABEA_NOALLOC_MAX_READS = 16384
+ABEA_DETECT_MAX_WINDOW = 16
+DETECT_DEFAULT = (3, 8, 1.5, 5.0)  # window_short, window_long, threshold_short, threshold_long
 
 EXPORTED = (
     "abea_create",
     "abea_align_batch",
     "abea_align_batch_device",
     "abea_align_batch_device_noalloc",
+    "abea_detect_events",
+    "abea_detect_events_device",
     "abea_get_timings",
     "abea_set_launch",
     "abea_cells_per_lane",
@@ -115,6 +119,30 @@ class abea_result_t(ctypes.Structure):
         ("log_likelihood", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
         ("cells", ctypes.c_void_p),
+    ]
+
+
+class abea_detect_params_t(ctypes.Structure):
+    _fields_ = [
+        ("window_short", ctypes.c_int32),
+        ("window_long", ctypes.c_int32),
+        ("threshold_short", ctypes.c_float),
+        ("threshold_long", ctypes.c_float),
+    ]
+
+
+def detect_params(window_short: int = DETECT_DEFAULT[0], window_long: int = DETECT_DEFAULT[1],
+                  threshold_short: float = DETECT_DEFAULT[2], threshold_long: float = DETECT_DEFAULT[3]):
+    return abea_detect_params_t(int(window_short), int(window_long), float(threshold_short), float(threshold_long))
+
+
+class abea_raw_batch_t(ctypes.Structure):
+    _fields_ = [
+        ("n_reads", ctypes.c_int32),
+        ("samples", ctypes.c_void_p),
+        ("sample_offset", ctypes.c_void_p),
+        ("offset", ctypes.c_void_p),
+        ("pa_scale", ctypes.c_void_p),
     ]
 
 
@@ -241,6 +269,12 @@ def lib() -> ctypes.CDLL:
         L.abea_align_batch_device_noalloc.argtypes = [P, ctypes.POINTER(abea_batch_t), ctypes.POINTER(abea_result_t),
                                                       P]
         L.abea_align_batch_device_noalloc.restype = ctypes.c_int
+        L.abea_detect_events.argtypes = [P, ctypes.POINTER(abea_raw_batch_t), ctypes.POINTER(abea_detect_params_t),
+                                         P, ctypes.c_uint64, P]
+        L.abea_detect_events.restype = ctypes.c_int
+        L.abea_detect_events_device.argtypes = [P, ctypes.POINTER(abea_raw_batch_t),
+                                                ctypes.POINTER(abea_detect_params_t), P, ctypes.c_uint64, P, P]
+        L.abea_detect_events_device.restype = ctypes.c_int
         L.abea_get_timings.argtypes = [P, P, ctypes.c_int]
         L.abea_get_timings.restype = ctypes.c_int
         L.abea_set_launch.argtypes = [P, ctypes.POINTER(abea_launch_t)]
@@ -419,6 +453,38 @@ class Aligner:
             "abea_align_batch_device_noalloc",
         )
 
+    def detect_events(self, raw_batch, params=None, event_capacity: Optional[int] = None):
+        """Event detection of a host raw batch (``synth.RawBatch``-like) through
+        abea_detect_events: (events float32 [m, 3], event_offset uint64 [n+1])."""
+        n = raw_batch.n_reads
+        x = np.ascontiguousarray(raw_batch.raw, np.int16)
+        so = np.ascontiguousarray(raw_batch.sample_offset, np.uint64)
+        off = np.ascontiguousarray(raw_batch.offset, np.float32)
+        sc = np.ascontiguousarray(raw_batch.pa_scale, np.float32)
+        cap = int(so[-1]) if event_capacity is None else int(event_capacity)
+        ev = np.zeros((max(cap, 1), 3), np.float32)
+        eo = np.zeros(n + 1, np.uint64)
+        b = abea_raw_batch_t(n, _ptr(x), _ptr(so), _ptr(off), _ptr(sc))
+        p = params if params is not None else detect_params()
+        self._check(lib().abea_detect_events(self.handle, ctypes.byref(b), ctypes.byref(p), _ptr(ev), cap, _ptr(eo)),
+                    "abea_detect_events")
+        return ev[: int(eo[-1])], eo
+
+    def detect_events_device(self, draw: "DeviceRawBatch", events, event_offset, params=None,
+                             event_capacity: Optional[int] = None, stream=None) -> None:
+        """Device raw batch through abea_detect_events_device (asynchronous):
+        ``events`` a torch float32 [cap, 3] and ``event_offset`` a torch int64
+        [n+1] on the device."""
+        cap = int(events.shape[0]) if event_capacity is None else int(event_capacity)
+        b = abea_raw_batch_t(draw.n_reads, _ptr(draw.samples), _ptr(draw.sample_offset), _ptr(draw.offset),
+                             _ptr(draw.pa_scale))
+        p = params if params is not None else detect_params()
+        self._check(
+            lib().abea_detect_events_device(self.handle, ctypes.byref(b), ctypes.byref(p), _ptr(events), cap,
+                                            _ptr(event_offset), ctypes.c_void_p(_stream_ptr(stream, self.device))),
+            "abea_detect_events_device",
+        )
+
     def timings(self) -> np.ndarray:
         """Milliseconds of [prep, band, backtrack, compaction] of the last call."""
         out = np.zeros(4, np.float32)
@@ -514,6 +580,32 @@ def to_device(batch, device: int = 0) -> DeviceBatch:
         torch.from_numpy(np.ascontiguousarray(batch.shift, np.float32)).to(dev),
         np.ascontiguousarray(batch.event_offset, np.uint64),
         np.ascontiguousarray(batch.kmer_offset, np.uint64),
+    )
+
+
+@dataclasses.dataclass
+class DeviceRawBatch:
+    n_reads: int
+    samples: object  # torch int16 [S] on the device
+    offset: object  # torch float32 [n]
+    pa_scale: object  # torch float32 [n]
+    sample_offset: np.ndarray  # host uint64 [n+1]
+
+    @property
+    def n_samples(self) -> int:
+        return int(self.sample_offset[-1])
+
+
+def raw_to_device(raw_batch, device: int = 0) -> DeviceRawBatch:
+    import torch
+
+    dev = torch.device("cuda", device)
+    return DeviceRawBatch(
+        raw_batch.n_reads,
+        torch.from_numpy(np.ascontiguousarray(raw_batch.raw, np.int16)).to(dev),
+        torch.from_numpy(np.ascontiguousarray(raw_batch.offset, np.float32)).to(dev),
+        torch.from_numpy(np.ascontiguousarray(raw_batch.pa_scale, np.float32)).to(dev),
+        np.ascontiguousarray(raw_batch.sample_offset, np.uint64),
     )
 
 

@@ -12,6 +12,8 @@ SOURCES = [
     os.path.join(CSRC, "abea_kernels.hip"),
     os.path.join(CSRC, "abea_host.cpp"),
     os.path.join(CSRC, "abea_server.cpp"),
+    os.path.join(CSRC, "abea_detect.hip"),
+    os.path.join(CSRC, "abea_detect_host.cpp"),
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

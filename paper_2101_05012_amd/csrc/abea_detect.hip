@@ -1,0 +1,411 @@
+/*
+ * abea_detect.hip -- gfx950 kernels of event detection: the segmentation of
+ * each read's raw signal into events {mean, stdv, n} at sudden changes of the
+ * signal level (the thesis, Ch. 5 §5.2.2 "Methylation calling", its
+ * event-detection paragraph; its output is the event table of Alg. 5.1).
+ *
+ * The thesis gives no algorithm for the step.  The detector is a two-window
+ * change-point test:
+ *   - at a boundary i (between samples i-1 and i; defined for
+ *     w <= i <= n-w) the squared two-sample t statistic of the w samples
+ *     before and the w after, with population variances, is w D^2 / V with
+ *     D = S_r - S_l and V = w (Q_l + Q_r) - S_l^2 - S_r^2 (S sums, Q sums of
+ *     squares: exact integers); the quotient is taken in float32 as
+ *     ((float)D * (float)D) * (float)w / (float)(double)V, +inf for V = 0 and
+ *     D != 0, 0 for V = 0 and D = 0;
+ *   - i is a peak of the detector (w, t) if its statistic exceeds t^2 (as a
+ *     float), is greater than the statistic at every defined boundary up to
+ *     w-1 before it and not less than at every one up to w-1 after it;
+ *   - a short and a long detector; every peak of either starts an event;
+ *   - an event's mean and stdv come from its exact integer sum S and sum of
+ *     squares Q: m = (double)S / len, V = len*Q - S^2 (exact, then rounded
+ *     once to double), mean = (float)((m + offset) * pa_scale),
+ *     stdv = (float)(sqrt(V) / len * pa_scale), pA = (raw + offset) * pa_scale.
+ *
+ * The work is a stream over the raw samples:
+ *   k_ed_tiles     the tile table (one thread per read);
+ *   k_ed_detect    one workgroup per tile of 1024 boundaries of one read:
+ *                  samples to LDS, both statistics, peaks, one bit per
+ *                  boundary, and the tile's event count;
+ *   k_ed_scan      exclusive scan of the tile counts, per 1024 tiles, then
+ *                  over the blocks (k_ed_scan_top);
+ *   k_ed_events    one workgroup per tile: the tile's event starts in order,
+ *                  the end of its last event from the first change point of
+ *                  the read's next tiles, and one thread per event for its
+ *                  statistics;
+ *   k_ed_offsets   each read's first event.
+ */
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "abea_internal.h"
+
+namespace abea {
+
+namespace {
+
+constexpr int TS = ED_TILE;   /* boundaries per tile */
+constexpr int WMAX = ED_MAX_WINDOW;
+constexpr int XH = 2 * WMAX;  /* samples kept before (and after) the tile */
+constexpr int THL = WMAX;     /* statistics kept before (and after) the tile */
+constexpr int NX = TS + 2 * XH;
+constexpr int NT = TS + 2 * THL;
+constexpr int WORDS = TS / 64; /* flag words per tile */
+constexpr int THREADS = 256;
+constexpr int SCAN_TILES = 1024; /* tiles per block of the first scan level */
+constexpr int EXT = 256; /* samples staged after the tile for events that run past it */
+constexpr int NE = TS + EXT; /* samples the event kernel stages per tile */
+
+/* statistic of the detector with window w at boundary j of a read of n
+ * samples, from prefix sums: P[c] and PQ[c] sum the staged samples before
+ * sample j (and their squares).  Branch-free: the loads stay inside the
+ * staged range for every boundary of the tile and its halo. */
+__device__ __forceinline__ float ed_stat(const int *P, const long long *PQ, int c, int w, int64_t j, int64_t n) {
+  const int sl = P[c] - P[c - w];
+  const int sr = P[c + w] - P[c];
+  const int64_t ql = PQ[c] - PQ[c - w];
+  const int64_t qr = PQ[c + w] - PQ[c];
+  const int d = sr - sl;
+  const int64_t v = (int64_t)w * (ql + qr) - (int64_t)sl * sl - (int64_t)sr * sr;
+  const float df = (float)d;
+  const float num = (df * df) * (float)w;
+  const float den = (float)(double)v;
+  const float q = num / (v == 0 ? 1.0f : den);
+  const float t = v != 0 ? q : (d != 0 ? INFINITY : 0.0f);
+  return (j >= w && j <= n - w) ? t : -1.0f;
+}
+
+/* a peak of the detector (w, thr = t^2) at ts[q]: above the threshold,
+ * above the largest statistic up to w-1 before it, not below the largest up
+ * to w-1 after it.  Undefined boundaries hold -1, below every defined
+ * statistic, so they never block a peak. */
+template <int W>
+__device__ __forceinline__ bool ed_peak(const float *ts, int q, int w_rt, float thr) {
+  const float t = ts[q];
+  float lm = -1.0f, rm = -1.0f;
+  if constexpr (W > 0) {
+#pragma unroll
+    for (int m = 1; m < W; ++m) {
+      lm = fmaxf(lm, ts[q - m]);
+      rm = fmaxf(rm, ts[q + m]);
+    }
+  } else {
+    for (int m = 1; m < w_rt; ++m) {
+      lm = fmaxf(lm, ts[q - m]);
+      rm = fmaxf(rm, ts[q + m]);
+    }
+  }
+  return (t > thr) & (t > lm) & (t >= rm);
+}
+
+/* Stage samples base+k, k in [0, NS), of a read (zero outside [0, lim)) as
+ * prefix sums: P[k] and PQ[k] sum the first k values and their squares.
+ * Thread t takes PER_ consecutive samples; the sums are scanned over the wave
+ * and over the waves.  Ends with a barrier. */
+template <int NS>
+__device__ __forceinline__ void stage_prefix(const int16_t *x, int64_t base, int64_t lim, int *P, long long *PQ,
+                                             int *wsum, long long *wsq) {
+  constexpr int PER_ = (NS + THREADS - 1) / THREADS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int v[PER_];
+  int s = 0;
+  long long q = 0;
+#pragma unroll
+  for (int e = 0; e < PER_; ++e) {
+    const int k = PER_ * (int)threadIdx.x + e;
+    const int64_t si = base + k;
+    v[e] = (k < NS && si >= 0 && si < lim) ? (int)x[si] : 0;
+    s += v[e];
+    q += (long long)v[e] * v[e];
+  }
+  int si = s;
+  long long qi = q;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int so = __shfl_up(si, d, 64);
+    const long long qo = __shfl_up(qi, d, 64);
+    if (lane >= d) {
+      si += so;
+      qi += qo;
+    }
+  }
+  if (lane == 63) {
+    wsum[wave] = si;
+    wsq[wave] = qi;
+  }
+  __syncthreads();
+  int ps = si - s;
+  long long pq = qi - q;
+  for (int w = 0; w < wave; ++w) {
+    ps += wsum[w];
+    pq += wsq[w];
+  }
+  if (threadIdx.x == 0) {
+    P[0] = 0;
+    PQ[0] = 0;
+  }
+#pragma unroll
+  for (int e = 0; e < PER_; ++e) {
+    const int k = PER_ * (int)threadIdx.x + e;
+    ps += v[e];
+    pq += (long long)v[e] * v[e];
+    if (k < NS) {
+      P[k + 1] = ps;
+      PQ[k + 1] = pq;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+/* the tile table: one thread per read writes its tiles' entries */
+__global__ void k_ed_tiles(DetectArgs a) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n_reads) return;
+  const uint64_t s0 = a.sample_offset[r];
+  const uint32_t n = (uint32_t)(a.sample_offset[r + 1] - s0);
+  const uint32_t t0 = a.tile_first[r], t1 = a.tile_first[r + 1];
+  for (uint32_t t = t0; t < t1; ++t) {
+    EdTile e;
+    e.s0 = s0;
+    e.n = n;
+    e.i0 = (t - t0) * (uint32_t)TS;
+    e.read = (uint32_t)r;
+    e.g_end = t1;
+    a.tiles[t] = e;
+  }
+}
+
+/* WS, WL: the detector windows fixed at compile time, or 0 to read them
+ * from the arguments */
+template <int WS, int WL>
+__global__ __launch_bounds__(THREADS) void k_ed_detect(DetectArgs a) {
+  __shared__ int P[NX + 1];
+  __shared__ long long PQ[NX + 1];
+  __shared__ int wsum[THREADS / 64];
+  __shared__ long long wsq[THREADS / 64];
+  __shared__ float tsh[NT], tlg[NT];
+  __shared__ uint32_t wcnt[THREADS / 64];
+  __shared__ int32_t first_cp;
+  const uint32_t g = blockIdx.x;
+  const EdTile tl = a.tiles[g];
+  const int64_t n = tl.n;
+  const int64_t i0 = tl.i0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ws = WS > 0 ? WS : a.w_short;
+  const int wl = WL > 0 ? WL : a.w_long;
+
+  if (threadIdx.x == 0) first_cp = INT32_MAX;
+  /* samples i0-XH .. i0+TS+XH-1 */
+  stage_prefix<NX>(a.raw + tl.s0, i0 - XH, n, P, PQ, wsum, wsq);
+  /* boundary j = i0 - THL + k: the sums before it are P[k + XH - THL] */
+  for (int k = threadIdx.x; k < NT; k += THREADS) {
+    const int64_t j = i0 - THL + k;
+    const int c = k + XH - THL;
+    tsh[k] = ed_stat(P, PQ, c, ws, j, n);
+    tlg[k] = ed_stat(P, PQ, c, wl, j, n);
+  }
+  __syncthreads();
+  uint32_t cnt = 0;
+  for (int k0 = 0; k0 < TS; k0 += THREADS) {
+    const int q = k0 + (int)threadIdx.x + THL;
+    const bool cp = ((int)ed_peak<WS>(tsh, q, ws, a.thr_short) | (int)ed_peak<WL>(tlg, q, wl, a.thr_long)) != 0;
+    const uint64_t m = __ballot(cp);
+    if (lane == 0) {
+      a.flags[(uint64_t)g * WORDS + (k0 >> 6) + wave] = m;
+      cnt += (uint32_t)__popcll(m);
+      if (m) atomicMin(&first_cp, k0 + 64 * wave + __builtin_ctzll(m));
+    }
+  }
+  if (lane == 0) wcnt[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t c = (i0 == 0) ? 1u : 0u; /* the read's first event starts at sample 0 */
+    for (int w = 0; w < THREADS / 64; ++w) c += wcnt[w];
+    a.count[g] = c;
+    /* the tile's first change point in the read, -1 if it has none */
+    a.first_cp[g] = first_cp == INT32_MAX ? -1 : (int32_t)(i0 + first_cp);
+  }
+}
+
+namespace {
+
+/* exclusive scan of v over the workgroup (THREADS lanes); returns the prefix
+ * and sets total */
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *sh, uint64_t &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t inc = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wave) before += sh[w];
+    all += sh[w];
+  }
+  __syncthreads();
+  total = all;
+  return before + inc - v;
+}
+
+}  // namespace
+
+/* first level: tiles [b*1024, (b+1)*1024), four consecutive per thread */
+__global__ __launch_bounds__(THREADS) void k_ed_scan(DetectArgs a) {
+  __shared__ uint64_t sh[THREADS / 64];
+  const uint64_t t0 = (uint64_t)blockIdx.x * SCAN_TILES + 4u * threadIdx.x;
+  uint32_t c[4];
+  uint64_t s = 0;
+  for (int q = 0; q < 4; ++q) {
+    c[q] = (t0 + q < a.n_tiles) ? a.count[t0 + q] : 0u;
+    s += c[q];
+  }
+  uint64_t total;
+  uint64_t p = block_exclusive_scan(s, sh, total);
+  for (int q = 0; q < 4; ++q) {
+    if (t0 + q < a.n_tiles) a.base[t0 + q] = p;
+    p += c[q];
+  }
+  if (threadIdx.x == 0) a.block_sum[blockIdx.x] = total;
+}
+
+/* second level, one workgroup: exclusive scan of the block sums in place;
+ * block_sum[n_blocks] receives the batch's event count */
+__global__ __launch_bounds__(THREADS) void k_ed_scan_top(DetectArgs a, uint32_t n_blocks) {
+  __shared__ uint64_t sh[THREADS / 64];
+  uint64_t carry = 0;
+  for (uint32_t b0 = 0; b0 < n_blocks; b0 += THREADS) {
+    const uint32_t b = b0 + threadIdx.x;
+    const uint64_t v = b < n_blocks ? a.block_sum[b] : 0;
+    uint64_t total;
+    const uint64_t p = block_exclusive_scan(v, sh, total);
+    if (b < n_blocks) a.block_sum[b] = carry + p;
+    carry += total;
+  }
+  if (threadIdx.x == 0) a.block_sum[n_blocks] = carry;
+}
+
+__global__ __launch_bounds__(THREADS) void k_ed_events(DetectArgs a) {
+  __shared__ uint64_t wf[WORDS];
+  __shared__ uint32_t wpre[WORDS + 1];
+  __shared__ int32_t starts[TS + 1];
+  __shared__ long long tail_end;
+  /* prefix sums of samples i0 .. i0+TS+EXT-1 of the read (zero past its end) */
+  __shared__ int P[NE + 1];
+  __shared__ long long PQ[NE + 1];
+  __shared__ int wsum[THREADS / 64];
+  __shared__ long long wsq[THREADS / 64];
+  const uint32_t g = blockIdx.x;
+  const EdTile tl = a.tiles[g];
+  const int r = (int)tl.read;
+  const int64_t n = tl.n;
+  const int64_t i0 = tl.i0;
+  const int first = (i0 == 0) ? 1 : 0;
+  const uint64_t gbase = a.base[g] + a.block_sum[g / SCAN_TILES];
+  const int16_t *x = a.raw + tl.s0;
+
+  if (threadIdx.x < WORDS) wf[threadIdx.x] = a.flags[(uint64_t)g * WORDS + threadIdx.x];
+  if (threadIdx.x == 0) tail_end = n;
+  stage_prefix<NE>(x, i0, n, P, PQ, wsum, wsq);
+  /* the event that runs past the tile ends at the read's next change point:
+   * the first change point of the first later tile of the read that has one
+   * (first_cp grows with the tile), or at the read's end; 256 tiles a step */
+  for (uint32_t h0 = g + 1; h0 < tl.g_end; h0 += THREADS) {
+    const uint32_t h = h0 + threadIdx.x;
+    const int32_t f = h < tl.g_end ? a.first_cp[h] : -1;
+    if (f >= 0) atomicMin(&tail_end, (long long)f);
+    if (__syncthreads_or(f >= 0)) break;
+  }
+  if (threadIdx.x == 0) {
+    uint32_t p = first;
+    for (int w = 0; w < WORDS; ++w) {
+      wpre[w] = p;
+      p += (uint32_t)__popcll(wf[w]);
+    }
+    wpre[WORDS] = p;
+    if (first) starts[0] = 0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < TS; k += THREADS) {
+    const uint64_t m = wf[k >> 6];
+    const int b = k & 63;
+    if ((m >> b) & 1u) {
+      const uint64_t below = b ? (m & ((1ull << b) - 1u)) : 0ull;
+      starts[wpre[k >> 6] + (uint32_t)__popcll(below)] = (int32_t)(i0 + k);
+    }
+  }
+  __syncthreads();
+  const int n_ev = (int)wpre[WORDS];
+  const double off = (double)a.offset[r];
+  const double sc = (double)a.pa_scale[r];
+  const int64_t lim = i0 + NE; /* staged: [i0, lim) */
+  for (int e = threadIdx.x; e < n_ev; e += THREADS) {
+    const uint64_t idx = gbase + (uint64_t)e;
+    if (idx >= a.capacity) continue;
+    const int64_t b0 = starts[e];
+    const int64_t b1 = (e + 1 < n_ev) ? (int64_t)starts[e + 1] : (int64_t)tail_end;
+    /* the event's sums from the staged prefix sums; past the staged range
+     * (an event that runs far beyond the tile) from memory */
+    const int64_t bs = b1 < lim ? b1 : lim;
+    int64_t s = (int64_t)P[bs - i0] - P[b0 - i0];
+    int64_t q = PQ[bs - i0] - PQ[b0 - i0];
+    for (int64_t j = bs; j < b1; ++j) {
+      const int64_t v = x[j];
+      s += v;
+      q += v * v;
+    }
+    const int64_t len = b1 - b0;
+    const double m = (double)s / (double)len;
+    /* len^2 times the population variance, exact, rounded once to double */
+    const unsigned __int128 vv =
+        (unsigned __int128)((__int128)len * q - (__int128)s * s);
+    const uint64_t hi = (uint64_t)(vv >> 64);
+    double vd;
+    if (hi == 0) {
+      vd = (double)(uint64_t)vv;
+    } else {
+      /* keep the top 64 bits and a sticky bit: one rounding to double */
+      const int k = 64 - __builtin_clzll(hi);
+      const unsigned __int128 low = vv & ((((unsigned __int128)1) << k) - 1);
+      const uint64_t top = (uint64_t)(vv >> k) | (low != 0 ? 1u : 0u);
+      vd = __builtin_ldexp((double)top, k);
+    }
+    float *ev = a.events + 3 * idx;
+    ev[0] = (float)((m + off) * sc);
+    ev[1] = (float)(__builtin_sqrt(vd) / (double)len * sc);
+    ev[2] = (float)len;
+  }
+}
+
+__global__ void k_ed_offsets(DetectArgs a, uint32_t n_blocks) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > a.n_reads) return;
+  const uint32_t t = a.tile_first[r];
+  a.event_offset[r] = t < a.n_tiles ? a.base[t] + a.block_sum[t / SCAN_TILES] : a.block_sum[n_blocks];
+}
+
+uint32_t ed_scan_blocks(uint32_t n_tiles) { return (n_tiles + SCAN_TILES - 1) / SCAN_TILES; }
+
+hipError_t launch_detect(const DetectArgs &a, hipStream_t st) {
+  const uint32_t nb = ed_scan_blocks(a.n_tiles);
+  if (a.n_tiles > 0) {
+    hipLaunchKernelGGL(k_ed_tiles, dim3((a.n_reads + 255) / 256), dim3(256), 0, st, a);
+    if (a.w_short == 3 && a.w_long == 8)
+      hipLaunchKernelGGL((k_ed_detect<3, 8>), dim3(a.n_tiles), dim3(THREADS), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_ed_detect<0, 0>), dim3(a.n_tiles), dim3(THREADS), 0, st, a);
+    hipLaunchKernelGGL(k_ed_scan, dim3(nb), dim3(THREADS), 0, st, a);
+  }
+  hipLaunchKernelGGL(k_ed_scan_top, dim3(1), dim3(THREADS), 0, st, a, nb);
+  if (a.n_tiles > 0) hipLaunchKernelGGL(k_ed_events, dim3(a.n_tiles), dim3(THREADS), 0, st, a);
+  const int nr = a.n_reads + 1;
+  hipLaunchKernelGGL(k_ed_offsets, dim3((nr + 255) / 256), dim3(256), 0, st, a, nb);
+  return hipGetLastError();
+}
+
+}  // namespace abea

@@ -534,6 +534,13 @@ int stage_down(abea_ctx *ctx, const void *src, size_t bytes, Drain drain) {
   return ABEA_OK;
 }
 
+int stage_copy_down(abea_ctx *ctx, void *dst, const void *src, size_t bytes) {
+  char *d = (char *)dst;
+  return stage_down(ctx, src, bytes, [d](size_t off, size_t len, const char *s) {
+    parallel_for(len, 1u << 20, [d, off, s](size_t lo, size_t hi) { std::memcpy(d + off + lo, s + lo, hi - lo); });
+  });
+}
+
 int check_batch(abea_ctx *ctx, const abea_batch_t *b, const abea_result_t *r) {
   if (!ctx) return ABEA_E_INVAL;
   if (!b || !r) return fail(ctx, ABEA_E_INVAL, "null batch or result");
@@ -655,6 +662,7 @@ void abea_destroy(abea_ctx *ctx) {
   hipStream_t st = ctx->own_stream;
   (void)work_wait(ctx, ctx->noalloc);
   if (st) (void)hipStreamSynchronize(st);
+  detect_free(ctx, st);
   work_free(ctx->main, st);
   work_free(ctx->noalloc, st);
   DevBuf *bufs[] = {&ctx->model, &ctx->events, &ctx->ranks, &ctx->scale, &ctx->shift,
@@ -874,12 +882,7 @@ int abea_align_batch(abea_ctx *ctx, const abea_batch_t *b, abea_result_t *r) {
   const uint64_t total = r->pair_offset[n];
   if (total > r->pair_capacity) return fail(ctx, ABEA_E_HIP, "internal: %llu pairs exceed capacity",
                                             (unsigned long long)total);
-  char *dst = (char *)r->pairs;
-  rc = stage_down(ctx, io.pairs, sizeof(abea_pair_t) * total, [dst](size_t off, size_t len, const char *src) {
-    parallel_for(len, 1u << 20, [dst, off, src](size_t lo, size_t hi) { std::memcpy(dst + off + lo, src + lo, hi - lo); });
-  });
-  if (rc) return rc;
-  return ABEA_OK;
+  return stage_copy_down(ctx, r->pairs, io.pairs, sizeof(abea_pair_t) * total);
 }
 
 int abea_get_timings(abea_ctx *ctx, float *out, int n) {

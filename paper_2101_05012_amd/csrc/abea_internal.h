@@ -139,6 +139,48 @@ hipError_t noalloc_scratch(int device, void **ptr);
 hipError_t launch_compact(const int2 *scratch, const uint64_t *path_src, const uint64_t *offset,
                           int n, int2 *pairs, hipStream_t st);
 
+/* ---- event detection (abea_detect.hip) ---- */
+constexpr int ED_TILE = 1024;       /* boundaries per tile of one read */
+constexpr int ED_MAX_WINDOW = 16;   /* largest detector window */
+
+/* One tile of event detection: its read, where the read's samples start,
+ * the read's length, the tile's first boundary in the read and the end of
+ * the read's tiles. */
+struct EdTile {
+  uint64_t s0;
+  uint32_t n;
+  uint32_t i0;
+  uint32_t read;
+  uint32_t g_end;
+};
+static_assert(sizeof(EdTile) == 24, "EdTile is 24 bytes");
+
+struct DetectArgs {
+  const int16_t *raw;            /* the batch's samples, concatenated */
+  const uint64_t *sample_offset; /* [n_reads+1] */
+  const uint32_t *tile_first;    /* [n_reads+1]: first tile of each read (ceil(n/ED_TILE) tiles) */
+  EdTile *tiles;                 /* [n_tiles], made by the first launch from the two above */
+  const float *offset;           /* [n_reads] pA = (raw + offset) * pa_scale */
+  const float *pa_scale;         /* [n_reads] */
+  int32_t n_reads;
+  uint32_t n_tiles;
+  int32_t w_short, w_long;       /* detector windows */
+  float thr_short, thr_long;     /* squared t thresholds */
+  uint64_t *flags;               /* [n_tiles * ED_TILE/64]: one bit per boundary, set at change points */
+  uint32_t *count;               /* [n_tiles]: events starting in the tile */
+  int32_t *first_cp;             /* [n_tiles]: the tile's first change point, -1 if none */
+  uint64_t *base;                /* [n_tiles]: first event of the tile within its scan block */
+  uint64_t *block_sum;           /* [blocks+1]: first event of each scan block, then the total */
+  float *events;                 /* [capacity][3]: mean, stdv, duration */
+  uint64_t capacity;
+  uint64_t *event_offset;        /* [n_reads+1] */
+};
+/* Blocks of the tile-count scan for n_tiles tiles. */
+uint32_t ed_scan_blocks(uint32_t n_tiles);
+/* Detection of a planned batch: change points, the scan of the event counts,
+ * the events (those beyond a.capacity are not written) and event_offset. */
+hipError_t launch_detect(const DetectArgs &a, hipStream_t st);
+
 }  // namespace abea
 
 #endif

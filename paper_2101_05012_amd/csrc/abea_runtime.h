@@ -85,6 +85,8 @@ struct DevIO {
   uint64_t *cells;
 };
 
+struct DetectWork; /* event detection's state (abea_detect_host.cpp), made at its first call */
+
 }  // namespace abea_rt
 
 struct abea_ctx {
@@ -113,6 +115,7 @@ struct abea_ctx {
   hipEvent_t stage_ev[2] = {nullptr, nullptr};
   bool stage_pending[2] = {false, false};
   int stage_next = 0;
+  abea_rt::DetectWork *detect = nullptr;
   std::string err;
 };
 
@@ -156,6 +159,14 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
 int ensure_work(abea_ctx *ctx, Work &w, hipStream_t st, bool staged_events = false);
 /* Kernels of a planned batch whose plan is on the device. */
 int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, bool timed);
+/* The host API's pinned staging ring (two chunks, made at the first call)
+ * and copies through it on the context's own stream; the copy down returns
+ * once the data is in dst. */
+int stage_init(abea_ctx *ctx);
+int stage_copy_up(abea_ctx *ctx, void *dst, const void *src, size_t bytes);
+int stage_copy_down(abea_ctx *ctx, void *dst, const void *src, size_t bytes);
+/* Release the detection state on `st` after its last work. */
+void detect_free(abea_ctx *ctx, hipStream_t st);
 
 }  // namespace abea_rt
 

@@ -98,8 +98,23 @@ def test_binding_constants_and_structs_match_the_header():
         assert name in defs and hasattr(abea, name), name
     assert checked >= 8
     body = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    for cname, cls in (("abea_launch_t", abea.abea_launch_t), ("abea_plan_info_t", abea.abea_plan_info_t)):
+    for cname, cls in (("abea_launch_t", abea.abea_launch_t), ("abea_plan_info_t", abea.abea_plan_info_t),
+                       ("abea_detect_params_t", abea.abea_detect_params_t),
+                       ("abea_raw_batch_t", abea.abea_raw_batch_t)):
         m = re.search(r"typedef struct \{([^}]*)\}\s*" + cname + ";", body)
         assert m, cname
         fields = re.findall(r"\b([a-z_]+);", m.group(1))
         assert fields == [f for f, _ in cls._fields_], cname
+
+
+def test_detect_defaults_agree():
+    """The header's default detector, the binding's and the oracle's default
+    parameters are the same four numbers."""
+    src = open(os.path.join(ROOT, "include", "abea.h")).read()
+    m = re.search(r"#define ABEA_DETECT_DEFAULT_PARAMS \{([^}]*)\}", src)
+    vals = [float(v.strip().rstrip("f")) for v in m.group(1).split(",")]
+    assert vals == [float(v) for v in abea.DETECT_DEFAULT]
+    from oracle import oracle as orc
+
+    p = orc.ed_params()
+    assert vals == [p.w_short, p.w_long, p.t_short, p.t_long]
