@@ -33,6 +33,9 @@ Other workloads (``--workload``):
   ultralong-200-*: 200 reads of 200 kb..1 Mb (W = 100 or 250, k = 6 or 9).
       The persistent kernel under a trace budget, and the backtrack's
       throughput.
+  raw-4000-lognormal5kb: event detection (the step before the alignment)
+      on the raw signal of 4000 log-normal reads, 4 kHz samples at 450
+      bases/s (293 M int16 samples); value in G samples/s, roofline on HBM.
   serving-512ch: reads arrive from 512 simulated channels (Poisson, 400
       bases/s each, log-normal lengths with median 8 kb) into the library's
       continuous-batching server.  The replay is sped up 1x..10000x; each
@@ -95,7 +98,17 @@ WORKLOADS = {
     "ultralong-200-w250-k9": dict(kind="persistent", source="ultralong-200", W=250, k=9, plain_batches=1,
                                   launch=(4, 1, 4, 1)),
     "serving-512ch": dict(kind="serving", source="serving-lognormal8kb", W=100, k=6),
+    # event detection: the raw signal of 4000 log-normal reads (4 kHz samples,
+    # 450 bases/s) cut into events on the GPU
+    "raw-4000-lognormal5kb": dict(kind="detect", source="raw-4000-lognormal5kb", W=100, k=6),
 }
+
+HBM_PEAK_GBS = 8000.0
+# HBM bytes of one k_ed_events launch (the slower detection kernel), from
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE with the same calibration factors
+# as ALIGN_TRAFFIC_BYTES; null for a workload without a measurement of the
+# current kernels.
+DETECT_TRAFFIC_BYTES = {"raw-4000-lognormal5kb": 1.5632e9}
 
 # serving: (time compression, reads) per load level; x1 is real time for 512
 # channels at 400 bases/s each
@@ -501,6 +514,9 @@ def bench_persistent(args, wl):
                              job_gcups=gcups if launch.batches == 1 else None),
     })
     if wl.get("extras") and not args.no_extras:
+        log("bench: event detection (raw-4000-lognormal5kb)")
+        out["event_detection"] = detect_summary(detect_run(args, WORKLOADS["raw-4000-lognormal5kb"], dev,
+                                                           steps=10, warmup=2))
         log("bench: host-buffer API on the first 4000 reads")
         sub = batch.subset(range(min(4000, n)))
         alh = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
@@ -521,6 +537,125 @@ def bench_persistent(args, wl):
         idx = sample_reads(batch, W, args.cpu_sample_gcells * 1e9)
         stride = idx[1] - idx[0] if len(idx) > 1 else 1
         out["cpu_baseline"] = cpu_baseline(batch, model, W, idx, f"every {stride}-th read of the same workload")
+    return out
+
+
+# ------------------------------------------------------------ event detection
+
+
+def detect_run(args, wl, dev, steps, warmup):
+    """Event detection of a whole raw workload resident in HBM: ``warmup``
+    untimed passes, then ``steps`` timed passes (HIP events on the launch
+    stream around them), and one timed pass's kernel times from the
+    library's own dispatch events."""
+    import torch
+
+    from paper_2101_05012_amd import abea, synth
+
+    model = synth.pore_model(wl["k"])
+    t0 = time.perf_counter()
+    rb = synth.workload_raw_batch(wl["source"], model)
+    S = int(rb.sample_offset[-1])
+    log(f"bench: {rb.n_reads} raw reads, {S} samples, generated in {time.perf_counter() - t0:.1f} s")
+    al = abea.Aligner(model.level_mean, model.level_stdv, wl["k"], W=wl["W"], device=dev, timing=True)
+    d = abea.raw_to_device(rb, dev)
+    ev = torch.empty((max(S, 1), 3), dtype=torch.float32, device=f"cuda:{dev}")
+    eo = torch.empty(rb.n_reads + 1, dtype=torch.int64, device=f"cuda:{dev}")
+    st = torch.cuda.current_stream(dev)
+    for _ in range(warmup):
+        al.detect_events_device(d, ev, eo, stream=st)
+    torch.cuda.synchronize()
+    kms = al.detect_timings()  # the last warmup pass, alone on the stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        al.detect_events_device(d, ev, eo, stream=st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    n_ev = int(eo[-1].item())
+    al.close()
+    return {"rb": rb, "S": S, "n_events": n_ev, "ms": ms, "kernel_ms": [float(x) for x in kms],
+            "steps": steps, "warmup": warmup}
+
+
+def detect_roofline(r, workload):
+    """HBM roofline of the slower of the two streaming kernels, on their
+    algorithmic bytes: k_ed_detect reads 2 B per sample; k_ed_events reads
+    2 B per sample and writes one 12-byte event record per event."""
+    S, E = r["S"], r["n_events"]
+    det_ms, ev_ms = r["kernel_ms"][0], r["kernel_ms"][1]
+    by = {"k_ed_detect": (2.0 * S, det_ms), "k_ed_events": (2.0 * S + 12.0 * E, ev_ms)}
+    name = max(by, key=lambda k: by[k][1])
+    nbytes, kms = by[name]
+    gbs = nbytes / (kms / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": DETECT_TRAFFIC_BYTES.get(workload),
+            "algorithmic_bytes": nbytes,
+            "achieved_job": round((2.0 * S + 12.0 * E) / (r["ms"] / 1e3) / 1e9, 1)}
+
+
+def detect_summary(r):
+    return {"workload": "raw-4000-lognormal5kb", "samples": r["S"], "events": r["n_events"],
+            "ms_per_pass": round(r["ms"], 4), "gsamples_per_s": round(r["S"] / r["ms"] / 1e6, 2),
+            "events_per_kmer": round(r["n_events"] / float(r["rb"].kmer_offset[-1]), 3),
+            "kernel_ms": {"k_ed_detect": round(r["kernel_ms"][0], 4), "k_ed_events": round(r["kernel_ms"][1], 4),
+                          "pass": round(r["kernel_ms"][2], 4)},
+            "roofline": detect_roofline(r, "raw-4000-lognormal5kb")}
+
+
+def bench_detect(args, wl):
+    dev = 0
+    r = detect_run(args, wl, dev, args.steps, args.warmup)
+    S, ms = r["S"], r["ms"]
+    out = {
+        "metric": "event detection throughput (raw samples cut into events per second) on 1 MI355X",
+        "value": round(S / ms / 1e6, 3),
+        "unit": "G samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64+f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_reads": r["rb"].n_reads, "samples_per_step": S,
+                   "detector": "windows 3 and 8 samples, t thresholds 1.5 and 5.0"},
+        "events_per_step": r["n_events"],
+        "events_per_kmer": round(r["n_events"] / float(r["rb"].kmer_offset[-1]), 3),
+        "kernel_ms": {"k_ed_detect": round(r["kernel_ms"][0], 4), "k_ed_events": round(r["kernel_ms"][1], 4),
+                      "pass": round(r["kernel_ms"][2], 4)},
+        "roofline": detect_roofline(r, args.workload),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+
+        cores = min(16, os.cpu_count() or 1)
+        log("bench: cpu baseline (oracle)")
+        t0 = time.perf_counter()
+        O.ed_batch(r["rb"], n_threads=cores)
+        dt = time.perf_counter() - t0
+        sub = r["rb"]
+        n1 = 200
+        from paper_2101_05012_amd import synth
+
+        one = synth.make_raw_batch([synth.RawRead(sub.read_raw(i), sub.read_ranks(i), sub.offset[i],
+                                                  sub.pa_scale[i], sub.scale[i], sub.shift[i],
+                                                  np.zeros(0, np.int64)) for i in range(n1)])
+        t1 = time.perf_counter()
+        O.ed_batch(one, n_threads=1)
+        dt1 = time.perf_counter() - t1
+        s1 = int(one.sample_offset[-1])
+        out["cpu_baseline"] = {
+            "value": round(S / dt / 1e9, 4), "unit": "G samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole workload: {S} samples, {dt:.2f} s",
+            "one_thread": {"value": round(s1 / dt1 / 1e9, 4), "unit": "G samples/s",
+                           "sample": f"the first {n1} reads, {s1} samples, {dt1:.2f} s"},
+            "host_cpu": host_cpu(),
+        }
     return out
 
 
@@ -761,9 +896,9 @@ def main():
     # plain: enough batches that the drain of the last ones in flight is a
     # small part of the timed region; persistent: whole passes of the job
     if args.steps is None:
-        args.steps = 200 if wl["kind"] == "plain" else 10
+        args.steps = {"plain": 200, "detect": 20}.get(wl["kind"], 10)
     if args.warmup is None:
-        args.warmup = 16 if wl["kind"] == "plain" else 1
+        args.warmup = {"plain": 16, "detect": 3}.get(wl["kind"], 1)
     if args.wpg <= 0 and wl["kind"] != "persistent":
         args.wpg = 1
     if 0 < args.hw_queues <= 32:
@@ -773,6 +908,8 @@ def main():
         copy_calibration(args.copy_calibration_mb)
     if wl["kind"] == "plain":
         out = bench_plain(args, wl)
+    elif wl["kind"] == "detect":
+        out = bench_detect(args, wl)
     elif wl["kind"] == "serving":
         out = bench_serving(args, wl)
     else:

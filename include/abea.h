@@ -315,6 +315,16 @@ int abea_detect_events(abea_ctx *ctx, const abea_raw_batch_t *raw, const abea_de
                        abea_event_t *events, uint64_t event_capacity, uint64_t *event_offset);
 
 /*
+ * Device time in milliseconds of the last detection call on a context created
+ * with ABEA_F_TIMING: out[0] the change-point kernel (statistics and peaks),
+ * out[1] the event kernel (event statistics), each from the start to the end
+ * of its own dispatch, out[2] the whole batch on its stream.  Synchronises
+ * with that call.  n is the length of out.
+ * Errors: ABEA_E_INVAL (no timed detection call), ABEA_E_HIP.
+ */
+int abea_get_detect_timings(abea_ctx *ctx, float *out, int n);
+
+/*
  * Device time in milliseconds of each stage of the last direct call
  * (abea_align_batch or abea_align_batch_device), when the context was
  * created with ABEA_F_TIMING: out[0] k-mer parameter preparation, out[1] band

@@ -51,6 +51,7 @@ EXPORTED = (
     "abea_align_batch_device_noalloc",
     "abea_detect_events",
     "abea_detect_events_device",
+    "abea_get_detect_timings",
     "abea_get_timings",
     "abea_set_launch",
     "abea_cells_per_lane",
@@ -275,6 +276,8 @@ def lib() -> ctypes.CDLL:
         L.abea_detect_events_device.argtypes = [P, ctypes.POINTER(abea_raw_batch_t),
                                                 ctypes.POINTER(abea_detect_params_t), P, ctypes.c_uint64, P, P]
         L.abea_detect_events_device.restype = ctypes.c_int
+        L.abea_get_detect_timings.argtypes = [P, P, ctypes.c_int]
+        L.abea_get_detect_timings.restype = ctypes.c_int
         L.abea_get_timings.argtypes = [P, P, ctypes.c_int]
         L.abea_get_timings.restype = ctypes.c_int
         L.abea_set_launch.argtypes = [P, ctypes.POINTER(abea_launch_t)]
@@ -484,6 +487,13 @@ class Aligner:
                                             _ptr(event_offset), ctypes.c_void_p(_stream_ptr(stream, self.device))),
             "abea_detect_events_device",
         )
+
+    def detect_timings(self) -> np.ndarray:
+        """Milliseconds of [change-point kernel, event kernel, whole batch] of
+        the last detection call (the context needs timing=True)."""
+        out = np.zeros(3, np.float32)
+        self._check(lib().abea_get_detect_timings(self.handle, _ptr(out), 3), "abea_get_detect_timings")
+        return out
 
     def timings(self) -> np.ndarray:
         """Milliseconds of [prep, band, backtrack, compaction] of the last call."""

@@ -23,7 +23,7 @@
  *     stdv = (float)(sqrt(V) / len * pa_scale), pA = (raw + offset) * pa_scale.
  *
  * The work is a stream over the raw samples:
- *   k_ed_tiles     the tile table (one thread per read);
+ *   k_ed_tiles     the tile table (one wavefront per read);
  *   k_ed_detect    one workgroup per tile of 1024 boundaries of one read:
  *                  samples to LDS, both statistics, peaks, one bit per
  *                  boundary, and the tile's event count;
@@ -35,6 +35,7 @@
  *                  statistics;
  *   k_ed_offsets   each read's first event.
  */
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -160,14 +161,14 @@ __device__ __forceinline__ void stage_prefix(const int16_t *x, int64_t base, int
 
 }  // namespace
 
-/* the tile table: one thread per read writes its tiles' entries */
+/* the tile table: one wavefront per read writes its tiles' entries */
 __global__ void k_ed_tiles(DetectArgs a) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= a.n_reads) return;
   const uint64_t s0 = a.sample_offset[r];
   const uint32_t n = (uint32_t)(a.sample_offset[r + 1] - s0);
   const uint32_t t0 = a.tile_first[r], t1 = a.tile_first[r + 1];
-  for (uint32_t t = t0; t < t1; ++t) {
+  for (uint32_t t = t0 + (threadIdx.x & 63); t < t1; t += 64) {
     EdTile e;
     e.s0 = s0;
     e.n = n;
@@ -391,20 +392,40 @@ __global__ void k_ed_offsets(DetectArgs a, uint32_t n_blocks) {
 
 uint32_t ed_scan_blocks(uint32_t n_tiles) { return (n_tiles + SCAN_TILES - 1) / SCAN_TILES; }
 
-hipError_t launch_detect(const DetectArgs &a, hipStream_t st) {
+hipError_t launch_detect(const DetectArgs &a, hipStream_t st, hipEvent_t *tev) {
   const uint32_t nb = ed_scan_blocks(a.n_tiles);
+  hipEvent_t e0 = tev ? tev[0] : nullptr, e1 = tev ? tev[1] : nullptr;
+  hipEvent_t e2 = tev ? tev[2] : nullptr, e3 = tev ? tev[3] : nullptr;
+  if (tev) {
+    const hipError_t e = hipEventRecord(tev[4], st);
+    if (e != hipSuccess) return e;
+  }
   if (a.n_tiles > 0) {
-    hipLaunchKernelGGL(k_ed_tiles, dim3((a.n_reads + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_ed_tiles, dim3((a.n_reads + 3) / 4), dim3(256), 0, st, a);
+    /* the two streaming kernels take their start and end from their own
+     * dispatch when timed */
     if (a.w_short == 3 && a.w_long == 8)
-      hipLaunchKernelGGL((k_ed_detect<3, 8>), dim3(a.n_tiles), dim3(THREADS), 0, st, a);
+      hipExtLaunchKernelGGL((k_ed_detect<3, 8>), dim3(a.n_tiles), dim3(THREADS), 0, st, e0, e1, 0, a);
     else
-      hipLaunchKernelGGL((k_ed_detect<0, 0>), dim3(a.n_tiles), dim3(THREADS), 0, st, a);
+      hipExtLaunchKernelGGL((k_ed_detect<0, 0>), dim3(a.n_tiles), dim3(THREADS), 0, st, e0, e1, 0, a);
     hipLaunchKernelGGL(k_ed_scan, dim3(nb), dim3(THREADS), 0, st, a);
+  } else if (tev) {
+    (void)hipEventRecord(e0, st);
+    (void)hipEventRecord(e1, st);
   }
   hipLaunchKernelGGL(k_ed_scan_top, dim3(1), dim3(THREADS), 0, st, a, nb);
-  if (a.n_tiles > 0) hipLaunchKernelGGL(k_ed_events, dim3(a.n_tiles), dim3(THREADS), 0, st, a);
+  if (a.n_tiles > 0) {
+    hipExtLaunchKernelGGL(k_ed_events, dim3(a.n_tiles), dim3(THREADS), 0, st, e2, e3, 0, a);
+  } else if (tev) {
+    (void)hipEventRecord(e2, st);
+    (void)hipEventRecord(e3, st);
+  }
   const int nr = a.n_reads + 1;
   hipLaunchKernelGGL(k_ed_offsets, dim3((nr + 255) / 256), dim3(256), 0, st, a, nb);
+  if (tev) {
+    const hipError_t e = hipEventRecord(tev[5], st);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

@@ -32,6 +32,9 @@ struct DetectWork {
   char *h_plan = nullptr; /* pinned: sample offsets, then first tiles */
   size_t h_cap = 0;
   std::vector<void *> retired_host;
+  /* ABEA_F_TIMING: k_ed_detect's dispatch, k_ed_events's, the whole batch */
+  hipEvent_t tev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
 };
 
 void detect_free(abea_ctx *ctx, hipStream_t st) {
@@ -45,6 +48,8 @@ void detect_free(abea_ctx *ctx, hipStream_t st) {
   d->w.staging_pending = false;
   if (d->h_plan) (void)hipHostFree(d->h_plan);
   for (void *h : d->retired_host) (void)hipHostFree(h);
+  for (hipEvent_t &e : d->tev)
+    if (e) (void)hipEventDestroy(e);
   work_free(d->w, st);
   delete d;
   ctx->detect = nullptr;
@@ -86,8 +91,12 @@ int detect_work(abea_ctx *ctx, DetectWork **out) {
   if (!ctx->detect) {
     DetectWork *d = new (std::nothrow) DetectWork();
     if (!d) return fail(ctx, ABEA_E_NOMEM, "detection state");
-    const int rc = work_init(ctx, d->w);
+    int rc = work_init(ctx, d->w);
+    for (hipEvent_t &e : d->tev)
+      if (rc == ABEA_OK && hipEventCreate(&e) != hipSuccess) rc = fail(ctx, ABEA_E_HIP, "hipEventCreate failed");
     if (rc) {
+      for (hipEvent_t &e : d->tev)
+        if (e) (void)hipEventDestroy(e);
       work_free(d->w);
       delete d;
       return rc;
@@ -168,7 +177,8 @@ int detect_enqueue(abea_ctx *ctx, DetectWork *D, const abea_raw_batch_t *raw, co
   a.events = events;
   a.capacity = cap;
   a.event_offset = event_offset;
-  HIP_TRY(ctx, launch_detect(a, st));
+  D->timed = (ctx->flags & ABEA_F_TIMING) != 0;
+  HIP_TRY(ctx, launch_detect(a, st, D->timed ? D->tev : nullptr));
   return work_mark(ctx, D->w, st);
 }
 
@@ -224,6 +234,20 @@ int abea_detect_events(abea_ctx *ctx, const abea_raw_batch_t *raw, const abea_de
     return fail(ctx, ABEA_E_CAPACITY, "event_capacity %llu < %llu events", (unsigned long long)event_capacity,
                 (unsigned long long)total);
   return stage_copy_down(ctx, events, D->events.p, sizeof(abea_event_t) * (size_t)total);
+}
+
+int abea_get_detect_timings(abea_ctx *ctx, float *out, int n) {
+  if (!ctx || !out || n < 0) return ABEA_E_INVAL;
+  DetectWork *D = ctx->detect;
+  if (!(ctx->flags & ABEA_F_TIMING) || !D || !D->timed)
+    return fail(ctx, ABEA_E_INVAL, "no timed detection call (ABEA_F_TIMING)");
+  HIP_TRY(ctx, hipEventSynchronize(D->tev[5]));
+  float t[3] = {0.f, 0.f, 0.f};
+  HIP_TRY(ctx, hipEventElapsedTime(&t[0], D->tev[0], D->tev[1]));
+  HIP_TRY(ctx, hipEventElapsedTime(&t[1], D->tev[2], D->tev[3]));
+  HIP_TRY(ctx, hipEventElapsedTime(&t[2], D->tev[4], D->tev[5]));
+  for (int i = 0; i < n && i < 3; ++i) out[i] = t[i];
+  return ABEA_OK;
 }
 
 }  // extern "C"

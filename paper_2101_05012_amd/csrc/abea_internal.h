@@ -178,8 +178,10 @@ struct DetectArgs {
 /* Blocks of the tile-count scan for n_tiles tiles. */
 uint32_t ed_scan_blocks(uint32_t n_tiles);
 /* Detection of a planned batch: change points, the scan of the event counts,
- * the events (those beyond a.capacity are not written) and event_offset. */
-hipError_t launch_detect(const DetectArgs &a, hipStream_t st);
+ * the events (those beyond a.capacity are not written) and event_offset.
+ * tev: null, or six events: start and end of k_ed_detect's dispatch, of
+ * k_ed_events's, and before and after the whole batch. */
+hipError_t launch_detect(const DetectArgs &a, hipStream_t st, hipEvent_t *tev = nullptr);
 
 }  // namespace abea
 

@@ -179,3 +179,35 @@ def test_detected_events_align_like_the_oracle(aligner, m6, oracle_mod):
         assert np.array_equal(got.read_pairs(r), ores.read_pairs(r)), r
         ok += int(got.status[r] == abea.READ_OK)
     assert ok >= rb.n_reads - 1
+
+
+def test_whole_raw_workload(aligner, oracle_mod):
+    """All 4000 reads of raw-4000-lognormal5kb (293 M samples) in one device
+    call, in the launch form the benchmark times, against the oracle on 16
+    threads: every read's events identical."""
+    import os
+
+    from paper_2101_05012_amd import synth as S
+
+    rb = S.workload_raw_batch("raw-4000-lognormal5kb")
+    say(f"gpu: detect whole raw-4000 ({int(rb.sample_offset[-1])} samples)")
+    want_ev, want_eo = oracle_events(oracle_mod, rb, threads=min(16, os.cpu_count() or 1))
+    ev, eo = gpu_events_device(aligner, rb)
+    compare("raw-4000 whole", ev, eo, want_ev, want_eo)
+    ratio = float(want_eo[-1]) / float(rb.kmer_offset[-1])
+    say(f"raw-4000: {ratio:.3f} events per k-mer")
+    assert 1.5 <= ratio <= 2.0
+
+
+def test_detect_timings(m6):
+    """abea_get_detect_timings after a timed call: both streaming kernels'
+    dispatch times are positive and lie within the batch's time."""
+    al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, timing=True)
+    rb = synth.workload_raw_batch("raw-4000-lognormal5kb", read_ids=range(100))
+    say("gpu: detect timings")
+    with pytest.raises(abea.AbeaError):
+        al.detect_timings()  # no detection call yet
+    al.detect_events(rb)
+    t = al.detect_timings()
+    assert t[0] > 0 and t[1] > 0 and t[2] >= t[0] + t[1] - 1e-3, t
+    al.close()
