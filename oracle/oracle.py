@@ -18,7 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "abea_oracle.c")
-SRCS = [SRC, os.path.join(HERE, "event_oracle.c")]
+SRCS = [SRC, os.path.join(HERE, "event_oracle.c"), os.path.join(HERE, "meth_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 READ_OK, READ_EMPTY, READ_BAND_LOST, READ_BAD_RANK = 0, 1, 2, 3
@@ -93,6 +93,14 @@ def lib():
         L.oracle_ed_read.restype = i64
         L.oracle_ed_batch.argtypes = [i32, P, P, P, P, P, i32, P, P]
         L.oracle_ed_batch.restype = ctypes.c_int
+        L.oracle_meth_is_site.argtypes = [u32, i32]
+        L.oracle_meth_is_site.restype = ctypes.c_int
+        L.oracle_meth_profile.argtypes = [P, i64, P, P, P, P, i64, P, u32]
+        L.oracle_meth_profile.restype = f32
+        L.oracle_meth_read.argtypes = [P, i64, i64, P, i64, i32, P, P, f32, f32, u32, P, i64, P, P]
+        L.oracle_meth_read.restype = ctypes.c_int
+        L.oracle_meth_batch.argtypes = [i32, P, i64, P, P, P, i32, P, P, P, P, u32, P, P, P, i32, P, P]
+        L.oracle_meth_batch.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -312,3 +320,72 @@ def ed_batch(raw_batch, params: Optional[EdParams] = None, n_threads: int = 1):
         a = int(so[r])
         out[int(eo[r]):int(eo[r + 1])] = ev[a:a + int(cnt[r])]
     return out, eo
+
+
+# ---- methylation scoring (meth_oracle.c) ----------------------------------------
+
+
+class _MethModel(ctypes.Structure):
+    _fields_ = [("level_mean", ctypes.c_void_p), ("level_stdv", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("h", ctypes.c_void_p)]
+
+
+def _meth_struct(model: Model) -> _MethModel:
+    return _MethModel(model.level_mean.ctypes.data, model.level_stdv.ctypes.data, model.c.ctypes.data,
+                      model.h.ctypes.data)
+
+
+def meth_is_site(rank: int, k: int) -> bool:
+    return bool(lib().oracle_meth_is_site(int(rank), int(k)))
+
+
+def meth_profile(x, mu, sigma, c, h, lp, flags: int = 0) -> np.float32:
+    """Best-path score of events x through a window of k-mers."""
+    x = np.ascontiguousarray(x, np.float32)
+    arrs = [np.ascontiguousarray(a, np.float32) for a in (mu, sigma, c, h)]
+    lpa = np.ascontiguousarray(lp, np.float32)
+    return np.float32(lib().oracle_meth_profile(_p(x), x.shape[0], *[_p(a) for a in arrs], arrs[0].shape[0],
+                                                _p(lpa), flags))
+
+
+def meth_read(event_mean, ranks, k: int, model_u: Model, model_m: Model, scale, shift, pairs, flags: int = 0):
+    """One read: (llr float32 [n_k], n_ev int32 [n_k]); NaN / 0 off the sites."""
+    ev = np.ascontiguousarray(event_mean, np.float32)
+    stride = 1 if ev.ndim == 1 else ev.shape[1]
+    rk = np.ascontiguousarray(ranks, np.uint32)
+    pr = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+    llr = np.zeros(rk.shape[0], np.float32)
+    nev = np.zeros(rk.shape[0], np.int32)
+    mu, mm = _meth_struct(model_u), _meth_struct(model_m)
+    rc = lib().oracle_meth_read(_p(ev), stride, ev.shape[0], _p(rk), rk.shape[0], k, ctypes.byref(mu),
+                                ctypes.byref(mm), float(np.float32(scale)), float(np.float32(shift)), flags,
+                                _p(pr), pr.shape[0], _p(llr), _p(nev))
+    if rc < 0:
+        raise RuntimeError("oracle_meth_read failed")
+    return llr, nev
+
+
+def meth_batch(batch, k: int, model_u: Model, model_m: Model, pairs, pair_offset, status, n_threads: int = 1,
+               flags: int = 0):
+    """A batch (``synth.Batch``) with its alignment (pairs int32 [P, 2] in
+    path order per read, pair_offset [n+1], status [n]): (llr, n_ev) per
+    k-mer of the batch."""
+    n = batch.n_reads
+    ev = np.ascontiguousarray(batch.events, np.float32)
+    eo = np.ascontiguousarray(batch.event_offset, np.uint64)
+    ko = np.ascontiguousarray(batch.kmer_offset, np.uint64)
+    rk = np.ascontiguousarray(batch.ranks, np.uint32)
+    sc = np.ascontiguousarray(batch.scale, np.float32)
+    sh = np.ascontiguousarray(batch.shift, np.float32)
+    pr = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+    po = np.ascontiguousarray(pair_offset, np.uint64)
+    st = np.ascontiguousarray(status, np.int32)
+    K = int(ko[-1]) if n else 0
+    llr = np.zeros(max(K, 1), np.float32)
+    nev = np.zeros(max(K, 1), np.int32)
+    mu, mm = _meth_struct(model_u), _meth_struct(model_m)
+    rc = lib().oracle_meth_batch(n, _p(ev), 3, _p(eo), _p(rk), _p(ko), k, ctypes.byref(mu), ctypes.byref(mm),
+                                 _p(sc), _p(sh), flags, _p(pr), _p(po), _p(st), n_threads, _p(llr), _p(nev))
+    if rc < 0:
+        raise RuntimeError("oracle_meth_batch failed")
+    return llr[:K], nev[:K]

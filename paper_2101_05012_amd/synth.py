@@ -33,6 +33,13 @@ round(pA / pa_scale - offset) into int16 with, per read,
 pa_scale = U(1380, 1420) pA / 8192 levels and offset ~ U(-20, 20): the
 reading back to pA is (raw + offset) * pa_scale.
 
+Methylation (row f3 of the scope; Ch. 5 §5.2.2 names HMM profiling of the
+aligned events as the step after the alignment): a synthetic methylated pore
+model equals the pore model except that every k-mer containing the
+dinucleotide CG has its level shifted by +-U(2, 5) pA (seeded per k); a read
+of a methylation workload is methylated with probability 1/2, and then the
+events of its CG-containing k-mers are drawn from the methylated levels.
+
 Every read draws from its own stream ``default_rng([workload_seed, read_id])``,
 so a read's bytes do not depend on which batch it is in or where.
 """
@@ -71,6 +78,8 @@ WORKLOADS = {
     # the read ends
     "plain-4000-lognormal5kb-ends": dict(seed_index=5, n_reads=4000, W=100, k=6, lengths="lognormal5k",
                                          ends=True),
+    # plain-4000's length mix, each read methylated with probability 1/2
+    "meth-4000-lognormal5kb": dict(seed_index=7, n_reads=4000, W=100, k=6, lengths="lognormal5k", meth=True),
     # raw signal of reads of the same length mix (event detection's input)
     "raw-4000-lognormal5kb": dict(seed_index=6, n_reads=4000, W=100, k=6, lengths="lognormal5k", raw=True),
 }
@@ -129,6 +138,30 @@ class Batch:
         return make_batch([self.read(int(i)) for i in idx])
 
 
+def kmer_has_cpg(ranks: np.ndarray, k: int) -> np.ndarray:
+    """True for each rank whose k-mer contains the dinucleotide CG (C = 1,
+    G = 2; the first base is the most significant digit)."""
+    r = np.asarray(ranks, np.int64)
+    out = np.zeros(r.shape, bool)
+    for t in range(k - 1):
+        b0 = (r >> (2 * (k - 1 - t))) & 3
+        b1 = (r >> (2 * (k - 2 - t))) & 3
+        out |= (b0 == 1) & (b1 == 2)
+    return out
+
+
+def methylated_model(model: PoreModel, seed: Optional[int] = None) -> PoreModel:
+    """The pore model with every CG-containing k-mer's level shifted by
+    +-U(2, 5) pA; level_stdv unchanged."""
+    k = model.k
+    rng = np.random.default_rng(MODEL_SEED_BASE + 100 + k if seed is None else seed)
+    n = 4**k
+    shift = rng.uniform(2.0, 5.0, n) * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    cpg = kmer_has_cpg(np.arange(n), k)
+    lm = (model.level_mean.astype(np.float64) + np.where(cpg, shift, 0.0)).astype(np.float32)
+    return PoreModel(k, lm, model.level_stdv.copy())
+
+
 def pore_model(k: int, seed: Optional[int] = None) -> PoreModel:
     rng = np.random.default_rng(MODEL_SEED_BASE + k if seed is None else seed)
     n = 4**k
@@ -172,11 +205,14 @@ def gen_read(
     model: PoreModel,
     noiseless: bool = False,
     ends: bool = False,
+    meth_model: Optional[PoreModel] = None,
 ) -> Read:
     """Draw one read of reference length L (see the module docstring).
 
     ``noiseless``: one event per k-mer, scale 1, shift 0 and every event mean
     equal to the model level of its k-mer, so the model levels need no scaling.
+    ``meth_model``: with probability 1/2 (drawn after the event counts) the
+    event means come from its levels (a methylated read).
     ``ends``: the read is preceded by U{0..30} open-pore events and U{0..10}
     adaptor events and followed by U{0..30} open-pore events (drawn after
     everything else, so the read's own events are those without ``ends``).
@@ -198,7 +234,10 @@ def gen_read(
     cnt[skipped] = 0
     r_ev = np.repeat(ranks, cnt)
     n_e = r_ev.shape[0]
-    loc = model.level_mean[r_ev].astype(np.float64) * float(scale) + float(shift)
+    levels = model.level_mean
+    if meth_model is not None and rng.random() < 0.5:
+        levels = meth_model.level_mean  # a methylated read: CG k-mers at the methylated levels
+    loc = levels[r_ev].astype(np.float64) * float(scale) + float(shift)
     ev = np.empty((n_e, 3), np.float32)
     ev[:, 0] = rng.normal(loc, model.level_stdv[r_ev].astype(np.float64))
     ev[:, 1] = rng.uniform(0.5, 3.0, n_e)
@@ -348,8 +387,10 @@ def read_rng(workload: str, read_id: int) -> np.random.Generator:
 def workload_read(workload: str, read_id: int, model: PoreModel) -> Read:
     """Read ``read_id`` of a workload; identical whatever batch it is in."""
     rng = read_rng(workload, read_id)
-    L = draw_length(rng, WORKLOADS[workload]["lengths"])
-    return gen_read(rng, L, model, ends=WORKLOADS[workload].get("ends", False))
+    cfg = WORKLOADS[workload]
+    L = draw_length(rng, cfg["lengths"])
+    mm = methylated_model(model) if cfg.get("meth") else None
+    return gen_read(rng, L, model, ends=cfg.get("ends", False), meth_model=mm)
 
 
 def workload_batch(
@@ -452,6 +493,20 @@ def workload_batch_parallel(
             shm.close()
             shm.unlink()
     return Batch(ev, eo, rk, ko, sc, sh)
+
+
+def read_is_methylated(workload: str, read_id: int, model: PoreModel) -> bool:
+    """Whether read ``read_id`` of a methylation workload was drawn
+    methylated (replays its stream up to that draw)."""
+    rng = read_rng(workload, read_id)
+    L = draw_length(rng, WORKLOADS[workload]["lengths"])
+    rng.integers(0, 4, L)
+    n_k = max(L - model.k + 1, 0)
+    rng.uniform(0.9, 1.1)
+    rng.uniform(-5.0, 5.0)
+    rng.random(n_k)
+    rng.geometric(1.0 / EVENTS_PER_KMER_MEAN, n_k)
+    return bool(rng.random() < 0.5)
 
 
 def workload_lengths(workload: str, read_ids: Sequence[int]) -> np.ndarray:
