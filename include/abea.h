@@ -324,6 +324,54 @@ int abea_detect_events(abea_ctx *ctx, const abea_raw_batch_t *raw, const abea_de
  */
 int abea_get_detect_timings(abea_ctx *ctx, float *out, int n);
 
+/* ---- methylation scoring ---------------------------------------------------
+ * The step after the alignment: the events aligned to the k-mers go through
+ * HMM profiling to decide whether a base is methylated (the thesis, Ch. 5
+ * §5.2.2 "Methylation calling"; the thesis gives no algorithm for the
+ * profile).  The profile here:
+ *   - a site is a CpG whose C starts k-mer i of a read (the first two bases of
+ *     k-mer i are C, G; k >= 2); its window is the k-mers holding that C,
+ *     max(0, i-k+1) .. i;
+ *   - the window's events run from the first event the alignment paired with
+ *     the window's first k-mer to the last it paired with k-mer i;
+ *   - under the context's pore model and under a methylated model, the
+ *     best-path score of those events through the window's k-mers with the
+ *     alignment's own cell score (Alg. 5.2 moves with the read's transition
+ *     constants, Alg. 5.3 emission, the model scaled per read, or the events
+ *     with ABEA_F_SCALE_EVENTS): a virtual origin before the first cell scores
+ *     0, cells outside the window -inf, the score is the window's last cell's;
+ *   - LLR = score(methylated) - score(unmethylated), float32: above 0 favours
+ *     a methylated C.
+ * Results are bit-identical to the CPU reference of the same definition. */
+
+/*
+ * The context's methylated pore model: 4^k entries indexed by k-mer rank
+ * (k the context's), level_stdv > 0, host pointers copied by the call (the
+ * emission terms are prepared as for abea_create's model).  Replaces an
+ * earlier one after the context's queued methylation work.
+ * Errors: ABEA_E_INVAL (null, another k, a bad entry), ABEA_E_NOMEM, ABEA_E_HIP.
+ */
+int abea_set_methylated_model(abea_ctx *ctx, const abea_model_t *model);
+
+/*
+ * Methylation scores of an aligned batch in device memory; asynchronous on
+ * `stream` (NULL = the default stream).
+ *   batch : the batch as aligned (abea_align_batch_device): events, kmer_rank,
+ *       scale, shift DEVICE pointers, event_offset and kmer_offset HOST arrays;
+ *   res : its alignment, DEVICE pointers: pairs, pair_offset [n_reads+1],
+ *       status [n_reads] (reads whose status is not ABEA_READ_OK get no score);
+ *   llr : DEVICE float [total k-mers]: at each k-mer that starts a CpG the
+ *       site's LLR, NaN elsewhere;
+ *   n_events : DEVICE int32 [total k-mers] or NULL: the events of each site's
+ *       window, 0 elsewhere.
+ * The alignment must be complete on `stream` (enqueue it there first).
+ * Calls on one context must be ordered on one stream.
+ * Errors: ABEA_E_INVAL (null pointer, no methylated model, offsets not
+ * starting at 0 or decreasing, 2^32 k-mers or more), ABEA_E_NOMEM, ABEA_E_HIP.
+ */
+int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *batch, const abea_result_t *res, float *llr,
+                            int32_t *n_events, void *stream);
+
 /*
  * Device time in milliseconds of each stage of the last direct call
  * (abea_align_batch or abea_align_batch_device), when the context was

@@ -52,6 +52,8 @@ EXPORTED = (
     "abea_detect_events",
     "abea_detect_events_device",
     "abea_get_detect_timings",
+    "abea_set_methylated_model",
+    "abea_methylation_device",
     "abea_get_timings",
     "abea_set_launch",
     "abea_cells_per_lane",
@@ -276,6 +278,10 @@ def lib() -> ctypes.CDLL:
         L.abea_detect_events_device.argtypes = [P, ctypes.POINTER(abea_raw_batch_t),
                                                 ctypes.POINTER(abea_detect_params_t), P, ctypes.c_uint64, P, P]
         L.abea_detect_events_device.restype = ctypes.c_int
+        L.abea_set_methylated_model.argtypes = [P, ctypes.POINTER(abea_model_t)]
+        L.abea_set_methylated_model.restype = ctypes.c_int
+        L.abea_methylation_device.argtypes = [P, ctypes.POINTER(abea_batch_t), ctypes.POINTER(abea_result_t), P, P, P]
+        L.abea_methylation_device.restype = ctypes.c_int
         L.abea_get_detect_timings.argtypes = [P, P, ctypes.c_int]
         L.abea_get_detect_timings.restype = ctypes.c_int
         L.abea_get_timings.argtypes = [P, P, ctypes.c_int]
@@ -486,6 +492,24 @@ class Aligner:
             lib().abea_detect_events_device(self.handle, ctypes.byref(b), ctypes.byref(p), _ptr(events), cap,
                                             _ptr(event_offset), ctypes.c_void_p(_stream_ptr(stream, self.device))),
             "abea_detect_events_device",
+        )
+
+    def set_methylated_model(self, level_mean, level_stdv) -> None:
+        """The methylated pore model (abea_set_methylated_model); same k."""
+        self._mlm = np.ascontiguousarray(level_mean, np.float32)
+        self._mls = np.ascontiguousarray(level_stdv, np.float32)
+        mdl = abea_model_t(self.k, self._mlm.ctypes.data, self._mls.ctypes.data)
+        self._check(lib().abea_set_methylated_model(self.handle, ctypes.byref(mdl)), "abea_set_methylated_model")
+
+    def methylation_device(self, dbatch: "DeviceBatch", dres: "DeviceResult", llr, n_events=None, stream=None) -> None:
+        """Methylation LLR per k-mer of an aligned device batch
+        (abea_methylation_device): ``llr`` a torch float32 [total k-mers],
+        ``n_events`` a torch int32 [total k-mers] or None."""
+        b, r = _dev_structs(dbatch, dres)
+        self._check(
+            lib().abea_methylation_device(self.handle, ctypes.byref(b), ctypes.byref(r), _ptr(llr), _ptr(n_events),
+                                          ctypes.c_void_p(_stream_ptr(stream, self.device))),
+            "abea_methylation_device",
         )
 
     def detect_timings(self) -> np.ndarray:

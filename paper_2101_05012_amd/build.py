@@ -14,6 +14,8 @@ SOURCES = [
     os.path.join(CSRC, "abea_server.cpp"),
     os.path.join(CSRC, "abea_detect.hip"),
     os.path.join(CSRC, "abea_detect_host.cpp"),
+    os.path.join(CSRC, "abea_meth.hip"),
+    os.path.join(CSRC, "abea_meth_host.cpp"),
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -534,6 +534,25 @@ int stage_down(abea_ctx *ctx, const void *src, size_t bytes, Drain drain) {
   return ABEA_OK;
 }
 
+int model_entries(const abea_model_t *model, std::vector<ModelEntry> &me) {
+  if (!model->level_mean || !model->level_stdv || model->k < 1 || model->k > ABEA_MAX_K) return ABEA_E_INVAL;
+  const uint32_t n_model = 1u << (2 * model->k);
+  me.resize(n_model);
+  /* Alg. 5.3: ln(1/sqrt(2 pi)) - ln(sigma) - 0.5 z^2, split into a per-entry
+   * constant c and the factor h = 0.5/sigma^2 of (x - mu')^2, each computed
+   * in double and rounded once. */
+  for (uint32_t r = 0; r < n_model; ++r) {
+    const float sd = model->level_stdv[r];
+    if (!(sd > 0.0f) || !std::isfinite(sd) || !std::isfinite(model->level_mean[r])) return ABEA_E_INVAL;
+    const double sigma = (double)sd;
+    me[r].mean = model->level_mean[r];
+    me[r].c = (float)(std::log(1.0 / std::sqrt(2.0 * M_PI)) - std::log(sigma));
+    me[r].h = (float)(0.5 / (sigma * sigma));
+    me[r].pad = 0.0f;
+  }
+  return ABEA_OK;
+}
+
 int stage_copy_down(abea_ctx *ctx, void *dst, const void *src, size_t bytes) {
   char *d = (char *)dst;
   return stage_down(ctx, src, bytes, [d](size_t off, size_t len, const char *s) {
@@ -582,21 +601,9 @@ int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **
   if (cfg->bandwidth < 2 || cfg->bandwidth > ABEA_MAX_BANDWIDTH) return ABEA_E_INVAL;
   if (model->k < 1 || model->k > ABEA_MAX_K) return ABEA_E_INVAL;
   if (cfg->flags & ~ABEA_F_ALL) return ABEA_E_INVAL;
-  if (!model->level_mean || !model->level_stdv) return ABEA_E_INVAL;
   const uint32_t n_model = 1u << (2 * model->k);
-  std::vector<ModelEntry> me(n_model);
-  /* Alg. 5.3: ln(1/sqrt(2 pi)) - ln(sigma) - 0.5 z^2, split into a per-entry
-   * constant c and the factor h = 0.5/sigma^2 of (x - mu')^2, each computed
-   * in double and rounded once. */
-  for (uint32_t r = 0; r < n_model; ++r) {
-    const float sd = model->level_stdv[r];
-    if (!(sd > 0.0f) || !std::isfinite(sd) || !std::isfinite(model->level_mean[r])) return ABEA_E_INVAL;
-    const double sigma = (double)sd;
-    me[r].mean = model->level_mean[r];
-    me[r].c = (float)(std::log(1.0 / std::sqrt(2.0 * M_PI)) - std::log(sigma));
-    me[r].h = (float)(0.5 / (sigma * sigma));
-    me[r].pad = 0.0f;
-  }
+  std::vector<ModelEntry> me;
+  if (model_entries(model, me) != ABEA_OK) return ABEA_E_INVAL;
   abea_ctx *ctx = new (std::nothrow) abea_ctx();
   if (!ctx) return ABEA_E_NOMEM;
   ctx->device = cfg->device;
@@ -663,6 +670,7 @@ void abea_destroy(abea_ctx *ctx) {
   (void)work_wait(ctx, ctx->noalloc);
   if (st) (void)hipStreamSynchronize(st);
   detect_free(ctx, st);
+  meth_free(ctx, st);
   work_free(ctx->main, st);
   work_free(ctx->noalloc, st);
   DevBuf *bufs[] = {&ctx->model, &ctx->events, &ctx->ranks, &ctx->scale, &ctx->shift,

@@ -183,6 +183,38 @@ uint32_t ed_scan_blocks(uint32_t n_tiles);
  * k_ed_events's, and before and after the whole batch. */
 hipError_t launch_detect(const DetectArgs &a, hipStream_t st, hipEvent_t *tev = nullptr);
 
+/* ---- methylation scoring (abea_meth.hip) ---- */
+/* One read of a batch to score, in the caller's order. */
+struct MethRead {
+  uint64_t ev_off; /* first event of the read in the batch */
+  uint64_t km_off; /* first k-mer of the read in the batch */
+  int32_t n_k;
+  float lp_skip, lp_stay, lp_step; /* the read's transition constants (Alg. 5.2) */
+};
+static_assert(sizeof(MethRead) == 32, "MethRead is 32 bytes");
+
+struct MethArgs {
+  const MethRead *reads;       /* [n_reads] */
+  int32_t n_reads;
+  int32_t k;
+  const float *events;         /* the batch's event records (ev_stride floats apart) */
+  int32_t ev_stride;
+  int32_t scale_events;        /* events scaled to the model instead of the model to the events */
+  const uint32_t *ranks;
+  const float *scale, *shift;  /* [n_reads] */
+  const ModelEntry *model;      /* the pore model */
+  const ModelEntry *meth_model; /* the methylated model */
+  const int2 *pairs;           /* the batch's alignment: pairs, pair_offset [n_reads+1], status */
+  const uint64_t *pair_offset;
+  const int32_t *status;
+  int32_t *kfirst, *klast;     /* [n_kmers]: first and last event paired with each k-mer */
+  uint2 *sites;                /* [n_kmers]: (read, k-mer) of each site, in no particular order */
+  uint32_t *n_sites;           /* zeroed before the launch */
+  float *llr;                  /* [n_kmers] */
+  int32_t *n_ev;               /* [n_kmers] or null */
+};
+hipError_t launch_meth(const MethArgs &a, hipStream_t st);
+
 }  // namespace abea
 
 #endif

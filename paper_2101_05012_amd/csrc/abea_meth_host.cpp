@@ -1,0 +1,158 @@
+/*
+ * abea_meth_host.cpp -- host side of methylation scoring (include/abea.h,
+ * abea_set_methylated_model and abea_methylation_device): the methylated
+ * model table, the per-read plan (offsets and the Alg. 5.2 transition
+ * constants, which need the host offsets) and the launches of abea_meth.hip.
+ */
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/abea.h"
+#include "abea_internal.h"
+#include "abea_runtime.h"
+
+using namespace abea;
+
+namespace abea_rt {
+
+struct MethWork {
+  Work w; /* its events order buffer growth and the plan's staging */
+  DevBuf model, reads, kfirst, klast, sites, n_sites;
+  MethRead *h_reads = nullptr; /* pinned plan staging */
+  size_t h_cap = 0;
+  std::vector<void *> retired_host;
+};
+
+void meth_free(abea_ctx *ctx, hipStream_t st) {
+  MethWork *m = ctx->meth;
+  if (!m) return;
+  (void)work_wait(ctx, m->w);
+  DevBuf *bufs[] = {&m->model, &m->reads, &m->kfirst, &m->klast, &m->sites, &m->n_sites};
+  for (DevBuf *b : bufs) free_buf(*b, st);
+  if (m->w.staging_pending && m->w.staging_done) (void)hipEventSynchronize(m->w.staging_done);
+  m->w.staging_pending = false;
+  if (m->h_reads) (void)hipHostFree(m->h_reads);
+  for (void *h : m->retired_host) (void)hipHostFree(h);
+  work_free(m->w, st);
+  delete m;
+  ctx->meth = nullptr;
+}
+
+}  // namespace abea_rt
+
+using namespace abea_rt;
+
+extern "C" {
+
+int abea_set_methylated_model(abea_ctx *ctx, const abea_model_t *model) {
+  if (!ctx) return ABEA_E_INVAL;
+  if (!model) return fail(ctx, ABEA_E_INVAL, "null methylated model");
+  if (model->k != ctx->k) return fail(ctx, ABEA_E_INVAL, "methylated model has k = %u, the context %u", model->k, ctx->k);
+  std::vector<ModelEntry> me;
+  if (model_entries(model, me) != ABEA_OK) return fail(ctx, ABEA_E_INVAL, "bad methylated model entries");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (!ctx->meth) {
+    MethWork *m = new (std::nothrow) MethWork();
+    if (!m) return fail(ctx, ABEA_E_NOMEM, "methylation state");
+    const int rc = work_init(ctx, m->w);
+    if (rc) {
+      work_free(m->w);
+      delete m;
+      return rc;
+    }
+    ctx->meth = m;
+  }
+  MethWork *m = ctx->meth;
+  /* the previous table may still be read by a queued call */
+  int rc = work_wait(ctx, m->w);
+  if (rc) return rc;
+  if ((rc = ensure(ctx, nullptr, m->model, sizeof(ModelEntry) * me.size()))) return rc;
+  HIP_TRY(ctx, hipMemcpy(m->model.p, me.data(), sizeof(ModelEntry) * me.size(), hipMemcpyHostToDevice));
+  return ABEA_OK;
+}
+
+int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *b, const abea_result_t *res, float *llr,
+                            int32_t *n_events, void *stream) {
+  if (!ctx) return ABEA_E_INVAL;
+  if (!b || !res) return fail(ctx, ABEA_E_INVAL, "null batch or alignment result");
+  if (!ctx->meth || !ctx->meth->model.p) return fail(ctx, ABEA_E_INVAL, "no methylated model (abea_set_methylated_model)");
+  const int n = b->n_reads;
+  if (n < 0) return fail(ctx, ABEA_E_INVAL, "n_reads < 0");
+  if (!b->event_offset || !b->kmer_offset) return fail(ctx, ABEA_E_INVAL, "null offsets");
+  const uint64_t *eo = b->event_offset, *ko = b->kmer_offset;
+  if (eo[0] != 0 || ko[0] != 0) return fail(ctx, ABEA_E_INVAL, "offsets must start at 0");
+  for (int r = 0; r < n; ++r)
+    if (eo[r + 1] < eo[r] || ko[r + 1] < ko[r]) return fail(ctx, ABEA_E_INVAL, "offsets decrease at read %d", r);
+  const uint64_t K = ko[n];
+  if (K >= (1ull << 32)) return fail(ctx, ABEA_E_INVAL, "batch of %llu k-mers is too large", (unsigned long long)K);
+  if (n > 0) {
+    if (!b->scale || !b->shift || !res->pair_offset || !res->status)
+      return fail(ctx, ABEA_E_INVAL, "null per-read array");
+    if (eo[n] > 0 && !b->events) return fail(ctx, ABEA_E_INVAL, "null events");
+    if (K > 0 && (!b->kmer_rank || !llr)) return fail(ctx, ABEA_E_INVAL, "null k-mer ranks or llr");
+  }
+  if (n == 0 || K == 0) return ABEA_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  MethWork *M = ctx->meth;
+  hipStream_t st = (hipStream_t)stream;
+  if ((size_t)n > M->h_cap) {
+    const size_t cap = std::max<size_t>({(size_t)n, 2 * M->h_cap, 1024});
+    MethRead *h = nullptr;
+    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap * sizeof(MethRead), hipHostMallocDefault));
+    if (M->h_reads) M->retired_host.push_back(M->h_reads);
+    M->h_reads = h;
+    M->h_cap = cap;
+    M->w.staging_pending = false;
+  }
+  if (M->w.staging_pending) HIP_TRY(ctx, hipEventSynchronize(M->w.staging_done));
+  M->w.staging_pending = false;
+  for (int r = 0; r < n; ++r) {
+    MethRead &d = M->h_reads[r];
+    const uint64_t ne = eo[r + 1] - eo[r], nk = ko[r + 1] - ko[r];
+    d.ev_off = eo[r];
+    d.km_off = ko[r];
+    d.n_k = (int32_t)std::min<uint64_t>(nk, 0x7fffffff);
+    d.lp_skip = d.lp_stay = d.lp_step = 0.f;
+    if (ne > 0 && nk > 0) transitions((int64_t)ne, (int64_t)nk, &d.lp_skip, &d.lp_stay, &d.lp_step);
+  }
+  Work *w = &M->w;
+  int rc;
+  if ((rc = ensure(ctx, w, M->reads, sizeof(MethRead) * (size_t)n, st))) return rc;
+  if ((rc = ensure(ctx, w, M->kfirst, sizeof(int32_t) * (size_t)K, st))) return rc;
+  if ((rc = ensure(ctx, w, M->klast, sizeof(int32_t) * (size_t)K, st))) return rc;
+  if ((rc = ensure(ctx, w, M->sites, sizeof(uint2) * (size_t)K, st))) return rc;
+  if ((rc = ensure(ctx, w, M->n_sites, sizeof(uint32_t), st))) return rc;
+  HIP_TRY(ctx, hipMemcpyAsync(M->reads.p, M->h_reads, sizeof(MethRead) * (size_t)n, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipEventRecord(M->w.staging_done, st));
+  M->w.staging_pending = true;
+  HIP_TRY(ctx, hipMemsetAsync(M->n_sites.p, 0, sizeof(uint32_t), st));
+
+  MethArgs a;
+  a.reads = (const MethRead *)M->reads.p;
+  a.n_reads = n;
+  a.k = (int32_t)ctx->k;
+  a.events = (const float *)b->events;
+  a.ev_stride = 3;
+  a.scale_events = (ctx->flags & ABEA_F_SCALE_EVENTS) != 0;
+  a.ranks = b->kmer_rank;
+  a.scale = b->scale;
+  a.shift = b->shift;
+  a.model = (const ModelEntry *)ctx->model.p;
+  a.meth_model = (const ModelEntry *)M->model.p;
+  a.pairs = (const int2 *)res->pairs;
+  a.pair_offset = res->pair_offset;
+  a.status = res->status;
+  a.kfirst = (int32_t *)M->kfirst.p;
+  a.klast = (int32_t *)M->klast.p;
+  a.sites = (uint2 *)M->sites.p;
+  a.n_sites = (uint32_t *)M->n_sites.p;
+  a.llr = llr;
+  a.n_ev = n_events;
+  HIP_TRY(ctx, launch_meth(a, st));
+  return work_mark(ctx, M->w, st);
+}
+
+}  // extern "C"

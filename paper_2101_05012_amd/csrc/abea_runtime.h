@@ -86,6 +86,7 @@ struct DevIO {
 };
 
 struct DetectWork; /* event detection's state (abea_detect_host.cpp), made at its first call */
+struct MethWork;   /* methylation scoring's state (abea_meth_host.cpp), made with its model */
 
 }  // namespace abea_rt
 
@@ -116,6 +117,7 @@ struct abea_ctx {
   bool stage_pending[2] = {false, false};
   int stage_next = 0;
   abea_rt::DetectWork *detect = nullptr;
+  abea_rt::MethWork *meth = nullptr;
   std::string err;
 };
 
@@ -167,6 +169,13 @@ int stage_copy_up(abea_ctx *ctx, void *dst, const void *src, size_t bytes);
 int stage_copy_down(abea_ctx *ctx, void *dst, const void *src, size_t bytes);
 /* Release the detection state on `st` after its last work. */
 void detect_free(abea_ctx *ctx, hipStream_t st);
+/* Release the methylation state on `st` after its last work. */
+void meth_free(abea_ctx *ctx, hipStream_t st);
+/* Device model table of a pore model (Alg. 5.3 terms per entry); ABEA_E_INVAL
+ * for a bad model. */
+int model_entries(const abea_model_t *model, std::vector<ModelEntry> &me);
+/* Alg. 5.2 transition constants of a read (double, rounded once). */
+void transitions(int64_t n_events, int64_t n_kmers, float *skip, float *stay, float *step);
 
 }  // namespace abea_rt
 

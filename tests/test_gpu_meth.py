@@ -1,0 +1,162 @@
+"""Methylation scoring on the GPU (abea_methylation_device) against the CPU
+oracle (oracle/meth_oracle.c): the GPU scores the GPU's own alignment, the
+oracle the oracle's; every site's LLR must be identical bit for bit (the
+profile is max-plus in float32 with the alignment's cell arithmetic), every
+other k-mer NaN, and the window event counts equal."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2101_05012_amd import abea, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_scores(al, batch):
+    import torch
+
+    db = abea.to_device(batch)
+    dr = abea.DeviceResult.empty(db)
+    al.align_device(db, dr)
+    K = int(batch.kmer_offset[-1])
+    llr = torch.full((max(K, 1),), 7.0, dtype=torch.float32, device="cuda")
+    nev = torch.full((max(K, 1),), -5, dtype=torch.int32, device="cuda")
+    al.methylation_device(db, dr, llr, nev)
+    torch.cuda.synchronize()
+    return llr[:K].cpu().numpy(), nev[:K].cpu().numpy()
+
+
+def oracle_scores(oracle_mod, batch, m, mm, W=100, flags=0, threads=16):
+    Mu = oracle_mod.Model(m.level_mean, m.level_stdv)
+    Mm = oracle_mod.Model(mm.level_mean, mm.level_stdv)
+    res = oracle_mod.align_batch(batch, Mu, W, n_threads=threads, flags=flags)
+    po = np.zeros(batch.n_reads + 1, np.uint64)
+    po[1:] = np.cumsum(np.where(res.status == 0, res.path_len, 0))
+    pairs = [res.read_pairs(r) for r in range(batch.n_reads) if res.status[r] == 0]
+    pairs = np.concatenate(pairs) if pairs else np.zeros((0, 2), np.int32)
+    return oracle_mod.meth_batch(batch, m.k, Mu, Mm, pairs, po, res.status, n_threads=threads, flags=flags)
+
+
+def compare(tag, got, want):
+    gl, gn = got
+    wl, wn = want
+    sites = wn > 0
+    assert np.array_equal(gn, wn), f"{tag}: window event counts differ"
+    assert np.all(np.isnan(gl[~sites])), f"{tag}: a k-mer that is not a site has a score"
+    assert np.array_equal(gl[sites].view(np.uint32), wl[sites].view(np.uint32)), f"{tag}: LLR differs"
+    say(f"{tag}: {int(sites.sum())} sites identical")
+    return int(sites.sum())
+
+
+@pytest.fixture(scope="module")
+def models():
+    m = synth.pore_model(6)
+    return m, synth.methylated_model(m)
+
+
+@pytest.fixture(scope="module")
+def aligner(models):
+    m, mm = models
+    al = abea.Aligner(m.level_mean, m.level_stdv, 6, W=100)
+    al.set_methylated_model(mm.level_mean, mm.level_stdv)
+    yield al
+    al.close()
+
+
+def test_meth_workload_subset_and_edges(aligner, models, oracle_mod):
+    m, mm = models
+    b = synth.workload_batch("meth-4000-lognormal5kb", m, read_ids=range(300))
+    # degenerate reads: no events, no k-mers, a bad rank, a read of k-mers that are all sites
+    rng = np.random.default_rng(5)
+    extra = [synth.Read(np.zeros((0, 3), np.float32), np.array([100, 200], np.uint32), np.float32(1), np.float32(0)),
+             synth.Read(np.ones((5, 3), np.float32) * 80, np.zeros(0, np.uint32), np.float32(1), np.float32(0)),
+             synth.Read(np.ones((5, 3), np.float32) * 80, np.array([5, 4096 + 3, 7], np.uint32), np.float32(1),
+                        np.float32(0))]
+    cg = (1 << 10) | (2 << 8)  # k-mers C G x x x x: every one a site
+    ranks = (cg | rng.integers(0, 256, 40)).astype(np.uint32)
+    ev = np.repeat(m.level_mean[ranks], 2).astype(np.float32)
+    extra.append(synth.Read(np.stack([ev, np.ones_like(ev), np.ones_like(ev)], 1).astype(np.float32), ranks,
+                            np.float32(1), np.float32(0)))
+    b = synth.make_batch([b.read(i) for i in range(b.n_reads)] + extra)
+    say("gpu: methylation, 300 reads and edge cases")
+    n = compare("meth300", gpu_scores(aligner, b), oracle_scores(oracle_mod, b, m, mm))
+    assert n > 10000
+
+
+def test_identical_models_score_zero(models, oracle_mod):
+    m, mm = models
+    al = abea.Aligner(m.level_mean, m.level_stdv, 6, W=100)
+    al.set_methylated_model(m.level_mean, m.level_stdv)
+    b = synth.workload_batch("meth-4000-lognormal5kb", m, read_ids=range(300, 340))
+    say("gpu: methylation with identical models")
+    llr, nev = gpu_scores(al, b)
+    assert np.all(llr[nev > 0] == 0.0) and (nev > 0).sum() > 1000
+    al.close()
+
+
+def test_scale_events_and_k9(oracle_mod):
+    """Events scaled to the model, and k = 9 windows (nine k-mers)."""
+    m6 = synth.pore_model(6)
+    mm6 = synth.methylated_model(m6)
+    al = abea.Aligner(m6.level_mean, m6.level_stdv, 6, W=100, scale_events=True)
+    al.set_methylated_model(mm6.level_mean, mm6.level_stdv)
+    b = synth.workload_batch("meth-4000-lognormal5kb", m6, read_ids=range(400, 460))
+    say("gpu: methylation with events scaled to the model")
+    compare("scale-events", gpu_scores(al, b), oracle_scores(oracle_mod, b, m6, mm6, flags=oracle_mod.SCALE_EVENTS))
+    al.close()
+    m9 = synth.pore_model(9)
+    mm9 = synth.methylated_model(m9)
+    reads = [synth.gen_read(np.random.default_rng([77, i]), 3000, m9, meth_model=mm9) for i in range(40)]
+    b9 = synth.make_batch(reads)
+    al9 = abea.Aligner(m9.level_mean, m9.level_stdv, 9, W=100)
+    al9.set_methylated_model(mm9.level_mean, mm9.level_stdv)
+    say("gpu: methylation, k = 9")
+    compare("k9", gpu_scores(al9, b9), oracle_scores(oracle_mod, b9, m9, mm9))
+    al9.close()
+
+
+def test_whole_meth_workload(aligner, models, oracle_mod):
+    """All 4000 reads of meth-4000-lognormal5kb, aligned and scored on the
+    GPU, against the oracle's alignment and scores."""
+    import os
+
+    m, mm = models
+    b = synth.workload_batch_parallel("meth-4000-lognormal5kb", 6)
+    say("gpu: methylation, whole meth-4000")
+    got = gpu_scores(aligner, b)
+    want = oracle_scores(oracle_mod, b, m, mm, threads=min(16, os.cpu_count() or 1))
+    n = compare("meth-4000 whole", got, want)
+    assert n > 1_500_000
+
+
+def test_errors(models):
+    m, mm = models
+    al = abea.Aligner(m.level_mean, m.level_stdv, 6, W=100)
+    b = synth.workload_batch("meth-4000-lognormal5kb", m, read_ids=range(3))
+    import torch
+
+    db = abea.to_device(b)
+    dr = abea.DeviceResult.empty(db)
+    al.align_device(db, dr)
+    llr = torch.empty(int(b.kmer_offset[-1]), dtype=torch.float32, device="cuda")
+    with pytest.raises(abea.AbeaError) as ei:  # no methylated model yet
+        al.methylation_device(db, dr, llr)
+    assert ei.value.code == abea.ABEA_E_INVAL
+    m5 = synth.pore_model(5)
+    with pytest.raises(abea.AbeaError) as ei:  # another k
+        al.set_methylated_model(m5.level_mean, m5.level_stdv)
+    assert ei.value.code == abea.ABEA_E_INVAL
+    bad = mm.level_stdv.copy()
+    bad[7] = 0.0
+    with pytest.raises(abea.AbeaError) as ei:
+        al.set_methylated_model(mm.level_mean, bad)
+    assert ei.value.code == abea.ABEA_E_INVAL
+    torch.cuda.synchronize()
+    al.close()
