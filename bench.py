@@ -36,6 +36,9 @@ Other workloads (``--workload``):
   raw-4000-lognormal5kb: event detection (the step before the alignment)
       on the raw signal of 4000 log-normal reads, 4 kHz samples at 450
       bases/s (293 M int16 samples); value in G samples/s, roofline on HBM.
+  meth-4000-lognormal5kb: methylation scoring (the step after the
+      alignment) of the CpG sites of 4000 aligned reads, half of them
+      methylated; value in M sites/s, roofline on the FP32 issue ceiling.
   serving-512ch: reads arrive from 512 simulated channels (Poisson, 400
       bases/s each, log-normal lengths with median 8 kb) into the library's
       continuous-batching server.  The replay is sped up 1x..10000x; each
@@ -101,6 +104,9 @@ WORKLOADS = {
     # event detection: the raw signal of 4000 log-normal reads (4 kHz samples,
     # 450 bases/s) cut into events on the GPU
     "raw-4000-lognormal5kb": dict(kind="detect", source="raw-4000-lognormal5kb", W=100, k=6),
+    # methylation scoring: the CpG sites of 4000 aligned reads, half of them
+    # methylated, under a methylated and an unmethylated model
+    "meth-4000-lognormal5kb": dict(kind="meth", source="meth-4000-lognormal5kb", W=100, k=6),
 }
 
 HBM_PEAK_GBS = 8000.0
@@ -517,6 +523,13 @@ def bench_persistent(args, wl):
         log("bench: event detection (raw-4000-lognormal5kb)")
         out["event_detection"] = detect_summary(detect_run(args, WORKLOADS["raw-4000-lognormal5kb"], dev,
                                                            steps=10, warmup=2))
+        log("bench: methylation scoring (meth-4000-lognormal5kb)")
+        ma = argparse.Namespace(steps=10, warmup=2, no_cpu_baseline=True, workload="meth-4000-lognormal5kb")
+        mo = bench_meth(ma, WORKLOADS["meth-4000-lognormal5kb"])
+        out["methylation"] = {"workload": "meth-4000-lognormal5kb", "sites": mo["config"]["sites_per_step"],
+                              "ms_per_call": mo["ms_per_step"], "m_sites_per_s": mo["value"],
+                              "kernel_ms": mo["kernel_ms"], "alignment_ms": mo["alignment_ms"],
+                              "sites_right_sign": mo["sites_right_sign"], "roofline": mo["roofline"]}
         log("bench: host-buffer API on the first 4000 reads")
         sub = batch.subset(range(min(4000, n)))
         alh = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
@@ -656,6 +669,108 @@ def bench_detect(args, wl):
                            "sample": f"the first {n1} reads, {s1} samples, {dt1:.2f} s"},
             "host_cpu": host_cpu(),
         }
+    return out
+
+
+# ------------------------------------------------------ methylation scoring
+
+
+def bench_meth(args, wl):
+    """Methylation scores of a whole aligned batch resident in HBM: the
+    batch is aligned once (not timed), then ``steps`` timed calls of
+    abea_methylation_device (HIP events on the launch stream) and one call's
+    kernel times from the library's dispatch events."""
+    import torch
+
+    from paper_2101_05012_amd import abea, synth
+
+    dev = 0
+    k, W = wl["k"], wl["W"]
+    model = synth.pore_model(k)
+    mm = synth.methylated_model(model)
+    t0 = time.perf_counter()
+    batch = synth.workload_batch_parallel(wl["source"], k)
+    log(f"bench: {batch.n_reads} reads generated in {time.perf_counter() - t0:.1f} s")
+    al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev, timing=True)
+    al.set_methylated_model(mm.level_mean, mm.level_stdv)
+    db = abea.to_device(batch, dev)
+    dr = abea.DeviceResult.empty(db, dev)
+    st = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    al.align_device(db, dr, stream=st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    align_ms = e0.elapsed_time(e1)
+    K = int(batch.kmer_offset[-1])
+    llr = torch.empty(K, dtype=torch.float32, device=f"cuda:{dev}")
+    nev = torch.empty(K, dtype=torch.int32, device=f"cuda:{dev}")
+    for _ in range(args.warmup):
+        al.methylation_device(db, dr, llr, nev, stream=st)
+    torch.cuda.synchronize()
+    kms = al.meth_timings()
+    e0.record(st)
+    for _ in range(args.steps):
+        al.methylation_device(db, dr, llr, nev, stream=st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    nv = nev.cpu().numpy()
+    lv = llr.cpu().numpy()
+    sites = nv > 0
+    n_sites = int(sites.sum())
+    # window cells: events x k-mers of each site's window (the k-mers holding its C)
+    ko = batch.kmer_offset.astype(np.int64)
+    local = np.arange(K, dtype=np.int64) - np.repeat(ko[:-1], np.diff(ko))
+    nk = np.minimum(local, k - 1) + 1
+    cells = int((nv[sites].astype(np.int64) * nk[sites]).sum())
+    ops = cells * 2 * OPS_PER_CELL  # two models, the alignment's 11 FP32 ops per cell
+    llr_ms = float(kms[1])
+    achieved = ops / (llr_ms / 1e3) / 1e12
+    meth = np.array([synth.read_is_methylated(wl["source"], r, model) for r in range(batch.n_reads)])
+    read_of = np.repeat(np.arange(batch.n_reads), np.diff(ko))
+    right = np.where(meth[read_of[sites]], lv[sites] > 0, lv[sites] < 0)
+    out = {
+        "metric": "methylation scoring throughput (CpG sites of aligned reads scored per second) on 1 MI355X",
+        "value": round(n_sites / ms / 1e3, 3),
+        "unit": "M sites/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_reads": batch.n_reads, "k": k, "sites_per_step": n_sites,
+                   "window_cells_per_step": cells},
+        "kernel_ms": {"k_meth_bounds+sites": round(float(kms[0]), 4), "k_meth_llr": round(llr_ms, 4)},
+        "alignment_ms": round(align_ms, 3),
+        "sites_right_sign": round(float(right.mean()), 4),
+        "roofline": {"bound": "alu", "kernel": "k_meth_llr", "achieved": round(achieved, 3),
+                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": None, "ops_per_window_cell": 2 * OPS_PER_CELL},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+
+        cores = min(16, os.cpu_count() or 1)
+        log("bench: cpu baseline (oracle alignment, then the timed oracle scoring)")
+        Mu = O.Model(model.level_mean, model.level_stdv)
+        Mm = O.Model(mm.level_mean, mm.level_stdv)
+        res = O.align_batch(batch, Mu, W, n_threads=cores)
+        po = np.zeros(batch.n_reads + 1, np.uint64)
+        po[1:] = np.cumsum(np.where(res.status == 0, res.path_len, 0))
+        pairs = np.concatenate([res.read_pairs(r) for r in range(batch.n_reads) if res.status[r] == 0])
+        t1 = time.perf_counter()
+        O.meth_batch(batch, k, Mu, Mm, pairs, po, res.status, n_threads=cores)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": round(n_sites / dt / 1e6, 3), "unit": "M sites/s", "cores": cores,
+                               "kind": "oracle", "sample": f"the whole workload's {n_sites} sites, {dt:.2f} s",
+                               "host_cpu": host_cpu()}
+    al.close()
     return out
 
 
@@ -896,9 +1011,9 @@ def main():
     # plain: enough batches that the drain of the last ones in flight is a
     # small part of the timed region; persistent: whole passes of the job
     if args.steps is None:
-        args.steps = {"plain": 200, "detect": 20}.get(wl["kind"], 10)
+        args.steps = {"plain": 200, "detect": 20, "meth": 20}.get(wl["kind"], 10)
     if args.warmup is None:
-        args.warmup = {"plain": 16, "detect": 3}.get(wl["kind"], 1)
+        args.warmup = {"plain": 16, "detect": 3, "meth": 3}.get(wl["kind"], 1)
     if args.wpg <= 0 and wl["kind"] != "persistent":
         args.wpg = 1
     if 0 < args.hw_queues <= 32:
@@ -910,6 +1025,8 @@ def main():
         out = bench_plain(args, wl)
     elif wl["kind"] == "detect":
         out = bench_detect(args, wl)
+    elif wl["kind"] == "meth":
+        out = bench_meth(args, wl)
     elif wl["kind"] == "serving":
         out = bench_serving(args, wl)
     else:

@@ -373,6 +373,16 @@ int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *batch, const abea
                             int32_t *n_events, void *stream);
 
 /*
+ * Device time in milliseconds of the last methylation call on a context
+ * created with ABEA_F_TIMING: out[0] the k-mer event ranges and the site list
+ * (from the start of the first kernel's dispatch to the end of the second's),
+ * out[1] the per-site profile kernel (its dispatch).  Synchronises with that
+ * call.
+ * Errors: ABEA_E_INVAL (no timed methylation call), ABEA_E_HIP.
+ */
+int abea_get_meth_timings(abea_ctx *ctx, float *out, int n);
+
+/*
  * Device time in milliseconds of each stage of the last direct call
  * (abea_align_batch or abea_align_batch_device), when the context was
  * created with ABEA_F_TIMING: out[0] k-mer parameter preparation, out[1] band

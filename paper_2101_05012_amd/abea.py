@@ -54,6 +54,7 @@ EXPORTED = (
     "abea_get_detect_timings",
     "abea_set_methylated_model",
     "abea_methylation_device",
+    "abea_get_meth_timings",
     "abea_get_timings",
     "abea_set_launch",
     "abea_cells_per_lane",
@@ -282,6 +283,8 @@ def lib() -> ctypes.CDLL:
         L.abea_set_methylated_model.restype = ctypes.c_int
         L.abea_methylation_device.argtypes = [P, ctypes.POINTER(abea_batch_t), ctypes.POINTER(abea_result_t), P, P, P]
         L.abea_methylation_device.restype = ctypes.c_int
+        L.abea_get_meth_timings.argtypes = [P, P, ctypes.c_int]
+        L.abea_get_meth_timings.restype = ctypes.c_int
         L.abea_get_detect_timings.argtypes = [P, P, ctypes.c_int]
         L.abea_get_detect_timings.restype = ctypes.c_int
         L.abea_get_timings.argtypes = [P, P, ctypes.c_int]
@@ -511,6 +514,13 @@ class Aligner:
                                           ctypes.c_void_p(_stream_ptr(stream, self.device))),
             "abea_methylation_device",
         )
+
+    def meth_timings(self) -> np.ndarray:
+        """Milliseconds of [per-read kernel, per-site kernel] of the last
+        methylation call (the context needs timing=True)."""
+        out = np.zeros(2, np.float32)
+        self._check(lib().abea_get_meth_timings(self.handle, _ptr(out), 2), "abea_get_meth_timings")
+        return out
 
     def detect_timings(self) -> np.ndarray:
         """Milliseconds of [change-point kernel, event kernel, whole batch] of

@@ -197,6 +197,8 @@ struct MethArgs {
   const MethRead *reads;       /* [n_reads] */
   int32_t n_reads;
   int32_t k;
+  uint64_t n_kmers;            /* of the batch */
+  uint64_t max_pairs;          /* an upper bound of the batch's pairs (sum of n_e + n_k - 1) */
   const float *events;         /* the batch's event records (ev_stride floats apart) */
   int32_t ev_stride;
   int32_t scale_events;        /* events scaled to the model instead of the model to the events */
@@ -213,7 +215,9 @@ struct MethArgs {
   float *llr;                  /* [n_kmers] */
   int32_t *n_ev;               /* [n_kmers] or null */
 };
-hipError_t launch_meth(const MethArgs &a, hipStream_t st);
+/* tev: null, or four events: start of k_meth_bounds's dispatch and end of
+ * k_meth_sites's, start and end of k_meth_llr's. */
+hipError_t launch_meth(const MethArgs &a, hipStream_t st, hipEvent_t *tev = nullptr);
 
 }  // namespace abea
 

@@ -19,13 +19,16 @@
  *   - LLR = score(methylated) - score(unmethylated), float32.
  *
  * Kernels:
- *   k_meth_prep  one wavefront per read: the first and last event paired with
- *                each k-mer (the pairs run in path order, so a k-mer's pairs
- *                are consecutive), the sites appended to a list, and NaN / 0
- *                written for every k-mer that is not a scored site;
- *   k_meth_llr   one thread per listed site: both profiles in registers (a
- *                column of at most ABEA_MAX_K cells per model), then the LLR.
+ *   k_meth_bounds  one workgroup per 8192 pairs of the batch: the first and
+ *                  last event paired with each k-mer (the pairs run in path
+ *                  order, so a k-mer's pairs are consecutive);
+ *   k_meth_sites   one workgroup per 8192 k-mers: the sites appended to a list
+ *                  (one atomic per workgroup), NaN / 0 written for every k-mer
+ *                  that is not a scored site;
+ *   k_meth_llr     one thread per listed site: both profiles in registers (a
+ *                  column of at most ABEA_MAX_K cells per model), then the LLR.
  */
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,6 +41,7 @@ namespace abea {
 namespace {
 
 constexpr int KMAX = 12; /* the longest window: k <= ABEA_MAX_K */
+constexpr int CHUNK = 8192; /* pairs or k-mers per workgroup of the first two kernels */
 
 __device__ __forceinline__ bool is_site(uint32_t rank, int k) {
   return k >= 2 && ((rank >> (2 * (k - 1))) & 3u) == 1u && ((rank >> (2 * (k - 2))) & 3u) == 2u;
@@ -45,39 +49,93 @@ __device__ __forceinline__ bool is_site(uint32_t rank, int k) {
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_meth_prep(MethArgs a) {
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (r >= a.n_reads) return;
-  const MethRead rd = a.reads[r];
-  const bool ok = a.status[r] == READ_OK;
-  const uint64_t p0 = a.pair_offset[r], p1 = a.pair_offset[r + 1];
-  const int32_t n = (int32_t)(p1 - p0);
-  const int2 *pr = a.pairs + p0;
-  int32_t *kf = a.kfirst + rd.km_off;
-  int32_t *kl = a.klast + rd.km_off;
-  if (ok) {
-    for (int32_t t = lane; t < n; t += 64) {
-      const int2 p = pr[t];
-      if (p.y < 0 || p.y >= rd.n_k) continue;
-      if (t == 0 || pr[t - 1].y != p.y) kf[p.y] = p.x;
-      if (t == n - 1 || pr[t + 1].y != p.y) kl[p.y] = p.x;
+/* the last read r with key(r) <= v, keys non-decreasing over r = 0..n */
+template <typename Key>
+__device__ __forceinline__ int last_at_most(int n, uint64_t v, Key key) {
+  int lo = 0, hi = n; /* key(lo) <= v < key(hi) */
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (key(mid) <= v)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+/* one workgroup per chunk of CHUNK pairs of the batch (thread t takes pairs
+ * t, t+256, ...): the first and the last event paired with each k-mer (a
+ * k-mer's pairs are consecutive in the path order).  The chunk's first read
+ * is found once; each thread then follows the read boundaries forward. */
+__global__ __launch_bounds__(256) void k_meth_bounds(MethArgs a) {
+  const uint64_t total = a.pair_offset[a.n_reads];
+  const uint64_t c0 = (uint64_t)blockIdx.x * CHUNK;
+  if (c0 >= total) return;
+  int r = last_at_most(a.n_reads, c0, [&](int i) { return a.pair_offset[i]; });
+  for (int it = 0; it < CHUNK / 256; ++it) {
+    const uint64_t p = c0 + (uint64_t)it * 256 + threadIdx.x;
+    if (p >= total) break;
+    while (a.pair_offset[r + 1] <= p) ++r;
+    if (a.status[r] != READ_OK) continue;
+    const uint64_t p0 = a.pair_offset[r], p1 = a.pair_offset[r + 1];
+    const MethRead rd = a.reads[r];
+    const int2 q = a.pairs[p];
+    if (q.y < 0 || q.y >= rd.n_k) continue;
+    if (p == p0 || a.pairs[p - 1].y != q.y) a.kfirst[rd.km_off + q.y] = q.x;
+    if (p + 1 == p1 || a.pairs[p + 1].y != q.y) a.klast[rd.km_off + q.y] = q.x;
+  }
+}
+
+/* one workgroup per chunk of CHUNK k-mers: the sites of aligned reads go to
+ * the list (one atomic per workgroup: the chunk's sites are counted first,
+ * then written at the workgroup's base), every other k-mer gets NaN and 0 */
+__global__ __launch_bounds__(256) void k_meth_sites(MethArgs a) {
+  __shared__ uint32_t wcount[4], wbase[4];
+  const uint64_t c0 = (uint64_t)blockIdx.x * CHUNK;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto km = [&](int j) -> uint64_t { return j < a.n_reads ? a.reads[j].km_off : a.n_kmers; };
+  const int r0 = last_at_most(a.n_reads, c0 < a.n_kmers ? c0 : a.n_kmers - 1, km);
+  /* the k-mer of iteration it, its read (followed forward), and whether it
+   * is a site of an aligned read */
+  auto probe = [&](int it, int &r, uint64_t &i) -> bool {
+    i = c0 + (uint64_t)it * 256 + threadIdx.x;
+    if (i >= a.n_kmers) return false;
+    while (km(r + 1) <= i) ++r;
+    return a.status[r] == READ_OK && is_site(a.ranks[i], a.k);
+  };
+  uint32_t cnt = 0;
+  int r = r0;
+  for (int it = 0; it < CHUNK / 256; ++it) {
+    uint64_t i;
+    const bool site = probe(it, r, i);
+    cnt += (uint32_t)__popcll(__ballot(site));
+  }
+  if (lane == 0) wcount[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < 4; ++w) t += wcount[w];
+    uint32_t b = t ? atomicAdd(a.n_sites, t) : 0u;
+    for (int w = 0; w < 4; ++w) {
+      wbase[w] = b;
+      b += wcount[w];
     }
   }
-  for (int32_t i0 = 0; i0 < rd.n_k; i0 += 64) {
-    const int32_t i = i0 + lane;
-    const bool site = ok && i < rd.n_k && is_site(a.ranks[rd.km_off + i], a.k);
+  __syncthreads();
+  uint32_t run = wbase[wave];
+  r = r0;
+  for (int it = 0; it < CHUNK / 256; ++it) {
+    uint64_t i;
+    const bool site = probe(it, r, i);
     const uint64_t m = __ballot(site);
-    uint32_t base = 0;
-    if (lane == 0 && m) base = atomicAdd(a.n_sites, (uint32_t)__popcll(m));
-    base = __shfl(base, 0, 64);
     if (site) {
-      const uint32_t slot = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-      a.sites[slot] = make_uint2((uint32_t)r, (uint32_t)i);
-    } else if (i < rd.n_k) {
-      a.llr[rd.km_off + i] = NAN;
-      if (a.n_ev) a.n_ev[rd.km_off + i] = 0;
+      const uint32_t slot = run + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      a.sites[slot] = make_uint2((uint32_t)r, (uint32_t)(i - a.reads[r].km_off));
+    } else if (i < a.n_kmers) {
+      a.llr[i] = NAN;
+      if (a.n_ev) a.n_ev[i] = 0;
     }
+    run += (uint32_t)__popcll(m);
   }
 }
 
@@ -153,10 +211,17 @@ __global__ __launch_bounds__(256) void k_meth_llr(MethArgs a) {
   }
 }
 
-hipError_t launch_meth(const MethArgs &a, hipStream_t st) {
-  if (a.n_reads > 0) {
-    hipLaunchKernelGGL(k_meth_prep, dim3((a.n_reads + 3) / 4), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_meth_llr, dim3(2048), dim3(256), 0, st, a);
+hipError_t launch_meth(const MethArgs &a, hipStream_t st, hipEvent_t *tev) {
+  if (a.n_reads > 0 && a.n_kmers > 0) {
+    const uint64_t bp = (a.max_pairs + CHUNK - 1) / CHUNK, bk = (a.n_kmers + CHUNK - 1) / CHUNK;
+    if (bp > 0)
+      hipExtLaunchKernelGGL(k_meth_bounds, dim3((uint32_t)bp), dim3(256), 0, st, tev ? tev[0] : nullptr, nullptr, 0,
+                            a);
+    else if (tev)
+      (void)hipEventRecord(tev[0], st);
+    hipExtLaunchKernelGGL(k_meth_sites, dim3((uint32_t)bk), dim3(256), 0, st, nullptr, tev ? tev[1] : nullptr, 0, a);
+    hipExtLaunchKernelGGL(k_meth_llr, dim3(2048), dim3(256), 0, st, tev ? tev[2] : nullptr,
+                          tev ? tev[3] : nullptr, 0, a);
   }
   return hipGetLastError();
 }

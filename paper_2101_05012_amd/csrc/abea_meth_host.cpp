@@ -24,6 +24,9 @@ struct MethWork {
   MethRead *h_reads = nullptr; /* pinned plan staging */
   size_t h_cap = 0;
   std::vector<void *> retired_host;
+  /* ABEA_F_TIMING: the two kernels' dispatches */
+  hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
 };
 
 void meth_free(abea_ctx *ctx, hipStream_t st) {
@@ -36,6 +39,8 @@ void meth_free(abea_ctx *ctx, hipStream_t st) {
   m->w.staging_pending = false;
   if (m->h_reads) (void)hipHostFree(m->h_reads);
   for (void *h : m->retired_host) (void)hipHostFree(h);
+  for (hipEvent_t &e : m->tev)
+    if (e) (void)hipEventDestroy(e);
   work_free(m->w, st);
   delete m;
   ctx->meth = nullptr;
@@ -57,8 +62,12 @@ int abea_set_methylated_model(abea_ctx *ctx, const abea_model_t *model) {
   if (!ctx->meth) {
     MethWork *m = new (std::nothrow) MethWork();
     if (!m) return fail(ctx, ABEA_E_NOMEM, "methylation state");
-    const int rc = work_init(ctx, m->w);
+    int rc = work_init(ctx, m->w);
+    for (hipEvent_t &e : m->tev)
+      if (rc == ABEA_OK && hipEventCreate(&e) != hipSuccess) rc = fail(ctx, ABEA_E_HIP, "hipEventCreate failed");
     if (rc) {
+      for (hipEvent_t &e : m->tev)
+        if (e) (void)hipEventDestroy(e);
       work_free(m->w);
       delete m;
       return rc;
@@ -109,9 +118,11 @@ int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   }
   if (M->w.staging_pending) HIP_TRY(ctx, hipEventSynchronize(M->w.staging_done));
   M->w.staging_pending = false;
+  uint64_t max_pairs = 0;
   for (int r = 0; r < n; ++r) {
     MethRead &d = M->h_reads[r];
     const uint64_t ne = eo[r + 1] - eo[r], nk = ko[r + 1] - ko[r];
+    if (ne > 0 && nk > 0) max_pairs += ne + nk - 1;
     d.ev_off = eo[r];
     d.km_off = ko[r];
     d.n_k = (int32_t)std::min<uint64_t>(nk, 0x7fffffff);
@@ -134,6 +145,8 @@ int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   a.reads = (const MethRead *)M->reads.p;
   a.n_reads = n;
   a.k = (int32_t)ctx->k;
+  a.n_kmers = K;
+  a.max_pairs = max_pairs;
   a.events = (const float *)b->events;
   a.ev_stride = 3;
   a.scale_events = (ctx->flags & ABEA_F_SCALE_EVENTS) != 0;
@@ -151,8 +164,22 @@ int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   a.n_sites = (uint32_t *)M->n_sites.p;
   a.llr = llr;
   a.n_ev = n_events;
-  HIP_TRY(ctx, launch_meth(a, st));
+  M->timed = (ctx->flags & ABEA_F_TIMING) != 0;
+  HIP_TRY(ctx, launch_meth(a, st, M->timed ? M->tev : nullptr));
   return work_mark(ctx, M->w, st);
+}
+
+int abea_get_meth_timings(abea_ctx *ctx, float *out, int n) {
+  if (!ctx || !out || n < 0) return ABEA_E_INVAL;
+  MethWork *M = ctx->meth;
+  if (!(ctx->flags & ABEA_F_TIMING) || !M || !M->timed)
+    return fail(ctx, ABEA_E_INVAL, "no timed methylation call (ABEA_F_TIMING)");
+  HIP_TRY(ctx, hipEventSynchronize(M->tev[3]));
+  float t[2] = {0.f, 0.f};
+  HIP_TRY(ctx, hipEventElapsedTime(&t[0], M->tev[0], M->tev[1]));
+  HIP_TRY(ctx, hipEventElapsedTime(&t[1], M->tev[2], M->tev[3]));
+  for (int i = 0; i < n && i < 2; ++i) out[i] = t[i];
+  return ABEA_OK;
 }
 
 }  // extern "C"

@@ -160,3 +160,17 @@ def test_errors(models):
     assert ei.value.code == abea.ABEA_E_INVAL
     torch.cuda.synchronize()
     al.close()
+
+
+def test_meth_timings(models):
+    m, mm = models
+    al = abea.Aligner(m.level_mean, m.level_stdv, 6, W=100, timing=True)
+    al.set_methylated_model(mm.level_mean, mm.level_stdv)
+    b = synth.workload_batch("meth-4000-lognormal5kb", m, read_ids=range(50))
+    say("gpu: methylation timings")
+    with pytest.raises(abea.AbeaError):
+        al.meth_timings()
+    gpu_scores(al, b)
+    t = al.meth_timings()
+    assert t[0] > 0 and t[1] > 0, t
+    al.close()
