@@ -39,6 +39,9 @@ Other workloads (``--workload``):
   meth-4000-lognormal5kb: methylation scoring (the step after the
       alignment) of the CpG sites of 4000 aligned reads, half of them
       methylated; value in M sites/s, roofline on the FP32 issue ceiling.
+  pipeline-4000-lognormal5kb: the whole methylation call on one GPU, raw
+      signal of 4000 reads (half methylated) to events, alignment and per-site
+      LLRs; value in G samples/s, with each stage's time.
   serving-512ch: reads arrive from 512 simulated channels (Poisson, 400
       bases/s each, log-normal lengths with median 8 kb) into the library's
       continuous-batching server.  The replay is sped up 1x..10000x; each
@@ -107,6 +110,9 @@ WORKLOADS = {
     # methylation scoring: the CpG sites of 4000 aligned reads, half of them
     # methylated, under a methylated and an unmethylated model
     "meth-4000-lognormal5kb": dict(kind="meth", source="meth-4000-lognormal5kb", W=100, k=6),
+    # the three steps of methylation calling on one GPU: raw signal of 4000
+    # reads (half methylated) to events, alignment and per-site LLRs
+    "pipeline-4000-lognormal5kb": dict(kind="pipeline", source="pipeline-4000-lognormal5kb", W=100, k=6),
 }
 
 HBM_PEAK_GBS = 8000.0
@@ -774,6 +780,125 @@ def bench_meth(args, wl):
     return out
 
 
+# ------------------------------------------------ the whole methylation call
+
+
+def bench_pipeline(args, wl):
+    """Raw signal resident in HBM to per-site LLRs (event detection,
+    alignment, methylation scoring on one stream; the event offsets go to
+    the host between the first two, as the alignment plans from host
+    offsets).  ``steps`` timed calls after ``warmup`` untimed ones."""
+    import torch
+
+    from paper_2101_05012_amd import abea, pipeline, synth
+
+    dev = 0
+    k, W = wl["k"], wl["W"]
+    model = synth.pore_model(k)
+    mm = synth.methylated_model(model)
+    t0 = time.perf_counter()
+    rb = synth.workload_raw_batch(wl["source"], model)
+    log(f"bench: {rb.n_reads} raw reads generated in {time.perf_counter() - t0:.1f} s")
+    al = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
+    al.set_methylated_model(mm.level_mean, mm.level_stdv)
+    draw = abea.raw_to_device(rb, dev)
+    ranks = torch.from_numpy(rb.ranks.view(np.int32)).to(f"cuda:{dev}")
+    scale = torch.from_numpy(rb.scale).to(f"cuda:{dev}")
+    shift = torch.from_numpy(rb.shift).to(f"cuda:{dev}")
+    st = torch.cuda.current_stream(dev)
+    bufs = {}
+    for _ in range(args.warmup):
+        pipeline.call_methylation(al, draw, ranks, rb.kmer_offset, scale, shift, stream=st, bufs=bufs)
+    t1 = time.perf_counter()
+    stages = []
+    for _ in range(args.steps):
+        res = pipeline.call_methylation(al, draw, ranks, rb.kmer_offset, scale, shift, stream=st, bufs=bufs)
+        stages.append(res.ms)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t1) / args.steps * 1e3
+    S = int(rb.sample_offset[-1])
+    nev = res.n_ev.cpu().numpy()
+    llr = res.llr.cpu().numpy()
+    sites = nev > 0
+    ko = rb.kmer_offset.astype(np.int64)
+    read_of = np.repeat(np.arange(rb.n_reads), np.diff(ko))
+    right = np.where(rb.methylated[read_of[sites]], llr[sites] > 0, llr[sites] < 0)
+    cells = int(res.dres.cells[: rb.n_reads].sum().item())
+    med = {key: round(float(np.median([s_[key] for s_ in stages])), 4) for key in stages[0]}
+    # throughput: P batches in flight, each on its own context and stream
+    # (the same reads; inputs shared read-only), so that one batch's longest
+    # reads overlap the others' work
+    P = max(1, args.inflight)
+    als = [al]
+    for _ in range(P - 1):
+        a2 = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
+        a2.set_methylated_model(mm.level_mean, mm.level_stdv)
+        als.append(a2)
+    streams = [torch.cuda.Stream(dev) for _ in range(P)]
+    pbufs = [{} for _ in range(P)]
+
+    def flight():
+        for i in range(P):
+            pipeline.start(als[i], draw, rb.kmer_offset, pbufs[i], stream=streams[i])
+        return [pipeline.finish(als[i], draw, ranks, rb.kmer_offset, scale, shift, pbufs[i], stream=streams[i])
+                for i in range(P)]
+
+    flight()
+    torch.cuda.synchronize()
+    rounds = max(1, args.steps // P)
+    t3 = time.perf_counter()
+    for _ in range(rounds):
+        flight()
+    torch.cuda.synchronize()
+    flight_ms = (time.perf_counter() - t3) / (rounds * P) * 1e3
+    for a2 in als[1:]:
+        a2.close()
+    out = {
+        "metric": "methylation calling from raw signal (event detection + alignment + site scoring) on 1 MI355X",
+        "value": round(S / flight_ms / 1e6, 3),
+        "unit": "G samples/s",
+        "n_gpus": 1,
+        "steps": rounds * P,
+        "warmup": args.warmup,
+        "ms_per_step": round(flight_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64+f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_reads": rb.n_reads, "samples_per_step": S,
+                   "events_per_step": int(res.event_offset[-1]), "sites_per_step": int(sites.sum()),
+                   "alignment_cells_per_step": cells, "W": W, "k": k},
+        "reads_per_s": round(rb.n_reads / flight_ms * 1e3, 1),
+        "batches_in_flight": P,
+        "one_batch_alone": {"ms": round(wall_ms, 3), "g_samples_per_s": round(S / wall_ms / 1e6, 3),
+                            "stage_ms_median": med},
+        "alignment_gcups_alone": round(cells / (med["align"] / 1e3) / 1e9, 1),
+        "sites_right_sign": round(float(right.mean()), 4),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+
+        cores = min(16, os.cpu_count() or 1)
+        log("bench: cpu baseline (the three oracles chained)")
+        Mu = O.Model(model.level_mean, model.level_stdv)
+        Mm = O.Model(mm.level_mean, mm.level_stdv)
+        t2 = time.perf_counter()
+        ev, eo = O.ed_batch(rb, n_threads=cores)
+        b = synth.Batch(ev, eo, rb.ranks, rb.kmer_offset, rb.scale, rb.shift)
+        ores = O.align_batch(b, Mu, W, n_threads=cores)
+        po = np.zeros(b.n_reads + 1, np.uint64)
+        po[1:] = np.cumsum(np.where(ores.status == 0, ores.path_len, 0))
+        pairs = np.concatenate([ores.read_pairs(r) for r in range(b.n_reads) if ores.status[r] == 0])
+        O.meth_batch(b, k, Mu, Mm, pairs, po, ores.status, n_threads=cores)
+        dt = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": round(S / dt / 1e9, 4), "unit": "G samples/s", "cores": cores,
+                               "kind": "oracle", "sample": f"the whole workload: {S} samples, {dt:.2f} s",
+                               "host_cpu": host_cpu()}
+    al.close()
+    return out
+
+
 def backtrack_probe(model, k, W, job, dev, st):
     """The backtrack alone (split kernels, first batch): path steps per second
     and trace bytes walked per second."""
@@ -1011,9 +1136,9 @@ def main():
     # plain: enough batches that the drain of the last ones in flight is a
     # small part of the timed region; persistent: whole passes of the job
     if args.steps is None:
-        args.steps = {"plain": 200, "detect": 20, "meth": 20}.get(wl["kind"], 10)
+        args.steps = {"plain": 200, "detect": 20, "meth": 20, "pipeline": 10}.get(wl["kind"], 10)
     if args.warmup is None:
-        args.warmup = {"plain": 16, "detect": 3, "meth": 3}.get(wl["kind"], 1)
+        args.warmup = {"plain": 16, "detect": 3, "meth": 3, "pipeline": 2}.get(wl["kind"], 1)
     if args.wpg <= 0 and wl["kind"] != "persistent":
         args.wpg = 1
     if 0 < args.hw_queues <= 32:
@@ -1027,6 +1152,8 @@ def main():
         out = bench_detect(args, wl)
     elif wl["kind"] == "meth":
         out = bench_meth(args, wl)
+    elif wl["kind"] == "pipeline":
+        out = bench_pipeline(args, wl)
     elif wl["kind"] == "serving":
         out = bench_serving(args, wl)
     else:

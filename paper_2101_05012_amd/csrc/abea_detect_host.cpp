@@ -5,8 +5,11 @@
  *
  * A read of n samples has ceil(n / ED_TILE) tiles of ED_TILE boundaries;
  * the plan is each read's first tile (a prefix sum over the host sample
- * offsets), uploaded with the offsets through pinned staging on the call's
- * stream.  Buffers grow in stream order like the alignment's (abea_rt::ensure).
+ * offsets).  The plan and the offsets stay in mapped pinned host memory that
+ * the two kernels needing them read directly: the call issues no copy-engine
+ * command, which, queued behind this stream's earlier work, would hold back
+ * every other stream's copies.  Buffers grow in stream order like the
+ * alignment's (abea_rt::ensure).
  */
 #include <hip/hip_runtime.h>
 
@@ -26,10 +29,11 @@ namespace abea_rt {
 
 struct DetectWork {
   Work w; /* its events order buffer growth and the plan's staging */
-  DevBuf so, tile_first, tiles, flags, count, first_cp, base, bsum;
+  DevBuf tiles, flags, count, first_cp, base, bsum;
   /* the host entry point's device copies */
   DevBuf raw, offset, pa_scale, events, event_offset;
-  char *h_plan = nullptr; /* pinned: sample offsets, then first tiles */
+  char *h_plan = nullptr; /* mapped pinned: sample offsets, then first tiles */
+  char *d_plan = nullptr; /* h_plan as the device addresses it */
   size_t h_cap = 0;
   std::vector<void *> retired_host;
   /* ABEA_F_TIMING: k_ed_detect's dispatch, k_ed_events's, the whole batch */
@@ -41,8 +45,8 @@ void detect_free(abea_ctx *ctx, hipStream_t st) {
   DetectWork *d = ctx->detect;
   if (!d) return;
   (void)work_wait(ctx, d->w);
-  DevBuf *bufs[] = {&d->so,  &d->tile_first, &d->tiles, &d->flags,    &d->count,  &d->first_cp,    &d->base,
-                    &d->bsum, &d->raw,       &d->offset,   &d->pa_scale, &d->events, &d->event_offset};
+  DevBuf *bufs[] = {&d->tiles, &d->flags, &d->count,    &d->first_cp, &d->base,
+                    &d->bsum,  &d->raw,   &d->offset,   &d->pa_scale, &d->events, &d->event_offset};
   for (DevBuf *b : bufs) free_buf(*b, st);
   if (d->w.staging_pending && d->w.staging_done) (void)hipEventSynchronize(d->w.staging_done);
   d->w.staging_pending = false;
@@ -120,9 +124,15 @@ int detect_enqueue(abea_ctx *ctx, DetectWork *D, const abea_raw_batch_t *raw, co
      * upload and is freed with the detection state */
     const size_t cap_b = std::max<size_t>({need, 2 * D->h_cap, 4096});
     char *h = nullptr;
-    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap_b, hipHostMallocDefault));
+    void *dv = nullptr;
+    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap_b, hipHostMallocMapped | hipHostMallocCoherent));
+    if (hipHostGetDevicePointer(&dv, h, 0) != hipSuccess) {
+      (void)hipHostFree(h);
+      return fail(ctx, ABEA_E_HIP, "hipHostGetDevicePointer failed");
+    }
     if (D->h_plan) D->retired_host.push_back(D->h_plan);
     D->h_plan = h;
+    D->d_plan = (char *)dv;
     D->h_cap = cap_b;
     D->w.staging_pending = false;
   }
@@ -142,24 +152,17 @@ int detect_enqueue(abea_ctx *ctx, DetectWork *D, const abea_raw_batch_t *raw, co
   const uint32_t nb = ed_scan_blocks(n_tiles);
   Work *w = &D->w;
   int rc;
-  if ((rc = ensure(ctx, w, D->so, sizeof(uint64_t) * (size_t)(n + 1), st))) return rc;
-  if ((rc = ensure(ctx, w, D->tile_first, sizeof(uint32_t) * (size_t)(n + 1), st))) return rc;
   if ((rc = ensure(ctx, w, D->tiles, sizeof(EdTile) * (size_t)n_tiles, st))) return rc;
   if ((rc = ensure(ctx, w, D->flags, sizeof(uint64_t) * (size_t)n_tiles * (ED_TILE / 64), st))) return rc;
   if ((rc = ensure(ctx, w, D->count, sizeof(uint32_t) * (size_t)n_tiles, st))) return rc;
   if ((rc = ensure(ctx, w, D->first_cp, sizeof(int32_t) * (size_t)n_tiles, st))) return rc;
   if ((rc = ensure(ctx, w, D->base, sizeof(uint64_t) * (size_t)n_tiles, st))) return rc;
   if ((rc = ensure(ctx, w, D->bsum, sizeof(uint64_t) * (size_t)(nb + 1), st))) return rc;
-  HIP_TRY(ctx, hipMemcpyAsync(D->so.p, h_so, sizeof(uint64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(D->tile_first.p, h_tf, sizeof(uint32_t) * (size_t)(n + 1), hipMemcpyHostToDevice,
-                              st));
-  HIP_TRY(ctx, hipEventRecord(D->w.staging_done, st));
-  D->w.staging_pending = true;
 
   DetectArgs a;
   a.raw = samples;
-  a.sample_offset = (const uint64_t *)D->so.p;
-  a.tile_first = (const uint32_t *)D->tile_first.p;
+  a.sample_offset = (const uint64_t *)D->d_plan;
+  a.tile_first = (const uint32_t *)(D->d_plan + sizeof(uint64_t) * (size_t)(n + 1));
   a.tiles = (EdTile *)D->tiles.p;
   a.offset = offset;
   a.pa_scale = pa_scale;
@@ -179,6 +182,9 @@ int detect_enqueue(abea_ctx *ctx, DetectWork *D, const abea_raw_batch_t *raw, co
   a.event_offset = event_offset;
   D->timed = (ctx->flags & ABEA_F_TIMING) != 0;
   HIP_TRY(ctx, launch_detect(a, st, D->timed ? D->tev : nullptr));
+  /* the plan is read until the last kernel; the host may rewrite it after */
+  HIP_TRY(ctx, hipEventRecord(D->w.staging_done, st));
+  D->w.staging_pending = true;
   return work_mark(ctx, D->w, st);
 }
 

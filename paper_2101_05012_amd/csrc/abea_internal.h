@@ -218,6 +218,9 @@ struct MethArgs {
 /* tev: null, or four events: start of k_meth_bounds's dispatch and end of
  * k_meth_sites's, start and end of k_meth_llr's. */
 hipError_t launch_meth(const MethArgs &a, hipStream_t st, hipEvent_t *tev = nullptr);
+/* dst[0, n) = src[0, n) (src: device-readable pinned host memory) and
+ * *n_sites = 0, by a kernel on `st` */
+hipError_t launch_meth_stage(const MethRead *src, MethRead *dst, int n, uint32_t *n_sites, hipStream_t st);
 
 }  // namespace abea
 

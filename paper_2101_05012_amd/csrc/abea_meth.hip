@@ -49,6 +49,15 @@ __device__ __forceinline__ bool is_site(uint32_t rank, int k) {
 
 }  // namespace
 
+/* the plan from pinned host memory into device memory, and the site counter
+ * zeroed: a kernel, so that nothing of the call waits in the copy engines'
+ * queues behind another stream's work */
+__global__ __launch_bounds__(256) void k_meth_stage(const MethRead *src, MethRead *dst, int n, uint32_t *n_sites) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *n_sites = 0u;
+  if (i < n) dst[i] = src[i];
+}
+
 /* the last read r with key(r) <= v, keys non-decreasing over r = 0..n */
 template <typename Key>
 __device__ __forceinline__ int last_at_most(int n, uint64_t v, Key key) {
@@ -209,6 +218,11 @@ __global__ __launch_bounds__(256) void k_meth_llr(MethArgs a) {
     a.llr[rd.km_off + i] = vm - vu;
     if (a.n_ev) a.n_ev[rd.km_off + i] = e1 - e0 + 1;
   }
+}
+
+hipError_t launch_meth_stage(const MethRead *src, MethRead *dst, int n, uint32_t *n_sites, hipStream_t st) {
+  hipLaunchKernelGGL(k_meth_stage, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n, n_sites);
+  return hipGetLastError();
 }
 
 hipError_t launch_meth(const MethArgs &a, hipStream_t st, hipEvent_t *tev) {

@@ -21,7 +21,8 @@ namespace abea_rt {
 struct MethWork {
   Work w; /* its events order buffer growth and the plan's staging */
   DevBuf model, reads, kfirst, klast, sites, n_sites;
-  MethRead *h_reads = nullptr; /* pinned plan staging */
+  MethRead *h_reads = nullptr; /* pinned plan staging, read by k_meth_stage */
+  MethRead *d_view = nullptr;  /* h_reads as the device addresses it */
   size_t h_cap = 0;
   std::vector<void *> retired_host;
   /* ABEA_F_TIMING: the two kernels' dispatches */
@@ -110,9 +111,15 @@ int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   if ((size_t)n > M->h_cap) {
     const size_t cap = std::max<size_t>({(size_t)n, 2 * M->h_cap, 1024});
     MethRead *h = nullptr;
-    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap * sizeof(MethRead), hipHostMallocDefault));
+    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap * sizeof(MethRead), hipHostMallocMapped | hipHostMallocCoherent));
+    void *dv = nullptr;
+    if (hipHostGetDevicePointer(&dv, h, 0) != hipSuccess) {
+      (void)hipHostFree(h);
+      return fail(ctx, ABEA_E_HIP, "hipHostGetDevicePointer failed");
+    }
     if (M->h_reads) M->retired_host.push_back(M->h_reads);
     M->h_reads = h;
+    M->d_view = (MethRead *)dv;
     M->h_cap = cap;
     M->w.staging_pending = false;
   }
@@ -136,10 +143,12 @@ int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   if ((rc = ensure(ctx, w, M->klast, sizeof(int32_t) * (size_t)K, st))) return rc;
   if ((rc = ensure(ctx, w, M->sites, sizeof(uint2) * (size_t)K, st))) return rc;
   if ((rc = ensure(ctx, w, M->n_sites, sizeof(uint32_t), st))) return rc;
-  HIP_TRY(ctx, hipMemcpyAsync(M->reads.p, M->h_reads, sizeof(MethRead) * (size_t)n, hipMemcpyHostToDevice, st));
+  /* the plan staged and the site counter zeroed by a kernel (no copy-engine
+   * command: one queued behind this stream's work would hold back every other
+   * stream's copies); the host buffer is free again once it has run */
+  HIP_TRY(ctx, launch_meth_stage(M->d_view, (MethRead *)M->reads.p, n, (uint32_t *)M->n_sites.p, st));
   HIP_TRY(ctx, hipEventRecord(M->w.staging_done, st));
   M->w.staging_pending = true;
-  HIP_TRY(ctx, hipMemsetAsync(M->n_sites.p, 0, sizeof(uint32_t), st));
 
   MethArgs a;
   a.reads = (const MethRead *)M->reads.p;

@@ -82,6 +82,10 @@ WORKLOADS = {
     "meth-4000-lognormal5kb": dict(seed_index=7, n_reads=4000, W=100, k=6, lengths="lognormal5k", meth=True),
     # raw signal of reads of the same length mix (event detection's input)
     "raw-4000-lognormal5kb": dict(seed_index=6, n_reads=4000, W=100, k=6, lengths="lognormal5k", raw=True),
+    # raw signal again, each read methylated with probability 1/2: the input of
+    # the whole pipeline (event detection, alignment, methylation scoring)
+    "pipeline-4000-lognormal5kb": dict(seed_index=8, n_reads=4000, W=100, k=6, lengths="lognormal5k", raw=True,
+                                       meth=True),
 }
 
 SAMPLE_RATE_HZ = 4000.0
@@ -270,6 +274,7 @@ class RawRead:
     scale: np.float32  # model scaling of the alignment (mu' = level_mean * scale + shift)
     shift: np.float32
     dwell: np.ndarray  # int64 [n_k]: samples of each k-mer (ground truth)
+    methylated: bool = False  # drawn from the methylated levels (ground truth)
 
 
 @dataclasses.dataclass
@@ -285,6 +290,7 @@ class RawBatch:
     scale: np.ndarray  # float32 [n]
     shift: np.ndarray  # float32 [n]
     dwell: np.ndarray  # int64 [sum n_k]
+    methylated: Optional[np.ndarray] = None  # bool [n]
 
     @property
     def n_reads(self) -> int:
@@ -297,9 +303,13 @@ class RawBatch:
         return self.ranks[int(self.kmer_offset[i]) : int(self.kmer_offset[i + 1])]
 
 
-def gen_raw_read(rng: np.random.Generator, L: int, model: PoreModel, noiseless: bool = False) -> RawRead:
+def gen_raw_read(rng: np.random.Generator, L: int, model: PoreModel, noiseless: bool = False,
+                 meth_model: Optional[PoreModel] = None) -> RawRead:
     """Raw signal of one read of reference length L (see the module
-    docstring).  ``noiseless``: every sample is exactly its k-mer's level."""
+    docstring).  ``noiseless``: every sample is exactly its k-mer's level.
+    ``meth_model``: with probability 1/2 (drawn after everything else) the
+    levels come from it (a methylated read); the draw is kept in
+    ``RawRead.methylated``."""
     k = model.k
     bases = rng.integers(0, 4, L).astype(np.uint8)
     ranks = kmer_ranks(bases, k)
@@ -310,13 +320,16 @@ def gen_raw_read(rng: np.random.Generator, L: int, model: PoreModel, noiseless: 
     dwell = np.maximum(1, np.round(rng.gamma(DWELL_GAMMA_SHAPE, mean_dwell / DWELL_GAMMA_SHAPE, n_k))).astype(
         np.int64)
     r = np.repeat(ranks, dwell)
-    pa = model.level_mean[r].astype(np.float64) * float(scale) + float(shift)
-    if not noiseless:
-        pa = pa + rng.normal(0.0, 1.0, r.shape[0]) * model.level_stdv[r].astype(np.float64)
+    noise = None if noiseless else rng.normal(0.0, 1.0, r.shape[0])
     pa_scale = np.float32(rng.uniform(*RAW_RANGE_PA) / RAW_DIGITISATION)
     offset = np.float32(rng.uniform(*RAW_OFFSET))
+    methylated = bool(meth_model is not None and rng.random() < 0.5)
+    levels = meth_model.level_mean if methylated else model.level_mean
+    pa = levels[r].astype(np.float64) * float(scale) + float(shift)
+    if noise is not None:
+        pa = pa + noise * model.level_stdv[r].astype(np.float64)
     raw = np.clip(np.round(pa / float(pa_scale) - float(offset)), -32768, 32767).astype(np.int16)
-    return RawRead(raw, ranks, offset, pa_scale, scale, shift, dwell)
+    return RawRead(raw, ranks, offset, pa_scale, scale, shift, dwell, methylated)
 
 
 def make_raw_batch(reads: Sequence[RawRead]) -> RawBatch:
@@ -336,6 +349,7 @@ def make_raw_batch(reads: Sequence[RawRead]) -> RawBatch:
         np.array([r.offset for r in reads], np.float32), np.array([r.pa_scale for r in reads], np.float32),
         np.array([r.scale for r in reads], np.float32), np.array([r.shift for r in reads], np.float32),
         cat([r.dwell for r in reads], np.int64),
+        np.array([r.methylated for r in reads], bool),
     )
 
 
@@ -349,10 +363,11 @@ def workload_raw_batch(workload: str, model: Optional[PoreModel] = None,
         model = pore_model(cfg["k"])
     if read_ids is None:
         read_ids = range(cfg["n_reads"])
+    mm = methylated_model(model) if cfg.get("meth") else None
     out = []
     for i in read_ids:
         rng = read_rng(workload, int(i))
-        out.append(gen_raw_read(rng, draw_length(rng, cfg["lengths"]), model))
+        out.append(gen_raw_read(rng, draw_length(rng, cfg["lengths"]), model, meth_model=mm))
     return make_raw_batch(out)
 
 

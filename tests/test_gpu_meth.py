@@ -174,3 +174,37 @@ def test_meth_timings(models):
     t = al.meth_timings()
     assert t[0] > 0 and t[1] > 0, t
     al.close()
+
+
+def test_raw_signal_to_methylation_calls(models, oracle_mod):
+    """The whole methylation call of Ch. 5 §5.2.2 on the GPU: raw samples to
+    events, events to alignment, aligned events to site LLRs, against the
+    oracles chained the same way (event detection, alignment, scoring)."""
+    import torch
+
+    from paper_2101_05012_amd import pipeline
+
+    m, mm = models
+    rb = synth.workload_raw_batch("pipeline-4000-lognormal5kb", m, read_ids=range(200))
+    al = abea.Aligner(m.level_mean, m.level_stdv, 6, W=100)
+    al.set_methylated_model(mm.level_mean, mm.level_stdv)
+    draw = abea.raw_to_device(rb)
+    ranks = torch.from_numpy(rb.ranks.view(np.int32)).cuda()
+    scale = torch.from_numpy(rb.scale).cuda()
+    shift = torch.from_numpy(rb.shift).cuda()
+    say("gpu: raw signal to methylation calls (200 reads)")
+    res = pipeline.call_methylation(al, draw, ranks, rb.kmer_offset, scale, shift)
+    got = (res.llr.cpu().numpy(), res.n_ev.cpu().numpy())
+    ev, eo = oracle_mod.ed_batch(rb, n_threads=16)
+    assert np.array_equal(res.event_offset, eo)
+    b = synth.Batch(ev, eo, rb.ranks, rb.kmer_offset, rb.scale, rb.shift)
+    n = compare("pipeline200", got, oracle_scores(oracle_mod, b, m, mm))
+    assert n > 50000
+    # the calls' signs follow the reads' drawn states
+    ko = rb.kmer_offset.astype(np.int64)
+    read_of = np.repeat(np.arange(rb.n_reads), np.diff(ko))
+    sites = got[1] > 0
+    right = np.where(rb.methylated[read_of[sites]], got[0][sites] > 0, got[0][sites] < 0)
+    say(f"pipeline200: {right.mean():.4f} of the sites with the right sign")
+    assert right.mean() >= 0.9
+    al.close()
