@@ -264,9 +264,16 @@ int plan_batch(abea_ctx *ctx, Work &w, int n, const uint64_t *eo, const uint64_t
      * wait for the whole device) */
     const size_t cap = std::max<size_t>({(size_t)n, 2 * w.h_cap, 1024});
     ReadDesc *h = nullptr;
-    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap * sizeof(ReadDesc), hipHostMallocDefault));
+    void *dv = nullptr;
+    /* mapped: a kernel reads it (see stage_plan) */
+    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap * sizeof(ReadDesc), hipHostMallocMapped | hipHostMallocCoherent));
+    if (hipHostGetDevicePointer(&dv, h, 0) != hipSuccess) {
+      (void)hipHostFree(h);
+      return fail(ctx, ABEA_E_HIP, "hipHostGetDevicePointer failed");
+    }
     if (w.h_reads) w.retired_host.push_back(w.h_reads);
     w.h_reads = h;
+    w.d_view = (ReadDesc *)dv;
     w.h_cap = cap;
     w.staging_pending = false;
   }
@@ -420,11 +427,23 @@ int enqueue_kernels(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st, boo
   return ABEA_OK;
 }
 
+/* The plan into device memory on `st`: by a kernel reading the mapped pinned
+ * staging, so that the call issues no copy-engine command (a copy queued
+ * behind this stream's earlier work would hold back every other stream's
+ * copies until that work ends); a copy when the staging is not mapped. */
+int stage_plan(abea_ctx *ctx, Work &w, int n, hipStream_t st) {
+  if (w.d_view)
+    HIP_TRY(ctx, launch_stage_plan(w.d_view, (ReadDesc *)w.reads.p, n, st));
+  else
+    HIP_TRY(ctx, hipMemcpyAsync(w.reads.p, w.h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice, st));
+  return ABEA_OK;
+}
+
 /* Upload the plan and enqueue the batch on `st`. */
 int run_planned(abea_ctx *ctx, Work &w, const DevIO &io, hipStream_t st) {
   int rc;
   if ((rc = ensure_work(ctx, w, st))) return rc;
-  HIP_TRY(ctx, hipMemcpyAsync(w.reads.p, w.h_reads, sizeof(ReadDesc) * w.plan.n, hipMemcpyHostToDevice, st));
+  if ((rc = stage_plan(ctx, w, w.plan.n, st))) return rc;
   HIP_TRY(ctx, hipEventRecord(w.staging_done, st));
   w.staging_pending = true;
   if ((rc = enqueue_kernels(ctx, w, io, st, (ctx->flags & ABEA_F_TIMING) != 0))) return rc;
@@ -647,8 +666,14 @@ int abea_create(const abea_config_t *cfg, const abea_model_t *model, abea_ctx **
     ctx->noalloc.comp.reserve(ABEA_NOALLOC_MAX_READS);
     ctx->noalloc.plan.parts.reserve(ABEA_NOALLOC_MAX_READS + 2);
     e = hipHostMalloc((void **)&ctx->noalloc.h_reads, sizeof(ReadDesc) * ABEA_NOALLOC_MAX_READS,
-                      hipHostMallocDefault);
+                      hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) { rc = fail(ctx, ABEA_E_NOMEM, "pinned plan staging: %s", hipGetErrorString(e)); break; }
+    {
+      void *dv = nullptr;
+      e = hipHostGetDevicePointer(&dv, ctx->noalloc.h_reads, 0);
+      if (e != hipSuccess) { rc = fail(ctx, ABEA_E_HIP, "plan staging address: %s", hipGetErrorString(e)); break; }
+      ctx->noalloc.d_view = (ReadDesc *)dv;
+    }
     ctx->noalloc.h_cap = ABEA_NOALLOC_MAX_READS;
     ctx->err.reserve(512); /* error messages never reallocate */
   } while (0);
@@ -812,7 +837,7 @@ int abea_align_batch_device_noalloc(abea_ctx *ctx, const abea_batch_t *b, const 
   w.trace.p = base + off;
   w.trace.cap = budget;
   w.trace.borrowed = true;
-  HIP_TRY(ctx, hipMemcpyAsync(w.reads.p, w.h_reads, sizeof(ReadDesc) * n, hipMemcpyHostToDevice, st));
+  if ((rc = stage_plan(ctx, w, n, st))) return rc;
   HIP_TRY(ctx, hipEventRecord(w.staging_done, st));
   w.staging_pending = true;
   DevIO io;

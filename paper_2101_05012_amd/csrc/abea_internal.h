@@ -129,6 +129,8 @@ hipError_t launch_align(const AlignArgs &a, int cpl, int rpg, int wpg, bool edge
 /* resident workgroups of the fused kernel per CU (occupancy) for band width W */
 int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge, bool trim, int W);
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st);
+/* dst[0, n) = src[0, n) by a kernel (src: the plan in mapped pinned host memory) */
+hipError_t launch_stage_plan(const ReadDesc *src, ReadDesc *dst, int n, hipStream_t st);
 
 /* Fixed scratch of the no-allocation entry point (abea_kernels.hip). */
 constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20;

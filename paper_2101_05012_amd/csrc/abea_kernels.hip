@@ -1278,6 +1278,19 @@ int align_groups_per_cu(int cpl, int rpg, int wpg, bool edge, bool trim, int W) 
   return 0;
 }
 
+/* the plan from mapped pinned host memory into device memory, one thread per
+ * read */
+__global__ __launch_bounds__(256) void k_stage_plan(const ReadDesc *__restrict__ src, ReadDesc *__restrict__ dst,
+                                                    int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_stage_plan(const ReadDesc *src, ReadDesc *dst, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_stage_plan, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan(const uint64_t *len, int n, uint64_t *offset, hipStream_t st) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, len, n, offset);
   return hipGetLastError();

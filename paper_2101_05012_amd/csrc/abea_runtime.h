@@ -52,6 +52,7 @@ struct Work {
   std::vector<uint64_t> comp; /* per caller read: computed bands (n_e + n_k - 1, 0 if empty) */
   DevBuf reads, rstat, queue, xmean, krank, trace, scratch, path_len, path_src, tend;
   ReadDesc *h_reads = nullptr; /* pinned staging of the plan */
+  ReadDesc *d_view = nullptr;  /* h_reads as the device addresses it (mapped), or null */
   size_t h_cap = 0;
   hipEvent_t staging_done = nullptr;
   bool staging_pending = false;
