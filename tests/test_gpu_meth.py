@@ -208,3 +208,45 @@ def test_raw_signal_to_methylation_calls(models, oracle_mod):
     say(f"pipeline200: {right.mean():.4f} of the sites with the right sign")
     assert right.mean() >= 0.9
     al.close()
+
+
+def test_pipelines_in_flight_on_several_streams(models, oracle_mod):
+    """Four contexts, each with its own stream and its own batch of raw reads,
+    detection, alignment and scoring in flight together (the benchmark's
+    throughput form), two rounds: every batch's calls equal the oracles'
+    chain on that batch."""
+    import torch
+
+    from paper_2101_05012_amd import pipeline
+
+    m, mm = models
+    P = 4
+    batches = [synth.workload_raw_batch("pipeline-4000-lognormal5kb", m, read_ids=range(500 + 60 * i, 560 + 60 * i))
+               for i in range(P)]
+    want = []
+    for rb in batches:
+        ev, eo = oracle_mod.ed_batch(rb, n_threads=16)
+        b = synth.Batch(ev, eo, rb.ranks, rb.kmer_offset, rb.scale, rb.shift)
+        want.append((eo, oracle_scores(oracle_mod, b, m, mm)))
+    als, streams, bufs, dev = [], [], [], []
+    for rb in batches:
+        al = abea.Aligner(m.level_mean, m.level_stdv, 6, W=100)
+        al.set_methylated_model(mm.level_mean, mm.level_stdv)
+        als.append(al)
+        streams.append(torch.cuda.Stream())
+        bufs.append({})
+        dev.append((abea.raw_to_device(rb), torch.from_numpy(rb.ranks.view(np.int32)).cuda(),
+                    torch.from_numpy(rb.scale).cuda(), torch.from_numpy(rb.shift).cuda()))
+    say("gpu: four pipelines in flight")
+    for rnd in range(2):
+        for i in range(P):
+            pipeline.start(als[i], dev[i][0], batches[i].kmer_offset, bufs[i], stream=streams[i])
+        res = [pipeline.finish(als[i], dev[i][0], dev[i][1], batches[i].kmer_offset, dev[i][2], dev[i][3], bufs[i],
+                               stream=streams[i]) for i in range(P)]
+        torch.cuda.synchronize()
+        for i in range(P):
+            assert np.array_equal(res[i].event_offset, want[i][0]), (rnd, i)
+            compare(f"in flight, round {rnd}, batch {i}", (res[i].llr.cpu().numpy(), res[i].n_ev.cpu().numpy()),
+                    want[i][1])
+    for al in als:
+        al.close()
