@@ -29,6 +29,9 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # 16-byte LDS reads as one ds_read_b128 (contiguous across the lanes,
+    # free of bank conflicts) rather than a pair of 8-byte reads
+    "-Xclang", "-target-feature", "-Xclang", "+enable-ds128",
     "-Wall",
     "-Wno-unused-command-line-argument",
     "-pthread",

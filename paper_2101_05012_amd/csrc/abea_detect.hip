@@ -25,8 +25,10 @@
  * The work is a stream over the raw samples:
  *   k_ed_tiles     the tile table (one wavefront per read);
  *   k_ed_detect    one workgroup per tile of 1024 boundaries of one read:
- *                  samples to LDS, both statistics, peaks, one bit per
- *                  boundary, and the tile's event count;
+ *                  samples to LDS as prefix sums, both statistics, peaks
+ *                  (four consecutive boundaries per thread, their window
+ *                  maxima shared), one bit per boundary, and the tile's
+ *                  event count and first change point;
  *   k_ed_scan      exclusive scan of the tile counts, per 1024 tiles, then
  *                  over the blocks (k_ed_scan_top);
  *   k_ed_events    one workgroup per tile: the tile's event starts in order,
@@ -59,73 +61,175 @@ constexpr int SCAN_TILES = 1024; /* tiles per block of the first scan level */
 constexpr int EXT = 256; /* samples staged after the tile for events that run past it */
 constexpr int NE = TS + EXT; /* samples the event kernel stages per tile */
 
+/* a / b rounded to nearest, for 0 <= a < 2^64 and 1 <= b < 2^64: a
+ * reciprocal estimate refined by one Newton step, a first quotient, and two
+ * corrections from exact residuals (FMA).  It is the refinement the general
+ * FP32 division performs; the general one also scales operands whose
+ * quotient or reciprocal would leave the normal range and patches zero,
+ * infinite and NaN operands, none of which arises here (a = 0 gives +0). */
+__device__ __forceinline__ float div_small(float a, float b) {
+  const float y0 = __builtin_amdgcn_rcpf(b);
+  const float e = __builtin_fmaf(-b, y0, 1.0f);
+  const float y = __builtin_fmaf(e, y0, y0);
+  const float q0 = a * y;
+  const float r0 = __builtin_fmaf(-b, q0, a);
+  const float q1 = __builtin_fmaf(r0, y, q0);
+  const float r1 = __builtin_fmaf(-b, q1, a);
+  return __builtin_fmaf(r1, y, q1);
+}
+
 /* statistic of the detector with window w at boundary j of a read of n
  * samples, from prefix sums: P[c] and PQ[c] sum the staged samples before
- * sample j (and their squares).  Branch-free: the loads stay inside the
- * staged range for every boundary of the tile and its halo. */
-__device__ __forceinline__ float ed_stat(const int *P, const long long *PQ, int c, int w, int64_t j, int64_t n) {
+ * sample j (and their squares).  Q_l + Q_r and V are taken in double, where
+ * every value is an integer below 2^41 (at most 2 * 16 * 2^30 for the sums of
+ * squares, 2^40 for w (Q_l + Q_r) and S^2), so each operation is exact and V
+ * is the exact integer.  Branch-free: the loads stay inside the staged range
+ * for every boundary of the tile and its halo. */
+__device__ __forceinline__ float ed_stat(const int *P, const double *PQ, int c, int w, int j, int n) {
   const int sl = P[c] - P[c - w];
   const int sr = P[c + w] - P[c];
-  const int64_t ql = PQ[c] - PQ[c - w];
-  const int64_t qr = PQ[c + w] - PQ[c];
+  const double q = PQ[c + w] - PQ[c - w];
+  const double dl = (double)sl, dr = (double)sr;
+  const double v = __builtin_fma(-dl, dl, __builtin_fma(-dr, dr, (double)w * q));
   const int d = sr - sl;
-  const int64_t v = (int64_t)w * (ql + qr) - (int64_t)sl * sl - (int64_t)sr * sr;
   const float df = (float)d;
   const float num = (df * df) * (float)w;
-  const float den = (float)(double)v;
-  const float q = num / (v == 0 ? 1.0f : den);
-  const float t = v != 0 ? q : (d != 0 ? INFINITY : 0.0f);
+  const float den = (float)v;
+  const float qt = div_small(num, v == 0.0 ? 1.0f : den);
+  const float t = v != 0.0 ? qt : (d != 0 ? INFINITY : 0.0f);
   return (j >= w && j <= n - w) ? t : -1.0f;
 }
 
-/* a peak of the detector (w, thr = t^2) at ts[q]: above the threshold,
- * above the largest statistic up to w-1 before it, not below the largest up
- * to w-1 after it.  Undefined boundaries hold -1, below every defined
- * statistic, so they never block a peak. */
-template <int W>
-__device__ __forceinline__ bool ed_peak(const float *ts, int q, int w_rt, float thr) {
-  const float t = ts[q];
-  float lm = -1.0f, rm = -1.0f;
-  if constexpr (W > 0) {
+/* per lane: the larger of a and b, and the largest of a, b and c (one
+ * v_max_f32 / v_max3_f32 without canonicalisation: the statistics are never
+ * NaN) */
+__device__ __forceinline__ float max2(float a, float b) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float max3(float a, float b, float c) {
+  float r;
+  asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+/* largest of v[i0 .. i0+cnt-1] and init (cnt >= 0, compile-time indices) */
+template <int I0, int CNT, int NV>
+__device__ __forceinline__ float run_max(const float (&v)[NV], float init) {
+  float m = init;
+  int i = I0;
 #pragma unroll
-    for (int m = 1; m < W; ++m) {
-      lm = fmaxf(lm, ts[q - m]);
-      rm = fmaxf(rm, ts[q + m]);
+  for (; i + 1 < I0 + CNT; i += 2) m = max3(m, v[i], v[i + 1]);
+  if constexpr ((CNT & 1) != 0) m = max2(m, v[I0 + CNT - 1]);
+  return m;
+}
+
+/* Peaks of the detector (window W, thr = t^2) at the four boundaries
+ * ts[q0 .. q0+3]: boundary q is a peak if ts[q] is above thr and above every
+ * statistic up to W-1 before it, and not below any up to W-1 after it.
+ * Undefined boundaries hold -1, below every defined statistic, so they never
+ * block a peak; thr >= 0 takes part in the maximum before (t > thr and
+ * t > max(before) is t > max(thr, before)).  The four windows on each side
+ * share all but three of their W-1 values, so their maxima are built from
+ * one common maximum.  With W = 0 the window is w_rt (at run time). */
+template <int W>
+__device__ __forceinline__ uint32_t ed_peaks4(const float *ts, int q0, int w_rt, float thr) {
+  uint32_t bits = 0;
+  if constexpr (W > 0) {
+    constexpr int H = W - 1;          /* neighbours on each side, >= 1 */
+    constexpr int R = (H + 3) / 4;    /* float4s of neighbours on each side */
+    constexpr int NV = 4 + 8 * R;
+    constexpr int C = 4 * R;          /* v[C + j] is ts[q0 + j] */
+    float v[NV];
+    const float4 *p = reinterpret_cast<const float4 *>(ts + q0 - C);
+#pragma unroll
+    for (int f = 0; f < NV / 4; ++f) {
+      const float4 x = p[f];
+      v[4 * f] = x.x;
+      v[4 * f + 1] = x.y;
+      v[4 * f + 2] = x.z;
+      v[4 * f + 3] = x.w;
     }
+    float L[4], Rm[4];
+    if constexpr (H >= 4) {
+      /* before: window j is v[C+j-H .. C+j-1]; all four hold v[C+3-H .. C-1] */
+      const float cl = run_max<C + 3 - H, H - 3>(v, thr);
+      const float a12 = max2(v[C - H + 1], v[C - H + 2]);
+      const float b01 = max2(v[C], v[C + 1]);
+      L[0] = max3(v[C - H], a12, cl);
+      L[1] = max3(a12, cl, v[C]);
+      L[2] = max3(v[C - H + 2], cl, b01);
+      L[3] = max3(cl, b01, v[C + 2]);
+      /* after: window j is v[C+j+1 .. C+j+H]; all four hold v[C+4 .. C+H] */
+      const float cr = run_max<C + 5, H - 4>(v, v[C + 4]);
+      const float c23 = max2(v[C + 2], v[C + 3]);
+      const float e12 = max2(v[C + H + 1], v[C + H + 2]);
+      Rm[0] = max3(v[C + 1], c23, cr);
+      Rm[1] = max3(c23, cr, v[C + H + 1]);
+      Rm[2] = max3(v[C + 3], cr, e12);
+      Rm[3] = max3(cr, e12, v[C + H + 3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        L[j] = thr;
+        Rm[j] = v[C + j + 1];
+#pragma unroll
+        for (int m = 1; m <= H; ++m) L[j] = max2(L[j], v[C + j - m]);
+#pragma unroll
+        for (int m = 2; m <= H; ++m) Rm[j] = max2(Rm[j], v[C + j + m]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bits |= ((v[C + j] > L[j]) & (v[C + j] >= Rm[j])) ? (1u << j) : 0u;
   } else {
-    for (int m = 1; m < w_rt; ++m) {
-      lm = fmaxf(lm, ts[q - m]);
-      rm = fmaxf(rm, ts[q + m]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = q0 + j;
+      const float t = ts[q];
+      float lm = thr, rm = -1.0f;
+      for (int m = 1; m < w_rt; ++m) {
+        lm = fmaxf(lm, ts[q - m]);
+        rm = fmaxf(rm, ts[q + m]);
+      }
+      bits |= ((t > lm) & (t >= rm)) ? (1u << j) : 0u;
     }
   }
-  return (t > thr) & (t > lm) & (t >= rm);
+  return bits;
+}
+
+/* v of lane l-n of the same row of 16 lanes, cyclically (DPP row_ror:n) */
+template <int N>
+__device__ __forceinline__ uint32_t row_ror(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x120 + N, 0xF, 0xF, true);
 }
 
 /* Stage samples base+k, k in [0, NS), of a read (zero outside [0, lim)) as
- * prefix sums: P[k] and PQ[k] sum the first k values and their squares.
+ * prefix sums: P[k] and PQ[k] sum the first k values and their squares
+ * (QT: long long, or double, exact for NS * 2^30 < 2^53).
  * Thread t takes PER_ consecutive samples; the sums are scanned over the wave
  * and over the waves.  Ends with a barrier. */
-template <int NS>
-__device__ __forceinline__ void stage_prefix(const int16_t *x, int64_t base, int64_t lim, int *P, long long *PQ,
-                                             int *wsum, long long *wsq) {
+template <int NS, typename QT>
+__device__ __forceinline__ void stage_prefix(const int16_t *x, int64_t base, int64_t lim, int *P, QT *PQ, int *wsum,
+                                             QT *wsq) {
   constexpr int PER_ = (NS + THREADS - 1) / THREADS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int v[PER_];
   int s = 0;
-  long long q = 0;
+  QT q = 0;
 #pragma unroll
   for (int e = 0; e < PER_; ++e) {
     const int k = PER_ * (int)threadIdx.x + e;
     const int64_t si = base + k;
     v[e] = (k < NS && si >= 0 && si < lim) ? (int)x[si] : 0;
     s += v[e];
-    q += (long long)v[e] * v[e];
+    q += (QT)(v[e] * v[e]);
   }
   int si = s;
-  long long qi = q;
+  QT qi = q;
   for (int d = 1; d < 64; d <<= 1) {
     const int so = __shfl_up(si, d, 64);
-    const long long qo = __shfl_up(qi, d, 64);
+    const QT qo = __shfl_up(qi, d, 64);
     if (lane >= d) {
       si += so;
       qi += qo;
@@ -137,7 +241,7 @@ __device__ __forceinline__ void stage_prefix(const int16_t *x, int64_t base, int
   }
   __syncthreads();
   int ps = si - s;
-  long long pq = qi - q;
+  QT pq = qi - q;
   for (int w = 0; w < wave; ++w) {
     ps += wsum[w];
     pq += wsq[w];
@@ -150,7 +254,7 @@ __device__ __forceinline__ void stage_prefix(const int16_t *x, int64_t base, int
   for (int e = 0; e < PER_; ++e) {
     const int k = PER_ * (int)threadIdx.x + e;
     ps += v[e];
-    pq += (long long)v[e] * v[e];
+    pq += (QT)(v[e] * v[e]);
     if (k < NS) {
       P[k + 1] = ps;
       PQ[k + 1] = pq;
@@ -184,12 +288,15 @@ __global__ void k_ed_tiles(DetectArgs a) {
 template <int WS, int WL>
 __global__ __launch_bounds__(THREADS) void k_ed_detect(DetectArgs a) {
   __shared__ int P[NX + 1];
-  __shared__ long long PQ[NX + 1];
+  __shared__ double PQ[NX + 1];
   __shared__ int wsum[THREADS / 64];
-  __shared__ long long wsq[THREADS / 64];
-  __shared__ float tsh[NT], tlg[NT];
+  __shared__ double wsq[THREADS / 64];
+  __shared__ __align__(16) float tsh[NT];
+  __shared__ __align__(16) float tlg[NT];
   __shared__ uint32_t wcnt[THREADS / 64];
-  __shared__ int32_t first_cp;
+  __shared__ int32_t wfirst[THREADS / 64];
+  static_assert(TS == 4 * THREADS, "four boundaries per thread");
+  static_assert(THL == WMAX && THL % 4 == 0, "the peak loads stay inside the statistics");
   const uint32_t g = blockIdx.x;
   const EdTile tl = a.tiles[g];
   const int64_t n = tl.n;
@@ -198,36 +305,59 @@ __global__ __launch_bounds__(THREADS) void k_ed_detect(DetectArgs a) {
   const int ws = WS > 0 ? WS : a.w_short;
   const int wl = WL > 0 ? WL : a.w_long;
 
-  if (threadIdx.x == 0) first_cp = INT32_MAX;
   /* samples i0-XH .. i0+TS+XH-1 */
   stage_prefix<NX>(a.raw + tl.s0, i0 - XH, n, P, PQ, wsum, wsq);
   /* boundary j = i0 - THL + k: the sums before it are P[k + XH - THL] */
+  /* j in 32 bits: reads hold fewer than 2^31 samples, so n - w fits, and a
+   * j of 2^31 or more (past the read's end) wraps to a negative value, which
+   * is outside [w, n - w] like j itself */
   for (int k = threadIdx.x; k < NT; k += THREADS) {
-    const int64_t j = i0 - THL + k;
+    const int j = (int)((uint32_t)i0 - (uint32_t)THL + (uint32_t)k);
     const int c = k + XH - THL;
-    tsh[k] = ed_stat(P, PQ, c, ws, j, n);
-    tlg[k] = ed_stat(P, PQ, c, wl, j, n);
+    tsh[k] = ed_stat(P, PQ, c, ws, j, (int)n);
+    tlg[k] = ed_stat(P, PQ, c, wl, j, (int)n);
   }
   __syncthreads();
-  uint32_t cnt = 0;
-  for (int k0 = 0; k0 < TS; k0 += THREADS) {
-    const int q = k0 + (int)threadIdx.x + THL;
-    const bool cp = ((int)ed_peak<WS>(tsh, q, ws, a.thr_short) | (int)ed_peak<WL>(tlg, q, wl, a.thr_long)) != 0;
-    const uint64_t m = __ballot(cp);
-    if (lane == 0) {
-      a.flags[(uint64_t)g * WORDS + (k0 >> 6) + wave] = m;
-      cnt += (uint32_t)__popcll(m);
-      if (m) atomicMin(&first_cp, k0 + 64 * wave + __builtin_ctzll(m));
-    }
+  /* thread t: boundaries 4t .. 4t+3 of the tile (statistics q0 .. q0+3);
+   * the neighbours read lie in q0-16 .. q0+19, inside [0, NT) */
+  const int q0 = 4 * (int)threadIdx.x + THL;
+  const uint32_t nib = ed_peaks4<WS>(tsh, q0, ws, a.thr_short) | ed_peaks4<WL>(tlg, q0, wl, a.thr_long);
+  /* flag word m of the wave (its boundaries 64m .. 64m+63) is lanes 16m ..
+   * 16m+15, four bits each: its low half from the row's lanes 0-7, its high
+   * half from lanes 8-15, gathered by three row rotations (lane 7 and lane
+   * 15 of the row end with the halves) */
+  uint32_t x = nib << (4 * (lane & 7));
+  x |= row_ror<1>(x);
+  x |= row_ror<2>(x);
+  x |= row_ror<4>(x);
+  if ((lane & 7) == 7) {
+    uint32_t *f32 = reinterpret_cast<uint32_t *>(a.flags + (uint64_t)g * WORDS + 4 * wave);
+    f32[lane >> 3] = x;
   }
-  if (lane == 0) wcnt[wave] = cnt;
+  /* the wave's change points and its first one (wave-uniform masks) */
+  const uint64_t b0 = __ballot(nib & 1u), b1 = __ballot(nib & 2u), b2 = __ballot(nib & 4u), b3 = __ballot(nib & 8u);
+  if (lane == 0) {
+    wcnt[wave] = (uint32_t)(__popcll(b0) + __popcll(b1) + __popcll(b2) + __popcll(b3));
+    const uint64_t any = b0 | b1 | b2 | b3;
+    int32_t f = INT32_MAX;
+    if (any) {
+      const int l = __builtin_ctzll(any);
+      const int j = ((b0 >> l) & 1u) ? 0 : ((b1 >> l) & 1u) ? 1 : ((b2 >> l) & 1u) ? 2 : 3;
+      f = 256 * wave + 4 * l + j;
+    }
+    wfirst[wave] = f;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t c = (i0 == 0) ? 1u : 0u; /* the read's first event starts at sample 0 */
-    for (int w = 0; w < THREADS / 64; ++w) c += wcnt[w];
+    int32_t f = INT32_MAX;
+    for (int w = 0; w < THREADS / 64; ++w) {
+      c += wcnt[w];
+      f = min(f, wfirst[w]);
+    }
     a.count[g] = c;
     /* the tile's first change point in the read, -1 if it has none */
-    a.first_cp[g] = first_cp == INT32_MAX ? -1 : (int32_t)(i0 + first_cp);
+    a.first_cp[g] = f == INT32_MAX ? -1 : (int32_t)(i0 + f);
   }
 }
 
@@ -362,19 +492,24 @@ __global__ __launch_bounds__(THREADS) void k_ed_events(DetectArgs a) {
     }
     const int64_t len = b1 - b0;
     const double m = (double)s / (double)len;
-    /* len^2 times the population variance, exact, rounded once to double */
-    const unsigned __int128 vv =
-        (unsigned __int128)((__int128)len * q - (__int128)s * s);
-    const uint64_t hi = (uint64_t)(vv >> 64);
+    /* len^2 times the population variance, exact, rounded once to double:
+     * below 2^16 samples len * Q and S^2 stay below 2^62 (samples are 16-bit),
+     * so 64 bits hold it; longer events take 128 */
     double vd;
-    if (hi == 0) {
-      vd = (double)(uint64_t)vv;
+    if (len < 65536) {
+      vd = (double)(uint64_t)(len * q - s * s);
     } else {
-      /* keep the top 64 bits and a sticky bit: one rounding to double */
-      const int k = 64 - __builtin_clzll(hi);
-      const unsigned __int128 low = vv & ((((unsigned __int128)1) << k) - 1);
-      const uint64_t top = (uint64_t)(vv >> k) | (low != 0 ? 1u : 0u);
-      vd = __builtin_ldexp((double)top, k);
+      const unsigned __int128 vv = (unsigned __int128)((__int128)len * q - (__int128)s * s);
+      const uint64_t hi = (uint64_t)(vv >> 64);
+      if (hi == 0) {
+        vd = (double)(uint64_t)vv;
+      } else {
+        /* keep the top 64 bits and a sticky bit: one rounding to double */
+        const int k = 64 - __builtin_clzll(hi);
+        const unsigned __int128 low = vv & ((((unsigned __int128)1) << k) - 1);
+        const uint64_t top = (uint64_t)(vv >> k) | (low != 0 ? 1u : 0u);
+        vd = __builtin_ldexp((double)top, k);
+      }
     }
     float *ev = a.events + 3 * idx;
     ev[0] = (float)((m + off) * sc);
