@@ -47,6 +47,54 @@ def start(al: abea.Aligner, draw: abea.DeviceRawBatch, kmer_offset: np.ndarray, 
         bufs["llr"] = torch.empty(max(K, 1), dtype=torch.float32, device=dev)
         bufs["nev"] = torch.empty(max(K, 1), dtype=torch.int32, device=dev)
     al.detect_events_device(draw, bufs["ev"], bufs["eo"], params, stream=st)
+    ev = bufs.get("detected")
+    if ev is None:
+        ev = bufs["detected"] = torch.cuda.Event()
+    ev.record(st)
+
+
+def ready(bufs: dict) -> bool:
+    """True once the detection that ``start`` enqueued with ``bufs`` has run
+    (``finish`` then waits for nothing but the offsets' copy)."""
+    return bufs["detected"].query()
+
+
+def run_in_flight(n_slots: int, n_batches: int, start_fn, finish_fn, slot_bufs: list, poll_s: float = 20e-6) -> list:
+    """Batches 0 .. n_batches-1 over n_slots slots (a context and a stream
+    each): ``start_fn(slot, b)`` enqueues batch b's detection on the slot
+    (with ``start``), ``finish_fn(slot, b)`` its alignment and scoring (with
+    ``finish``) and returns what is kept of it.  A batch is finished as soon
+    as its detection has run, in whatever order the slots get there, and the
+    slot's next batch is enqueued behind it at once: a slot whose detection
+    waits behind its previous batch's longest read holds back no other slot.
+    Returns finish_fn's results in batch order."""
+    import time
+
+    results = [None] * n_batches
+    busy = [None] * n_slots  # the batch whose detection each slot holds
+    nxt = 0
+    for i in range(min(n_slots, n_batches)):
+        start_fn(i, nxt)
+        busy[i] = nxt
+        nxt += 1
+    done = 0
+    while done < n_batches:
+        moved = False
+        for i in range(n_slots):
+            b = busy[i]
+            if b is None or not ready(slot_bufs[i]):
+                continue
+            results[b] = finish_fn(i, b)
+            done += 1
+            busy[i] = None
+            moved = True
+            if nxt < n_batches:
+                start_fn(i, nxt)
+                busy[i] = nxt
+                nxt += 1
+        if not moved:
+            time.sleep(poll_s)
+    return results
 
 
 def finish(al: abea.Aligner, draw: abea.DeviceRawBatch, ranks, kmer_offset: np.ndarray, scale, shift, bufs: dict,

@@ -212,9 +212,10 @@ def test_raw_signal_to_methylation_calls(models, oracle_mod):
 
 def test_pipelines_in_flight_on_several_streams(models, oracle_mod):
     """Four contexts, each with its own stream and its own batch of raw reads,
-    detection, alignment and scoring in flight together (the benchmark's
-    throughput form), two rounds: every batch's calls equal the oracles'
-    chain on that batch."""
+    detection, alignment and scoring in flight together, two rounds; then
+    eleven batches through the same four slots by pipeline.run_in_flight (the
+    benchmark's throughput form): every batch's calls equal the oracles' chain
+    on its reads."""
     import torch
 
     from paper_2101_05012_amd import pipeline
@@ -237,7 +238,7 @@ def test_pipelines_in_flight_on_several_streams(models, oracle_mod):
         bufs.append({})
         dev.append((abea.raw_to_device(rb), torch.from_numpy(rb.ranks.view(np.int32)).cuda(),
                     torch.from_numpy(rb.scale).cuda(), torch.from_numpy(rb.shift).cuda()))
-    say("gpu: four pipelines in flight")
+    say("gpu: four pipelines in flight, round by round")
     for rnd in range(2):
         for i in range(P):
             pipeline.start(als[i], dev[i][0], batches[i].kmer_offset, bufs[i], stream=streams[i])
@@ -248,5 +249,30 @@ def test_pipelines_in_flight_on_several_streams(models, oracle_mod):
             assert np.array_equal(res[i].event_offset, want[i][0]), (rnd, i)
             compare(f"in flight, round {rnd}, batch {i}", (res[i].llr.cpu().numpy(), res[i].n_ev.cpu().numpy()),
                     want[i][1])
+    # the benchmark's form: batches finished in the order their detections
+    # end, each slot refilled at once; batch b is batches[b % P]'s reads on
+    # whichever slot takes it, its results copied on the slot's stream before
+    # the slot's next batch overwrites them
+    say("gpu: eleven batches over four slots, finished as their detections end")
+    slot_of = {}
+
+    def start_fn(i, b):
+        d = dev[b % P]
+        slot_of[b] = i
+        pipeline.start(als[i], d[0], batches[b % P].kmer_offset, bufs[i], stream=streams[i])
+
+    def finish_fn(i, b):
+        d = dev[b % P]
+        r = pipeline.finish(als[i], d[0], d[1], batches[b % P].kmer_offset, d[2], d[3], bufs[i], stream=streams[i])
+        with torch.cuda.stream(streams[i]):
+            return r.event_offset, r.llr.clone(), r.n_ev.clone()
+
+    out = pipeline.run_in_flight(P, 11, start_fn, finish_fn, bufs)
+    torch.cuda.synchronize()
+    assert sorted(set(slot_of.values())) == list(range(P))
+    for b, (eo, llr, nev) in enumerate(out):
+        assert np.array_equal(eo, want[b % P][0]), b
+        compare(f"scheduled batch {b} (reads of batch {b % P}, slot {slot_of[b]})",
+                (llr.cpu().numpy(), nev.cpu().numpy()), want[b % P][1])
     for al in als:
         al.close()
