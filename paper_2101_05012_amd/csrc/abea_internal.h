@@ -195,12 +195,24 @@ struct MethRead {
 };
 static_assert(sizeof(MethRead) == 32, "MethRead is 32 bytes");
 
+constexpr int METH_CHUNK = 8192; /* pairs or k-mers of one read per workgroup */
+
+/* One workgroup's share of a read: its chunk-th run of METH_CHUNK pairs (or
+ * k-mers) */
+struct MethTile {
+  uint32_t read;
+  uint32_t chunk;
+};
+static_assert(sizeof(MethTile) == 8, "MethTile is 8 bytes");
+
 struct MethArgs {
   const MethRead *reads;       /* [n_reads] */
   int32_t n_reads;
   int32_t k;
   uint64_t n_kmers;            /* of the batch */
-  uint64_t max_pairs;          /* an upper bound of the batch's pairs (sum of n_e + n_k - 1) */
+  const MethTile *pair_tiles;  /* [n_pair_tiles]: ceil((n_e + n_k - 1) / METH_CHUNK) per read, a bound of its pairs */
+  const MethTile *kmer_tiles;  /* [n_kmer_tiles]: ceil(n_k / METH_CHUNK) per read */
+  uint32_t n_pair_tiles, n_kmer_tiles;
   const float *events;         /* the batch's event records (ev_stride floats apart) */
   int32_t ev_stride;
   int32_t scale_events;        /* events scaled to the model instead of the model to the events */
@@ -220,9 +232,9 @@ struct MethArgs {
 /* tev: null, or four events: start of k_meth_bounds's dispatch and end of
  * k_meth_sites's, start and end of k_meth_llr's. */
 hipError_t launch_meth(const MethArgs &a, hipStream_t st, hipEvent_t *tev = nullptr);
-/* dst[0, n) = src[0, n) (src: device-readable pinned host memory) and
- * *n_sites = 0, by a kernel on `st` */
-hipError_t launch_meth_stage(const MethRead *src, MethRead *dst, int n, uint32_t *n_sites, hipStream_t st);
+/* dst[0, words) = src[0, words) (src: device-readable pinned host memory)
+ * and *n_sites = 0, by a kernel on `st` */
+hipError_t launch_meth_stage(const uint64_t *src, uint64_t *dst, size_t words, uint32_t *n_sites, hipStream_t st);
 
 }  // namespace abea
 

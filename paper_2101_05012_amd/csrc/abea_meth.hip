@@ -19,12 +19,13 @@
  *   - LLR = score(methylated) - score(unmethylated), float32.
  *
  * Kernels:
- *   k_meth_bounds  one workgroup per 8192 pairs of the batch: the first and
- *                  last event paired with each k-mer (the pairs run in path
- *                  order, so a k-mer's pairs are consecutive);
- *   k_meth_sites   one workgroup per 8192 k-mers: the sites appended to a list
- *                  (one atomic per workgroup), NaN / 0 written for every k-mer
- *                  that is not a scored site;
+ *   k_meth_bounds  one workgroup per 8192 pairs of one read (the tiles of a
+ *                  bound of each read's path, from the host's offsets): the
+ *                  first and last event paired with each k-mer (the pairs run
+ *                  in path order, so a k-mer's pairs are consecutive);
+ *   k_meth_sites   one workgroup per 8192 k-mers of one read: the sites
+ *                  appended to a list (one atomic per workgroup), NaN / 0
+ *                  written for every k-mer that is not a scored site;
  *   k_meth_llr     one thread per listed site: both profiles in registers (a
  *                  column of at most ABEA_MAX_K cells per model), then the LLR.
  */
@@ -41,7 +42,7 @@ namespace abea {
 namespace {
 
 constexpr int KMAX = 12; /* the longest window: k <= ABEA_MAX_K */
-constexpr int CHUNK = 8192; /* pairs or k-mers per workgroup of the first two kernels */
+constexpr int CHUNK = METH_CHUNK; /* pairs or k-mers per workgroup of the first two kernels */
 
 __device__ __forceinline__ bool is_site(uint32_t rank, int k) {
   return k >= 2 && ((rank >> (2 * (k - 1))) & 3u) == 1u && ((rank >> (2 * (k - 2))) & 3u) == 2u;
@@ -49,74 +50,73 @@ __device__ __forceinline__ bool is_site(uint32_t rank, int k) {
 
 }  // namespace
 
-/* the plan from pinned host memory into device memory, and the site counter
- * zeroed: a kernel, so that nothing of the call waits in the copy engines'
- * queues behind another stream's work */
-__global__ __launch_bounds__(256) void k_meth_stage(const MethRead *src, MethRead *dst, int n, uint32_t *n_sites) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+/* the plan (reads and tile tables) from pinned host memory into device
+ * memory, and the site counter zeroed: a kernel, so that nothing of the call
+ * waits in the copy engines' queues behind another stream's work */
+__global__ __launch_bounds__(256) void k_meth_stage(const uint64_t *src, uint64_t *dst, size_t words,
+                                                    uint32_t *n_sites) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *n_sites = 0u;
-  if (i < n) dst[i] = src[i];
+  if (i < words) dst[i] = src[i];
 }
 
-/* the last read r with key(r) <= v, keys non-decreasing over r = 0..n */
-template <typename Key>
-__device__ __forceinline__ int last_at_most(int n, uint64_t v, Key key) {
-  int lo = 0, hi = n; /* key(lo) <= v < key(hi) */
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (key(mid) <= v)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-/* one workgroup per chunk of CHUNK pairs of the batch (thread t takes pairs
- * t, t+256, ...): the first and the last event paired with each k-mer (a
- * k-mer's pairs are consecutive in the path order).  The chunk's first read
- * is found once; each thread then follows the read boundaries forward. */
+/* one workgroup per tile, a run of CHUNK pairs of one read (thread t takes
+ * the run's pairs t, t+256, ...): the first and the last event paired with
+ * each k-mer (a k-mer's pairs are consecutive in the path order).  The
+ * read's fields are workgroup-uniform; the pairs are loaded eight
+ * iterations ahead of the stores that use them. */
 __global__ __launch_bounds__(256) void k_meth_bounds(MethArgs a) {
-  const uint64_t total = a.pair_offset[a.n_reads];
-  const uint64_t c0 = (uint64_t)blockIdx.x * CHUNK;
-  if (c0 >= total) return;
-  int r = last_at_most(a.n_reads, c0, [&](int i) { return a.pair_offset[i]; });
-  for (int it = 0; it < CHUNK / 256; ++it) {
-    const uint64_t p = c0 + (uint64_t)it * 256 + threadIdx.x;
-    if (p >= total) break;
-    while (a.pair_offset[r + 1] <= p) ++r;
-    if (a.status[r] != READ_OK) continue;
-    const uint64_t p0 = a.pair_offset[r], p1 = a.pair_offset[r + 1];
-    const MethRead rd = a.reads[r];
-    const int2 q = a.pairs[p];
-    if (q.y < 0 || q.y >= rd.n_k) continue;
-    if (p == p0 || a.pairs[p - 1].y != q.y) a.kfirst[rd.km_off + q.y] = q.x;
-    if (p + 1 == p1 || a.pairs[p + 1].y != q.y) a.klast[rd.km_off + q.y] = q.x;
+  const MethTile tl = a.pair_tiles[blockIdx.x];
+  const int r = (int)tl.read;
+  if (a.status[r] != READ_OK) return;
+  const uint64_t p0 = a.pair_offset[r], p1 = a.pair_offset[r + 1];
+  const uint64_t c0 = p0 + (uint64_t)tl.chunk * CHUNK;
+  if (c0 >= p1) return;
+  const uint64_t c1 = c0 + CHUNK < p1 ? c0 + CHUNK : p1;
+  const MethRead rd = a.reads[r];
+  constexpr int G = 8;
+  for (int g = 0; g < CHUNK / 256; g += G) {
+    int2 q[G];
+    int yp[G], yn[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const uint64_t p = c0 + (uint64_t)(g + u) * 256 + threadIdx.x;
+      q[u] = make_int2(0, -1);
+      yp[u] = yn[u] = INT32_MIN; /* no neighbour: the run of the k-mer ends here */
+      if (p < c1) {
+        q[u] = a.pairs[p];
+        if (p > p0) yp[u] = a.pairs[p - 1].y;
+        if (p + 1 < p1) yn[u] = a.pairs[p + 1].y;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (q[u].y < 0 || q[u].y >= rd.n_k) continue;
+      if (yp[u] != q[u].y) a.kfirst[rd.km_off + q[u].y] = q[u].x;
+      if (yn[u] != q[u].y) a.klast[rd.km_off + q[u].y] = q[u].x;
+    }
   }
 }
 
-/* one workgroup per chunk of CHUNK k-mers: the sites of aligned reads go to
- * the list (one atomic per workgroup: the chunk's sites are counted first,
- * then written at the workgroup's base), every other k-mer gets NaN and 0 */
+/* one workgroup per tile, a run of CHUNK k-mers of one read: the sites of an
+ * aligned read go to the list (one atomic per workgroup: the sites are found
+ * and counted first, one bit per iteration kept by each thread, then written
+ * at the workgroup's base), every other k-mer gets NaN and 0 */
 __global__ __launch_bounds__(256) void k_meth_sites(MethArgs a) {
   __shared__ uint32_t wcount[4], wbase[4];
-  const uint64_t c0 = (uint64_t)blockIdx.x * CHUNK;
+  const MethTile tl = a.kmer_tiles[blockIdx.x];
+  const int r = (int)tl.read;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  auto km = [&](int j) -> uint64_t { return j < a.n_reads ? a.reads[j].km_off : a.n_kmers; };
-  const int r0 = last_at_most(a.n_reads, c0 < a.n_kmers ? c0 : a.n_kmers - 1, km);
-  /* the k-mer of iteration it, its read (followed forward), and whether it
-   * is a site of an aligned read */
-  auto probe = [&](int it, int &r, uint64_t &i) -> bool {
-    i = c0 + (uint64_t)it * 256 + threadIdx.x;
-    if (i >= a.n_kmers) return false;
-    while (km(r + 1) <= i) ++r;
-    return a.status[r] == READ_OK && is_site(a.ranks[i], a.k);
-  };
-  uint32_t cnt = 0;
-  int r = r0;
+  const MethRead rd = a.reads[r];
+  const bool ok = a.status[r] == READ_OK;
+  const uint32_t j0 = tl.chunk * (uint32_t)CHUNK; /* the run's first k-mer in the read */
+  const uint32_t j1 = (uint32_t)rd.n_k - j0 < (uint32_t)CHUNK ? (uint32_t)rd.n_k : j0 + CHUNK;
+  uint32_t bits = 0, cnt = 0;
+#pragma unroll 8
   for (int it = 0; it < CHUNK / 256; ++it) {
-    uint64_t i;
-    const bool site = probe(it, r, i);
+    const uint32_t j = j0 + (uint32_t)it * 256 + threadIdx.x;
+    const bool site = ok && j < j1 && is_site(a.ranks[rd.km_off + j], a.k);
+    bits |= (uint32_t)site << it;
     cnt += (uint32_t)__popcll(__ballot(site));
   }
   if (lane == 0) wcount[wave] = cnt;
@@ -132,17 +132,16 @@ __global__ __launch_bounds__(256) void k_meth_sites(MethArgs a) {
   }
   __syncthreads();
   uint32_t run = wbase[wave];
-  r = r0;
   for (int it = 0; it < CHUNK / 256; ++it) {
-    uint64_t i;
-    const bool site = probe(it, r, i);
+    const uint32_t j = j0 + (uint32_t)it * 256 + threadIdx.x;
+    const bool site = (bits >> it) & 1u;
     const uint64_t m = __ballot(site);
     if (site) {
       const uint32_t slot = run + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-      a.sites[slot] = make_uint2((uint32_t)r, (uint32_t)(i - a.reads[r].km_off));
-    } else if (i < a.n_kmers) {
-      a.llr[i] = NAN;
-      if (a.n_ev) a.n_ev[i] = 0;
+      a.sites[slot] = make_uint2((uint32_t)r, j);
+    } else if (j < j1) {
+      a.llr[rd.km_off + j] = NAN;
+      if (a.n_ev) a.n_ev[rd.km_off + j] = 0;
     }
     run += (uint32_t)__popcll(m);
   }
@@ -181,8 +180,11 @@ __global__ __launch_bounds__(256) void k_meth_llr(MethArgs a) {
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) su[j] = sm[j] = NI;
     const float *xm = a.events + (uint64_t)a.ev_stride * rd.ev_off;
+    /* the next event's mean is loaded while this one's row is computed */
+    float xnext = xm[(uint64_t)a.ev_stride * e0];
     for (int32_t e = e0; e <= e1; ++e) {
-      float x = xm[(uint64_t)a.ev_stride * e];
+      float x = xnext;
+      if (e < e1) xnext = xm[(uint64_t)a.ev_stride * (e + 1)];
       if (a.scale_events) {
         const float d = x - shift;
         x = d / scale;
@@ -220,20 +222,22 @@ __global__ __launch_bounds__(256) void k_meth_llr(MethArgs a) {
   }
 }
 
-hipError_t launch_meth_stage(const MethRead *src, MethRead *dst, int n, uint32_t *n_sites, hipStream_t st) {
-  hipLaunchKernelGGL(k_meth_stage, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n, n_sites);
+hipError_t launch_meth_stage(const uint64_t *src, uint64_t *dst, size_t words, uint32_t *n_sites, hipStream_t st) {
+  const size_t blocks = (words + 255) / 256;
+  hipLaunchKernelGGL(k_meth_stage, dim3((uint32_t)(blocks > 0 ? blocks : 1)), dim3(256), 0, st, src, dst, words,
+                     n_sites);
   return hipGetLastError();
 }
 
 hipError_t launch_meth(const MethArgs &a, hipStream_t st, hipEvent_t *tev) {
   if (a.n_reads > 0 && a.n_kmers > 0) {
-    const uint64_t bp = (a.max_pairs + CHUNK - 1) / CHUNK, bk = (a.n_kmers + CHUNK - 1) / CHUNK;
-    if (bp > 0)
-      hipExtLaunchKernelGGL(k_meth_bounds, dim3((uint32_t)bp), dim3(256), 0, st, tev ? tev[0] : nullptr, nullptr, 0,
+    if (a.n_pair_tiles > 0)
+      hipExtLaunchKernelGGL(k_meth_bounds, dim3(a.n_pair_tiles), dim3(256), 0, st, tev ? tev[0] : nullptr, nullptr, 0,
                             a);
     else if (tev)
       (void)hipEventRecord(tev[0], st);
-    hipExtLaunchKernelGGL(k_meth_sites, dim3((uint32_t)bk), dim3(256), 0, st, nullptr, tev ? tev[1] : nullptr, 0, a);
+    hipExtLaunchKernelGGL(k_meth_sites, dim3(a.n_kmer_tiles), dim3(256), 0, st, nullptr, tev ? tev[1] : nullptr, 0,
+                          a);
     hipExtLaunchKernelGGL(k_meth_llr, dim3(2048), dim3(256), 0, st, tev ? tev[2] : nullptr,
                           tev ? tev[3] : nullptr, 0, a);
   }

@@ -21,9 +21,11 @@ namespace abea_rt {
 struct MethWork {
   Work w; /* its events order buffer growth and the plan's staging */
   DevBuf model, reads, kfirst, klast, sites, n_sites;
-  MethRead *h_reads = nullptr; /* pinned plan staging, read by k_meth_stage */
-  MethRead *d_view = nullptr;  /* h_reads as the device addresses it */
-  size_t h_cap = 0;
+  /* pinned plan staging, read by k_meth_stage: the reads (MethRead), then
+   * the pair tiles and the k-mer tiles (MethTile), in 8-byte words */
+  uint64_t *h_plan = nullptr;
+  uint64_t *d_view = nullptr; /* h_plan as the device addresses it */
+  size_t h_cap = 0;           /* words */
   std::vector<void *> retired_host;
   /* ABEA_F_TIMING: the two kernels' dispatches */
   hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -38,7 +40,7 @@ void meth_free(abea_ctx *ctx, hipStream_t st) {
   for (DevBuf *b : bufs) free_buf(*b, st);
   if (m->w.staging_pending && m->w.staging_done) (void)hipEventSynchronize(m->w.staging_done);
   m->w.staging_pending = false;
-  if (m->h_reads) (void)hipHostFree(m->h_reads);
+  if (m->h_plan) (void)hipHostFree(m->h_plan);
   for (void *h : m->retired_host) (void)hipHostFree(h);
   for (hipEvent_t &e : m->tev)
     if (e) (void)hipEventDestroy(e);
@@ -108,37 +110,55 @@ int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   MethWork *M = ctx->meth;
   hipStream_t st = (hipStream_t)stream;
-  if ((size_t)n > M->h_cap) {
-    const size_t cap = std::max<size_t>({(size_t)n, 2 * M->h_cap, 1024});
-    MethRead *h = nullptr;
-    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap * sizeof(MethRead), hipHostMallocMapped | hipHostMallocCoherent));
+  /* the tiles: ceil((n_e + n_k - 1) / METH_CHUNK) runs of a bound of each
+   * read's pairs, ceil(n_k / METH_CHUNK) runs of its k-mers */
+  uint64_t n_pt = 0, n_kt = 0;
+  for (int r = 0; r < n; ++r) {
+    const uint64_t ne = eo[r + 1] - eo[r], nk = ko[r + 1] - ko[r];
+    if (ne > 0 && nk > 0) n_pt += (ne + nk - 1 + METH_CHUNK - 1) / METH_CHUNK;
+    n_kt += (nk + METH_CHUNK - 1) / METH_CHUNK;
+  }
+  if (n_pt >= (1ull << 31) || n_kt >= (1ull << 31))
+    return fail(ctx, ABEA_E_INVAL, "batch too large for methylation scoring");
+  const size_t rw = sizeof(MethRead) / 8, tw = sizeof(MethTile) / 8;
+  const size_t words = rw * (size_t)n + tw * (size_t)(n_pt + n_kt);
+  if (words > M->h_cap) {
+    const size_t cap = std::max<size_t>({words, 2 * M->h_cap, 8192});
+    uint64_t *h = nullptr;
+    HIP_TRY(ctx, hipHostMalloc((void **)&h, cap * 8, hipHostMallocMapped | hipHostMallocCoherent));
     void *dv = nullptr;
     if (hipHostGetDevicePointer(&dv, h, 0) != hipSuccess) {
       (void)hipHostFree(h);
       return fail(ctx, ABEA_E_HIP, "hipHostGetDevicePointer failed");
     }
-    if (M->h_reads) M->retired_host.push_back(M->h_reads);
-    M->h_reads = h;
-    M->d_view = (MethRead *)dv;
+    if (M->h_plan) M->retired_host.push_back(M->h_plan);
+    M->h_plan = h;
+    M->d_view = (uint64_t *)dv;
     M->h_cap = cap;
     M->w.staging_pending = false;
   }
   if (M->w.staging_pending) HIP_TRY(ctx, hipEventSynchronize(M->w.staging_done));
   M->w.staging_pending = false;
-  uint64_t max_pairs = 0;
+  MethRead *h_reads = reinterpret_cast<MethRead *>(M->h_plan);
+  MethTile *h_pt = reinterpret_cast<MethTile *>(M->h_plan + rw * (size_t)n);
+  MethTile *h_kt = h_pt + n_pt;
+  uint64_t ip = 0, ik = 0;
   for (int r = 0; r < n; ++r) {
-    MethRead &d = M->h_reads[r];
+    MethRead &d = h_reads[r];
     const uint64_t ne = eo[r + 1] - eo[r], nk = ko[r + 1] - ko[r];
-    if (ne > 0 && nk > 0) max_pairs += ne + nk - 1;
     d.ev_off = eo[r];
     d.km_off = ko[r];
     d.n_k = (int32_t)std::min<uint64_t>(nk, 0x7fffffff);
     d.lp_skip = d.lp_stay = d.lp_step = 0.f;
-    if (ne > 0 && nk > 0) transitions((int64_t)ne, (int64_t)nk, &d.lp_skip, &d.lp_stay, &d.lp_step);
+    if (ne > 0 && nk > 0) {
+      transitions((int64_t)ne, (int64_t)nk, &d.lp_skip, &d.lp_stay, &d.lp_step);
+      for (uint64_t c = 0; c * METH_CHUNK < ne + nk - 1; ++c) h_pt[ip++] = MethTile{(uint32_t)r, (uint32_t)c};
+    }
+    for (uint64_t c = 0; c * METH_CHUNK < nk; ++c) h_kt[ik++] = MethTile{(uint32_t)r, (uint32_t)c};
   }
   Work *w = &M->w;
   int rc;
-  if ((rc = ensure(ctx, w, M->reads, sizeof(MethRead) * (size_t)n, st))) return rc;
+  if ((rc = ensure(ctx, w, M->reads, 8 * words, st))) return rc;
   if ((rc = ensure(ctx, w, M->kfirst, sizeof(int32_t) * (size_t)K, st))) return rc;
   if ((rc = ensure(ctx, w, M->klast, sizeof(int32_t) * (size_t)K, st))) return rc;
   if ((rc = ensure(ctx, w, M->sites, sizeof(uint2) * (size_t)K, st))) return rc;
@@ -146,7 +166,7 @@ int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   /* the plan staged and the site counter zeroed by a kernel (no copy-engine
    * command: one queued behind this stream's work would hold back every other
    * stream's copies); the host buffer is free again once it has run */
-  HIP_TRY(ctx, launch_meth_stage(M->d_view, (MethRead *)M->reads.p, n, (uint32_t *)M->n_sites.p, st));
+  HIP_TRY(ctx, launch_meth_stage(M->d_view, (uint64_t *)M->reads.p, words, (uint32_t *)M->n_sites.p, st));
   HIP_TRY(ctx, hipEventRecord(M->w.staging_done, st));
   M->w.staging_pending = true;
 
@@ -155,7 +175,10 @@ int abea_methylation_device(abea_ctx *ctx, const abea_batch_t *b, const abea_res
   a.n_reads = n;
   a.k = (int32_t)ctx->k;
   a.n_kmers = K;
-  a.max_pairs = max_pairs;
+  a.pair_tiles = (const MethTile *)((const uint64_t *)M->reads.p + rw * (size_t)n);
+  a.kmer_tiles = a.pair_tiles + n_pt;
+  a.n_pair_tiles = (uint32_t)n_pt;
+  a.n_kmer_tiles = (uint32_t)n_kt;
   a.events = (const float *)b->events;
   a.ev_stride = 3;
   a.scale_events = (ctx->flags & ABEA_F_SCALE_EVENTS) != 0;
