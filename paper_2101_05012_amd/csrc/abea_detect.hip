@@ -287,12 +287,17 @@ __global__ void k_ed_tiles(DetectArgs a) {
  * from the arguments */
 template <int WS, int WL>
 __global__ __launch_bounds__(THREADS) void k_ed_detect(DetectArgs a) {
-  __shared__ int P[NX + 1];
-  __shared__ double PQ[NX + 1];
+  /* the prefix sums, then (once every thread holds its statistics in
+   * registers) the two rows of statistics in the same bytes: a smaller LDS
+   * footprint, more workgroups per CU */
+  __shared__ __align__(16) unsigned char lds[(NX + 1) * (sizeof(double) + sizeof(int))];
+  double *PQ = reinterpret_cast<double *>(lds);
+  int *P = reinterpret_cast<int *>(lds + (NX + 1) * sizeof(double));
+  float *tsh = reinterpret_cast<float *>(lds);
+  float *tlg = tsh + NT;
+  static_assert(2 * NT * sizeof(float) <= sizeof(lds) && (NT * sizeof(float)) % 16 == 0, "statistics fit");
   __shared__ int wsum[THREADS / 64];
   __shared__ double wsq[THREADS / 64];
-  __shared__ __align__(16) float tsh[NT];
-  __shared__ __align__(16) float tlg[NT];
   __shared__ uint32_t wcnt[THREADS / 64];
   __shared__ int32_t wfirst[THREADS / 64];
   static_assert(TS == 4 * THREADS, "four boundaries per thread");
@@ -311,11 +316,26 @@ __global__ __launch_bounds__(THREADS) void k_ed_detect(DetectArgs a) {
   /* j in 32 bits: reads hold fewer than 2^31 samples, so n - w fits, and a
    * j of 2^31 or more (past the read's end) wraps to a negative value, which
    * is outside [w, n - w] like j itself */
-  for (int k = threadIdx.x; k < NT; k += THREADS) {
-    const int j = (int)((uint32_t)i0 - (uint32_t)THL + (uint32_t)k);
-    const int c = k + XH - THL;
-    tsh[k] = ed_stat(P, PQ, c, ws, j, (int)n);
-    tlg[k] = ed_stat(P, PQ, c, wl, j, (int)n);
+  constexpr int NIT = (NT + THREADS - 1) / THREADS;
+  float rs[NIT], rl[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int k = (int)threadIdx.x + THREADS * it;
+    if (k < NT) {
+      const int j = (int)((uint32_t)i0 - (uint32_t)THL + (uint32_t)k);
+      const int c = k + XH - THL;
+      rs[it] = ed_stat(P, PQ, c, ws, j, (int)n);
+      rl[it] = ed_stat(P, PQ, c, wl, j, (int)n);
+    }
+  }
+  __syncthreads(); /* every thread is done with the prefix sums */
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int k = (int)threadIdx.x + THREADS * it;
+    if (k < NT) {
+      tsh[k] = rs[it];
+      tlg[k] = rl[it];
+    }
   }
   __syncthreads();
   /* thread t: boundaries 4t .. 4t+3 of the tile (statistics q0 .. q0+3);
