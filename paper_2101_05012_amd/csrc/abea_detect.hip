@@ -472,14 +472,21 @@ __global__ __launch_bounds__(THREADS) void k_ed_events(DetectArgs a) {
     if (f >= 0) atomicMin(&tail_end, (long long)f);
     if (__syncthreads_or(f >= 0)) break;
   }
-  if (threadIdx.x == 0) {
-    uint32_t p = first;
-    for (int w = 0; w < WORDS; ++w) {
-      wpre[w] = p;
-      p += (uint32_t)__popcll(wf[w]);
+  /* the events before each flag word (wf is visible: stage_prefix ends with
+   * a barrier): a scan of the 16 words' counts over 16 lanes of the first
+   * wavefront */
+  static_assert(WORDS == 16, "one lane per flag word");
+  if (threadIdx.x < WORDS) {
+    const uint32_t c = (uint32_t)__popcll(wf[threadIdx.x]);
+    uint32_t inc = c;
+#pragma unroll
+    for (int d = 1; d < WORDS; d <<= 1) {
+      const uint32_t o = __shfl_up(inc, d, WORDS);
+      if ((int)threadIdx.x >= d) inc += o;
     }
-    wpre[WORDS] = p;
-    if (first) starts[0] = 0;
+    wpre[threadIdx.x] = (uint32_t)first + inc - c;
+    if (threadIdx.x == WORDS - 1) wpre[WORDS] = (uint32_t)first + inc;
+    if (threadIdx.x == 0 && first) starts[0] = 0;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < TS; k += THREADS) {
