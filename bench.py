@@ -374,6 +374,7 @@ def bench_plain(args, wl):
         "parallelism": "one wavefront per read",
         "launch": "fused band+backtrack, one launch per batch" if fused else "band and backtrack kernels",
         "batches_in_flight": P,
+        "alignment_launch": {"workers": args.workers} if args.workers > 0 else "one wavefront per read",
         "warmup_batches": warm,
         "band_clear": {1: "window", 2: "edges"}.get(plan.get("band_clear"), "?"),
         "per_read_scaling": "events to the model" if wl.get("scale_events") else "model to the events",
@@ -835,6 +836,12 @@ def bench_pipeline(args, wl):
         a2 = abea.Aligner(model.level_mean, model.level_stdv, k, W=W, device=dev)
         a2.set_methylated_model(mm.level_mean, mm.level_stdv)
         als.append(a2)
+    # in flight, each alignment launch as a pool of --workers wavefronts (the
+    # plain workload's form: 16 pools of 320 fill the chip's resident slots)
+    if args.workers > 0:
+        clear = abea.ABEA_CLEAR_EDGES if abea.min_cells_per_lane(W) in (2, 4) else abea.ABEA_CLEAR_AUTO
+        for a2 in als:
+            a2.set_launch(workers=args.workers, waves_per_group=1, band_clear=clear)
     streams = [torch.cuda.Stream(dev) for _ in range(P)]
     pbufs = [{} for _ in range(P)]
 
@@ -874,6 +881,7 @@ def bench_pipeline(args, wl):
                    "alignment_cells_per_step": cells, "W": W, "k": k},
         "reads_per_s": round(rb.n_reads / flight_ms * 1e3, 1),
         "batches_in_flight": P,
+        "alignment_launch": {"workers": args.workers} if args.workers > 0 else "one wavefront per read",
         "one_batch_alone": {"ms": round(wall_ms, 3), "g_samples_per_s": round(S / wall_ms / 1e6, 3),
                             "stage_ms_median": med},
         "alignment_gcups_alone": round(cells / (med["align"] / 1e3) / 1e9, 1),
