@@ -209,6 +209,58 @@ __device__ __forceinline__ uint32_t row_ror(uint32_t v) {
  * (QT: long long, or double, exact for NS * 2^30 < 2^53).
  * Thread t takes PER_ consecutive samples; the sums are scanned over the wave
  * and over the waves.  Ends with a barrier. */
+/* inclusive scan over the 64 lanes of a wavefront by DPP: within each row
+ * of 16 lanes by shifts of 1, 2, 4 and 8 (lanes without a source add 0),
+ * then lane 15 of each row into the next row and lane 31 into the upper
+ * half */
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+__device__ __forceinline__ int wave_scan(int v) {
+  v += dpp_i<0x111, 0xF>(v); /* row_shr:1 */
+  v += dpp_i<0x112, 0xF>(v); /* row_shr:2 */
+  v += dpp_i<0x114, 0xF>(v); /* row_shr:4 */
+  v += dpp_i<0x118, 0xF>(v); /* row_shr:8 */
+  v += dpp_i<0x142, 0xA>(v); /* row_bcast:15 into rows 1 and 3 */
+  v += dpp_i<0x143, 0xC>(v); /* row_bcast:31 into rows 2 and 3 */
+  return v;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)dpp_i<CTRL, ROWS>((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)dpp_i<CTRL, ROWS>((int)(uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+/* the same over 64-bit integers, and over doubles that hold integers below
+ * 2^53 (every sum exact) */
+__device__ __forceinline__ double wave_scan(double v) {
+  v += dpp_d<0x111, 0xF>(v);
+  v += dpp_d<0x112, 0xF>(v);
+  v += dpp_d<0x114, 0xF>(v);
+  v += dpp_d<0x118, 0xF>(v);
+  v += dpp_d<0x142, 0xA>(v);
+  v += dpp_d<0x143, 0xC>(v);
+  return v;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ long long dpp_l(long long v) {
+  const uint64_t b = (uint64_t)v;
+  const uint32_t lo = (uint32_t)dpp_i<CTRL, ROWS>((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)dpp_i<CTRL, ROWS>((int)(uint32_t)(b >> 32));
+  return (long long)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ long long wave_scan(long long v) {
+  v += dpp_l<0x111, 0xF>(v);
+  v += dpp_l<0x112, 0xF>(v);
+  v += dpp_l<0x114, 0xF>(v);
+  v += dpp_l<0x118, 0xF>(v);
+  v += dpp_l<0x142, 0xA>(v);
+  v += dpp_l<0x143, 0xC>(v);
+  return v;
+}
+
 template <int NS, typename QT>
 __device__ __forceinline__ void stage_prefix(const int16_t *x, int64_t base, int64_t lim, int *P, QT *PQ, int *wsum,
                                              QT *wsq) {
@@ -225,16 +277,8 @@ __device__ __forceinline__ void stage_prefix(const int16_t *x, int64_t base, int
     s += v[e];
     q += (QT)(v[e] * v[e]);
   }
-  int si = s;
-  QT qi = q;
-  for (int d = 1; d < 64; d <<= 1) {
-    const int so = __shfl_up(si, d, 64);
-    const QT qo = __shfl_up(qi, d, 64);
-    if (lane >= d) {
-      si += so;
-      qi += qo;
-    }
-  }
+  const int si = wave_scan(s);
+  const QT qi = wave_scan(q);
   if (lane == 63) {
     wsum[wave] = si;
     wsq[wave] = qi;
