@@ -562,7 +562,11 @@ __global__ __launch_bounds__(THREADS) void k_ed_events(DetectArgs a) {
       q += v * v;
     }
     const int64_t len = b1 - b0;
-    const double m = (double)s / (double)len;
+    /* an event is no longer than its read (< 2^31 samples): its length
+     * converts from 32 bits, to the same value */
+    const int32_t len32 = (int32_t)len;
+    const double dlen = (double)len32;
+    const double m = (double)s / dlen;
     /* len^2 times the population variance, exact, rounded once to double:
      * below 2^16 samples len * Q and S^2 stay below 2^62 (samples are 16-bit),
      * so 64 bits hold it; longer events take 128 */
@@ -584,8 +588,8 @@ __global__ __launch_bounds__(THREADS) void k_ed_events(DetectArgs a) {
     }
     float *ev = a.events + 3 * idx;
     ev[0] = (float)((m + off) * sc);
-    ev[1] = (float)(__builtin_sqrt(vd) / (double)len * sc);
-    ev[2] = (float)len;
+    ev[1] = (float)(__builtin_sqrt(vd) / dlen * sc);
+    ev[2] = (float)len32;
   }
 }
 
