@@ -533,12 +533,13 @@ __global__ __launch_bounds__(THREADS) void k_ed_events(DetectArgs a) {
     if (threadIdx.x == 0 && first) starts[0] = 0;
   }
   __syncthreads();
+  /* a wavefront holds one flag word (k & 63 is the lane): a set bit's rank
+   * in it is the count of set bits of the lanes below (mbcnt) */
   for (int k = threadIdx.x; k < TS; k += THREADS) {
     const uint64_t m = wf[k >> 6];
-    const int b = k & 63;
-    if ((m >> b) & 1u) {
-      const uint64_t below = b ? (m & ((1ull << b) - 1u)) : 0ull;
-      starts[wpre[k >> 6] + (uint32_t)__popcll(below)] = (int32_t)(i0 + k);
+    if ((m >> (k & 63)) & 1u) {
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      starts[wpre[k >> 6] + below] = (int32_t)(i0 + k);
     }
   }
   __syncthreads();
@@ -566,14 +567,16 @@ __global__ __launch_bounds__(THREADS) void k_ed_events(DetectArgs a) {
      * converts from 32 bits, to the same value */
     const int32_t len32 = (int32_t)len;
     const double dlen = (double)len32;
-    const double m = (double)s / dlen;
     /* len^2 times the population variance, exact, rounded once to double:
-     * below 2^16 samples len * Q and S^2 stay below 2^62 (samples are 16-bit),
-     * so 64 bits hold it; longer events take 128 */
-    double vd;
+     * below 2^16 samples S fits 32 bits and len * Q and S^2 stay below 2^62
+     * (samples are 16-bit), so 64 bits hold it; longer events take 128 */
+    double m, vd;
     if (len < 65536) {
-      vd = (double)(uint64_t)(len * q - s * s);
+      const int32_t s32 = (int32_t)s;
+      m = (double)s32 / dlen;
+      vd = (double)(uint64_t)((int64_t)len32 * q - (int64_t)s32 * s32);
     } else {
+      m = (double)s / dlen;
       const unsigned __int128 vv = (unsigned __int128)((__int128)len * q - (__int128)s * s);
       const uint64_t hi = (uint64_t)(vv >> 64);
       if (hi == 0) {
