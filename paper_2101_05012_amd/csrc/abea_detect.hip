@@ -36,6 +36,9 @@
  *                  the read's next tiles, and one thread per event for its
  *                  statistics;
  *   k_ed_offsets   each read's first event.
+ * Both streaming kernels stage their samples as prefix sums with wavefront
+ * scans by DPP (no LDS permutes), and the statistics share the prefix
+ * sums' LDS once those are no longer read.
  */
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
