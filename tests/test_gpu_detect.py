@@ -129,6 +129,38 @@ def test_other_detectors(aligner, oracle_mod, m6, params):
         compare(f"{tag} {params}", ev, eo, want_ev, want_eo)
 
 
+def test_long_events_wide_variance(aligner, oracle_mod):
+    """Events far longer than a tile and than the 2^16 samples below which the
+    events' variance is taken in 64 bits: full-range uniform noise under
+    thresholds no finite statistic of two-sample windows reaches in practice
+    (t^2 above 10^6), so each read is one event or very few; at 300000 samples
+    len * Q - S^2 exceeds 2^64, the 128-bit path's rounding with a sticky
+    bit."""
+    rng = np.random.default_rng(44)
+
+    def rr(x):
+        return synth.RawRead(np.ascontiguousarray(x, np.int16), np.zeros(0, np.uint32), np.float32(2.0),
+                             np.float32(0.17), np.float32(1), np.float32(0), np.zeros(0, np.int64))
+
+    rb = synth.make_raw_batch([rr(rng.integers(-32768, 32768, n)) for n in (70000, 300000)])
+    params = (2, 2, 1000.0, 1000.0)
+    say(f"gpu: detect two long full-range reads with {params}")
+    pa = abea.detect_params(*params)
+    po = oracle_mod.ed_params(params[0], params[2], params[1], params[3])
+    want_ev, want_eo = oracle_events(oracle_mod, rb, po)
+    ev, eo = gpu_events_device(aligner, rb, pa)
+    compare("long events", ev, eo, want_ev, want_eo)
+    dur = want_ev[: int(want_eo[-1]), 2]
+    assert (dur > 65536).sum() >= 2, dur
+    # the longest event of the second read: len * Q - S^2 above 2^64
+    k0, k1 = int(want_eo[1]), int(want_eo[2])
+    j = k0 + int(np.argmax(dur[k0:k1]))
+    start = int(dur[k0:j].sum())
+    x = rb.raw[int(rb.sample_offset[1]) + start: int(rb.sample_offset[1]) + start + int(dur[j])].astype(np.int64)
+    n, S, Q = len(x), int(x.sum()), int((x * x).sum())
+    assert n * Q - S * S >= 2 ** 64
+
+
 def test_capacity(aligner, oracle_mod):
     rb = synth.workload_raw_batch("raw-4000-lognormal5kb", read_ids=range(20))
     want_ev, want_eo = oracle_events(oracle_mod, rb)
