@@ -73,7 +73,7 @@ def aligner(models):
 def test_meth_workload_subset_and_edges(aligner, models, oracle_mod):
     m, mm = models
     b = synth.workload_batch("meth-4000-lognormal5kb", m, read_ids=range(300))
-    # degenerate reads: no events, no k-mers, a bad rank, a read of k-mers that are all sites
+    # degenerate reads: no events, no k-mers, a bad rank, reads of k-mers that are all sites
     rng = np.random.default_rng(5)
     extra = [synth.Read(np.zeros((0, 3), np.float32), np.array([100, 200], np.uint32), np.float32(1), np.float32(0)),
              synth.Read(np.ones((5, 3), np.float32) * 80, np.zeros(0, np.uint32), np.float32(1), np.float32(0)),
@@ -84,6 +84,18 @@ def test_meth_workload_subset_and_edges(aligner, models, oracle_mod):
     ev = np.repeat(m.level_mean[ranks], 2).astype(np.float32)
     extra.append(synth.Read(np.stack([ev, np.ones_like(ev), np.ones_like(ev)], 1).astype(np.float32), ranks,
                             np.float32(1), np.float32(0)))
+    # the 8192-element tiles of the scoring kernels at their edges, on reads
+    # whose k-mers are all sites: 8192 and 8193 k-mers (one k-mer tile, and one
+    # plus a tile of one k-mer), paths bounded by exactly 8192 and 8193 pairs
+    for nk, extra_ev in ((8192, 8192), (8193, 8193), (4096, 1), (4096, 2)):
+        rk = (cg | rng.integers(0, 256, nk)).astype(np.uint32)
+        lv = m.level_mean[rk].astype(np.float32)
+        rep = np.ones(nk, np.int64)  # one event per k-mer, a second for extra_ev of them
+        rep[rng.choice(nk, extra_ev, replace=False)] += 1
+        e = np.repeat(lv, rep)
+        assert len(e) == nk + extra_ev
+        extra.append(synth.Read(np.stack([e, np.ones_like(e), np.ones_like(e)], 1).astype(np.float32), rk,
+                                np.float32(1), np.float32(0)))
     b = synth.make_batch([b.read(i) for i in range(b.n_reads)] + extra)
     say("gpu: methylation, 300 reads and edge cases")
     n = compare("meth300", gpu_scores(aligner, b), oracle_scores(oracle_mod, b, m, mm))
