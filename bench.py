@@ -547,6 +547,16 @@ def bench_persistent(args, wl):
         alh.close()
         del sub
         out["serving"] = serving_level(args, dev)
+        # ultra-long reads: the longest reads' serial chains set the pass
+        log("bench: ultra-long reads (ultralong-200-w100)")
+        ua = argparse.Namespace(**vars(args))
+        ua.workload, ua.steps, ua.warmup = "ultralong-200-w100", 2, 1
+        ua.no_extras, ua.no_cpu_baseline, ua.tune, ua.backtrack_probe = True, True, False, False
+        ua.cpl, ua.wpg, ua.wps, ua.nb, ua.max_reads, ua.trace_budget_gb = -1, 0, 0, 0, 0, 0.0
+        uo = bench_persistent(ua, WORKLOADS["ultralong-200-w100"])
+        out["ultralong"] = {"workload": "ultralong-200-w100", "gcups": uo["value"], "ms_per_pass": uo["ms_per_step"],
+                            "reads_per_s": uo.get("reads_per_s"), "reads_ok": uo.get("reads_ok"),
+                            "steps": ua.steps, "roofline": uo["roofline"]}
     if tune_report:
         out["autotune"] = tune_report
     if args.backtrack_probe:
