@@ -554,6 +554,16 @@ def bench_persistent(args, wl):
         ua.no_extras, ua.no_cpu_baseline, ua.tune, ua.backtrack_probe = True, True, False, False
         ua.cpl, ua.wpg, ua.wps, ua.nb, ua.max_reads, ua.trace_budget_gb = -1, 0, 0, 0, 0, 0.0
         uo = bench_persistent(ua, WORKLOADS["ultralong-200-w100"])
+        # the raw-signal pipeline: detection, alignment and scoring in flight
+        log("bench: raw-signal pipeline (pipeline-4000-lognormal5kb)")
+        pa = argparse.Namespace(workload="pipeline-4000-lognormal5kb", steps=64, warmup=2, inflight=16,
+                                workers=320, no_cpu_baseline=True)
+        po_ = bench_pipeline(pa, WORKLOADS["pipeline-4000-lognormal5kb"])
+        out["pipeline"] = {"workload": "pipeline-4000-lognormal5kb", "g_samples_per_s": po_["value"],
+                           "ms_per_batch": po_["ms_per_step"], "batches": po_["steps"],
+                           "batches_in_flight": po_["batches_in_flight"], "reads_per_s": po_["reads_per_s"],
+                           "one_batch_alone_ms": po_["one_batch_alone"]["ms"],
+                           "sites_right_sign": po_["sites_right_sign"]}
         out["ultralong"] = {"workload": "ultralong-200-w100", "gcups": uo["value"], "ms_per_pass": uo["ms_per_step"],
                             "reads_per_s": uo.get("reads_per_s"), "reads_ok": uo.get("reads_ok"),
                             "steps": ua.steps, "roofline": uo["roofline"]}
