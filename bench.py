@@ -554,6 +554,14 @@ def bench_persistent(args, wl):
         ua.no_extras, ua.no_cpu_baseline, ua.tune, ua.backtrack_probe = True, True, False, False
         ua.cpl, ua.wpg, ua.wps, ua.nb, ua.max_reads, ua.trace_budget_gb = -1, 0, 0, 0, 0, 0.0
         uo = bench_persistent(ua, WORKLOADS["ultralong-200-w100"])
+        # the same job at W = 200 in its tuned form
+        log("bench: uneven-20000-w200")
+        wa = argparse.Namespace(**vars(ua))
+        wa.workload = "uneven-20000-w200"
+        wo = bench_persistent(wa, WORKLOADS["uneven-20000-w200"])
+        out["uneven_w200"] = {"workload": "uneven-20000-w200", "gcups": wo["value"], "ms_per_pass": wo["ms_per_step"],
+                              "reads_per_s": wo.get("reads_per_s"), "reads_ok": wo.get("reads_ok"),
+                              "launch": wo["config"]["launch"], "steps": wa.steps, "roofline": wo["roofline"]}
         # the raw-signal pipeline: detection, alignment and scoring in flight
         log("bench: raw-signal pipeline (pipeline-4000-lognormal5kb)")
         pa = argparse.Namespace(workload="pipeline-4000-lognormal5kb", steps=64, warmup=2, inflight=16,
